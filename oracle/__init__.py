@@ -1,0 +1,303 @@
+"""FP64 CPU oracle for surface-based fixation density maps (arXiv 2601.07571).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``.  The product library never imports
+it, and it imports nothing from the product library.
+
+The arithmetic lives in ``gm_oracle.c`` (plain C, FP64, ``-ffp-contract=off``),
+loaded here through ctypes; this module adds the per-scene orchestration and a
+second, pure-Python Philox4x32-10 used to pin the C one.
+
+Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
+  philox4x32_10 / philox_py ... pinned (published known answers, two codes)
+  triangle_areas .............. pinned (Heron in Kahan's ordering, closed forms)
+  mesh_weights / sample_count . pinned (exact integer brute force, k*area)
+  sample_scene ................ pinned (chi-square, KS, brute force, invariants)
+  pair_value / density ........ pinned (plane closed form, 4-sigma mass,
+                                 linearity, rigid motion, hand-computed cases)
+  visibility .................. pinned (brute force == BVH, convex sphere ==
+                                 front-facing, hand-placed occluders)
+  normalize ................... pinned (max == 1, range)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile gm_oracle.c into liboracle.so (gcc, FP64, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+             "-pthread", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.POINTER
+    c_f, c_d, c_i32, c_i64, c_u32, c_u64, c_u8 = (
+        ctypes.c_float, ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
+        ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint8)
+    lib.or_philox4x32_10.argtypes = [P(c_u32), P(c_u32), P(c_u32)]
+    lib.or_philox_stream.argtypes = [c_u64, c_i64, c_u32, c_u32, c_u64, P(c_u32)]
+    lib.or_triangle_areas.argtypes = [P(c_f), P(c_i32), c_i64, P(c_d)]
+    lib.or_mesh_weights.argtypes = [P(c_d), c_i64, P(c_u64), P(c_u64), P(c_i32)]
+    lib.or_mesh_weights.restype = c_u64
+    lib.or_sample_count.argtypes = [c_u64, c_i32, c_d]
+    lib.or_sample_count.restype = c_i64
+    lib.or_sample_mesh.argtypes = [P(c_f), P(c_i32), P(c_u64), c_i64, c_u32, c_u64, c_i64, c_i64,
+                                   P(c_i32), P(c_d), P(c_d), P(c_f), P(c_f)]
+    lib.or_scene_create.argtypes = [P(c_f), P(c_i32), P(c_i32), c_i64]
+    lib.or_scene_create.restype = ctypes.c_void_p
+    lib.or_scene_destroy.argtypes = [ctypes.c_void_p]
+    lib.or_visible.argtypes = [ctypes.c_void_p, P(c_d), P(c_d), c_i32, c_i32, ctypes.c_int, c_d,
+                               ctypes.c_int, P(ctypes.c_int)]
+    lib.or_visible.restype = ctypes.c_int
+    lib.or_pair_value.argtypes = [P(c_d), P(c_d), P(c_d), c_d, c_d, P(c_d), P(c_d)]
+    lib.or_pair_value.restype = ctypes.c_int
+    lib.or_density.argtypes = [ctypes.c_void_p, P(c_f), P(c_i32), P(c_i32), c_i64, P(c_f), P(c_f),
+                               P(c_f), c_i64, c_d, ctypes.c_int, c_d, ctypes.c_int, ctypes.c_int,
+                               P(c_d), P(c_d), P(c_i64)]
+    lib.or_pair_visibility.argtypes = [ctypes.c_void_p, P(c_f), P(c_i32), P(c_i32), P(c_f),
+                                       P(c_i64), P(c_i64), c_i64, ctypes.c_int, c_d, ctypes.c_int,
+                                       P(c_u8), P(c_u8)]
+    lib.or_normalize.argtypes = [P(c_d), c_i64, P(c_d)]
+    lib.or_normalize.restype = c_d
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+# ----------------------------------------------------------------------------
+# Philox4x32-10 (Salmon et al., SC'11)
+# ----------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key):
+    """C oracle: one block for counter (4 x u32) and key (2 x u32)."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib.or_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32), _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def philox_stream(first: int, n: int, w2: int, w3: int, seed: int):
+    """C oracle: blocks for counters (first+i as 64 bits, w2, w3), key = seed."""
+    lib = _load()
+    out = np.zeros((n, 4), dtype=np.uint32)
+    lib.or_philox_stream(first, n, w2, w3, seed, _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def philox_py(ctr, key):
+    """Second, independent Philox4x32-10 in Python integers (pins the C one)."""
+    m = (0xD2511F53, 0xCD9E8D57)
+    weyl = (0x9E3779B9, 0xBB67AE85)
+    mask = 0xFFFFFFFF
+    c = [int(v) & mask for v in ctr]
+    k = [int(v) & mask for v in key]
+    for _ in range(10):
+        a = m[0] * c[0]
+        b = m[1] * c[2]
+        c = [((b >> 32) ^ c[1] ^ k[0]) & mask, b & mask,
+             ((a >> 32) ^ c[3] ^ k[1]) & mask, a & mask]
+        k = [(k[0] + weyl[0]) & mask, (k[1] + weyl[1]) & mask]
+    return c
+
+
+# ----------------------------------------------------------------------------
+# Areas, weights, counts, sampling (Sec. 3.1)
+# ----------------------------------------------------------------------------
+
+def triangle_areas(V, I):
+    lib = _load()
+    V = np.ascontiguousarray(V, dtype=np.float32)
+    I = np.ascontiguousarray(I, dtype=np.int32)
+    A = np.zeros(len(I), dtype=np.float64)
+    lib.or_triangle_areas(_ptr(V, ctypes.c_float), _ptr(I, ctypes.c_int32), len(I), _ptr(A, ctypes.c_double))
+    return A
+
+
+def mesh_weights(A):
+    """(W uint64[T], C inclusive uint64[T], S, total)."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    W = np.zeros(len(A), dtype=np.uint64)
+    C = np.zeros(len(A), dtype=np.uint64)
+    S = ctypes.c_int32(0)
+    tot = lib.or_mesh_weights(_ptr(A, ctypes.c_double), len(A), _ptr(W, ctypes.c_uint64),
+                              _ptr(C, ctypes.c_uint64), ctypes.byref(S))
+    return W, C, int(S.value), int(tot)
+
+
+def sample_count(Wm: int, S: int, k: float) -> int:
+    return int(_load().or_sample_count(Wm, S, k))
+
+
+@dataclass
+class OracleSamples:
+    tri_local: np.ndarray    # int32 [N], mesh-local triangle index
+    tri: np.ndarray          # int32 [N], scene-global triangle index
+    mesh: np.ndarray         # int32 [N]
+    bary64: np.ndarray       # float64 [N][2]  (b1, b2)
+    pos64: np.ndarray        # float64 [N][3]
+    bary32: np.ndarray       # float32 [N][2]
+    pos32: np.ndarray        # float32 [N][3]
+    counts: np.ndarray       # int64 [M]
+    S: np.ndarray            # int32 [M]
+    Wm: np.ndarray           # uint64 [M]
+
+
+def sample_scene(meshes, k: float, seed: int) -> OracleSamples:
+    """Samples of every mesh, mesh order then Philox counter order."""
+    lib = _load()
+    parts = []
+    counts, Ss, Wms = [], [], []
+    tri_base = 0
+    for m, (V, I) in enumerate(meshes):
+        V = np.ascontiguousarray(V, dtype=np.float32)
+        I = np.ascontiguousarray(I, dtype=np.int32)
+        A = triangle_areas(V, I)
+        W, C, S, Wm = mesh_weights(A)
+        n = sample_count(Wm, S, k) if Wm > 0 else 0
+        counts.append(n); Ss.append(S); Wms.append(Wm)
+        tri = np.zeros(n, np.int32)
+        b64 = np.zeros((n, 2)); p64 = np.zeros((n, 3))
+        b32 = np.zeros((n, 2), np.float32); p32 = np.zeros((n, 3), np.float32)
+        if n > 0:
+            lib.or_sample_mesh(_ptr(V, ctypes.c_float), _ptr(I, ctypes.c_int32), _ptr(C, ctypes.c_uint64),
+                               len(I), m, seed, 0, n, _ptr(tri, ctypes.c_int32), _ptr(b64, ctypes.c_double),
+                               _ptr(p64, ctypes.c_double), _ptr(b32, ctypes.c_float), _ptr(p32, ctypes.c_float))
+        parts.append((tri, tri + tri_base, np.full(n, m, np.int32), b64, p64, b32, p32))
+        tri_base += len(I)
+    cat = [np.concatenate([p[i] for p in parts]) if parts else None for i in range(7)]
+    return OracleSamples(cat[0].astype(np.int32), cat[1].astype(np.int32), cat[2].astype(np.int32),
+                         cat[3], cat[4], cat[5].astype(np.float32), cat[6].astype(np.float32),
+                         np.array(counts, np.int64), np.array(Ss, np.int32), np.array(Wms, np.uint64))
+
+
+# ----------------------------------------------------------------------------
+# Density (Sec. 3.2)
+# ----------------------------------------------------------------------------
+
+OCC_NONE, OCC_SELF, OCC_FULL = 0, 1, 2
+EPS_V = 1e-4
+
+
+class Scene:
+    """Triangle soup of all meshes with the oracle's own median-split BVH."""
+
+    def __init__(self, meshes):
+        lib = _load()
+        Vs, Is, Ms = [], [], []
+        vbase = 0
+        for m, (V, I) in enumerate(meshes):
+            V = np.asarray(V, np.float32); I = np.asarray(I, np.int32)
+            Vs.append(V); Is.append(I + vbase); Ms.append(np.full(len(I), m, np.int32))
+            vbase += len(V)
+        self.V = np.ascontiguousarray(np.concatenate(Vs) if Vs else np.zeros((0, 3), np.float32))
+        self.I = np.ascontiguousarray(np.concatenate(Is) if Is else np.zeros((0, 3), np.int32))
+        self.tri_mesh = np.ascontiguousarray(np.concatenate(Ms) if Ms else np.zeros(0, np.int32))
+        self._h = lib.or_scene_create(_ptr(self.V, ctypes.c_float), _ptr(self.I, ctypes.c_int32),
+                                      _ptr(self.tri_mesh, ctypes.c_int32), len(self.I))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.or_scene_destroy(self._h)
+            self._h = None
+
+    def visible(self, e, x, own_tri=-1, own_mesh=-1, mode=OCC_FULL, eps=EPS_V, brute=False):
+        e = np.ascontiguousarray(e, np.float64); x = np.ascontiguousarray(x, np.float64)
+        fr = ctypes.c_int(0)
+        v = _lib.or_visible(self._h, _ptr(e, ctypes.c_double), _ptr(x, ctypes.c_double), own_tri, own_mesh,
+                            mode, eps, int(brute), ctypes.byref(fr))
+        return bool(v), bool(fr.value)
+
+    def pair_visibility(self, pos, tri, mesh, eye, pair_s, pair_f, mode=OCC_FULL, eps=EPS_V, brute=False):
+        pos = np.ascontiguousarray(pos, np.float32); eye = np.ascontiguousarray(eye, np.float32)
+        tri = None if tri is None else np.ascontiguousarray(tri, np.int32)
+        mesh = None if mesh is None else np.ascontiguousarray(mesh, np.int32)
+        ps = np.ascontiguousarray(pair_s, np.int64); pf = np.ascontiguousarray(pair_f, np.int64)
+        vis = np.zeros(len(ps), np.uint8); frag = np.zeros(len(ps), np.uint8)
+        _lib.or_pair_visibility(self._h, _ptr(pos, ctypes.c_float), _ptr(tri, ctypes.c_int32),
+                                _ptr(mesh, ctypes.c_int32), _ptr(eye, ctypes.c_float),
+                                _ptr(ps, ctypes.c_int64), _ptr(pf, ctypes.c_int64), len(ps), mode, eps,
+                                int(brute), _ptr(vis, ctypes.c_uint8), _ptr(frag, ctypes.c_uint8))
+        return vis.astype(bool), frag.astype(bool)
+
+
+def pair_value(x, e, r, t, theta_deg):
+    """(in_cone, g, margin) of one pair in FP64."""
+    lib = _load()
+    x = np.ascontiguousarray(x, np.float64); e = np.ascontiguousarray(e, np.float64)
+    r = np.ascontiguousarray(r, np.float64)
+    g = ctypes.c_double(0.0); mg = ctypes.c_double(0.0)
+    sigma = math.tan(math.radians(theta_deg))
+    inside = lib.or_pair_value(_ptr(x, ctypes.c_double), _ptr(e, ctypes.c_double), _ptr(r, ctypes.c_double),
+                               float(t), sigma, ctypes.byref(g), ctypes.byref(mg))
+    return bool(inside), g.value, mg.value
+
+
+@dataclass
+class OracleDensity:
+    rho: np.ndarray      # float64 [n], raw density
+    budget: np.ndarray   # float64 [n], sum of g over boundary-ambiguous / fragile pairs
+    stats: np.ndarray    # int64 [n][4]: in-cone, visible, ambiguous, fragile
+
+
+def density(scene: Scene | None, pos, tri, mesh, eye, gaze, dur, theta_deg, mode=OCC_FULL,
+            eps=EPS_V, brute=False, nthreads=None) -> OracleDensity:
+    lib = _load()
+    pos = np.ascontiguousarray(pos, np.float32).reshape(-1, 3)
+    n = len(pos)
+    tri = None if tri is None else np.ascontiguousarray(tri, np.int32)
+    mesh = None if mesh is None else np.ascontiguousarray(mesh, np.int32)
+    eye = np.ascontiguousarray(eye, np.float32).reshape(-1, 3)
+    gaze = np.ascontiguousarray(gaze, np.float32).reshape(-1, 3)
+    dur = np.ascontiguousarray(dur, np.float32).reshape(-1)
+    F = len(eye)
+    rho = np.zeros(n); budget = np.zeros(n); stats = np.zeros((n, 4), np.int64)
+    if scene is None:
+        scene = Scene([])
+        mode = OCC_NONE
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    lib.or_density(scene._h, _ptr(pos, ctypes.c_float), _ptr(tri, ctypes.c_int32), _ptr(mesh, ctypes.c_int32),
+                   n, _ptr(eye, ctypes.c_float), _ptr(gaze, ctypes.c_float), _ptr(dur, ctypes.c_float), F,
+                   float(theta_deg), mode, eps, int(brute), int(nthreads), _ptr(rho, ctypes.c_double),
+                   _ptr(budget, ctypes.c_double), _ptr(stats, ctypes.c_int64))
+    return OracleDensity(rho, budget, stats)
+
+
+def normalize(rho):
+    lib = _load()
+    rho = np.ascontiguousarray(rho, np.float64)
+    out = np.zeros_like(rho)
+    mx = lib.or_normalize(_ptr(rho, ctypes.c_double), len(rho), _ptr(out, ctypes.c_double))
+    return out, mx

@@ -1,0 +1,561 @@
+/*
+ * gm_oracle.c -- plain FP64 CPU oracle for surface-based fixation density maps
+ * (Javerliat & Lavoue, "GPU accelerated surface-based gaze mapping for XR
+ * experiences", arXiv 2601.07571).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or helper with
+ * the HIP path.  Built with -O2 -ffp-contract=off and no fast-math so that
+ * every FP64 operation below is a single IEEE round-to-nearest operation in
+ * the order written.
+ *
+ * What it computes, step by step, in the paper's notation:
+ *   - triangle area (Sec. 3.1.2, the area that feeds the adaptive sampling
+ *     rule; written as half the cross-product norm, pinned against Heron);
+ *   - area-proportional surface sampling (Sec. 3.1: samples per square metre
+ *     independent of mesh resolution) as fixed-point area weights, an exact
+ *     integer prefix sum, Philox4x32-10 counters and a square-root warp;
+ *   - the duration-weighted angular Gaussian of Sec. 3.2.1 (d1, d2, sigma,
+ *     d, sigma_k, g), truncated at the 4-sigma cone (Sec. 3.2, Sec. 3.3.2);
+ *   - visibility (Sec. 3.2.2) as an exact segment test eye -> sample against
+ *     the occluding triangles (Moller-Trumbore in FP64), brute force or over
+ *     the oracle's own median-split BVH;
+ *   - normalisation by the maximum (Sec. 3.2.3).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from the description in Salmon, Moraes, Dror and Shaw,    */
+/* "Parallel random numbers: as easy as 1, 2, 3" (SC'11): ten rounds of two */
+/* 32x32->64 multiplications whose high halves are xored with the other two */
+/* counter words and the round key; the key is bumped by the Weyl constants */
+/* (golden ratio and sqrt(3)-1 in 32-bit fixed point) between rounds.       */
+/* ------------------------------------------------------------------------ */
+static const uint32_t PHILOX_MUL_A = 0xD2511F53u;
+static const uint32_t PHILOX_MUL_B = 0xCD9E8D57u;
+static const uint32_t PHILOX_WEYL_A = 0x9E3779B9u;
+static const uint32_t PHILOX_WEYL_B = 0xBB67AE85u;
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod_a = (uint64_t)PHILOX_MUL_A * (uint64_t)x[0];
+        uint64_t prod_b = (uint64_t)PHILOX_MUL_B * (uint64_t)x[2];
+        uint32_t y0 = (uint32_t)(prod_b >> 32) ^ x[1] ^ k[0];
+        uint32_t y1 = (uint32_t)prod_b;
+        uint32_t y2 = (uint32_t)(prod_a >> 32) ^ x[3] ^ k[1];
+        uint32_t y3 = (uint32_t)prod_a;
+        x[0] = y0; x[1] = y1; x[2] = y2; x[3] = y3;
+        k[0] += PHILOX_WEYL_A;
+        k[1] += PHILOX_WEYL_B;
+    }
+    out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; out[3] = x[3];
+}
+
+/* n consecutive counters (c0 + i, c1, c2, c3) as 64-bit increments of the low words. */
+void or_philox_stream(uint64_t first, int64_t n, uint32_t w2, uint32_t w3,
+                      uint64_t seed, uint32_t* out /* [n][4] */)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t j = first + (uint64_t)i;
+        uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(j >> 32), w2, w3};
+        or_philox4x32_10(ctr, key, out + 4 * i);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Triangle area (Sec. 3.1.2).  The paper evaluates it with Heron's formula; */
+/* here it is half the norm of the edge cross product, the same quantity,   */
+/* evaluated in one fixed FP64 order:                                       */
+/*   u = v1 - v0, w = v2 - v0, c = u x w,                                   */
+/*   A = 0.5 * sqrt((cx*cx + cy*cy) + cz*cz).                               */
+/* ------------------------------------------------------------------------ */
+static double tri_area_fp64(const float* a, const float* b, const float* c)
+{
+    double ux = (double)b[0] - (double)a[0];
+    double uy = (double)b[1] - (double)a[1];
+    double uz = (double)b[2] - (double)a[2];
+    double wx = (double)c[0] - (double)a[0];
+    double wy = (double)c[1] - (double)a[1];
+    double wz = (double)c[2] - (double)a[2];
+    double cx = uy * wz - uz * wy;
+    double cy = uz * wx - ux * wz;
+    double cz = ux * wy - uy * wx;
+    double s = cx * cx + cy * cy;
+    s = s + cz * cz;
+    return 0.5 * sqrt(s);
+}
+
+void or_triangle_areas(const float* V, const int32_t* I, int64_t T, double* A)
+{
+    for (int64_t i = 0; i < T; ++i)
+        A[i] = tri_area_fp64(V + 3 * (int64_t)I[3 * i], V + 3 * (int64_t)I[3 * i + 1],
+                             V + 3 * (int64_t)I[3 * i + 2]);
+}
+
+/*
+ * Fixed-point area weights of one mesh.  Sampling must put samples in
+ * proportion to area (Sec. 3.1.2: a target number of samples per square
+ * metre).  Areas are turned into integers W_i = floor(A_i * 2^S) with one
+ * power-of-two scale per mesh, chosen from the largest area M and the
+ * triangle count T so that the mesh total stays below 2^52:
+ *   T*M = f * 2^e (f in [0.5, 1)),  S = 52 - e.
+ * C is the inclusive prefix sum of W (exact integer arithmetic).
+ * Returns the total W_m (= C[T-1]) and writes S.  A zero-area mesh gives 0.
+ */
+uint64_t or_mesh_weights(const double* A, int64_t T, uint64_t* W, uint64_t* C, int32_t* S_out)
+{
+    double M = 0.0;
+    for (int64_t i = 0; i < T; ++i)
+        if (A[i] > M) M = A[i];
+    if (!(M > 0.0)) {
+        for (int64_t i = 0; i < T; ++i) { W[i] = 0; C[i] = 0; }
+        *S_out = 0;
+        return 0;
+    }
+    int e = 0;
+    (void)frexp((double)T * M, &e);
+    int S = 52 - e;
+    uint64_t run = 0;
+    for (int64_t i = 0; i < T; ++i) {
+        double scaled = floor(ldexp(A[i], S));
+        W[i] = (uint64_t)scaled;
+        run += W[i];
+        C[i] = run;
+    }
+    *S_out = S;
+    return run;
+}
+
+/* Samples of a mesh: round(k * area), with area = W_m * 2^-S. */
+int64_t or_sample_count(uint64_t Wm, int32_t S, double k)
+{
+    double area = ldexp((double)Wm, -S);
+    return (int64_t)floor(area * k + 0.5);
+}
+
+/*
+ * Area-weighted sample placement for samples j in [j0, j0+n) of mesh `mesh_id`.
+ * Counter (j_lo, j_hi, mesh_id, 0), key (seed_lo, seed_hi):
+ *   U = x0 * 2^32 + x1, target = floor(U * W_m / 2^64),
+ *   tri = smallest i with C_i > target          (triangle chosen with
+ *                                                probability W_i / W_m);
+ *   u = x2 / 2^32, v = x3 / 2^32, s = sqrt(u),
+ *   (b0, b1, b2) = (1 - s, s (1 - v), s v)     (uniform in the triangle,
+ *                                                Osada et al. 2002);
+ *   P = (b0 v0 + b1 v1) + b2 v2 in FP64, rounded to FP32.
+ * tri_out gets the mesh-local triangle index; bary_out (b1, b2) and pos_out
+ * the FP64 values, pos32_out / bary32_out their FP32 roundings.
+ */
+void or_sample_mesh(const float* V, const int32_t* I, const uint64_t* C, int64_t T,
+                    uint32_t mesh_id, uint64_t seed, int64_t j0, int64_t n,
+                    int32_t* tri_out, double* bary_out, double* pos_out,
+                    float* bary32_out, float* pos32_out)
+{
+    uint64_t Wm = C[T - 1];
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t s = 0; s < n; ++s) {
+        uint64_t j = (uint64_t)(j0 + s);
+        uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(j >> 32), mesh_id, 0u};
+        uint32_t x[4];
+        or_philox4x32_10(ctr, key, x);
+        uint64_t U = ((uint64_t)x[0] << 32) | (uint64_t)x[1];
+        uint64_t target = (uint64_t)(((unsigned __int128)U * (unsigned __int128)Wm) >> 64);
+        /* linear-time definition would be: first i with C[i] > target; bisection gives the same i */
+        int64_t lo = 0, hi = T - 1;
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (C[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        int64_t t = lo;
+        double u = ldexp((double)x[2], -32);
+        double v = ldexp((double)x[3], -32);
+        double su = sqrt(u);
+        double b1 = su * (1.0 - v);
+        double b2 = su * v;
+        double b0 = 1.0 - su;
+        const float* p0 = V + 3 * (int64_t)I[3 * t];
+        const float* p1 = V + 3 * (int64_t)I[3 * t + 1];
+        const float* p2 = V + 3 * (int64_t)I[3 * t + 2];
+        tri_out[s] = (int32_t)t;
+        if (bary_out) { bary_out[2 * s] = b1; bary_out[2 * s + 1] = b2; }
+        if (bary32_out) { bary32_out[2 * s] = (float)b1; bary32_out[2 * s + 1] = (float)b2; }
+        for (int c = 0; c < 3; ++c) {
+            double acc = b0 * (double)p0[c];
+            acc = acc + b1 * (double)p1[c];
+            acc = acc + b2 * (double)p2[c];
+            if (pos_out) pos_out[3 * s + c] = acc;
+            if (pos32_out) pos32_out[3 * s + c] = (float)acc;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Visibility (Sec. 3.2.2).  A sample x is visible from eye e when no       */
+/* occluding triangle other than the sample's own crosses the segment       */
+/* e + tau (x - e) at 0 < tau < 1 - eps.  Triangle test: Moller-Trumbore in  */
+/* FP64, inclusive edges, parallel (det == 0) is a miss.                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double lo[3], hi[3];
+    int32_t left, right;   /* children, or -1 */
+    int32_t first, count;  /* leaf triangle range in `order` */
+} or_node;
+
+typedef struct or_scene {
+    int64_t T;
+    double* v;           /* [T][9] triangle vertices, FP64 (exact copies of FP32) */
+    int32_t* tri_mesh;   /* [T] */
+    int32_t* order;      /* [T] triangle ids in leaf order */
+    or_node* nodes;
+    int64_t n_nodes, cap_nodes;
+} or_scene;
+
+static void node_bounds(or_scene* sc, int32_t first, int32_t count, double lo[3], double hi[3])
+{
+    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    for (int32_t i = first; i < first + count; ++i) {
+        const double* t = sc->v + 9 * (int64_t)sc->order[i];
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 3; ++a) {
+                double c = t[3 * k + a];
+                if (c < lo[a]) lo[a] = c;
+                if (c > hi[a]) hi[a] = c;
+            }
+    }
+    /* pad so that rounding in the box test can never cull a true hit */
+    for (int a = 0; a < 3; ++a) {
+        double pad = 1e-9 * (fabs(lo[a]) + fabs(hi[a]) + (hi[a] - lo[a])) + 1e-12;
+        lo[a] -= pad; hi[a] += pad;
+    }
+}
+
+static double centroid(const or_scene* sc, int32_t t, int a)
+{
+    const double* p = sc->v + 9 * (int64_t)t;
+    return (p[a] + p[3 + a] + p[6 + a]) / 3.0;
+}
+
+static int32_t build_node(or_scene* sc, int32_t first, int32_t count)
+{
+    if (sc->n_nodes == sc->cap_nodes) {
+        sc->cap_nodes = sc->cap_nodes ? 2 * sc->cap_nodes : 1024;
+        sc->nodes = (or_node*)realloc(sc->nodes, sizeof(or_node) * (size_t)sc->cap_nodes);
+    }
+    int32_t id = (int32_t)sc->n_nodes++;
+    or_node nd;
+    node_bounds(sc, first, count, nd.lo, nd.hi);
+    nd.left = nd.right = -1;
+    nd.first = first; nd.count = count;
+    if (count > 4) {
+        /* median split of centroids along the widest centroid axis */
+        double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int32_t i = first; i < first + count; ++i)
+            for (int a = 0; a < 3; ++a) {
+                double c = centroid(sc, sc->order[i], a);
+                if (c < clo[a]) clo[a] = c;
+                if (c > chi[a]) chi[a] = c;
+            }
+        int ax = 0;
+        for (int a = 1; a < 3; ++a)
+            if (chi[a] - clo[a] > chi[ax] - clo[ax]) ax = a;
+        int32_t mid = count / 2;
+        /* nth_element by quickselect on centroid[ax] */
+        int32_t lo = first, hi = first + count - 1, k = first + mid;
+        while (lo < hi) {
+            double pivot = centroid(sc, sc->order[(lo + hi) / 2], ax);
+            int32_t i = lo, j = hi;
+            while (i <= j) {
+                while (centroid(sc, sc->order[i], ax) < pivot) ++i;
+                while (centroid(sc, sc->order[j], ax) > pivot) --j;
+                if (i <= j) { int32_t tmp = sc->order[i]; sc->order[i] = sc->order[j]; sc->order[j] = tmp; ++i; --j; }
+            }
+            if (k <= j) hi = j; else if (k >= i) lo = i; else break;
+        }
+        nd.count = 0;
+        sc->nodes[id] = nd;
+        int32_t l = build_node(sc, first, mid);
+        int32_t r = build_node(sc, first + mid, count - mid);
+        sc->nodes[id].left = l;
+        sc->nodes[id].right = r;
+        return id;
+    }
+    sc->nodes[id] = nd;
+    return id;
+}
+
+or_scene* or_scene_create(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T)
+{
+    or_scene* sc = (or_scene*)calloc(1, sizeof(or_scene));
+    sc->T = T;
+    sc->v = (double*)malloc(sizeof(double) * 9 * (size_t)(T > 0 ? T : 1));
+    sc->tri_mesh = (int32_t*)malloc(sizeof(int32_t) * (size_t)(T > 0 ? T : 1));
+    sc->order = (int32_t*)malloc(sizeof(int32_t) * (size_t)(T > 0 ? T : 1));
+    for (int64_t t = 0; t < T; ++t) {
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 3; ++a)
+                sc->v[9 * t + 3 * k + a] = (double)V[3 * (int64_t)I[3 * t + k] + a];
+        sc->tri_mesh[t] = tri_mesh[t];
+        sc->order[t] = (int32_t)t;
+    }
+    if (T > 0) build_node(sc, 0, (int32_t)T);
+    return sc;
+}
+
+void or_scene_destroy(or_scene* sc)
+{
+    if (!sc) return;
+    free(sc->v); free(sc->tri_mesh); free(sc->order); free(sc->nodes);
+    free(sc);
+}
+
+/* bookkeeping tolerances for "fragile" decisions (comparison only) */
+static const double FRAG_BARY = 1e-4;
+static const double FRAG_TAU = 1e-5;
+
+/* Moller-Trumbore in FP64.  Returns 1 on a hit with 0 < tau < 1-eps (edges
+ * inclusive), 0 otherwise; sets *near when the decision sits within the
+ * bookkeeping tolerances of flipping. */
+static int seg_tri(const double o[3], const double d[3], const double* t, double eps, int* near)
+{
+    double e1[3] = {t[3] - t[0], t[4] - t[1], t[5] - t[2]};
+    double e2[3] = {t[6] - t[0], t[7] - t[1], t[8] - t[2]};
+    double pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+    double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+    *near = 0;
+    if (det == 0.0) return 0;
+    double inv = 1.0 / det;
+    double tv[3] = {o[0] - t[0], o[1] - t[1], o[2] - t[2]};
+    double u = (tv[0] * pv[0] + tv[1] * pv[1] + tv[2] * pv[2]) * inv;
+    double qv[3] = {tv[1] * e1[2] - tv[2] * e1[1], tv[2] * e1[0] - tv[0] * e1[2], tv[0] * e1[1] - tv[1] * e1[0]};
+    double v = (d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2]) * inv;
+    double tau = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * inv;
+    double w = 1.0 - u - v;
+    double tmax = 1.0 - eps;
+    int hit = (u >= 0.0 && v >= 0.0 && w >= 0.0 && tau > 0.0 && tau < tmax);
+    int inside_loose = (u >= -FRAG_BARY && v >= -FRAG_BARY && w >= -FRAG_BARY &&
+                        tau > -FRAG_TAU && tau < tmax + FRAG_TAU);
+    int inside_tight = (u >= FRAG_BARY && v >= FRAG_BARY && w >= FRAG_BARY &&
+                        tau > FRAG_TAU && tau < tmax - FRAG_TAU);
+    *near = inside_loose && !inside_tight;
+    return hit;
+}
+
+static int seg_box(const double o[3], const double d[3], const double lo[3], const double hi[3], double tmax)
+{
+    double t0 = 0.0, t1 = tmax;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (o[a] < lo[a] || o[a] > hi[a]) return 0;
+            continue;
+        }
+        double ta = (lo[a] - o[a]) / d[a];
+        double tb = (hi[a] - o[a]) / d[a];
+        if (ta > tb) { double x = ta; ta = tb; tb = x; }
+        if (ta > t0) t0 = ta;
+        if (tb < t1) t1 = tb;
+        if (t0 > t1) return 0;
+    }
+    return 1;
+}
+
+/* mode: 0 = no occlusion, 1 = own mesh occludes, 2 = every mesh occludes.
+ * Returns 1 when visible.  *fragile (optional) = some triangle's decision is
+ * within the bookkeeping tolerances and no triangle occludes robustly. */
+int or_visible(const or_scene* sc, const double e[3], const double x[3], int32_t own_tri,
+               int32_t own_mesh, int mode, double eps, int brute, int* fragile)
+{
+    if (fragile) *fragile = 0;
+    if (mode == 0 || sc->T == 0) return 1;
+    double d[3] = {x[0] - e[0], x[1] - e[1], x[2] - e[2]};
+    int any_hit = 0, any_near = 0, robust_hit = 0;
+    int32_t stack[256];
+    int sp = 0;
+    int64_t lin = 0;
+    if (!brute) stack[sp++] = 0;
+    for (;;) {
+        int32_t first, count;
+        if (brute) {
+            if (lin >= sc->T) break;
+            first = (int32_t)lin; count = (int32_t)((sc->T - lin) < 1024 ? (sc->T - lin) : 1024);
+            lin += count;
+        } else {
+            if (sp == 0) break;
+            const or_node* nd = &sc->nodes[stack[--sp]];
+            if (!seg_box(e, d, nd->lo, nd->hi, 1.0 + FRAG_TAU)) continue;
+            if (nd->left >= 0) {
+                stack[sp++] = nd->left;
+                stack[sp++] = nd->right;
+                continue;
+            }
+            first = nd->first; count = nd->count;
+        }
+        for (int32_t i = first; i < first + count; ++i) {
+            int32_t t = brute ? i : sc->order[i];
+            if (t == own_tri) continue;
+            if (mode == 1 && sc->tri_mesh[t] != own_mesh) continue;
+            int near = 0;
+            int h = seg_tri(e, d, sc->v + 9 * (int64_t)t, eps, &near);
+            if (h && !fragile) return 0;      /* no bookkeeping asked: first hit decides */
+            if (h) any_hit = 1;
+            if (near) any_near = 1;
+            if (h && !near) robust_hit = 1;
+            if (robust_hit) { *fragile = 0; return 0; }
+        }
+    }
+    if (fragile) *fragile = any_near;
+    return any_hit ? 0 : 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The angular Gaussian of one (sample, fixation) pair, Sec. 3.2.1, in the   */
+/* paper's notation.  p = x - e, d1 = p.r/|r| (scalar projection), d2 = the  */
+/* scalar rejection |p x r|/|r|, sigma = tan(theta), d = d1 tan(theta),      */
+/* sigma_k = (d2/d) sigma, g = t/(sigma sqrt(2 pi)) exp(-sigma_k^2/(2 sigma^2)).*/
+/* Values propagate only inside the 4-sigma cone, sigma_k <= 4 sigma.        */
+/* Pairs with d <= 0 (sample at or behind the eye plane) give nothing.       */
+/* Returns 1 inside the cone and writes g; *margin (optional) gets          */
+/* 1 - (sigma_k / 4 sigma)^2, the relative distance to the cone boundary.    */
+/* ------------------------------------------------------------------------ */
+int or_pair_value(const double x[3], const double e[3], const double r[3], double t,
+                  double sigma, double* g_out, double* margin)
+{
+    double p[3] = {x[0] - e[0], x[1] - e[1], x[2] - e[2]};
+    double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    double rh[3] = {r[0] / rn, r[1] / rn, r[2] / rn};
+    double d1 = p[0] * rh[0] + p[1] * rh[1] + p[2] * rh[2];
+    double cx = p[1] * rh[2] - p[2] * rh[1];
+    double cy = p[2] * rh[0] - p[0] * rh[2];
+    double cz = p[0] * rh[1] - p[1] * rh[0];
+    double d2 = sqrt(cx * cx + cy * cy + cz * cz);
+    double d = d1 * sigma;
+    *g_out = 0.0;
+    if (margin) *margin = -INFINITY;
+    if (!(d > 0.0)) return 0;
+    double sigma_k = (d2 / d) * sigma;
+    double ratio = sigma_k / (4.0 * sigma);
+    if (margin) *margin = 1.0 - ratio * ratio;
+    double g = t / (sigma * sqrt(2.0 * M_PI)) * exp(-(sigma_k * sigma_k) / (2.0 * sigma * sigma));
+    *g_out = g;
+    return sigma_k <= 4.0 * sigma;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Density of a set of samples (Sec. 3.2): rho_s = sum_f V(f,s) g(f,s) over  */
+/* fixations inside the 4-sigma cone.  Threads split the samples statically. */
+/* Per-sample bookkeeping (comparison only): budget = sum of g over pairs   */
+/* whose gate margin is below 1e-5 or whose visibility is fragile; stats    */
+/* [n][4] = in-cone pairs, visible pairs, ambiguous-gate pairs, fragile     */
+/* visibility pairs.                                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const or_scene* sc;
+    const float *pos, *eye, *gaze, *dur;
+    const int32_t *tri, *mesh;
+    int64_t n, F, begin, end;
+    double sigma, eps;
+    int mode, brute;
+    double *rho, *budget;
+    int64_t* stats;
+} density_job;
+
+static const double GATE_AMBIG = 1e-5;
+
+static void* density_worker(void* arg)
+{
+    density_job* jb = (density_job*)arg;
+    for (int64_t s = jb->begin; s < jb->end; ++s) {
+        double x[3] = {jb->pos[3 * s], jb->pos[3 * s + 1], jb->pos[3 * s + 2]};
+        double rho = 0.0, budget = 0.0;
+        int64_t n_in = 0, n_vis = 0, n_amb = 0, n_frag = 0;
+        for (int64_t f = 0; f < jb->F; ++f) {
+            double e[3] = {jb->eye[3 * f], jb->eye[3 * f + 1], jb->eye[3 * f + 2]};
+            double r[3] = {jb->gaze[3 * f], jb->gaze[3 * f + 1], jb->gaze[3 * f + 2]};
+            double g, margin;
+            int in = or_pair_value(x, e, r, (double)jb->dur[f], jb->sigma, &g, &margin);
+            int ambiguous = fabs(margin) < GATE_AMBIG;
+            if (!in && !ambiguous) continue;
+            int fragile = 0;
+            int vis = or_visible(jb->sc, e, x, jb->tri ? jb->tri[s] : -1, jb->mesh ? jb->mesh[s] : -1,
+                                 jb->mode, jb->eps, jb->brute, &fragile);
+            if (in) {
+                ++n_in;
+                if (vis) { ++n_vis; rho += g; }
+            }
+            if (ambiguous) ++n_amb;
+            if (fragile && in) ++n_frag;
+            if (ambiguous || (fragile && in)) budget += g;
+        }
+        jb->rho[s] = rho;
+        if (jb->budget) jb->budget[s] = budget;
+        if (jb->stats) {
+            jb->stats[4 * s] = n_in; jb->stats[4 * s + 1] = n_vis;
+            jb->stats[4 * s + 2] = n_amb; jb->stats[4 * s + 3] = n_frag;
+        }
+    }
+    return NULL;
+}
+
+int or_density(const or_scene* sc, const float* pos, const int32_t* tri, const int32_t* mesh, int64_t n,
+               const float* eye, const float* gaze, const float* dur, int64_t F, double theta_deg,
+               int mode, double eps, int brute, int nthreads, double* rho, double* budget, int64_t* stats)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    double sigma = tan(theta_deg * M_PI / 180.0);
+    density_job jobs[256];
+    pthread_t th[256];
+    int64_t chunk = (n + nthreads - 1) / nthreads;
+    for (int i = 0; i < nthreads; ++i) {
+        density_job* jb = &jobs[i];
+        jb->sc = sc; jb->pos = pos; jb->eye = eye; jb->gaze = gaze; jb->dur = dur;
+        jb->tri = tri; jb->mesh = mesh; jb->n = n; jb->F = F;
+        jb->begin = i * chunk; jb->end = (i + 1) * chunk < n ? (i + 1) * chunk : n;
+        jb->sigma = sigma; jb->eps = eps; jb->mode = mode; jb->brute = brute;
+        jb->rho = rho; jb->budget = budget; jb->stats = stats;
+        if (jb->begin >= jb->end) continue;
+        if (nthreads == 1) { density_worker(jb); continue; }
+        pthread_create(&th[i], NULL, density_worker, jb);
+    }
+    if (nthreads > 1)
+        for (int i = 0; i < nthreads; ++i)
+            if (jobs[i].begin < jobs[i].end) pthread_join(th[i], NULL);
+    return 0;
+}
+
+/* Visibility of explicit (sample, fixation) pairs; vis/fragile are [m] bytes. */
+void or_pair_visibility(const or_scene* sc, const float* pos, const int32_t* tri, const int32_t* mesh,
+                        const float* eye, const int64_t* pair_s, const int64_t* pair_f, int64_t m,
+                        int mode, double eps, int brute, uint8_t* vis, uint8_t* fragile)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t s = pair_s[i], f = pair_f[i];
+        double x[3] = {pos[3 * s], pos[3 * s + 1], pos[3 * s + 2]};
+        double e[3] = {eye[3 * f], eye[3 * f + 1], eye[3 * f + 2]};
+        int fr = 0;
+        vis[i] = (uint8_t)or_visible(sc, e, x, tri ? tri[s] : -1, mesh ? mesh[s] : -1, mode, eps, brute, &fr);
+        if (fragile) fragile[i] = (uint8_t)fr;
+    }
+}
+
+/* Normalisation (Sec. 3.2.3): divide by the maximum; all zero stays zero. */
+double or_normalize(const double* rho, int64_t n, double* out)
+{
+    double mx = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (rho[i] > mx) mx = rho[i];
+    for (int64_t i = 0; i < n; ++i) out[i] = mx > 0.0 ? rho[i] / mx : 0.0;
+    return mx;
+}
