@@ -1,0 +1,184 @@
+/*
+ * gazemap.h -- C ABI of the MI355X (gfx950) surface-based fixation density map library.
+ *
+ * The method (Javerliat & Lavoue, "GPU accelerated surface-based gaze mapping
+ * for XR experiences", arXiv 2601.07571):
+ *   1. sample every mesh surface at k samples per square metre, independently of
+ *      the triangulation and of any UV mapping (Sec. 3.1);
+ *   2. for every sample, add the duration-weighted angular Gaussian of every
+ *      fixation whose 4-sigma gaze cone contains it and that sees it
+ *      (Sec. 3.2.1, Sec. 3.2.2, Sec. 3.3.2);
+ *   3. divide by the largest value (Sec. 3.2.3).
+ *
+ * Conventions shared by every call
+ *   - Return value: GM_OK or a negative gm_status; gm_last_error() then holds a
+ *     message (thread-local, valid until the next call on the same thread).
+ *     Nothing is thrown across the ABI.  On error no output is written, unless
+ *     the status is GM_ERR_DEVICE (a kernel may already have run).
+ *   - Device pointers are HIP device allocations owned by the caller (for
+ *     example torch tensors).  Host pointers are marked "host".
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Calls are asynchronous on that stream unless documented as blocking.
+ *   - Positions are world-space metres, float32, laid out [n][3].
+ *   - Scene-global triangle index: triangles of mesh 0 first, then mesh 1, ...
+ *   - Handles (gm_scene) are not thread-safe: one call at a time per handle.
+ */
+#ifndef GAZEMAP_H
+#define GAZEMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GM_OK = 0,
+    GM_ERR_INVALID_ARGUMENT = -1,
+    GM_ERR_OUT_OF_MEMORY = -2,
+    GM_ERR_DEVICE = -3,
+    GM_ERR_CAPACITY = -4,
+    GM_ERR_NOT_READY = -5,
+    GM_ERR_INTERNAL = -99
+} gm_status;
+
+/* Occlusion modes (Sec. 3.2.2), low two bits of `flags`. */
+#define GM_OCC_NONE 0u  /* every in-cone sample counts */
+#define GM_OCC_SELF 1u  /* only triangles of the sample's own mesh occlude */
+#define GM_OCC_FULL 2u  /* every triangle of the scene occludes */
+#define GM_OCC_MASK 3u
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* gm_last_error(void);
+
+/* ABI version, (major << 16) | minor. */
+int32_t gm_version(void);
+
+/* One triangle mesh, host memory: vertices [n_vertices][3] float32,
+ * indices [n_triangles][3] int32 into this mesh's own vertices. */
+typedef struct {
+    const float* vertices;
+    const int32_t* indices;
+    int32_t n_vertices;
+    int32_t n_triangles;
+} gm_mesh;
+
+typedef struct gm_scene gm_scene;
+
+/*
+ * gm_scene_create -- copy meshes to the current HIP device and build the
+ * occlusion BVH on the host (binned SAH over triangle centroids, two child
+ * boxes per 64-byte node in depth-first order, 48-byte triangle records in
+ * leaf order).  Blocking.  Rejects: n_meshes < 1 or > 4096, a mesh with no
+ * triangles, an index outside its mesh, a non-finite vertex.  Degenerate
+ * (zero-area) triangles are accepted: they are never sampled and never occlude.
+ */
+gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** out);
+gm_status gm_scene_destroy(gm_scene* scene);
+
+/* Host outputs (any may be NULL): triangle count, mesh count, BVH node count,
+ * BVH depth, scene bounding box [6] = (lo xyz, hi xyz). */
+gm_status gm_scene_info(const gm_scene* scene, int64_t* n_triangles, int32_t* n_meshes,
+                        int64_t* n_bvh_nodes, int32_t* bvh_depth, float* bbox);
+
+/*
+ * gm_count_surface_samples -- per-mesh sample counts for `samples_per_m2` (Sec. 3.1.2:
+ * the count follows the surface area): n_m = round(k * area_m), where area_m is
+ * the mesh area held as fixed-point triangle weights (floor(A_i * 2^S_m),
+ * S_m = 52 - exponent(T_m * max_i A_i)).  n_per_mesh: host int64 [n_meshes].
+ * Blocking (one small device-to-host copy).  samples_per_m2 must be finite and > 0.
+ */
+gm_status gm_count_surface_samples(gm_scene* scene, double samples_per_m2, int64_t* n_per_mesh,
+                                   void* stream);
+
+/*
+ * build_surface_samples -- area-weighted surface sampling (Sec. 3.1; the
+ * per-triangle lattice of Sec. 3.1.1 is replaced by area-proportional random
+ * placement, so the density does not depend on the triangulation).
+ *   a1  per-triangle FP64 area, fixed-point weight;
+ *   a2  exact integer prefix sum of the weights (per mesh);
+ *   a3  sample j of mesh m: Philox4x32-10(counter = (j_lo, j_hi, m, 0),
+ *       key = (seed_lo, seed_hi)) -> triangle = first i with C_i > floor(U*W_m/2^64),
+ *       U = x0*2^32 + x1; barycentric (1-sqrt(u), sqrt(u)(1-v), sqrt(u) v),
+ *       u = x2/2^32, v = x3/2^32; position in FP64, rounded to FP32.
+ * Sample order: mesh 0 first, then by j.  Outputs (device, caller-owned, each may
+ * be NULL): tri [N] scene-global triangle index, mesh [N], bary [N][2] = (b1, b2),
+ * pos [N][3].  N = sum of gm_count_surface_samples; N > capacity gives
+ * GM_ERR_CAPACITY with *n_out = N and nothing written.  *n_out (host) = N.
+ * Blocking (it reads back the counts); the sampling kernels are queued on `stream`.
+ */
+gm_status build_surface_samples(gm_scene* scene, double samples_per_m2, uint64_t seed,
+                                int32_t* tri, int32_t* mesh, float* bary, float* pos,
+                                int64_t capacity, int64_t* n_out, void* stream);
+
+/* Fixations, device memory: eye [n][3] and gaze [n][3] (direction, any non-zero
+ * length) in world space, duration [n] >= 0 (the weight t of Sec. 3.2.1). */
+typedef struct {
+    const float* eye;
+    const float* gaze;
+    const float* duration;
+    int32_t n;
+} gm_fixations;
+
+/*
+ * accumulate_density -- the density map of Sec. 3.2 on a set of surface points.
+ * For every point s and fixation f, with p = x_s - e_f and r_f the gaze:
+ *   tan(phi) = |p x r| / (p . r), sigma = tan(theta);
+ *   in the cone  <=>  p . r > 0 and tan(phi) <= 4 sigma          (Sec. 3.3.2);
+ *   g = t_f / (sigma sqrt(2 pi)) * exp(-tan^2(phi) / (2 sigma^2))  (Sec. 3.2.1,
+ *       sigma_k = (d2/d) sigma = tan(phi));
+ *   visible  <=>  no occluding triangle other than tri[s] crosses the segment
+ *       e_f + tau (x_s - e_f) at 0 < tau < 1 - 1e-4               (Sec. 3.2.2);
+ *   rho_s = sum over in-cone visible f of g.
+ * Inputs (device): pos [n][3]; tri [n] scene-global triangle of each point or NULL
+ * (no own-triangle exclusion); mesh [n] or NULL (then derived from tri; points
+ * with neither have no own mesh, so GM_OCC_SELF gives them no occluders).
+ * flags: one GM_OCC_* mode.  theta_deg in (0, 45).
+ * Outputs (device, each may be NULL): density [n] = rho (float32);
+ * density_norm [n] = rho / max rho (Sec. 3.2.3; all zero when max is 0);
+ * max_out [1] = max rho.
+ * Accumulation is exact integer fixed point, so results do not depend on the
+ * order of work (bit-reproducible).  Queued on `stream`; device scratch is held
+ * by the scene handle and grown on demand (the first call for a size allocates).
+ */
+gm_status accumulate_density(gm_scene* scene, const float* pos, const int32_t* tri,
+                             const int32_t* mesh, int64_t n, const gm_fixations* fix,
+                             double theta_deg, uint32_t flags, float* density,
+                             float* density_norm, float* max_out, void* stream);
+
+/*
+ * Stage-isolated checks (same device code as accumulate_density), for tests.
+ * gm_debug_pair_values: for m pairs (pair_s[i], pair_f[i]) (device int32) of the
+ *   n_points points pos [n_points][3] and the fixations, g_out[i] (device float) = g
+ *   (Sec. 3.2.1) if the pair is in the 4-sigma cone, else 0; no visibility.  A pair
+ *   index out of range gives NaN.  Blocking (it owns a temporary buffer).
+ * gm_debug_pair_visibility: vis_out[i] (device uint8) = 1 if the segment
+ *   eye[pair_f[i]] -> pos[pair_s[i]] is unoccluded under the occlusion mode in
+ *   `flags` (Sec. 3.2.2), 0 if occluded, 2 if an index is out of range.
+ *   tri / mesh as in accumulate_density.
+ */
+gm_status gm_debug_pair_values(const float* pos, int64_t n_points, const gm_fixations* fix,
+                               double theta_deg, const int32_t* pair_s, const int32_t* pair_f,
+                               int64_t m, float* g_out, void* stream);
+gm_status gm_debug_pair_visibility(gm_scene* scene, const float* pos, const int32_t* tri,
+                                   const int32_t* mesh, int64_t n_points, const float* eye,
+                                   int32_t n_eyes, const int32_t* pair_s, const int32_t* pair_f,
+                                   int64_t m, uint32_t flags, uint8_t* vis_out, void* stream);
+
+/*
+ * Stage timing with HIP events recorded on the caller's stream around the
+ * kernels of each stage (for measurement; off by default).
+ * gm_profile_enable(scene, 1) starts recording and clears the totals.
+ * gm_profile_read(scene, stage, total_ms, launches): blocking (waits for the
+ * recorded events); stage is one of "sample" (a1-a3), "prep" (fixation records
+ * and spatial sort), "density" (the gate / exact value / visibility kernel),
+ * "finalize" (maximum and outputs).  Unknown stage: GM_ERR_INVALID_ARGUMENT.
+ */
+gm_status gm_profile_enable(gm_scene* scene, int32_t on);
+gm_status gm_profile_read(gm_scene* scene, const char* stage, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAZEMAP_H */

@@ -81,6 +81,8 @@ def _load():
     lib.or_pair_visibility.argtypes = [ctypes.c_void_p, P(c_f), P(c_i32), P(c_i32), P(c_f),
                                        P(c_i64), P(c_i64), c_i64, ctypes.c_int, c_d, ctypes.c_int,
                                        P(c_u8), P(c_u8)]
+    lib.or_pair_values.argtypes = [P(c_f), P(c_f), P(c_f), P(c_f), P(c_i64), P(c_i64), c_i64, c_d,
+                                   P(c_d), P(c_d), P(c_u8)]
     lib.or_normalize.argtypes = [P(c_d), c_i64, P(c_d)]
     lib.or_normalize.restype = c_d
     _lib = lib
@@ -262,6 +264,20 @@ def pair_value(x, e, r, t, theta_deg):
     inside = lib.or_pair_value(_ptr(x, ctypes.c_double), _ptr(e, ctypes.c_double), _ptr(r, ctypes.c_double),
                                float(t), sigma, ctypes.byref(g), ctypes.byref(mg))
     return bool(inside), g.value, mg.value
+
+
+def pair_values(pos, eye, gaze, dur, pair_s, pair_f, theta_deg):
+    """(g, margin, in_cone) for explicit pairs, FP64, no visibility; g = 0 outside the cone."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, np.float32); eye = np.ascontiguousarray(eye, np.float32)
+    gaze = np.ascontiguousarray(gaze, np.float32); dur = np.ascontiguousarray(dur, np.float32)
+    ps = np.ascontiguousarray(pair_s, np.int64); pf = np.ascontiguousarray(pair_f, np.int64)
+    g = np.zeros(len(ps)); mg = np.zeros(len(ps)); inc = np.zeros(len(ps), np.uint8)
+    lib.or_pair_values(_ptr(pos, ctypes.c_float), _ptr(eye, ctypes.c_float), _ptr(gaze, ctypes.c_float),
+                       _ptr(dur, ctypes.c_float), _ptr(ps, ctypes.c_int64), _ptr(pf, ctypes.c_int64), len(ps),
+                       float(theta_deg), _ptr(g, ctypes.c_double), _ptr(mg, ctypes.c_double),
+                       _ptr(inc, ctypes.c_uint8))
+    return g, mg, inc.astype(bool)
 
 
 @dataclass

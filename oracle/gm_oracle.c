@@ -559,3 +559,22 @@ double or_normalize(const double* rho, int64_t n, double* out)
     for (int64_t i = 0; i < n; ++i) out[i] = mx > 0.0 ? rho[i] / mx : 0.0;
     return mx;
 }
+
+/* g and the gate margin for explicit (sample, fixation) pairs (no visibility). */
+void or_pair_values(const float* pos, const float* eye, const float* gaze, const float* dur,
+                    const int64_t* pair_s, const int64_t* pair_f, int64_t m, double theta_deg,
+                    double* g_out, double* margin_out, uint8_t* in_out)
+{
+    double sigma = tan(theta_deg * M_PI / 180.0);
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t s = pair_s[i], f = pair_f[i];
+        double x[3] = {pos[3 * s], pos[3 * s + 1], pos[3 * s + 2]};
+        double e[3] = {eye[3 * f], eye[3 * f + 1], eye[3 * f + 2]};
+        double r[3] = {gaze[3 * f], gaze[3 * f + 1], gaze[3 * f + 2]};
+        double g, mg;
+        int in = or_pair_value(x, e, r, (double)dur[f], sigma, &g, &mg);
+        g_out[i] = in ? g : 0.0;
+        if (margin_out) margin_out[i] = mg;
+        if (in_out) in_out[i] = (uint8_t)in;
+    }
+}

@@ -1,0 +1,244 @@
+"""Python binding of the gfx950 density-map library (include/gazemap.h).
+
+Argument marshalling only: every step runs in the HIP kernels of libgazemap.so.
+Torch is used for device memory and the current HIP stream.  The library must
+be built first (``__graft_entry__.build()`` or ``python -m
+paper_2601_07571_amd.build``); importing this module fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgazemap.so")
+
+GM_OK = 0
+STATUS = {0: "GM_OK", -1: "GM_ERR_INVALID_ARGUMENT", -2: "GM_ERR_OUT_OF_MEMORY", -3: "GM_ERR_DEVICE",
+          -4: "GM_ERR_CAPACITY", -5: "GM_ERR_NOT_READY", -99: "GM_ERR_INTERNAL"}
+OCC = {"none": 0, "self": 1, "full": 2}
+
+# exported symbols of include/gazemap.h
+SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy", "gm_scene_info",
+           "gm_count_surface_samples", "build_surface_samples", "accumulate_density",
+           "gm_debug_pair_values", "gm_debug_pair_visibility", "gm_profile_enable", "gm_profile_read")
+
+
+class GazemapError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("vertices", ctypes.c_void_p), ("indices", ctypes.c_void_p),
+                ("n_vertices", ctypes.c_int32), ("n_triangles", ctypes.c_int32)]
+
+
+class _Fix(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_void_p), ("gaze", ctypes.c_void_p), ("duration", ctypes.c_void_p),
+                ("n", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgazemap.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2601_07571_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                   ctypes.c_uint64, ctypes.c_double)
+    lib.gm_last_error.restype = ctypes.c_char_p
+    lib.gm_version.restype = i32
+    lib.gm_scene_create.argtypes = [ctypes.POINTER(_Mesh), i32, ctypes.POINTER(vp)]
+    lib.gm_scene_destroy.argtypes = [vp]
+    lib.gm_scene_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                  ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
+    lib.gm_count_surface_samples.argtypes = [vp, dbl, ctypes.POINTER(i64), vp]
+    lib.build_surface_samples.argtypes = [vp, dbl, u64, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
+    lib.accumulate_density.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(_Fix), dbl, u32, vp, vp, vp, vp]
+    lib.gm_debug_pair_values.argtypes = [vp, i64, ctypes.POINTER(_Fix), dbl, vp, vp, i64, vp, vp]
+    lib.gm_debug_pair_visibility.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, i64, u32, vp, vp]
+    lib.gm_profile_enable.argtypes = [vp, i32]
+    lib.gm_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    for name in SYMBOLS[2:]:
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != GM_OK:
+        raise GazemapError(status, _lib.gm_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device: this library runs on MI355X (gfx950) only")
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, shape_last=None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t))
+    t = t.to(device="cuda", dtype=dtype).contiguous()
+    if shape_last is not None:
+        t = t.reshape(-1, shape_last)
+    return t
+
+
+@dataclass
+class Samples:
+    tri: object    # int32 [N] scene-global triangle
+    mesh: object   # int32 [N]
+    bary: object   # float32 [N][2]
+    pos: object    # float32 [N][3]
+
+
+@dataclass
+class Density:
+    density: object       # float32 [n], raw rho
+    density_norm: object  # float32 [n], rho / max
+    max: object           # float32 [1] (device)
+
+
+class Fixations:
+    """Device copies of eye [F][3], gaze [F][3], duration [F]."""
+
+    def __init__(self, eye, gaze, duration):
+        torch = _torch()
+        self.eye = _dev(eye, torch.float32, 3)
+        self.gaze = _dev(gaze, torch.float32, 3)
+        self.duration = _dev(duration, torch.float32).reshape(-1)
+        self.n = int(self.eye.shape[0])
+        self._c = _Fix(self.eye.data_ptr(), self.gaze.data_ptr(), self.duration.data_ptr(), self.n)
+
+    def subset(self, begin, end):
+        return Fixations(self.eye[begin:end], self.gaze[begin:end], self.duration[begin:end])
+
+
+class Scene:
+    """A set of triangle meshes on the current device with its occlusion BVH."""
+
+    def __init__(self, meshes):
+        lib = load_library()
+        _torch()
+        self._keep = []
+        arr = (_Mesh * len(meshes))()
+        self.n_triangles_per_mesh = []
+        for i, (V, I) in enumerate(meshes):
+            V = np.ascontiguousarray(V, np.float32)
+            I = np.ascontiguousarray(I, np.int32)
+            self._keep += [V, I]
+            arr[i] = _Mesh(V.ctypes.data, I.ctypes.data, len(V), len(I))
+            self.n_triangles_per_mesh.append(len(I))
+        h = ctypes.c_void_p()
+        _check(lib.gm_scene_create(arr, len(meshes), ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+        self.n_meshes = len(meshes)
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.gm_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self):
+        T = ctypes.c_int64(); M = ctypes.c_int32(); nodes = ctypes.c_int64(); depth = ctypes.c_int32()
+        bbox = (ctypes.c_float * 6)()
+        _check(_lib.gm_scene_info(self._h, ctypes.byref(T), ctypes.byref(M), ctypes.byref(nodes),
+                                  ctypes.byref(depth), bbox))
+        return {"n_triangles": T.value, "n_meshes": M.value, "bvh_nodes": nodes.value,
+                "bvh_depth": depth.value, "bbox": list(bbox)}
+
+    def profile(self, on=True):
+        _check(_lib.gm_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, stage):
+        """(total milliseconds, launches) of a stage since profiling was enabled."""
+        ms = ctypes.c_double(0.0); n = ctypes.c_int64(0)
+        _check(_lib.gm_profile_read(self._h, stage.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def count_samples(self, samples_per_m2):
+        out = (ctypes.c_int64 * self.n_meshes)()
+        _check(_lib.gm_count_surface_samples(self._h, float(samples_per_m2), out, _stream()))
+        return np.array(out[:], np.int64)
+
+    def build_samples(self, samples_per_m2, seed=0, capacity=None):
+        torch = _torch()
+        if capacity is None:
+            capacity = int(self.count_samples(samples_per_m2).sum())
+        tri = torch.empty(capacity, dtype=torch.int32, device="cuda")
+        mesh = torch.empty(capacity, dtype=torch.int32, device="cuda")
+        bary = torch.empty((capacity, 2), dtype=torch.float32, device="cuda")
+        pos = torch.empty((capacity, 3), dtype=torch.float32, device="cuda")
+        n = ctypes.c_int64(0)
+        _check(_lib.build_surface_samples(self._h, float(samples_per_m2), int(seed) & (2 ** 64 - 1), _ptr(tri),
+                                          _ptr(mesh), _ptr(bary), _ptr(pos), capacity, ctypes.byref(n),
+                                          _stream()))
+        N = n.value
+        return Samples(tri[:N], mesh[:N], bary[:N], pos[:N])
+
+    def accumulate(self, pos, fix: Fixations, theta_deg, occlusion="full", tri=None, mesh=None, out=None):
+        torch = _torch()
+        pos = _dev(pos, torch.float32, 3)
+        tri = _dev(tri, torch.int32)
+        mesh = _dev(mesh, torch.int32)
+        n = int(pos.shape[0])
+        if out is None:
+            out = Density(torch.empty(n, dtype=torch.float32, device="cuda"),
+                          torch.empty(n, dtype=torch.float32, device="cuda"),
+                          torch.empty(1, dtype=torch.float32, device="cuda"))
+        _check(_lib.accumulate_density(self._h, _ptr(pos), _ptr(tri), _ptr(mesh), n, ctypes.byref(fix._c),
+                                       float(theta_deg), OCC[occlusion] if isinstance(occlusion, str) else occlusion,
+                                       _ptr(out.density), _ptr(out.density_norm), _ptr(out.max), _stream()))
+        return out
+
+    def pair_visibility(self, pos, eye, pair_s, pair_f, occlusion="full", tri=None, mesh=None):
+        torch = _torch()
+        pos = _dev(pos, torch.float32, 3)
+        eye = _dev(eye, torch.float32, 3)
+        ps = _dev(pair_s, torch.int32); pf = _dev(pair_f, torch.int32)
+        tri = _dev(tri, torch.int32); mesh = _dev(mesh, torch.int32)
+        vis = torch.empty(int(ps.shape[0]), dtype=torch.uint8, device="cuda")
+        _check(_lib.gm_debug_pair_visibility(self._h, _ptr(pos), _ptr(tri), _ptr(mesh), int(pos.shape[0]),
+                                             _ptr(eye), int(eye.shape[0]), _ptr(ps), _ptr(pf), int(ps.shape[0]),
+                                             OCC[occlusion], _ptr(vis), _stream()))
+        return vis
+
+
+def pair_values(pos, fix: Fixations, theta_deg, pair_s, pair_f):
+    """g for explicit (sample, fixation) pairs, 0 outside the 4-sigma cone (no visibility)."""
+    load_library()
+    torch = _torch()
+    pos = _dev(pos, torch.float32, 3)
+    ps = _dev(pair_s, torch.int32); pf = _dev(pair_f, torch.int32)
+    g = torch.empty(int(ps.shape[0]), dtype=torch.float32, device="cuda")
+    _check(_lib.gm_debug_pair_values(_ptr(pos), int(pos.shape[0]), ctypes.byref(fix._c), float(theta_deg),
+                                     _ptr(ps), _ptr(pf), int(ps.shape[0]), _ptr(g), _stream()))
+    return g

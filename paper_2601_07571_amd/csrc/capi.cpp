@@ -1,0 +1,523 @@
+// capi.cpp -- the C ABI (include/gazemap.h): argument checks, scene upload,
+// device scratch management and the launch sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gazemap.h"
+#include "gm_internal.h"
+
+using namespace gm;
+
+namespace {
+
+thread_local std::string g_error;
+
+gm_status fail(gm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+#define GM_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return fail(GM_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Device buffer that only grows.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t want)
+    {
+        if (want <= bytes) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        size_t cap = std::max<size_t>(want, 256);
+        hipError_t e = hipMalloc(&p, cap);
+        if (e == hipSuccess) bytes = cap;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Pairs of HIP events around the kernels of one stage.
+struct StageTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    double total_ms = 0.0;
+    int64_t launches = 0;
+    hipError_t begin(hipStream_t s)
+    {
+        if (used == ev.size()) {
+            hipEvent_t a, b;
+            hipError_t e = hipEventCreate(&a);
+            if (e != hipSuccess) return e;
+            e = hipEventCreate(&b);
+            if (e != hipSuccess) return e;
+            ev.emplace_back(a, b);
+        }
+        return hipEventRecord(ev[used].first, s);
+    }
+    hipError_t end(hipStream_t s) { return hipEventRecord(ev[used++].second, s); }
+    hipError_t collect()
+    {
+        for (size_t i = 0; i < used; ++i) {
+            hipError_t e = hipEventSynchronize(ev[i].second);
+            if (e != hipSuccess) return e;
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, ev[i].first, ev[i].second);
+            if (e != hipSuccess) return e;
+            total_ms += ms;
+            ++launches;
+        }
+        used = 0;
+        return hipSuccess;
+    }
+    void clear()
+    {
+        used = 0;
+        total_ms = 0.0;
+        launches = 0;
+    }
+    void release()
+    {
+        for (auto& p : ev) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+        ev.clear();
+        clear();
+    }
+};
+
+enum Stage { kStageSample = 0, kStagePrep, kStageDensity, kStageFinalize, kStages };
+const char* const kStageNames[kStages] = {"sample", "prep", "density", "finalize"};
+
+constexpr double kEpsV = 1e-4;         // visibility tolerance along the segment
+constexpr double kGateWiden = 2e-3;    // relative widening of the cheap cone gate
+
+}  // namespace
+
+struct gm_scene {
+    int device = 0;
+    int32_t M = 0;
+    int64_t T = 0, NV = 0;
+    std::vector<int64_t> tri_off;  // [M+1]
+    HostBvh bvh;
+    // static device data
+    DevBuf V, I, tri_mesh, tri_off_d, nodes, tris;
+    // sampler scratch
+    DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total;
+    // density scratch
+    DevBuf fix, fx_shift, key, hist, cursor, spos, smesh, perm, acc, max_acc, scan_tmp2;
+    int32_t spl = 4;
+    bool profiling = false;
+    StageTimer timers[kStages];
+
+    hipError_t tbegin(int st, hipStream_t s) { return profiling ? timers[st].begin(s) : hipSuccess; }
+    hipError_t tend(int st, hipStream_t s)
+    {
+        if (!profiling) return hipSuccess;
+        hipError_t e = timers[st].end(s);
+        // keep the event list bounded when nobody reads it
+        if (e == hipSuccess && timers[st].used >= 4096) e = timers[st].collect();
+        return e;
+    }
+
+    ~gm_scene()
+    {
+        for (auto& t : timers) t.release();
+        for (DevBuf* b : {&V, &I, &tri_mesh, &tri_off_d, &nodes, &tris, &area, &W, &C, &max_bits, &S, &scan_tmp,
+                          &counts, &offsets, &mesh_total, &fix, &fx_shift, &key, &hist, &cursor, &spos, &smesh,
+                          &perm, &acc, &max_acc, &scan_tmp2})
+            b->release();
+    }
+};
+
+namespace {
+
+gm_status check_device(const gm_scene* sc)
+{
+    int dev = -1;
+    GM_HIP(hipGetDevice(&dev));
+    if (dev != sc->device)
+        return fail(GM_ERR_INVALID_ARGUMENT, "scene lives on device %d but device %d is current", sc->device, dev);
+    return GM_OK;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// zero fill by a kernel (also safe inside captured graphs)
+void zero(void* p, size_t bytes, hipStream_t s)
+{
+    const int64_t n = (int64_t)((bytes + 3) / 4);
+    if (n > 0) k_fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(static_cast<uint32_t*>(p), n, 0u);
+}
+
+// a1 + a2 on the device, then the per-mesh counts (blocking read-back).
+gm_status sample_counts(gm_scene* sc, double k, hipStream_t s, std::vector<int64_t>& counts)
+{
+    if (!(k > 0.0) || !std::isfinite(k)) return fail(GM_ERR_INVALID_ARGUMENT, "samples_per_m2 must be finite and > 0");
+    const int64_t T = sc->T;
+    const int32_t M = sc->M;
+    GM_HIP(sc->area.ensure(sizeof(double) * T));
+    GM_HIP(sc->W.ensure(8 * T));
+    GM_HIP(sc->C.ensure(8 * T));
+    GM_HIP(sc->max_bits.ensure(8 * M));
+    GM_HIP(sc->S.ensure(4 * M));
+    GM_HIP(sc->scan_tmp.ensure(scan_tmp_bytes(T)));
+    GM_HIP(sc->counts.ensure(8 * M));
+    GM_HIP(sc->offsets.ensure(8 * (M + 1)));
+    GM_HIP(sc->mesh_total.ensure(8 * M));
+    GM_HIP(sc->tbegin(kStageSample, s));
+    zero(sc->max_bits.p, 8 * (size_t)M, s);
+    launch_tri_area(sc->V.as<float>(), sc->I.as<int32_t>(), sc->tri_mesh.as<int32_t>(), T, sc->area.as<double>(),
+                    sc->max_bits.as<unsigned long long>(), s);
+    launch_mesh_scale(sc->max_bits.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), M, sc->S.as<int32_t>(), s);
+    launch_tri_weight(sc->area.as<double>(), sc->tri_mesh.as<int32_t>(), sc->S.as<int32_t>(), T,
+                      sc->W.as<unsigned long long>(), s);
+    launch_inclusive_scan_u64(sc->W.as<unsigned long long>(), sc->C.as<unsigned long long>(), T, sc->scan_tmp.p, s);
+    launch_mesh_counts(sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), sc->S.as<int32_t>(), M, k,
+                       sc->counts.as<int64_t>(), sc->offsets.as<int64_t>(), sc->mesh_total.as<unsigned long long>(), s);
+    GM_HIP(hipGetLastError());
+    GM_HIP(sc->tend(kStageSample, s));
+    counts.assign((size_t)M, 0);
+    GM_HIP(hipMemcpyAsync(counts.data(), sc->counts.p, 8 * (size_t)M, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    return GM_OK;
+}
+
+bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+}  // namespace
+
+extern "C" {
+
+const char* gm_last_error(void) { return g_error.c_str(); }
+
+int32_t gm_version(void) { return (1 << 16) | 0; }
+
+gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** out)
+{
+    g_error.clear();
+    if (!out) return fail(GM_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    if (!meshes || n_meshes < 1 || n_meshes > 4096)
+        return fail(GM_ERR_INVALID_ARGUMENT, "n_meshes must be in [1, 4096] (got %d)", n_meshes);
+    int64_t T = 0, NV = 0;
+    for (int32_t m = 0; m < n_meshes; ++m) {
+        const gm_mesh& g = meshes[m];
+        if (!g.vertices || !g.indices || g.n_vertices < 3 || g.n_triangles < 1)
+            return fail(GM_ERR_INVALID_ARGUMENT, "mesh %d: needs >= 3 vertices and >= 1 triangle", m);
+        for (int64_t v = 0; v < g.n_vertices; ++v)
+            if (!finite3(g.vertices + 3 * v)) return fail(GM_ERR_INVALID_ARGUMENT, "mesh %d: vertex %lld not finite", m, (long long)v);
+        for (int64_t t = 0; t < 3 * (int64_t)g.n_triangles; ++t)
+            if (g.indices[t] < 0 || g.indices[t] >= g.n_vertices)
+                return fail(GM_ERR_INVALID_ARGUMENT, "mesh %d: index %d out of range", m, g.indices[t]);
+        T += g.n_triangles;
+        NV += g.n_vertices;
+    }
+    if (T >= (int64_t)1 << 31) return fail(GM_ERR_INVALID_ARGUMENT, "more than 2^31 - 1 triangles");
+    gm_scene* sc = new (std::nothrow) gm_scene();
+    if (!sc) return fail(GM_ERR_OUT_OF_MEMORY, "host allocation failed");
+    hipError_t he = hipGetDevice(&sc->device);
+    if (he != hipSuccess) {
+        delete sc;
+        return fail(GM_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(he));
+    }
+    sc->M = n_meshes;
+    sc->T = T;
+    sc->NV = NV;
+    std::vector<float> V((size_t)NV * 3);
+    std::vector<int32_t> I((size_t)T * 3), tm((size_t)T);
+    sc->tri_off.assign((size_t)n_meshes + 1, 0);
+    int64_t vb = 0, tb = 0;
+    for (int32_t m = 0; m < n_meshes; ++m) {
+        const gm_mesh& g = meshes[m];
+        std::memcpy(V.data() + 3 * vb, g.vertices, sizeof(float) * 3 * (size_t)g.n_vertices);
+        for (int64_t t = 0; t < g.n_triangles; ++t) {
+            for (int k = 0; k < 3; ++k) I[(size_t)(3 * (tb + t) + k)] = (int32_t)(g.indices[3 * t + k] + vb);
+            tm[(size_t)(tb + t)] = m;
+        }
+        sc->tri_off[(size_t)m] = tb;
+        vb += g.n_vertices;
+        tb += g.n_triangles;
+    }
+    sc->tri_off[(size_t)n_meshes] = tb;
+    build_bvh(V.data(), I.data(), tm.data(), T, sc->bvh);
+
+    auto up = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
+        hipError_t e = b.ensure(bytes);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(sc->V, V.data(), V.size() * 4);
+    if (e == hipSuccess) e = up(sc->I, I.data(), I.size() * 4);
+    if (e == hipSuccess) e = up(sc->tri_mesh, tm.data(), tm.size() * 4);
+    if (e == hipSuccess) e = up(sc->tri_off_d, sc->tri_off.data(), sc->tri_off.size() * 8);
+    if (e == hipSuccess) e = up(sc->nodes, sc->bvh.nodes.data(), sc->bvh.nodes.size() * sizeof(BvhNode));
+    if (e == hipSuccess) e = up(sc->tris, sc->bvh.tris.data(), sc->bvh.tris.size() * sizeof(BvhTri));
+    if (e != hipSuccess) {
+        delete sc;
+        return fail(e == hipErrorOutOfMemory ? GM_ERR_OUT_OF_MEMORY : GM_ERR_DEVICE, "scene upload: %s",
+                    hipGetErrorString(e));
+    }
+    *out = sc;
+    return GM_OK;
+}
+
+gm_status gm_scene_destroy(gm_scene* scene)
+{
+    g_error.clear();
+    if (scene) {
+        (void)hipDeviceSynchronize();
+        delete scene;
+    }
+    return GM_OK;
+}
+
+gm_status gm_scene_info(const gm_scene* sc, int64_t* n_triangles, int32_t* n_meshes, int64_t* n_bvh_nodes,
+                        int32_t* bvh_depth, float* bbox)
+{
+    g_error.clear();
+    if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
+    if (n_triangles) *n_triangles = sc->T;
+    if (n_meshes) *n_meshes = sc->M;
+    if (n_bvh_nodes) *n_bvh_nodes = (int64_t)sc->bvh.nodes.size();
+    if (bvh_depth) *bvh_depth = sc->bvh.depth;
+    if (bbox)
+        for (int a = 0; a < 3; ++a) {
+            bbox[a] = sc->bvh.lo[a];
+            bbox[3 + a] = sc->bvh.hi[a];
+        }
+    return GM_OK;
+}
+
+gm_status gm_count_surface_samples(gm_scene* sc, double k, int64_t* n_per_mesh, void* stream)
+{
+    g_error.clear();
+    if (!sc || !n_per_mesh) return fail(GM_ERR_INVALID_ARGUMENT, "scene and n_per_mesh must not be NULL");
+    gm_status st = check_device(sc);
+    if (st != GM_OK) return st;
+    std::vector<int64_t> counts;
+    st = sample_counts(sc, k, (hipStream_t)stream, counts);
+    if (st != GM_OK) return st;
+    std::memcpy(n_per_mesh, counts.data(), 8 * counts.size());
+    return GM_OK;
+}
+
+gm_status build_surface_samples(gm_scene* sc, double k, uint64_t seed, int32_t* tri, int32_t* mesh, float* bary,
+                                float* pos, int64_t capacity, int64_t* n_out, void* stream)
+{
+    g_error.clear();
+    if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
+    if (capacity < 0) return fail(GM_ERR_INVALID_ARGUMENT, "capacity < 0");
+    gm_status st = check_device(sc);
+    if (st != GM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> counts;
+    st = sample_counts(sc, k, s, counts);
+    if (st != GM_OK) return st;
+    int64_t N = 0;
+    for (int64_t c : counts) N += c;
+    if (n_out) *n_out = N;
+    if (N > capacity) return fail(GM_ERR_CAPACITY, "%lld samples do not fit capacity %lld", (long long)N, (long long)capacity);
+    if (N >= (int64_t)1 << 31) return fail(GM_ERR_INVALID_ARGUMENT, "more than 2^31 - 1 samples");
+    GM_HIP(sc->tbegin(kStageSample, s));
+    launch_sample(sc->V.as<float>(), sc->I.as<int32_t>(), sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(),
+                  sc->offsets.as<int64_t>(), sc->mesh_total.as<unsigned long long>(), sc->M, N, seed, tri, mesh, bary,
+                  pos, s);
+    GM_HIP(hipGetLastError());
+    GM_HIP(sc->tend(kStageSample, s));
+    return GM_OK;
+}
+
+gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri, const int32_t* mesh, int64_t n,
+                             const gm_fixations* fix, double theta_deg, uint32_t flags, float* density,
+                             float* density_norm, float* max_out, void* stream)
+{
+    g_error.clear();
+    if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
+    if (!fix) return fail(GM_ERR_INVALID_ARGUMENT, "fixations is NULL");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GM_ERR_INVALID_ARGUMENT, "n must be in [0, 2^31)");
+    if (n > 0 && !pos) return fail(GM_ERR_INVALID_ARGUMENT, "pos is NULL");
+    const int32_t F = fix->n;
+    if (F < 0) return fail(GM_ERR_INVALID_ARGUMENT, "fixation count < 0");
+    if (F > 0 && (!fix->eye || !fix->gaze || !fix->duration))
+        return fail(GM_ERR_INVALID_ARGUMENT, "fixation arrays must not be NULL");
+    if (!(theta_deg > 0.0 && theta_deg < 45.0)) return fail(GM_ERR_INVALID_ARGUMENT, "theta_deg must be in (0, 45)");
+    const uint32_t mode = flags & GM_OCC_MASK;
+    if (mode > GM_OCC_FULL || (flags & ~GM_OCC_MASK)) return fail(GM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", flags);
+    gm_status st = check_device(sc);
+    if (st != GM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+
+    const double sigma = std::tan(theta_deg * M_PI / 180.0);
+    // spatial buckets: about one sample per bucket, at most 2^21
+    int bits = 1;
+    while (bits < 7 && ((int64_t)1 << (3 * bits)) < n) ++bits;
+    const int64_t buckets = (int64_t)1 << (3 * bits);
+    const int64_t nn = std::max<int64_t>(n, 1);
+    GM_HIP(sc->fix.ensure(sizeof(FixRec) * (size_t)std::max(F, 1)));
+    GM_HIP(sc->fx_shift.ensure(16));
+    GM_HIP(sc->key.ensure(4 * nn));
+    GM_HIP(sc->hist.ensure(4 * buckets));
+    GM_HIP(sc->cursor.ensure(4 * buckets));
+    GM_HIP(sc->scan_tmp2.ensure(scan_tmp_bytes(buckets)));
+    GM_HIP(sc->spos.ensure(16 * nn));
+    GM_HIP(sc->smesh.ensure(4 * nn));
+    GM_HIP(sc->perm.ensure(4 * nn));
+    GM_HIP(sc->acc.ensure(8 * nn));
+    GM_HIP(sc->max_acc.ensure(8));
+
+    GM_HIP(sc->tbegin(kStagePrep, s));
+    zero(sc->fx_shift.p, 16, s);
+    zero(sc->max_acc.p, 8, s);
+    launch_fix_prep(fix->eye, fix->gaze, fix->duration, F, sigma, kGateWiden, sc->fix.as<FixRec>(), nullptr,
+                    sc->fx_shift.as<int32_t>(), s);
+    if (n > 0) {
+        zero(sc->acc.p, 8 * (size_t)n, s);
+        zero(sc->hist.p, 4 * (size_t)buckets, s);
+        float lo[3];
+        float ext = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = sc->bvh.lo[a];
+            ext = std::max(ext, sc->bvh.hi[a] - sc->bvh.lo[a]);
+        }
+        const int cells = 1 << bits;
+        const float inv_cell = ext > 0.0f ? (float)cells / ext : 1.0f;
+        launch_morton(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), n, lo, inv_cell, bits, sc->key.as<uint32_t>(),
+                      sc->hist.as<uint32_t>(), s);
+        launch_exclusive_scan_u32(sc->hist.as<uint32_t>(), sc->cursor.as<uint32_t>(), buckets, sc->scan_tmp2.p, s);
+        launch_scatter(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), sc->T, n, sc->key.as<uint32_t>(), sc->cursor.as<uint32_t>(),
+                       sc->spos.as<float4>(), sc->smesh.as<int32_t>(), sc->perm.as<int32_t>(), s);
+        DensityLaunch a;
+        GM_HIP(sc->tend(kStagePrep, s));
+        a.spos = sc->spos.as<float4>();
+        a.smesh = sc->smesh.as<int32_t>();
+        a.n = n;
+        a.fix = sc->fix.as<FixRec>();
+        a.F = F;
+        a.nodes = sc->nodes.as<BvhNode>();
+        a.tris = sc->tris.as<BvhTri>();
+        a.occ_mode = (int32_t)mode;
+        a.tmax = (float)(1.0 - kEpsV);
+        a.cone2 = (float)(16.0 * sigma * sigma);
+        a.kexp = (float)(1.0 / (2.0 * sigma * sigma * std::log(2.0)));
+        a.fx_shift = sc->fx_shift.as<int32_t>();
+        a.acc = sc->acc.as<unsigned long long>();
+        a.spl = sc->spl;
+        const int64_t tiles = (n + 256 * a.spl - 1) / (256 * a.spl);
+        const int64_t max_chunks = std::max<int64_t>(1, (F + 127) / 128);
+        int64_t chunks = std::min<int64_t>(max_chunks, std::max<int64_t>(1, (4096 + tiles - 1) / tiles));
+        a.fix_per_chunk = (int32_t)((F + chunks - 1) / std::max<int64_t>(chunks, 1));
+        if (a.fix_per_chunk < 1) a.fix_per_chunk = 1;
+        a.n_chunks = (int32_t)((F + a.fix_per_chunk - 1) / a.fix_per_chunk);
+        GM_HIP(sc->tbegin(kStageDensity, s));
+        launch_density(a, s);
+        GM_HIP(sc->tend(kStageDensity, s));
+    } else {
+        GM_HIP(sc->tend(kStagePrep, s));
+    }
+    GM_HIP(sc->tbegin(kStageFinalize, s));
+    launch_finalize(sc->acc.as<unsigned long long>(), sc->perm.as<int32_t>(), n, sc->fx_shift.as<int32_t>(),
+                    sc->max_acc.as<unsigned long long>(), density, density_norm, max_out, s);
+    GM_HIP(hipGetLastError());
+    GM_HIP(sc->tend(kStageFinalize, s));
+    return GM_OK;
+}
+
+gm_status gm_debug_pair_values(const float* pos, int64_t n_points, const gm_fixations* fix, double theta_deg,
+                               const int32_t* pair_s, const int32_t* pair_f, int64_t m, float* g_out, void* stream)
+{
+    g_error.clear();
+    if (!fix || (m > 0 && (!pos || !pair_s || !pair_f || !g_out)) || m < 0 || n_points < 0 || fix->n < 0)
+        return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or negative size");
+    if (!(theta_deg > 0.0 && theta_deg < 45.0)) return fail(GM_ERR_INVALID_ARGUMENT, "theta_deg must be in (0, 45)");
+    hipStream_t s = (hipStream_t)stream;
+    const double sigma = std::tan(theta_deg * M_PI / 180.0);
+    DevBuf rec, sh;
+    GM_HIP(rec.ensure(sizeof(FixRec) * (size_t)std::max(fix->n, 1)));
+    GM_HIP(sh.ensure(16));
+    zero(sh.p, 16, s);
+    launch_fix_prep(fix->eye, fix->gaze, fix->duration, fix->n, sigma, kGateWiden, rec.as<FixRec>(), nullptr,
+                    sh.as<int32_t>(), s);
+    launch_pair_values(pos, rec.as<FixRec>(), pair_s, pair_f, m, n_points, fix->n, (float)(16.0 * sigma * sigma),
+                       (float)(1.0 / (2.0 * sigma * sigma * std::log(2.0))), g_out, s);
+    hipError_t e = hipStreamSynchronize(s);
+    rec.release();
+    sh.release();
+    GM_HIP(e);
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
+gm_status gm_debug_pair_visibility(gm_scene* sc, const float* pos, const int32_t* tri, const int32_t* mesh,
+                                   int64_t n_points, const float* eye, int32_t n_eyes, const int32_t* pair_s,
+                                   const int32_t* pair_f, int64_t m, uint32_t flags, uint8_t* vis_out, void* stream)
+{
+    g_error.clear();
+    if (!sc || m < 0 || n_points < 0 || n_eyes < 0 || (m > 0 && (!pos || !eye || !pair_s || !pair_f || !vis_out)))
+        return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or negative size");
+    const uint32_t mode = flags & GM_OCC_MASK;
+    if (mode > GM_OCC_FULL) return fail(GM_ERR_INVALID_ARGUMENT, "unknown occlusion mode");
+    gm_status st = check_device(sc);
+    if (st != GM_OK) return st;
+    launch_pair_visibility(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), eye, pair_s, pair_f, m, n_points, n_eyes, sc->T,
+                           sc->nodes.as<BvhNode>(), sc->tris.as<BvhTri>(), (int32_t)mode, (float)(1.0 - kEpsV), vis_out, (hipStream_t)stream);
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
+gm_status gm_profile_enable(gm_scene* sc, int32_t on)
+{
+    g_error.clear();
+    if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
+    for (auto& t : sc->timers) {
+        GM_HIP(t.collect());
+        t.clear();
+    }
+    sc->profiling = on != 0;
+    return GM_OK;
+}
+
+gm_status gm_profile_read(gm_scene* sc, const char* stage, double* total_ms, int64_t* launches)
+{
+    g_error.clear();
+    if (!sc || !stage) return fail(GM_ERR_INVALID_ARGUMENT, "scene and stage must not be NULL");
+    for (int i = 0; i < kStages; ++i) {
+        if (std::strcmp(stage, kStageNames[i]) != 0) continue;
+        GM_HIP(sc->timers[i].collect());
+        if (total_ms) *total_ms = sc->timers[i].total_ms;
+        if (launches) *launches = sc->timers[i].launches;
+        return GM_OK;
+    }
+    return fail(GM_ERR_INVALID_ARGUMENT, "unknown stage '%s'", stage);
+}
+
+}  // extern "C"

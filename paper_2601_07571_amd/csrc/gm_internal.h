@@ -1,0 +1,120 @@
+// gm_internal.h -- layouts and launchers shared by the host runtime and the
+// gfx950 kernels of the density-map library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace gm {
+
+// ---------------------------------------------------------------------------
+// Occlusion BVH.  Two child boxes per node so that one 64-byte fetch feeds both
+// box tests; nodes in depth-first order (the first child usually follows its
+// parent); child >= 0 is a node index, child < 0 is a leaf whose triangles are
+// tris[~child .. ~child + count).  An empty child has count 0 and an inverted box.
+// ---------------------------------------------------------------------------
+struct alignas(16) BvhNode {
+    float lo0[3], hi0[3];
+    float lo1[3], hi1[3];
+    int32_t child0, child1;
+    int32_t count0, count1;
+};
+static_assert(sizeof(BvhNode) == 64, "node is one 64-byte line");
+
+// Leaf triangle record, 48 bytes, in leaf order.
+struct alignas(16) BvhTri {
+    float v0[3], v1[3], v2[3];
+    int32_t id;     // scene-global triangle index
+    int32_t mesh;   // mesh of the triangle
+    int32_t pad;
+};
+static_assert(sizeof(BvhTri) == 48, "triangle record is 48 bytes");
+
+// Per-fixation record written by the prep kernel (32 bytes).
+struct alignas(16) FixRec {
+    float ex, ey, ez;  // eye
+    float rx, ry, rz;  // gaze, as given (not normalised)
+    float w;           // t / (sigma sqrt(2 pi))
+    float kappa;       // |r|^2 / (1 + 16 sigma^2), widened: the cheap cone gate's factor
+};
+
+// Host-side BVH (bvh_build.cpp).
+struct HostBvh {
+    std::vector<BvhNode> nodes;
+    std::vector<BvhTri> tris;
+    int depth = 0;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+};
+void build_bvh(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T, HostBvh& out);
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files).  All asynchronous on `s`.
+// ---------------------------------------------------------------------------
+
+// a1: areas and per-mesh max (max_bits: uint64 [M], zeroed by the caller).
+void launch_tri_area(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T, double* area,
+                     unsigned long long* max_bits, hipStream_t s);
+// a1: per-mesh scale exponent S_m from T_m and the max area.
+void launch_mesh_scale(const unsigned long long* max_bits, const int64_t* tri_off, int32_t M, int32_t* S,
+                       hipStream_t s);
+// a1: fixed-point weights W_i = floor(A_i 2^S_m).
+void launch_tri_weight(const double* area, const int32_t* tri_mesh, const int32_t* S, int64_t T,
+                       unsigned long long* W, hipStream_t s);
+// a2: inclusive prefix sum of uint64 over n (tmp: scan_tmp_bytes(n)).
+size_t scan_tmp_bytes(int64_t n);
+void launch_inclusive_scan_u64(const unsigned long long* in, unsigned long long* out, int64_t n, void* tmp,
+                               hipStream_t s);
+void launch_exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp, hipStream_t s);
+// a2: per-mesh totals and sample counts/offsets: counts [M], offsets [M+1] (int64).
+void launch_mesh_counts(const unsigned long long* C, const int64_t* tri_off, const int32_t* S, int32_t M,
+                        double k, int64_t* counts, int64_t* offsets, unsigned long long* mesh_total,
+                        hipStream_t s);
+// a3: the sampler.
+void launch_sample(const float* V, const int32_t* I, const unsigned long long* C, const int64_t* tri_off,
+                   const int64_t* offsets, const unsigned long long* mesh_total, int32_t M, int64_t N,
+                   uint64_t seed, int32_t* tri, int32_t* mesh, float* bary, float* pos, hipStream_t s);
+
+// density path
+struct DensityLaunch {
+    // sorted samples
+    const float4* spos;        // xyz, w = own triangle (int bits, -1 = none)
+    const int32_t* smesh;      // own mesh (-1 = none)
+    int64_t n;
+    const FixRec* fix;
+    int32_t F;
+    const BvhNode* nodes;
+    const BvhTri* tris;
+    int32_t occ_mode;
+    float tmax;                // 1 - eps_v
+    float cone2;               // 16 sigma^2
+    float kexp;                // log2(e) / (2 sigma^2)
+    const int32_t* fx_shift;   // device scalar: fixed-point scale exponent
+    unsigned long long* acc;   // [n] fixed-point density, sorted order
+    int32_t fix_per_chunk;
+    int32_t n_chunks;
+    int32_t spl;               // samples per lane
+};
+
+void launch_fix_prep(const float* eye, const float* gaze, const float* dur, int32_t F, double sigma,
+                     double widen, FixRec* rec, double* wsum, int32_t* fx_shift, hipStream_t s);
+void launch_morton(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
+                   int64_t n, const float* bbox_lo, float inv_cell, int bits, uint32_t* key, uint32_t* hist,
+                   hipStream_t s);
+void launch_scatter(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
+                    int64_t T, int64_t n, const uint32_t* key, uint32_t* cursor, float4* spos, int32_t* smesh,
+                    int32_t* perm, hipStream_t s);
+void launch_density(const DensityLaunch& a, hipStream_t s);
+void launch_finalize(const unsigned long long* acc, const int32_t* perm, int64_t n, const int32_t* fx_shift,
+                     unsigned long long* max_acc, float* density, float* density_norm, float* max_out,
+                     hipStream_t s);
+void launch_pair_values(const float* pos, const FixRec* fix, const int32_t* ps, const int32_t* pf, int64_t m,
+                        int64_t n_points, int32_t F, float cone2, float kexp, float* g, hipStream_t s);
+void launch_pair_visibility(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
+                            const float* eye, const int32_t* ps, const int32_t* pf, int64_t m, int64_t n_points,
+                            int32_t n_eyes, int64_t T, const BvhNode* nodes, const BvhTri* tris, int32_t occ_mode,
+                            float tmax, uint8_t* vis, hipStream_t s);
+
+}  // namespace gm

@@ -1,0 +1,621 @@
+// k_density.hip -- fixation density accumulation on surface samples
+// (Sec. 3.2.1 angular Gaussian, Sec. 3.2.2 visibility, Sec. 3.2.3 normalisation,
+// Sec. 3.3.2 4-sigma truncation), for gfx950.
+//
+// Work decomposition.  Samples are first put in spatial (Morton) order.  A
+// workgroup owns a tile of 256*SPL consecutive samples (SPL per lane, held in
+// VGPRs in tile-local coordinates) and one chunk of the fixations.  Fixations
+// stream through LDS in blocks of kFB; every lane evaluates the cheap cone gate
+// for its SPL samples against each fixation (8 FMA per pair, all FMA):
+//     d = r.x' + c0,  m = a.x' + cc - kappa |x'|^2,  s = d|d| + m
+// with x' = x - (tile origin), c0 = -r.e', a = 2 kappa e', cc = -kappa |e'|^2,
+// kappa = |r|^2 / (1 + 16 sigma^2) slightly widened, so that s > 0 for every
+// pair inside the 4-sigma cone (d > 0 and tan(phi) <= 4 sigma).  Only when some
+// lane of the wave passes does the wave take the exact path: the pair value in
+// compensated FP32 (TwoSum for p = x - e, FMA difference of products for p x r),
+// then the visibility of the passing lanes as one packet (all rays share the eye)
+// through the BVH, with wave-uniform node and triangle fetches.  Contributions
+// are accumulated per lane as exact 64-bit fixed point, so the final value does
+// not depend on the order of work.
+//
+// Built with -ffp-contract=off: every fused multiply-add below is written out.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "gm_internal.h"
+
+namespace gm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kFB = 128;  // fixations per LDS block
+
+// Records whose address is the same for the whole wave are read through the
+// constant address space, which lets the compiler use scalar (SMEM) loads.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const vf4* CVec4Ptr;
+
+__device__ __forceinline__ BvhNode load_node(const BvhNode* base, int i)
+{
+    const CVec4Ptr q = (CVec4Ptr)(base + i);
+    const vf4 a = q[0], b = q[1], c = q[2], d = q[3];
+    BvhNode n;
+    n.lo0[0] = a.x; n.lo0[1] = a.y; n.lo0[2] = a.z;
+    n.hi0[0] = a.w; n.hi0[1] = b.x; n.hi0[2] = b.y;
+    n.lo1[0] = b.z; n.lo1[1] = b.w; n.lo1[2] = c.x;
+    n.hi1[0] = c.y; n.hi1[1] = c.z; n.hi1[2] = c.w;
+    n.child0 = __float_as_int(d.x); n.child1 = __float_as_int(d.y);
+    n.count0 = __float_as_int(d.z); n.count1 = __float_as_int(d.w);
+    return n;
+}
+
+__device__ __forceinline__ BvhTri load_tri(const BvhTri* base, int i)
+{
+    const CVec4Ptr q = (CVec4Ptr)(base + i);
+    const vf4 a = q[0], b = q[1], c = q[2];
+    BvhTri t;
+    t.v0[0] = a.x; t.v0[1] = a.y; t.v0[2] = a.z;
+    t.v1[0] = a.w; t.v1[1] = b.x; t.v1[2] = b.y;
+    t.v2[0] = b.z; t.v2[1] = b.w; t.v2[2] = c.x;
+    t.id = __float_as_int(c.y); t.mesh = __float_as_int(c.z); t.pad = 0;
+    return t;
+}
+
+__device__ __forceinline__ FixRec load_fix(const FixRec* base, int i)
+{
+    const CVec4Ptr q = (CVec4Ptr)(base + i);
+    const vf4 a = q[0], b = q[1];
+    FixRec f;
+    f.ex = a.x; f.ey = a.y; f.ez = a.z; f.rx = a.w;
+    f.ry = b.x; f.rz = b.y; f.w = b.z; f.kappa = b.w;
+    return f;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---------------------------------------------------------------------------
+// exact pair value
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& err)
+{
+    s = a + b;
+    const float bb = s - a;
+    err = (a - (s - bb)) + (b - bb);
+}
+
+// a*b - c*d with one rounding error (Kahan's FMA algorithm)
+__device__ __forceinline__ float diff_of_products(float a, float b, float c, float d)
+{
+    const float w = c * d;
+    const float e = __builtin_fmaf(-c, d, w);
+    const float f = __builtin_fmaf(a, b, -w);
+    return f + e;
+}
+
+// Returns g (0 outside the 4-sigma cone).  tan^2(phi) = |p x r|^2 / (p.r)^2 with the
+// gaze left unnormalised (its length cancels).
+__device__ __forceinline__ float pair_value(float x, float y, float z, float ex, float ey, float ez, float rx,
+                                            float ry, float rz, float w, float cone2, float kexp)
+{
+    float phx, plx, phy, ply, phz, plz;
+    two_sum(x, -ex, phx, plx);
+    two_sum(y, -ey, phy, ply);
+    two_sum(z, -ez, phz, plz);
+    const float cx = diff_of_products(phy, rz, phz, ry) + (ply * rz - plz * ry);
+    const float cy = diff_of_products(phz, rx, phx, rz) + (plz * rx - plx * rz);
+    const float cz = diff_of_products(phx, ry, phy, rx) + (plx * ry - ply * rx);
+    const float q = __builtin_fmaf(cx, cx, __builtin_fmaf(cy, cy, cz * cz));
+    const float lo = __builtin_fmaf(plx, rx, __builtin_fmaf(ply, ry, plz * rz));
+    const float d1 = __builtin_fmaf(phx, rx, __builtin_fmaf(phy, ry, __builtin_fmaf(phz, rz, lo)));
+    const float d12 = d1 * d1;
+    if (!(d1 > 0.0f) || !(q <= cone2 * d12)) return 0.0f;
+    const float t2 = q / d12;
+    return w * exp2f(-t2 * kexp);
+}
+
+// ---------------------------------------------------------------------------
+// packet visibility: every active lane holds one segment eye -> its point
+// ---------------------------------------------------------------------------
+struct Seg {
+    float ox, oy, oz;  // eye
+    float ix, iy, iz;  // 1 / direction (finite)
+    float qx, qy, qz;  // -eye / direction
+    float sx, sy, sz;  // watertight shear
+    int kx, ky, kz;
+};
+
+__device__ __forceinline__ float safe_inv(float d)
+{
+    return fabsf(d) > 1e-30f ? 1.0f / d : copysignf(1e30f, d);
+}
+
+__device__ __forceinline__ float pick(int k, float a, float b, float c) { return k == 0 ? a : (k == 1 ? b : c); }
+
+__device__ __forceinline__ Seg make_seg(float ex, float ey, float ez, float px, float py, float pz)
+{
+    Seg s;
+    s.ox = ex; s.oy = ey; s.oz = ez;
+    const float dx = px - ex, dy = py - ey, dz = pz - ez;
+    s.ix = safe_inv(dx); s.iy = safe_inv(dy); s.iz = safe_inv(dz);
+    s.qx = -ex * s.ix; s.qy = -ey * s.iy; s.qz = -ez * s.iz;
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    int kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    const float dkz = pick(kz, dx, dy, dz);
+    if (dkz < 0.0f) { const int t = kx; kx = ky; ky = t; }
+    s.kx = kx; s.ky = ky; s.kz = kz;
+    s.sx = pick(kx, dx, dy, dz) / dkz;
+    s.sy = pick(ky, dx, dy, dz) / dkz;
+    s.sz = 1.0f / dkz;
+    return s;
+}
+
+__device__ __forceinline__ bool box_hit(const Seg& s, const float* lo, const float* hi, float tmax, float& tnear)
+{
+    const float t0x = __builtin_fmaf(lo[0], s.ix, s.qx), t1x = __builtin_fmaf(hi[0], s.ix, s.qx);
+    const float t0y = __builtin_fmaf(lo[1], s.iy, s.qy), t1y = __builtin_fmaf(hi[1], s.iy, s.qy);
+    const float t0z = __builtin_fmaf(lo[2], s.iz, s.qz), t1z = __builtin_fmaf(hi[2], s.iz, s.qz);
+    const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+    const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    tnear = tn;
+    return tn <= tf;
+}
+
+// Watertight segment/triangle test (Woop, Benthin and Wald, JCGT 2013): shear the
+// triangle into the segment's frame, three edge functions with inclusive edges,
+// FP64 re-evaluation when an edge function is exactly zero; hit when the
+// parameter tau = T/det lies in (0, tmax).
+__device__ __forceinline__ bool seg_tri(const Seg& s, const BvhTri& t, float tmax)
+{
+    const float ax = t.v0[0] - s.ox, ay = t.v0[1] - s.oy, az = t.v0[2] - s.oz;
+    const float bx = t.v1[0] - s.ox, by = t.v1[1] - s.oy, bz = t.v1[2] - s.oz;
+    const float cx = t.v2[0] - s.ox, cy = t.v2[1] - s.oy, cz = t.v2[2] - s.oz;
+    const float akz = pick(s.kz, ax, ay, az), bkz = pick(s.kz, bx, by, bz), ckz = pick(s.kz, cx, cy, cz);
+    const float Ax = __builtin_fmaf(-s.sx, akz, pick(s.kx, ax, ay, az));
+    const float Ay = __builtin_fmaf(-s.sy, akz, pick(s.ky, ax, ay, az));
+    const float Bx = __builtin_fmaf(-s.sx, bkz, pick(s.kx, bx, by, bz));
+    const float By = __builtin_fmaf(-s.sy, bkz, pick(s.ky, bx, by, bz));
+    const float Cx = __builtin_fmaf(-s.sx, ckz, pick(s.kx, cx, cy, cz));
+    const float Cy = __builtin_fmaf(-s.sy, ckz, pick(s.ky, cx, cy, cz));
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    float det = U + V + W;
+    if (det == 0.0f) return false;
+    float T = U * (s.sz * akz) + V * (s.sz * bkz) + W * (s.sz * ckz);
+    if (det < 0.0f) { T = -T; det = -det; }
+    return T > 0.0f && T < tmax * det;
+}
+
+// Returns true for lanes whose segment is blocked.  `active` lanes take part; the
+// eye must be the same for every lane of the wave.  Node and triangle fetches use
+// wave-uniform addresses (scalar loads); the traversal stack lives in one VGPR,
+// lane i holding entry i.
+__device__ bool occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, const Seg& sg,
+                                int own_tri, int own_mesh, int mode, float tmax, bool active)
+{
+    const int lane = lane_id();
+    bool occ = false;
+    uint64_t alive = ballot(active);
+    if (alive == 0) return false;
+    int stack = 0;
+    int sp = 0;
+    int node = 0;
+    for (;;) {
+        const BvhNode nd = load_node(nodes, node);
+        const bool me = (alive >> lane) & 1ull;
+        float tn0, tn1;
+        const bool h0 = box_hit(sg, nd.lo0, nd.hi0, tmax, tn0) && me;
+        const bool h1 = box_hit(sg, nd.lo1, nd.hi1, tmax, tn1) && me;
+        const uint64_t m0 = ballot(h0), m1 = ballot(h1);
+        // visit order from the first live lane's entry distances
+        const int lead = __builtin_ctzll(alive);
+        const float l0 = __shfl(tn0, lead, 64), l1 = __shfl(tn1, lead, 64);
+        const bool swap = uniform(l1 < l0 ? 1 : 0) != 0;
+        int next = -1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const bool first = (c == 0) != swap;  // c==0 -> near child
+            const uint64_t mask = first ? m0 : m1;
+            if (mask == 0) continue;
+            const int child = first ? nd.child0 : nd.child1;
+            const int count = first ? nd.count0 : nd.count1;
+            const bool hit_box = first ? h0 : h1;
+            if (child < 0) {
+                const int t0 = ~child;
+                for (int k = 0; k < count; ++k) {
+                    const BvhTri tr = load_tri(tris, t0 + k);
+                    const bool skip = tr.id == own_tri || (mode == 1 && tr.mesh != own_mesh);
+                    const bool test = hit_box && !occ && !skip && ((alive >> lane) & 1ull);
+                    if (test && seg_tri(sg, tr, tmax)) occ = true;
+                }
+                alive = ballot(((alive >> lane) & 1ull) && !occ);
+                if (alive == 0) return occ;
+            } else if (next < 0) {
+                next = child;
+            } else {
+                stack = lane == sp ? child : stack;  // push
+                ++sp;
+            }
+        }
+        if (next < 0) {
+            if (sp == 0) break;
+            --sp;
+            next = __builtin_amdgcn_readlane(stack, sp);  // pop
+        }
+        node = uniform(next);
+    }
+    return occ;
+}
+
+__device__ __forceinline__ unsigned long long to_fixed(float g, int shift)
+{
+    return (unsigned long long)ldexp((double)g, shift);
+}
+
+// ---------------------------------------------------------------------------
+// a4: fixation records and the fixed-point scale
+// ---------------------------------------------------------------------------
+__global__ void k_fix_prep(const float* __restrict__ eye, const float* __restrict__ gaze,
+                           const float* __restrict__ dur, int32_t F, double inv_norm, double kappa_scale,
+                           FixRec* __restrict__ rec, unsigned int* __restrict__ wmax_bits)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    FixRec r;
+    r.ex = eye[3 * f]; r.ey = eye[3 * f + 1]; r.ez = eye[3 * f + 2];
+    r.rx = gaze[3 * f]; r.ry = gaze[3 * f + 1]; r.rz = gaze[3 * f + 2];
+    const float t = dur[f];
+    const double r2 = (double)r.rx * r.rx + (double)r.ry * r.ry + (double)r.rz * r.rz;
+    const bool ok = isfinite(r.ex) && isfinite(r.ey) && isfinite(r.ez) && isfinite(r2) && r2 > 0.0 &&
+                    isfinite(t) && t >= 0.0f;
+    if (ok) {
+        r.w = (float)((double)t * inv_norm);
+        r.kappa = (float)(r2 * kappa_scale);
+    } else {
+        // an invalid fixation contributes nothing: zero gaze makes the gate s <= 0
+        r.ex = r.ey = r.ez = 0.0f;
+        r.rx = r.ry = r.rz = 0.0f;
+        r.w = 0.0f;
+        r.kappa = 1.0f;
+    }
+    rec[f] = r;
+    atomicMax(wmax_bits, __float_as_uint(r.w));
+}
+
+// shift such that F * max w * 2^shift <= 2^62: no sample total can overflow 63 bits
+__global__ void k_fix_shift(const unsigned int* __restrict__ wmax_bits, int32_t F, int32_t* __restrict__ shift)
+{
+    const float wmax = __uint_as_float(*wmax_bits);
+    int e = 0;
+    if (wmax > 0.0f) {
+        (void)frexp((double)F * (double)wmax, &e);
+        *shift = 62 - e;
+    } else {
+        *shift = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// spatial order: 7-bit-per-axis Morton buckets, counting sort
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ void k_morton(const float* __restrict__ pos, int64_t n, float lox, float loy, float loz, float inv_cell,
+                         int cells, uint32_t* __restrict__ key, uint32_t* __restrict__ hist)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float fx = (pos[3 * i] - lox) * inv_cell, fy = (pos[3 * i + 1] - loy) * inv_cell,
+                fz = (pos[3 * i + 2] - loz) * inv_cell;
+    const uint32_t cx = (uint32_t)min(max((int)fx, 0), cells - 1);
+    const uint32_t cy = (uint32_t)min(max((int)fy, 0), cells - 1);
+    const uint32_t cz = (uint32_t)min(max((int)fz, 0), cells - 1);
+    const uint32_t k = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+    key[i] = k;
+    atomicAdd(&hist[k], 1u);
+}
+
+__global__ void k_scatter(const float* __restrict__ pos, const int32_t* __restrict__ tri,
+                          const int32_t* __restrict__ mesh, const int32_t* __restrict__ tri_mesh, int64_t T, int64_t n,
+                          const uint32_t* __restrict__ key, uint32_t* __restrict__ cursor, float4* __restrict__ spos,
+                          int32_t* __restrict__ smesh, int32_t* __restrict__ perm)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t dst = atomicAdd(&cursor[key[i]], 1u);
+    int32_t t = tri ? tri[i] : -1;
+    if (t < 0 || t >= T) t = -1;  // unknown triangle: no own-triangle exclusion
+    const int32_t m = mesh ? mesh[i] : (t >= 0 ? tri_mesh[t] : -1);
+    spos[dst] = make_float4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], __int_as_float(t));
+    smesh[dst] = m;
+    perm[dst] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// a5 + a6: gate, exact value, visibility, fixed-point accumulation
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned xcd_block(unsigned L, unsigned G)
+{
+    // consecutive tiles on the same XCD (workgroups go round-robin over 8 XCDs)
+    const unsigned q = G >> 3;
+    if (L >= (q << 3)) return L;
+    return (L & 7u) * q + (L >> 3);
+}
+
+template <int SPL>
+__global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
+{
+    __shared__ float4 s_ra[kFB];  // rx, ry, rz, c0
+    __shared__ float4 s_rb[kFB];  // ax, ay, az, cc
+    __shared__ float s_rc[kFB];   // -kappa
+    __shared__ unsigned long long s_acc[kThreads * SPL];  // one entry per sample, owned by one lane
+    __shared__ float s_rad;
+
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const unsigned G = gridDim.x * gridDim.y;
+    const unsigned L = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, G);
+    const int64_t tile = L % gridDim.x;
+    const int chunk = (int)(L / gridDim.x);
+    const int64_t tile_base = tile * (int64_t)(kThreads * SPL);
+    const int64_t wave_base = tile_base + wave * (64 * SPL);
+    const int64_t n = a.n;
+
+    // tile origin: its first sample; radius: largest distance of a tile sample to it
+    const float4 o4 = a.spos[tile_base];
+    if (threadIdx.x == 0) s_rad = 0.0f;
+    __syncthreads();
+
+    float px[SPL], py[SPL], pz[SPL], pq[SPL];
+    float rad = 0.0f;
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+        const int64_t i = wave_base + k * 64 + lane;
+        const float4 p = i < n ? a.spos[i] : o4;
+        px[k] = p.x - o4.x; py[k] = p.y - o4.y; pz[k] = p.z - o4.z;
+        pq[k] = __builtin_fmaf(px[k], px[k], __builtin_fmaf(py[k], py[k], pz[k] * pz[k]));
+        rad = fmaxf(rad, pq[k]);
+        s_acc[wave * (64 * SPL) + k * 64 + lane] = 0ull;
+    }
+    atomicMax((unsigned int*)&s_rad, __float_as_uint(rad));
+    __syncthreads();
+    // eyes within ~1.1 tile radii of the origin take the exact path for every pair
+    const float near2 = 1.21f * s_rad + 1e-12f;
+
+    const int shift = *a.fx_shift;
+    const int f_begin = chunk * a.fix_per_chunk;
+    const int f_end = min(a.F, f_begin + a.fix_per_chunk);
+
+    for (int fb = f_begin; fb < f_end; fb += kFB) {
+        const int nb = min(kFB, f_end - fb);
+        __syncthreads();
+        if (threadIdx.x < nb) {
+            const FixRec fr = a.fix[fb + threadIdx.x];
+            const float ex = fr.ex - o4.x, ey = fr.ey - o4.y, ez = fr.ez - o4.z;
+            const float e2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+            const float k = fr.kappa;
+            const float c0 = -__builtin_fmaf(fr.rx, ex, __builtin_fmaf(fr.ry, ey, fr.rz * ez));
+            float cc = -k * e2;
+            if (e2 <= near2 && fr.w > 0.0f) cc = 3.0e38f;  // force s > 0 for every sample of the tile
+            s_ra[threadIdx.x] = make_float4(fr.rx, fr.ry, fr.rz, c0);
+            s_rb[threadIdx.x] = make_float4(2.0f * k * ex, 2.0f * k * ey, 2.0f * k * ez, cc);
+            s_rc[threadIdx.x] = -k;
+        }
+        __syncthreads();
+        for (int j = 0; j < nb; ++j) {
+            const float4 ra = s_ra[j];
+            const float4 rb = s_rb[j];
+            const float nk = s_rc[j];
+            unsigned cand = 0;
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) {
+                float d = __builtin_fmaf(ra.x, px[k], ra.w);
+                d = __builtin_fmaf(ra.y, py[k], d);
+                d = __builtin_fmaf(ra.z, pz[k], d);
+                float m = __builtin_fmaf(rb.x, px[k], rb.w);
+                m = __builtin_fmaf(rb.y, py[k], m);
+                m = __builtin_fmaf(rb.z, pz[k], m);
+                m = __builtin_fmaf(nk, pq[k], m);
+                const float sv = __builtin_fmaf(d, fabsf(d), m);
+                cand |= (sv > 0.0f ? 1u : 0u) << k;
+            }
+            if (ballot(cand != 0) == 0) continue;
+
+            // exact path for this fixation, one sample slot at a time
+            const int f = uniform(fb + j);
+            const FixRec fr = load_fix(a.fix, f);
+            for (int k = 0; k < SPL; ++k) {
+                const int64_t i = wave_base + k * 64 + lane;
+                const bool c = ((cand >> k) & 1u) && i < n;
+                if (ballot(c) == 0) continue;
+                float g = 0.0f;
+                float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (c) {
+                    p = a.spos[i];
+                    g = pair_value(p.x, p.y, p.z, fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w, a.cone2, a.kexp);
+                }
+                bool vis = true;
+                const bool need = g > 0.0f && a.occ_mode != 0;
+                if (ballot(need) != 0) {
+                    const Seg sg = make_seg(fr.ex, fr.ey, fr.ez, p.x, p.y, p.z);
+                    const int own_mesh = need ? a.smesh[i] : -1;
+                    vis = !occluded_packet(a.nodes, a.tris, sg, __float_as_int(p.w), own_mesh, a.occ_mode,
+                                           a.tmax, need);
+                }
+                if (g > 0.0f && vis) s_acc[wave * (64 * SPL) + k * 64 + lane] += to_fixed(g, shift);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+        const int64_t i = wave_base + k * 64 + lane;
+        const unsigned long long v = s_acc[wave * (64 * SPL) + k * 64 + lane];
+        if (i < n && v != 0ull) atomicAdd(&a.acc[i], v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a7: maximum and outputs in the caller's order
+// ---------------------------------------------------------------------------
+__global__ void k_max(const unsigned long long* __restrict__ acc, int64_t n, unsigned long long* __restrict__ out)
+{
+    unsigned long long m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, acc[i]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, d, 64));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+
+__global__ void k_finalize(const unsigned long long* __restrict__ acc, const int32_t* __restrict__ perm, int64_t n,
+                           const int32_t* __restrict__ shift_p, const unsigned long long* __restrict__ max_acc,
+                           float* __restrict__ density, float* __restrict__ density_norm, float* __restrict__ max_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int shift = *shift_p;
+    const unsigned long long mx = *max_acc;
+    if (i == 0 && max_out) *max_out = (float)ldexp((double)mx, -shift);
+    if (i >= n) return;
+    const unsigned long long v = acc[i];
+    const int32_t o = perm[i];
+    if (density) density[o] = (float)ldexp((double)v, -shift);
+    if (density_norm) density_norm[o] = mx ? (float)((double)v / (double)mx) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// stage-isolated checks
+// ---------------------------------------------------------------------------
+__global__ void k_pair_values(const float* __restrict__ pos, const FixRec* __restrict__ fix,
+                              const int32_t* __restrict__ ps, const int32_t* __restrict__ pf, int64_t m,
+                              int64_t n_points, int32_t F, float cone2, float kexp, float* __restrict__ g)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int64_t s = ps[i];
+    const int32_t f = pf[i];
+    if (s < 0 || s >= n_points || f < 0 || f >= F) {
+        g[i] = __int_as_float(0x7fc00000);  // NaN marks an invalid pair
+        return;
+    }
+    const FixRec fr = fix[f];
+    g[i] = pair_value(pos[3 * s], pos[3 * s + 1], pos[3 * s + 2], fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w,
+                      cone2, kexp);
+}
+
+// one wave per pair, lane 0 active
+__global__ void __launch_bounds__(64) k_pair_visibility(const float* __restrict__ pos, const int32_t* __restrict__ tri,
+                                                        const int32_t* __restrict__ mesh,
+                                                        const int32_t* __restrict__ tri_mesh,
+                                                        const float* __restrict__ eye, const int32_t* __restrict__ ps,
+                                                        const int32_t* __restrict__ pf, int64_t m, int64_t n_points,
+                                                        int32_t n_eyes, int64_t T, const BvhNode* __restrict__ nodes,
+                                                        const BvhTri* __restrict__ tris, int mode, float tmax,
+                                                        uint8_t* __restrict__ vis)
+{
+    const int64_t i = blockIdx.x;
+    if (i >= m) return;
+    const int lane = lane_id();
+    const int64_t s = ps[i];
+    const int64_t f = pf[i];
+    if (s < 0 || s >= n_points || f < 0 || f >= n_eyes) {
+        if (lane == 0) vis[i] = 2;  // invalid pair
+        return;
+    }
+    int t = tri ? tri[s] : -1;
+    if (t < 0 || t >= T) t = -1;
+    const int me = mesh ? mesh[s] : (t >= 0 ? tri_mesh[t] : -1);
+    const Seg sg = make_seg(eye[3 * f], eye[3 * f + 1], eye[3 * f + 2], pos[3 * s], pos[3 * s + 1], pos[3 * s + 2]);
+    const bool occ = mode != 0 && occluded_packet(nodes, tris, sg, t, me, mode, tmax, lane == 0);
+    if (lane == 0) vis[i] = occ ? 0 : 1;
+}
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_fix_prep(const float* eye, const float* gaze, const float* dur, int32_t F, double sigma, double widen,
+                     FixRec* rec, double* wsum, int32_t* fx_shift, hipStream_t s)
+{
+    (void)wsum;
+    const double inv_norm = 1.0 / (sigma * std::sqrt(2.0 * M_PI));
+    const double kappa_scale = (1.0 - widen) / (1.0 + 16.0 * sigma * sigma);
+    unsigned int* wmax = reinterpret_cast<unsigned int*>(fx_shift + 1);
+    if (F > 0) k_fix_prep<<<blocks(F, 256), 256, 0, s>>>(eye, gaze, dur, F, inv_norm, kappa_scale, rec, wmax);
+    k_fix_shift<<<1, 1, 0, s>>>(wmax, F, fx_shift);
+}
+
+void launch_morton(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh, int64_t n,
+                   const float* bbox_lo, float inv_cell, int bits, uint32_t* key, uint32_t* hist, hipStream_t s)
+{
+    (void)tri; (void)mesh; (void)tri_mesh;
+    if (n > 0)
+        k_morton<<<blocks(n, 256), 256, 0, s>>>(pos, n, bbox_lo[0], bbox_lo[1], bbox_lo[2], inv_cell, 1 << bits, key,
+                                                hist);
+}
+
+void launch_scatter(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh, int64_t T,
+                    int64_t n, const uint32_t* key, uint32_t* cursor, float4* spos, int32_t* smesh, int32_t* perm,
+                    hipStream_t s)
+{
+    if (n > 0)
+        k_scatter<<<blocks(n, 256), 256, 0, s>>>(pos, tri, mesh, tri_mesh, T, n, key, cursor, spos, smesh, perm);
+}
+
+void launch_density(const DensityLaunch& a, hipStream_t s)
+{
+    if (a.n <= 0 || a.F <= 0) return;
+    const int64_t per_tile = (int64_t)kThreads * a.spl;
+    const dim3 grid(blocks(a.n, (int)per_tile), (unsigned)a.n_chunks);
+    switch (a.spl) {
+    case 1: k_density<1><<<grid, kThreads, 0, s>>>(a); break;
+    case 2: k_density<2><<<grid, kThreads, 0, s>>>(a); break;
+    case 4: k_density<4><<<grid, kThreads, 0, s>>>(a); break;
+    default: k_density<8><<<grid, kThreads, 0, s>>>(a); break;
+    }
+}
+
+void launch_finalize(const unsigned long long* acc, const int32_t* perm, int64_t n, const int32_t* fx_shift,
+                     unsigned long long* max_acc, float* density, float* density_norm, float* max_out, hipStream_t s)
+{
+    if (n > 0) k_max<<<std::min<unsigned>(blocks(n, 256), 2048u), 256, 0, s>>>(acc, n, max_acc);
+    k_finalize<<<blocks(n > 0 ? n : 1, 256), 256, 0, s>>>(acc, perm, n, fx_shift, max_acc, density, density_norm,
+                                                          max_out);
+}
+
+void launch_pair_values(const float* pos, const FixRec* fix, const int32_t* ps, const int32_t* pf, int64_t m,
+                        int64_t n_points, int32_t F, float cone2, float kexp, float* g, hipStream_t s)
+{
+    if (m > 0) k_pair_values<<<blocks(m, 256), 256, 0, s>>>(pos, fix, ps, pf, m, n_points, F, cone2, kexp, g);
+}
+
+void launch_pair_visibility(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
+                            const float* eye, const int32_t* ps, const int32_t* pf, int64_t m, int64_t n_points,
+                            int32_t n_eyes, int64_t T, const BvhNode* nodes, const BvhTri* tris, int32_t occ_mode,
+                            float tmax, uint8_t* vis, hipStream_t s)
+{
+    if (m > 0)
+        k_pair_visibility<<<(unsigned)m, 64, 0, s>>>(pos, tri, mesh, tri_mesh, eye, ps, pf, m, n_points, n_eyes, T,
+                                                     nodes, tris, occ_mode, tmax, vis);
+}
+
+}  // namespace gm

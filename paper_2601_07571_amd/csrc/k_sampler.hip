@@ -1,0 +1,198 @@
+// k_sampler.hip -- area weights, per-mesh counts and the area-weighted Philox
+// sampler (Sec. 3.1: sample density in samples per square metre, independent of
+// the triangulation).  Built with -ffp-contract=off: every FP64 expression below
+// is evaluated as written, one IEEE round-to-nearest operation at a time, so the
+// sample positions are reproducible bit for bit from the definition.
+#include <hip/hip_runtime.h>
+
+#include "gm_internal.h"
+
+namespace gm {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Philox4x32-10 (Salmon et al., SC'11): per round, two 32x32 products; the high
+// halves are mixed with the odd counter words and the round key, the low halves
+// move to the odd positions; the key advances by two Weyl increments.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                              uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t hi_a = __umulhi(0xD2511F53u, c0), lo_a = 0xD2511F53u * c0;
+        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2), lo_b = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi_b ^ c1 ^ k0;
+        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        c0 = n0; c1 = lo_b; c2 = n2; c3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Half the norm of the edge cross product, FP64, fixed order (the area that sets
+// the sample share of a triangle).
+__global__ void k_tri_area(const float* __restrict__ V, const int32_t* __restrict__ I,
+                           const int32_t* __restrict__ tri_mesh, int64_t T, double* __restrict__ area,
+                           unsigned long long* __restrict__ max_bits)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= T) return;
+    const int32_t i0 = I[3 * t], i1 = I[3 * t + 1], i2 = I[3 * t + 2];
+    const double ax = V[3 * i0], ay = V[3 * i0 + 1], az = V[3 * i0 + 2];
+    const double ux = (double)V[3 * i1] - ax, uy = (double)V[3 * i1 + 1] - ay, uz = (double)V[3 * i1 + 2] - az;
+    const double wx = (double)V[3 * i2] - ax, wy = (double)V[3 * i2 + 1] - ay, wz = (double)V[3 * i2 + 2] - az;
+    const double cx = uy * wz - uz * wy;
+    const double cy = uz * wx - ux * wz;
+    const double cz = ux * wy - uy * wx;
+    double sq = cx * cx + cy * cy;
+    sq = sq + cz * cz;
+    const double a = 0.5 * sqrt(sq);
+    area[t] = a;
+    // non-negative doubles order like their bit patterns
+    atomicMax(&max_bits[tri_mesh[t]], (unsigned long long)__double_as_longlong(a));
+}
+
+// S_m = 52 - e with T_m * max A = f 2^e, f in [0.5, 1): the mesh total of the
+// fixed-point weights then stays below 2^52.
+__global__ void k_mesh_scale(const unsigned long long* __restrict__ max_bits, const int64_t* __restrict__ tri_off,
+                             int32_t M, int32_t* __restrict__ S)
+{
+    const int m = blockIdx.x * kBlock + threadIdx.x;
+    if (m >= M) return;
+    const double mx = __longlong_as_double((long long)max_bits[m]);
+    int e = 0;
+    if (mx > 0.0) {
+        (void)frexp((double)(tri_off[m + 1] - tri_off[m]) * mx, &e);
+        S[m] = 52 - e;
+    } else {
+        S[m] = 0;
+    }
+}
+
+__global__ void k_tri_weight(const double* __restrict__ area, const int32_t* __restrict__ tri_mesh,
+                             const int32_t* __restrict__ S, int64_t T, unsigned long long* __restrict__ W)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= T) return;
+    W[t] = (unsigned long long)floor(ldexp(area[t], S[tri_mesh[t]]));
+}
+
+// One thread: per-mesh totals from the global inclusive scan, counts
+// round(k * total 2^-S) and sample offsets.  M is at most 4096.
+__global__ void k_mesh_counts(const unsigned long long* __restrict__ C, const int64_t* __restrict__ tri_off,
+                              const int32_t* __restrict__ S, int32_t M, double k, int64_t* __restrict__ counts,
+                              int64_t* __restrict__ offsets, unsigned long long* __restrict__ mesh_total)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t run = 0;
+    for (int32_t m = 0; m < M; ++m) {
+        const int64_t a = tri_off[m], b = tri_off[m + 1];
+        const unsigned long long base = a > 0 ? C[a - 1] : 0ull;
+        const unsigned long long tot = C[b - 1] - base;
+        const double area = ldexp((double)tot, -S[m]);
+        const int64_t n = tot ? (int64_t)floor(area * k + 0.5) : 0;
+        counts[m] = n;
+        offsets[m] = run;
+        mesh_total[m] = tot;
+        run += n;
+    }
+    offsets[M] = run;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_sample(const float* __restrict__ V, const int32_t* __restrict__ I, const unsigned long long* __restrict__ C,
+         const int64_t* __restrict__ tri_off, const int64_t* __restrict__ offsets,
+         const unsigned long long* __restrict__ mesh_total, int32_t M, int64_t N, uint32_t key0, uint32_t key1,
+         int32_t* __restrict__ tri_out, int32_t* __restrict__ mesh_out, float* __restrict__ bary_out,
+         float* __restrict__ pos_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    // mesh of sample i: last m with offsets[m] <= i (offsets is non-decreasing)
+    int32_t lo = 0, hi = M - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (offsets[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const int32_t m = lo;
+    const uint64_t j = (uint64_t)(i - offsets[m]);
+    uint32_t x0 = (uint32_t)j, x1 = (uint32_t)(j >> 32), x2 = (uint32_t)m, x3 = 0u;
+    philox4x32_10(x0, x1, x2, x3, key0, key1);
+
+    // area-weighted triangle: the first with inclusive weight sum above the target
+    const uint64_t U = ((uint64_t)x0 << 32) | (uint64_t)x1;
+    const uint64_t target = __umul64hi(U, mesh_total[m]);
+    const int64_t a = tri_off[m];
+    const uint64_t goal = (a > 0 ? C[a - 1] : 0ull) + target;
+    int64_t l = a, h = tri_off[m + 1] - 1;
+    while (l < h) {
+        const int64_t mid = l + ((h - l) >> 1);
+        if (C[mid] > goal) h = mid; else l = mid + 1;
+    }
+    const int64_t t = l;
+
+    // uniform point in the triangle by the square-root warp
+    const double u = ldexp((double)x2, -32);
+    const double v = ldexp((double)x3, -32);
+    const double su = sqrt(u);
+    const double b1 = su * (1.0 - v);
+    const double b2 = su * v;
+    const double b0 = 1.0 - su;
+    const int32_t i0 = I[3 * t], i1 = I[3 * t + 1], i2 = I[3 * t + 2];
+    if (tri_out) tri_out[i] = (int32_t)t;
+    if (mesh_out) mesh_out[i] = m;
+    if (bary_out) {
+        bary_out[2 * i] = (float)b1;
+        bary_out[2 * i + 1] = (float)b2;
+    }
+    if (pos_out) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double p = b0 * (double)V[3 * i0 + c];
+            p = p + b1 * (double)V[3 * i1 + c];
+            p = p + b2 * (double)V[3 * i2 + c];
+            pos_out[3 * i + c] = (float)p;
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+void launch_tri_area(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T, double* area,
+                     unsigned long long* max_bits, hipStream_t s)
+{
+    if (T > 0) k_tri_area<<<grid_for(T), kBlock, 0, s>>>(V, I, tri_mesh, T, area, max_bits);
+}
+
+void launch_mesh_scale(const unsigned long long* max_bits, const int64_t* tri_off, int32_t M, int32_t* S,
+                       hipStream_t s)
+{
+    k_mesh_scale<<<grid_for(M), kBlock, 0, s>>>(max_bits, tri_off, M, S);
+}
+
+void launch_tri_weight(const double* area, const int32_t* tri_mesh, const int32_t* S, int64_t T,
+                       unsigned long long* W, hipStream_t s)
+{
+    if (T > 0) k_tri_weight<<<grid_for(T), kBlock, 0, s>>>(area, tri_mesh, S, T, W);
+}
+
+void launch_mesh_counts(const unsigned long long* C, const int64_t* tri_off, const int32_t* S, int32_t M,
+                        double k, int64_t* counts, int64_t* offsets, unsigned long long* mesh_total,
+                        hipStream_t s)
+{
+    k_mesh_counts<<<1, 1, 0, s>>>(C, tri_off, S, M, k, counts, offsets, mesh_total);
+}
+
+void launch_sample(const float* V, const int32_t* I, const unsigned long long* C, const int64_t* tri_off,
+                   const int64_t* offsets, const unsigned long long* mesh_total, int32_t M, int64_t N,
+                   uint64_t seed, int32_t* tri, int32_t* mesh, float* bary, float* pos, hipStream_t s)
+{
+    if (N > 0)
+        k_sample<<<grid_for(N), kBlock, 0, s>>>(V, I, C, tri_off, offsets, mesh_total, M, N, (uint32_t)seed,
+                                                (uint32_t)(seed >> 32), tri, mesh, bary, pos);
+}
+
+}  // namespace gm

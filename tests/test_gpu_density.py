@@ -1,0 +1,171 @@
+"""GPU density path (a4-a7) against the FP64 oracle.
+
+Tolerance (from the FP32 arithmetic of the exact path): per sample
+|rho_gpu - rho_oracle| <= 1e-5 * rho_oracle + B_s, where B_s is the oracle's sum of g
+over the sample's pairs whose cone decision sits within 1e-5 of the 4-sigma boundary
+or whose visibility decision is within the bookkeeping tolerances of flipping.
+Visibility disagreements must stay <= 1e-4 of the in-cone pairs."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def gm():
+    import torch
+    import paper_2601_07571_amd as gm
+    assert torch.cuda.is_available()
+    gm.load_library()
+    return gm
+
+
+@pytest.fixture(scope="module")
+def tiny(gm):
+    w = workloads.tiny_icosphere_scene()
+    meshes = [(m.V, m.I) for m in w.meshes]
+    scene = gm.Scene(meshes)
+    s = scene.build_samples(w.k, w.seed)
+    fix = gm.Fixations(w.fix.eye, w.fix.gaze, w.fix.dur)
+    ref_s = oracle.sample_scene(meshes, w.k, w.seed)
+    return w, meshes, scene, s, fix, ref_s
+
+
+def _parity(got, ref, rel=REL):
+    got = np.asarray(got, np.float64)
+    err = np.abs(got - ref.rho)
+    ok = err <= rel * ref.rho + ref.budget + 1e-30
+    clean = (ref.budget == 0) & (ref.rho > 0)
+    worst = float(np.max(err[clean] / ref.rho[clean])) if clean.any() else 0.0
+    return ok, worst
+
+
+@pytest.mark.parametrize("occ", ["none", "self", "full"])
+def test_tiny_density_parity(gm, tiny, occ):
+    import torch
+    w, meshes, scene, s, fix, ref_s = tiny
+    out = scene.accumulate(s.pos, fix, w.theta_deg, occlusion=occ, tri=s.tri, mesh=s.mesh)
+    torch.cuda.synchronize()
+    sc = oracle.Scene(meshes)
+    ref = oracle.density(sc, ref_s.pos32, ref_s.tri, ref_s.mesh, w.fix.eye, w.fix.gaze, w.fix.dur, w.theta_deg,
+                         mode={"none": oracle.OCC_NONE, "self": oracle.OCC_SELF, "full": oracle.OCC_FULL}[occ])
+    ok, worst = _parity(out.density.cpu().numpy(), ref)
+    assert ok.all(), f"{(~ok).sum()} samples outside tolerance, worst clean rel err {worst:.2e}"
+    assert worst <= REL
+    # normalisation: max = max rho, rho_hat = rho / max
+    d = out.density.cpu().numpy().astype(np.float64)
+    mx = float(out.max.cpu().numpy()[0])
+    assert mx == np.float32(d.max())
+    dn = out.density_norm.cpu().numpy()
+    assert dn.max() == 1.0 and dn.min() >= 0.0
+    assert np.allclose(dn, d / d.max(), rtol=1e-6, atol=1e-7)
+    ref_n, ref_max = oracle.normalize(ref.rho)
+    assert abs(mx - ref_max) <= REL * ref_max + ref.budget.max()
+
+
+def test_pair_values_stage(gm, tiny):
+    """Every (sample, fixation) pair of the tiny scene: the exact-path value."""
+    import torch
+    w, meshes, scene, s, fix, ref_s = tiny
+    N, F = len(ref_s.tri), len(w.fix.eye)
+    ps = np.repeat(np.arange(N), F); pf = np.tile(np.arange(F), N)
+    g = gm.pair_values(s.pos, fix, w.theta_deg, ps, pf).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    rg, margin, inside = oracle.pair_values(ref_s.pos32, w.fix.eye, w.fix.gaze, w.fix.dur, ps, pf, w.theta_deg)
+    amb = np.abs(margin) < 1e-5
+    firm = ~amb
+    assert np.all((g[firm] > 0) == inside[firm])
+    rel = np.abs(g[firm & inside] - rg[firm & inside]) / rg[firm & inside]
+    assert rel.max() <= REL, rel.max()
+    assert inside.sum() > 10000
+
+
+def test_visibility_stage(gm, tiny):
+    w, meshes, scene, s, fix, ref_s = tiny
+    N, F = len(ref_s.tri), len(w.fix.eye)
+    ps = np.repeat(np.arange(N), F); pf = np.tile(np.arange(F), N)
+    _, _, inside = oracle.pair_values(ref_s.pos32, w.fix.eye, w.fix.gaze, w.fix.dur, ps, pf, w.theta_deg)
+    ps, pf = ps[inside], pf[inside]
+    sc = oracle.Scene(meshes)
+    for occ, mode in (("self", 1), ("full", 2)):
+        vis = scene.pair_visibility(s.pos, fix.eye, ps, pf, occlusion=occ, tri=s.tri, mesh=s.mesh).cpu().numpy()
+        rv, frag = sc.pair_visibility(ref_s.pos32, ref_s.tri, ref_s.mesh, w.fix.eye, ps, pf, mode=mode)
+        dis = (vis.astype(bool) != rv)
+        assert dis.sum() <= 1e-4 * len(ps) + (dis & frag).sum()
+        assert (dis & ~frag).sum() == 0
+        assert 0.2 < rv.mean() < 0.9
+
+
+def test_paper_shaped_sampled_parity(gm):
+    """Full paper-shaped workload (806k triangles, ~2M samples, 6,000 fixations, full occlusion)
+    in the launch configuration the benchmark times; the oracle recomputes 1,500 seeded samples."""
+    import torch
+    w = workloads.paper_shaped_scene()
+    meshes = [(m.V, m.I) for m in w.meshes]
+    scene = gm.Scene(meshes)
+    s = scene.build_samples(204240.0, w.seed)
+    fix = gm.Fixations(w.fix.eye, w.fix.gaze, w.fix.dur)
+    out = scene.accumulate(s.pos, fix, w.theta_deg, occlusion="full", tri=s.tri, mesh=s.mesh)
+    torch.cuda.synchronize()
+    d = out.density.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(123)
+    pick = rng.choice(len(d), 1500, replace=False)
+    hot = np.argsort(d)[-20:]                # the densest samples set the normalisation
+    pick = np.unique(np.concatenate([pick, hot]))
+    pos = s.pos.cpu().numpy()[pick]; tri = s.tri.cpu().numpy()[pick]; mesh = s.mesh.cpu().numpy()[pick]
+    sc = oracle.Scene(meshes)
+    ref = oracle.density(sc, pos, tri, mesh, w.fix.eye, w.fix.gaze, w.fix.dur, w.theta_deg, mode=oracle.OCC_FULL)
+    ok, worst = _parity(d[pick], ref)
+    assert ok.all(), f"{(~ok).sum()} of {len(pick)} samples outside tolerance"
+    assert worst <= REL
+    assert (ref.rho > 0).mean() > 0.2
+    dn = out.density_norm.cpu().numpy()
+    assert dn.max() == 1.0
+    assert float(out.max.cpu()[0]) == np.float32(d.max())
+
+
+def test_edge_cases(gm, tiny):
+    import torch
+    w, meshes, scene, s, fix, ref_s = tiny
+    # no samples
+    e = scene.accumulate(s.pos[:0], fix, 1.0, tri=s.tri[:0])
+    torch.cuda.synchronize()
+    assert e.density.numel() == 0 and float(e.max.cpu()[0]) == 0.0
+    # no fixations: all zero
+    z = scene.accumulate(s.pos, fix.subset(0, 0), 1.0, tri=s.tri)
+    assert float(z.density.abs().max().cpu()) == 0.0 and float(z.density_norm.abs().max().cpu()) == 0.0
+    # ragged sizes equal the prefix of the full run
+    full = scene.accumulate(s.pos, fix, w.theta_deg, occlusion="self", tri=s.tri).density.cpu().numpy()
+    for n in (1, 63, 1025, 4097):
+        part = scene.accumulate(s.pos[:n], fix, w.theta_deg, occlusion="self", tri=s.tri[:n]).density.cpu().numpy()
+        assert np.array_equal(part, full[:n])
+    # invalid fixations (zero gaze, NaN eye, negative duration) add nothing
+    eye = np.concatenate([w.fix.eye, [[0, 0, 2], [np.nan, 0, 2], [0, 0, 2]]]).astype(np.float32)
+    gaze = np.concatenate([w.fix.gaze, [[0, 0, 0], [0, 0, -1], [0, 0, -1]]]).astype(np.float32)
+    dur = np.concatenate([w.fix.dur, [1, 1, -1]]).astype(np.float32)
+    bad = scene.accumulate(s.pos, gm.Fixations(eye, gaze, dur), w.theta_deg, occlusion="self", tri=s.tri)
+    assert np.array_equal(bad.density.cpu().numpy(), full)
+    # theta outside (0, 45) is rejected
+    with pytest.raises(gm.GazemapError):
+        scene.accumulate(s.pos, fix, 0.0, tri=s.tri)
+
+
+def test_bitwise_repeatable_and_order_independent(gm, tiny):
+    w, meshes, scene, s, fix, ref_s = tiny
+    a = scene.accumulate(s.pos, fix, w.theta_deg, occlusion="self", tri=s.tri).density.cpu().numpy()
+    b = scene.accumulate(s.pos, fix, w.theta_deg, occlusion="self", tri=s.tri).density.cpu().numpy()
+    assert np.array_equal(a, b)
+    perm = np.random.default_rng(0).permutation(len(w.fix.eye))
+    fp = gm.Fixations(w.fix.eye[perm], w.fix.gaze[perm], w.fix.dur[perm])
+    c = scene.accumulate(s.pos, fp, w.theta_deg, occlusion="self", tri=s.tri).density.cpu().numpy()
+    assert np.array_equal(a, c)
+    # samples in a different order: same values, permuted
+    sp = np.random.default_rng(1).permutation(len(ref_s.tri))
+    d = scene.accumulate(s.pos.cpu().numpy()[sp], fix, w.theta_deg, occlusion="self",
+                         tri=s.tri.cpu().numpy()[sp]).density.cpu().numpy()
+    assert np.array_equal(d, a[sp])
