@@ -166,6 +166,14 @@ gm_status gm_debug_pair_visibility(gm_scene* scene, const float* pos, const int3
                                    int64_t m, uint32_t flags, uint8_t* vis_out, void* stream);
 
 /*
+ * gm_density_stats: counters of the last accumulate_density call on this scene,
+ * host int64 out[4] = {pairs inside the 4-sigma cone, of those visible, packet
+ * traversals of the BVH (one per wave, fixation and sample slot with at least one
+ * in-cone lane), BVH node visits}.  Blocking (synchronises the device).
+ */
+gm_status gm_density_stats(gm_scene* scene, int64_t* out);
+
+/*
  * Stage timing with HIP events recorded on the caller's stream around the
  * kernels of each stage (for measurement; off by default).
  * gm_profile_enable(scene, 1) starts recording and clears the totals.

@@ -24,7 +24,8 @@ OCC = {"none": 0, "self": 1, "full": 2}
 # exported symbols of include/gazemap.h
 SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy", "gm_scene_info",
            "gm_count_surface_samples", "build_surface_samples", "accumulate_density",
-           "gm_debug_pair_values", "gm_debug_pair_visibility", "gm_profile_enable", "gm_profile_read")
+           "gm_debug_pair_values", "gm_debug_pair_visibility", "gm_profile_enable", "gm_profile_read",
+           "gm_density_stats")
 
 
 class GazemapError(RuntimeError):
@@ -68,6 +69,7 @@ def load_library(path: str = LIB_PATH):
     lib.gm_debug_pair_values.argtypes = [vp, i64, ctypes.POINTER(_Fix), dbl, vp, vp, i64, vp, vp]
     lib.gm_debug_pair_visibility.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, i64, u32, vp, vp]
     lib.gm_profile_enable.argtypes = [vp, i32]
+    lib.gm_density_stats.argtypes = [vp, ctypes.POINTER(i64)]
     lib.gm_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in SYMBOLS[2:]:
         getattr(lib, name).restype = i32
@@ -175,6 +177,12 @@ class Scene:
         return {"n_triangles": T.value, "n_meshes": M.value, "bvh_nodes": nodes.value,
                 "bvh_depth": depth.value, "bbox": list(bbox)}
 
+    def density_stats(self):
+        """Counters of the last accumulate call: in-cone pairs, visible pairs, traversals, node visits."""
+        out = (ctypes.c_int64 * 4)()
+        _check(_lib.gm_density_stats(self._h, out))
+        return dict(zip(("in_cone", "visible", "traversals", "node_visits"), out[:]))
+
     def profile(self, on=True):
         _check(_lib.gm_profile_enable(self._h, 1 if on else 0))
 
@@ -189,14 +197,18 @@ class Scene:
         _check(_lib.gm_count_surface_samples(self._h, float(samples_per_m2), out, _stream()))
         return np.array(out[:], np.int64)
 
-    def build_samples(self, samples_per_m2, seed=0, capacity=None):
+    def build_samples(self, samples_per_m2, seed=0, capacity=None, out: Samples | None = None):
         torch = _torch()
-        if capacity is None:
-            capacity = int(self.count_samples(samples_per_m2).sum())
-        tri = torch.empty(capacity, dtype=torch.int32, device="cuda")
-        mesh = torch.empty(capacity, dtype=torch.int32, device="cuda")
-        bary = torch.empty((capacity, 2), dtype=torch.float32, device="cuda")
-        pos = torch.empty((capacity, 3), dtype=torch.float32, device="cuda")
+        if out is not None:
+            tri, mesh, bary, pos = out.tri, out.mesh, out.bary, out.pos
+            capacity = int(pos.shape[0])
+        else:
+            if capacity is None:
+                capacity = int(self.count_samples(samples_per_m2).sum())
+            tri = torch.empty(capacity, dtype=torch.int32, device="cuda")
+            mesh = torch.empty(capacity, dtype=torch.int32, device="cuda")
+            bary = torch.empty((capacity, 2), dtype=torch.float32, device="cuda")
+            pos = torch.empty((capacity, 3), dtype=torch.float32, device="cuda")
         n = ctypes.c_int64(0)
         _check(_lib.build_surface_samples(self._h, float(samples_per_m2), int(seed) & (2 ** 64 - 1), _ptr(tri),
                                           _ptr(mesh), _ptr(bary), _ptr(pos), capacity, ctypes.byref(n),

@@ -16,7 +16,6 @@ namespace gm {
 
 namespace {
 
-constexpr int kLeafMax = 4;
 constexpr int kBins = 16;
 constexpr int kMaxDepth = 60;
 
@@ -257,6 +256,11 @@ void build_bvh(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_
         out.nodes.push_back(nd);
         out.depth = 2;
     }
+    BvhTri pad;
+    std::memset(&pad, 0, sizeof(pad));
+    pad.id = -2;
+    pad.mesh = -2;
+    for (int k = 0; k < kLeafMax - 1; ++k) out.tris.push_back(pad);
 }
 
 }  // namespace gm

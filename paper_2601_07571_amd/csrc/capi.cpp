@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -114,7 +115,13 @@ enum Stage { kStageSample = 0, kStagePrep, kStageDensity, kStageFinalize, kStage
 const char* const kStageNames[kStages] = {"sample", "prep", "density", "finalize"};
 
 constexpr double kEpsV = 1e-4;         // visibility tolerance along the segment
-constexpr double kGateWiden = 2e-3;    // relative widening of the cheap cone gate
+// Relative widening of kappa in the cheap cone gate.  The FP32 error of the gate value
+// is below ~1e-6 |r|^2 (|e'| + |x'|)^2 (tile-local coordinates), the widening adds
+// kGateWiden * kappa |p|^2 of margin, so no pair of the exact cone is missed while
+// |p| > 0.46 R_tile; eyes closer than 2 R_tile to the tile origin take the exact
+// path for every pair.  It enlarges the cone solid angle by about
+// kGateWiden / (4 sigma)^2 (0.6 % at theta = 1 deg).
+constexpr double kGateWiden = 3e-5;
 
 }  // namespace
 
@@ -129,8 +136,8 @@ struct gm_scene {
     // sampler scratch
     DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total;
     // density scratch
-    DevBuf fix, fx_shift, key, hist, cursor, spos, smesh, perm, acc, max_acc, scan_tmp2;
-    int32_t spl = 4;
+    DevBuf fix, fx_shift, key, hist, cursor, spos, smesh, perm, acc, max_acc, scan_tmp2, stats;
+    int32_t spl = 2;
     bool profiling = false;
     StageTimer timers[kStages];
 
@@ -149,7 +156,7 @@ struct gm_scene {
         for (auto& t : timers) t.release();
         for (DevBuf* b : {&V, &I, &tri_mesh, &tri_off_d, &nodes, &tris, &area, &W, &C, &max_bits, &S, &scan_tmp,
                           &counts, &offsets, &mesh_total, &fix, &fx_shift, &key, &hist, &cursor, &spos, &smesh,
-                          &perm, &acc, &max_acc, &scan_tmp2})
+                          &perm, &acc, &max_acc, &scan_tmp2, &stats})
             b->release();
     }
 };
@@ -244,6 +251,10 @@ gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** ou
     if (T >= (int64_t)1 << 31) return fail(GM_ERR_INVALID_ARGUMENT, "more than 2^31 - 1 triangles");
     gm_scene* sc = new (std::nothrow) gm_scene();
     if (!sc) return fail(GM_ERR_OUT_OF_MEMORY, "host allocation failed");
+    if (const char* e = std::getenv("GM_SAMPLES_PER_LANE")) {
+        const int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8) sc->spl = v;
+    }
     hipError_t he = hipGetDevice(&sc->device);
     if (he != hipSuccess) {
         delete sc;
@@ -394,6 +405,8 @@ gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri,
     GM_HIP(sc->perm.ensure(4 * nn));
     GM_HIP(sc->acc.ensure(8 * nn));
     GM_HIP(sc->max_acc.ensure(8));
+    GM_HIP(sc->stats.ensure(8 * kDensityStats));
+    zero(sc->stats.p, 8 * kDensityStats, s);
 
     GM_HIP(sc->tbegin(kStagePrep, s));
     zero(sc->fx_shift.p, 16, s);
@@ -431,6 +444,7 @@ gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri,
         a.kexp = (float)(1.0 / (2.0 * sigma * sigma * std::log(2.0)));
         a.fx_shift = sc->fx_shift.as<int32_t>();
         a.acc = sc->acc.as<unsigned long long>();
+        a.stats = sc->stats.as<unsigned long long>();
         a.spl = sc->spl;
         const int64_t tiles = (n + 256 * a.spl - 1) / (256 * a.spl);
         const int64_t max_chunks = std::max<int64_t>(1, (F + 127) / 128);
@@ -491,6 +505,21 @@ gm_status gm_debug_pair_visibility(gm_scene* sc, const float* pos, const int32_t
     launch_pair_visibility(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), eye, pair_s, pair_f, m, n_points, n_eyes, sc->T,
                            sc->nodes.as<BvhNode>(), sc->tris.as<BvhTri>(), (int32_t)mode, (float)(1.0 - kEpsV), vis_out, (hipStream_t)stream);
     GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
+gm_status gm_density_stats(gm_scene* sc, int64_t* out)
+{
+    g_error.clear();
+    if (!sc || !out) return fail(GM_ERR_INVALID_ARGUMENT, "scene and out must not be NULL");
+    if (!sc->stats.p) {
+        for (int i = 0; i < kDensityStats; ++i) out[i] = 0;
+        return GM_OK;
+    }
+    GM_HIP(hipDeviceSynchronize());
+    unsigned long long v[kDensityStats];
+    GM_HIP(hipMemcpy(v, sc->stats.p, sizeof(v), hipMemcpyDeviceToHost));
+    for (int i = 0; i < kDensityStats; ++i) out[i] = (int64_t)v[i];
     return GM_OK;
 }
 

@@ -33,6 +33,10 @@ struct alignas(16) BvhTri {
 };
 static_assert(sizeof(BvhTri) == 48, "triangle record is 48 bytes");
 
+// Most triangles per leaf; the record array carries kLeafMax - 1 zeroed records past
+// the end so a leaf's records can always be fetched as one group of kLeafMax.
+constexpr int kLeafMax = 4;
+
 // Per-fixation record written by the prep kernel (32 bytes).
 struct alignas(16) FixRec {
     float ex, ey, ez;  // eye
@@ -78,6 +82,7 @@ void launch_sample(const float* V, const int32_t* I, const unsigned long long* C
                    uint64_t seed, int32_t* tri, int32_t* mesh, float* bary, float* pos, hipStream_t s);
 
 // density path
+constexpr int kDensityStats = 4;  // in-cone pairs, visible pairs, packet traversals, BVH node visits
 struct DensityLaunch {
     // sorted samples
     const float4* spos;        // xyz, w = own triangle (int bits, -1 = none)
@@ -93,6 +98,7 @@ struct DensityLaunch {
     float kexp;                // log2(e) / (2 sigma^2)
     const int32_t* fx_shift;   // device scalar: fixed-point scale exponent
     unsigned long long* acc;   // [n] fixed-point density, sorted order
+    unsigned long long* stats; // [kDensityStats] counters of the call
     int32_t fix_per_chunk;
     int32_t n_chunks;
     int32_t spl;               // samples per lane

@@ -203,7 +203,7 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const BvhTri& t, float tma
 // wave-uniform addresses (scalar loads); the traversal stack lives in one VGPR,
 // lane i holding entry i.
 __device__ bool occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, const Seg& sg,
-                                int own_tri, int own_mesh, int mode, float tmax, bool active)
+                                int own_tri, int own_mesh, int mode, float tmax, bool active, uint32_t& visits)
 {
     const int lane = lane_id();
     bool occ = false;
@@ -214,6 +214,7 @@ __device__ bool occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
     int node = 0;
     for (;;) {
         const BvhNode nd = load_node(nodes, node);
+        ++visits;
         const bool me = (alive >> lane) & 1ull;
         float tn0, tn1;
         const bool h0 = box_hit(sg, nd.lo0, nd.hi0, tmax, tn0) && me;
@@ -233,12 +234,18 @@ __device__ bool occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
             const int count = first ? nd.count0 : nd.count1;
             const bool hit_box = first ? h0 : h1;
             if (child < 0) {
+                // all records of the leaf are fetched together (the array is padded so
+                // that kLeafMax records from any leaf start are in bounds)
                 const int t0 = ~child;
-                for (int k = 0; k < count; ++k) {
-                    const BvhTri tr = load_tri(tris, t0 + k);
-                    const bool skip = tr.id == own_tri || (mode == 1 && tr.mesh != own_mesh);
+                BvhTri tr[kLeafMax];
+#pragma unroll
+                for (int k = 0; k < kLeafMax; ++k) tr[k] = load_tri(tris, t0 + k);
+#pragma unroll
+                for (int k = 0; k < kLeafMax; ++k) {
+                    if (k >= count) break;
+                    const bool skip = tr[k].id == own_tri || (mode == 1 && tr[k].mesh != own_mesh);
                     const bool test = hit_box && !occ && !skip && ((alive >> lane) & 1ull);
-                    if (test && seg_tri(sg, tr, tmax)) occ = true;
+                    if (test && seg_tri(sg, tr[k], tmax)) occ = true;
                 }
                 alive = ballot(((alive >> lane) & 1ull) && !occ);
                 if (alive == 0) return occ;
@@ -362,7 +369,8 @@ __device__ __forceinline__ unsigned xcd_block(unsigned L, unsigned G)
     return (L & 7u) * q + (L >> 3);
 }
 
-template <int SPL>
+// OCC = 0: no occlusion (no traversal code); OCC = 1: visibility by the BVH.
+template <int SPL, int OCC>
 __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
 {
     __shared__ float4 s_ra[kFB];  // rx, ry, rz, c0
@@ -370,6 +378,7 @@ __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
     __shared__ float s_rc[kFB];   // -kappa
     __shared__ unsigned long long s_acc[kThreads * SPL];  // one entry per sample, owned by one lane
     __shared__ float s_rad;
+    __shared__ uint32_t s_stats[kDensityStats];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -384,7 +393,9 @@ __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
     // tile origin: its first sample; radius: largest distance of a tile sample to it
     const float4 o4 = a.spos[tile_base];
     if (threadIdx.x == 0) s_rad = 0.0f;
+    if (threadIdx.x < kDensityStats) s_stats[threadIdx.x] = 0u;
     __syncthreads();
+    uint32_t n_in = 0, n_vis = 0, n_trav = 0, n_visits = 0;  // wave-uniform counters
 
     float px[SPL], py[SPL], pz[SPL], pq[SPL];
     float rad = 0.0f;
@@ -399,8 +410,8 @@ __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
     }
     atomicMax((unsigned int*)&s_rad, __float_as_uint(rad));
     __syncthreads();
-    // eyes within ~1.1 tile radii of the origin take the exact path for every pair
-    const float near2 = 1.21f * s_rad + 1e-12f;
+    // eyes within 2 tile radii of the origin take the exact path for every pair
+    const float near2 = 4.0f * s_rad + 1e-12f;
 
     const int shift = *a.fx_shift;
     const int f_begin = chunk * a.fix_per_chunk;
@@ -455,13 +466,17 @@ __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
                     g = pair_value(p.x, p.y, p.z, fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w, a.cone2, a.kexp);
                 }
                 bool vis = true;
-                const bool need = g > 0.0f && a.occ_mode != 0;
-                if (ballot(need) != 0) {
+                const bool need = OCC != 0 && g > 0.0f;
+                const uint64_t need_mask = ballot(need);
+                if (OCC != 0 && need_mask != 0) {
                     const Seg sg = make_seg(fr.ex, fr.ey, fr.ez, p.x, p.y, p.z);
                     const int own_mesh = need ? a.smesh[i] : -1;
                     vis = !occluded_packet(a.nodes, a.tris, sg, __float_as_int(p.w), own_mesh, a.occ_mode,
-                                           a.tmax, need);
+                                           a.tmax, need, n_visits);
+                    ++n_trav;
                 }
+                n_in += (uint32_t)__popcll(ballot(g > 0.0f));
+                n_vis += (uint32_t)__popcll(ballot(g > 0.0f && vis));
                 if (g > 0.0f && vis) s_acc[wave * (64 * SPL) + k * 64 + lane] += to_fixed(g, shift);
             }
         }
@@ -472,19 +487,34 @@ __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
         const unsigned long long v = s_acc[wave * (64 * SPL) + k * 64 + lane];
         if (i < n && v != 0ull) atomicAdd(&a.acc[i], v);
     }
+    if (lane == 0) {
+        atomicAdd(&s_stats[0], n_in);
+        atomicAdd(&s_stats[1], n_vis);
+        atomicAdd(&s_stats[2], n_trav);
+        atomicAdd(&s_stats[3], n_visits);
+    }
+    __syncthreads();
+    if (threadIdx.x < kDensityStats && s_stats[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], (unsigned long long)s_stats[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
 // a7: maximum and outputs in the caller's order
 // ---------------------------------------------------------------------------
-__global__ void k_max(const unsigned long long* __restrict__ acc, int64_t n, unsigned long long* __restrict__ out)
+__global__ void __launch_bounds__(256) k_max(const unsigned long long* __restrict__ acc, int64_t n,
+                                              unsigned long long* __restrict__ out)
 {
+    __shared__ unsigned long long s_m[4];
     unsigned long long m = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         m = max(m, acc[i]);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, d, 64));
-    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+        if (m) atomicMax(out, m);
+    }
 }
 
 __global__ void k_finalize(const unsigned long long* __restrict__ acc, const int32_t* __restrict__ perm, int64_t n,
@@ -545,7 +575,8 @@ __global__ void __launch_bounds__(64) k_pair_visibility(const float* __restrict_
     if (t < 0 || t >= T) t = -1;
     const int me = mesh ? mesh[s] : (t >= 0 ? tri_mesh[t] : -1);
     const Seg sg = make_seg(eye[3 * f], eye[3 * f + 1], eye[3 * f + 2], pos[3 * s], pos[3 * s + 1], pos[3 * s + 2]);
-    const bool occ = mode != 0 && occluded_packet(nodes, tris, sg, t, me, mode, tmax, lane == 0);
+    uint32_t visits = 0;
+    const bool occ = mode != 0 && occluded_packet(nodes, tris, sg, t, me, mode, tmax, lane == 0, visits);
     if (lane == 0) vis[i] = occ ? 0 : 1;
 }
 
@@ -586,18 +617,19 @@ void launch_density(const DensityLaunch& a, hipStream_t s)
     if (a.n <= 0 || a.F <= 0) return;
     const int64_t per_tile = (int64_t)kThreads * a.spl;
     const dim3 grid(blocks(a.n, (int)per_tile), (unsigned)a.n_chunks);
+    const bool occ = a.occ_mode != 0;
     switch (a.spl) {
-    case 1: k_density<1><<<grid, kThreads, 0, s>>>(a); break;
-    case 2: k_density<2><<<grid, kThreads, 0, s>>>(a); break;
-    case 4: k_density<4><<<grid, kThreads, 0, s>>>(a); break;
-    default: k_density<8><<<grid, kThreads, 0, s>>>(a); break;
+    case 1: occ ? k_density<1, 1><<<grid, kThreads, 0, s>>>(a) : k_density<1, 0><<<grid, kThreads, 0, s>>>(a); break;
+    case 2: occ ? k_density<2, 1><<<grid, kThreads, 0, s>>>(a) : k_density<2, 0><<<grid, kThreads, 0, s>>>(a); break;
+    case 4: occ ? k_density<4, 1><<<grid, kThreads, 0, s>>>(a) : k_density<4, 0><<<grid, kThreads, 0, s>>>(a); break;
+    default: occ ? k_density<8, 1><<<grid, kThreads, 0, s>>>(a) : k_density<8, 0><<<grid, kThreads, 0, s>>>(a); break;
     }
 }
 
 void launch_finalize(const unsigned long long* acc, const int32_t* perm, int64_t n, const int32_t* fx_shift,
                      unsigned long long* max_acc, float* density, float* density_norm, float* max_out, hipStream_t s)
 {
-    if (n > 0) k_max<<<std::min<unsigned>(blocks(n, 256), 2048u), 256, 0, s>>>(acc, n, max_acc);
+    if (n > 0) k_max<<<std::min<unsigned>(blocks(n, 256), 512u), 256, 0, s>>>(acc, n, max_acc);
     k_finalize<<<blocks(n > 0 ? n : 1, 256), 256, 0, s>>>(acc, perm, n, fx_shift, max_acc, density, density_norm,
                                                           max_out);
 }

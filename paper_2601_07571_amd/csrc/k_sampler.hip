@@ -37,8 +37,9 @@ __global__ void k_tri_area(const float* __restrict__ V, const int32_t* __restric
                            unsigned long long* __restrict__ max_bits)
 {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= T) return;
-    const int32_t i0 = I[3 * t], i1 = I[3 * t + 1], i2 = I[3 * t + 2];
+    const bool live = t < T;
+    const int64_t tt = live ? t : T - 1;
+    const int32_t i0 = I[3 * tt], i1 = I[3 * tt + 1], i2 = I[3 * tt + 2];
     const double ax = V[3 * i0], ay = V[3 * i0 + 1], az = V[3 * i0 + 2];
     const double ux = (double)V[3 * i1] - ax, uy = (double)V[3 * i1 + 1] - ay, uz = (double)V[3 * i1 + 2] - az;
     const double wx = (double)V[3 * i2] - ax, wy = (double)V[3 * i2 + 1] - ay, wz = (double)V[3 * i2 + 2] - az;
@@ -48,9 +49,20 @@ __global__ void k_tri_area(const float* __restrict__ V, const int32_t* __restric
     double sq = cx * cx + cy * cy;
     sq = sq + cz * cz;
     const double a = 0.5 * sqrt(sq);
-    area[t] = a;
-    // non-negative doubles order like their bit patterns
-    atomicMax(&max_bits[tri_mesh[t]], (unsigned long long)__double_as_longlong(a));
+    if (live) area[t] = a;
+    // Per-mesh maximum.  Non-negative doubles order like their bit patterns, so the
+    // maximum is an integer maximum; reduce across the wave first when the whole
+    // wave lies in one mesh (all but a few waves), else one atomic per lane.
+    const int mesh = tri_mesh[tt];
+    unsigned long long bits = live ? (unsigned long long)__double_as_longlong(a) : 0ull;
+    const int mesh0 = __builtin_amdgcn_readfirstlane(mesh);
+    if (__ballot(mesh != mesh0) == 0) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) bits = max(bits, (unsigned long long)__shfl_xor(bits, d, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(&max_bits[mesh0], bits);
+    } else if (live) {
+        atomicMax(&max_bits[mesh], bits);
+    }
 }
 
 // S_m = 52 - e with T_m * max A = f 2^e, f in [0.5, 1): the mesh total of the

@@ -169,3 +169,32 @@ def test_bitwise_repeatable_and_order_independent(gm, tiny):
     d = scene.accumulate(s.pos.cpu().numpy()[sp], fix, w.theta_deg, occlusion="self",
                          tri=s.tri.cpu().numpy()[sp]).density.cpu().numpy()
     assert np.array_equal(d, a[sp])
+
+
+def test_eyes_close_to_surface(gm):
+    """Eyes a few centimetres from a dense plane, oblique gazes: the tile-local cheap gate
+    must hand every in-cone pair to the exact path (near-eye tiles are forced)."""
+    import torch
+    xs = np.linspace(-0.3, 0.3, 121)
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    V = np.stack([X, Y, np.zeros_like(X)], -1).reshape(-1, 3).astype(np.float32)
+    i = np.arange(120)[:, None]; j = np.arange(120)[None, :]
+    a = i * 121 + j; b = (i + 1) * 121 + j
+    I = np.concatenate([np.stack([a, b, b + 1], -1).reshape(-1, 3), np.stack([a, b + 1, a + 1], -1).reshape(-1, 3)])
+    meshes = [(V, I.astype(np.int32))]
+    scene = gm.Scene(meshes)
+    s = scene.build_samples(300000.0, 5)
+    rng = np.random.default_rng(9)
+    F = 64
+    eye = np.stack([rng.uniform(-0.2, 0.2, F), rng.uniform(-0.2, 0.2, F), rng.uniform(0.005, 0.05, F)], -1)
+    tgt = np.stack([rng.uniform(-0.25, 0.25, F), rng.uniform(-0.25, 0.25, F), np.zeros(F)], -1)
+    eye, gaze = eye.astype(np.float32), (tgt - eye).astype(np.float32)
+    dur = rng.uniform(0.1, 0.5, F).astype(np.float32)
+    for theta in (0.5, 2.0):
+        out = scene.accumulate(s.pos, gm.Fixations(eye, gaze, dur), theta, occlusion="none", tri=s.tri)
+        torch.cuda.synchronize()
+        ref = oracle.density(None, s.pos.cpu().numpy(), None, None, eye, gaze, dur, theta, mode=oracle.OCC_NONE)
+        ok, worst = _parity(out.density.cpu().numpy(), ref)
+        assert ok.all(), f"theta {theta}: {(~ok).sum()} samples off"
+        assert worst <= REL
+        assert (ref.rho > 0).sum() > 1000
