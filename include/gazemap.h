@@ -165,6 +165,79 @@ gm_status gm_debug_pair_visibility(gm_scene* scene, const float* pos, const int3
                                    int32_t n_eyes, const int32_t* pair_s, const int32_t* pair_f,
                                    int64_t m, uint32_t flags, uint8_t* vis_out, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Neural density field.  Not part of the paper's method: a Fourier-feature   */
+/* MLP that learns the normalised map from (sample position, rho / max rho)  */
+/* pairs produced by build_surface_samples + accumulate_density, and answers */
+/* density queries at arbitrary surface points.  Network: 96 features        */
+/* [sin, cos](2 pi 2^(0.6 b) x~_a), b = 0..15, x~ = (x - lo) / ext in the     */
+/* scene's bounding cube -> 4 x (64, ReLU) -> 1 -> softplus; bf16 matrix-core */
+/* products with fp32 accumulation; Adam on fp32 master weights.  Parameters */
+/* (18,753 floats, host order): W1 [96][64] (input, output), b1 [64], W2, b2, */
+/* W3, b3, W4, b4 (64 x 64, 64), w5 [64], b5; feature index 6 b + 2 a + c   */
+/* (c = 0 sin, 1 cos).  The plain accumulation stays the fallback and the    */
+/* judge: a mesh whose held-out relative L2 error exceeds max_rel_l2 (or a    */
+/* field never trained, or with a non-finite error) is answered by           */
+/* accumulate_density at the query points.                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct gm_field gm_field;
+
+typedef struct {
+    int32_t steps;       /* Adam steps */
+    int32_t batch;       /* points per step, drawn with replacement from the training split */
+    float lr;            /* initial learning rate, cosine-decayed to lr_final */
+    float lr_final;
+    float beta1, beta2, eps;
+    float holdout;       /* fraction of points held out (per point, Philox hash of its index) */
+    float max_rel_l2;    /* gate threshold on the per-mesh held-out relative L2 error */
+    float target_max;    /* raw density that a target of 1 stands for (used by the fallback) */
+    uint64_t seed;       /* key of the split and of the batch draws */
+} gm_train_params;
+
+#define GM_FIELD_PARAMS 18753
+
+/* gm_field_create: a field over the scene's bounding cube with He-uniform weights
+ * drawn from `seed` (zero biases); every mesh gate closed until trained.  Blocking. */
+gm_status gm_field_create(gm_scene* scene, uint64_t seed, gm_field** out);
+gm_status gm_field_destroy(gm_field* field);
+/* host float [GM_FIELD_PARAMS] in, out (blocking) */
+gm_status gm_field_set_params(gm_field* field, const float* params);
+gm_status gm_field_get_params(gm_field* field, float* params);
+/*
+ * gm_field_train: pos [n][3], mesh [n] (mesh of each point, device) and target [n]
+ * (device, the normalised density in [0, 1]).  Runs `steps` Adam steps of mean
+ * squared error on the training split, then evaluates every mesh's relative L2
+ * error sqrt(sum (y - t)^2 / sum t^2) on its held-out points and opens the gate of
+ * the meshes at or below max_rel_l2.  Blocking.
+ */
+gm_status gm_field_train(gm_field* field, const float* pos, const int32_t* mesh, const float* target,
+                         int64_t n, const gm_train_params* params, void* stream);
+/* host outputs (each may be NULL): rel_l2 [n_meshes] (NaN where a mesh had no held-out
+ * point), gate [n_meshes] (1 = field answers), final training loss, steps done. */
+gm_status gm_field_info(gm_field* field, float* rel_l2, uint8_t* gate, double* loss, int64_t* steps);
+/* The field's value (softplus output) at q points, device pos [q][3] -> out [q], whatever
+ * the gates say; queued on `stream`. */
+gm_status gm_field_predict(gm_field* field, const float* pos, int64_t q, float* out, void* stream);
+/* One forward and backward pass over all n points (no update): the mean-squared-error
+ * gradient (host float [GM_FIELD_PARAMS]) and loss.  Blocking.  For gradient checks. */
+gm_status gm_field_gradient(gm_field* field, const float* pos, const float* target, int64_t n, float* grad,
+                            double* loss);
+
+/*
+ * query_density -- the normalised density at q query points (device pos [q][3];
+ * tri / mesh [q] as in accumulate_density, at least one of them for the per-mesh
+ * gate).  With a trained field, points of meshes whose gate is open get the
+ * field's value; every other point (and every point when field is NULL) gets the
+ * plain accumulation (fixations, theta_deg, flags as in accumulate_density)
+ * divided by ref_max (> 0), else by the field's target_max, else by the largest
+ * plain value among the query points.  out [q] (device float); used_fallback [q]
+ * (device uint8, may be NULL) = 1 where the plain path answered.  Blocking when the
+ * plain path runs (one count read-back).
+ */
+gm_status query_density(gm_field* field, gm_scene* scene, const gm_fixations* fix, double theta_deg,
+                        uint32_t flags, const float* pos, const int32_t* tri, const int32_t* mesh, int64_t q,
+                        double ref_max, float* out, uint8_t* used_fallback, void* stream);
+
 /*
  * gm_density_stats: counters of the last accumulate_density call on this scene,
  * host int64 out[4] = {pairs inside the 4-sigma cone, of those visible, packet

@@ -25,7 +25,8 @@ OCC = {"none": 0, "self": 1, "full": 2}
 SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy", "gm_scene_info",
            "gm_count_surface_samples", "build_surface_samples", "accumulate_density",
            "gm_debug_pair_values", "gm_debug_pair_visibility", "gm_profile_enable", "gm_profile_read",
-           "gm_density_stats")
+           "gm_density_stats", "gm_field_create", "gm_field_destroy", "gm_field_set_params",
+           "gm_field_get_params", "gm_field_train", "gm_field_info", "gm_field_gradient", "gm_field_predict", "query_density")
 
 
 class GazemapError(RuntimeError):
@@ -43,6 +44,15 @@ class _Fix(ctypes.Structure):
     _fields_ = [("eye", ctypes.c_void_p), ("gaze", ctypes.c_void_p), ("duration", ctypes.c_void_p),
                 ("n", ctypes.c_int32)]
 
+
+class _TrainParams(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("lr_final", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("holdout", ctypes.c_float), ("max_rel_l2", ctypes.c_float),
+                ("target_max", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+FIELD_PARAMS = 18753
 
 _lib = None
 
@@ -70,6 +80,17 @@ def load_library(path: str = LIB_PATH):
     lib.gm_debug_pair_visibility.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, i64, u32, vp, vp]
     lib.gm_profile_enable.argtypes = [vp, i32]
     lib.gm_density_stats.argtypes = [vp, ctypes.POINTER(i64)]
+    f32p = ctypes.POINTER(ctypes.c_float)
+    lib.gm_field_create.argtypes = [vp, u64, ctypes.POINTER(vp)]
+    lib.gm_field_destroy.argtypes = [vp]
+    lib.gm_field_set_params.argtypes = [vp, f32p]
+    lib.gm_field_get_params.argtypes = [vp, f32p]
+    lib.gm_field_train.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(_TrainParams), vp]
+    lib.gm_field_info.argtypes = [vp, f32p, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(dbl),
+                                  ctypes.POINTER(i64)]
+    lib.gm_field_gradient.argtypes = [vp, vp, vp, i64, f32p, ctypes.POINTER(dbl)]
+    lib.gm_field_predict.argtypes = [vp, vp, i64, vp, vp]
+    lib.query_density.argtypes = [vp, vp, ctypes.POINTER(_Fix), dbl, u32, vp, vp, vp, i64, dbl, vp, vp, vp]
     lib.gm_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in SYMBOLS[2:]:
         getattr(lib, name).restype = i32
@@ -254,3 +275,90 @@ def pair_values(pos, fix: Fixations, theta_deg, pair_s, pair_f):
     _check(_lib.gm_debug_pair_values(_ptr(pos), int(pos.shape[0]), ctypes.byref(fix._c), float(theta_deg),
                                      _ptr(ps), _ptr(pf), int(ps.shape[0]), _ptr(g), _stream()))
     return g
+
+
+class Field:
+    """Neural density field over a scene (see include/gazemap.h)."""
+
+    def __init__(self, scene: Scene, seed=0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.gm_field_create(scene._h, int(seed) & (2 ** 64 - 1), ctypes.byref(h)))
+        self._h = h
+        self.scene = scene
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.gm_field_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.size == FIELD_PARAMS
+        _check(_lib.gm_field_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_params(self):
+        p = np.zeros(FIELD_PARAMS, np.float32)
+        _check(_lib.gm_field_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return p
+
+    def predict(self, pos, out=None):
+        torch = _torch()
+        pos = _dev(pos, torch.float32, 3)
+        q = int(pos.shape[0])
+        if out is None:
+            out = torch.empty(q, dtype=torch.float32, device="cuda")
+        _check(_lib.gm_field_predict(self._h, _ptr(pos), q, _ptr(out), _stream()))
+        return out
+
+    def gradient(self, pos, target):
+        torch = _torch()
+        pos = _dev(pos, torch.float32, 3)
+        target = _dev(target, torch.float32).reshape(-1)
+        g = np.zeros(FIELD_PARAMS, np.float32)
+        loss = ctypes.c_double(0.0)
+        _check(_lib.gm_field_gradient(self._h, _ptr(pos), _ptr(target), int(pos.shape[0]),
+                                      g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train(self, pos, mesh, target, steps=2000, batch=16384, lr=2e-3, lr_final=1e-4, beta1=0.9, beta2=0.999,
+              eps=1e-8, holdout=0.1, max_rel_l2=0.02, target_max=1.0, seed=0):
+        torch = _torch()
+        pos = _dev(pos, torch.float32, 3)
+        mesh = _dev(mesh, torch.int32).reshape(-1)
+        target = _dev(target, torch.float32).reshape(-1)
+        P = _TrainParams(steps, batch, lr, lr_final, beta1, beta2, eps, holdout, max_rel_l2, target_max,
+                         int(seed) & (2 ** 64 - 1))
+        _check(_lib.gm_field_train(self._h, _ptr(pos), _ptr(mesh), _ptr(target), int(pos.shape[0]),
+                                   ctypes.byref(P), _stream()))
+        return self.info()
+
+    def info(self):
+        M = self.scene.n_meshes
+        rel = np.zeros(M, np.float32); gate = np.zeros(M, np.uint8)
+        loss = ctypes.c_double(0.0); steps = ctypes.c_int64(0)
+        _check(_lib.gm_field_info(self._h, rel.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                  gate.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(loss),
+                                  ctypes.byref(steps)))
+        return {"rel_l2": rel, "gate": gate.astype(bool), "loss": loss.value, "steps": steps.value}
+
+
+def query_density(field, scene: Scene, fix: Fixations, theta_deg, pos, tri=None, mesh=None, occlusion="full",
+                  ref_max=0.0, out=None, used=None):
+    """Normalised density at query points: the field where its mesh gate is open, else the plain path."""
+    torch = _torch()
+    pos = _dev(pos, torch.float32, 3)
+    tri = _dev(tri, torch.int32)
+    mesh = _dev(mesh, torch.int32)
+    q = int(pos.shape[0])
+    if out is None:
+        out = torch.empty(q, dtype=torch.float32, device="cuda")
+    if used is None:
+        used = torch.empty(q, dtype=torch.uint8, device="cuda")
+    _check(_lib.query_density(field._h if field is not None else None, scene._h, ctypes.byref(fix._c),
+                              float(theta_deg), OCC[occlusion], _ptr(pos), _ptr(tri), _ptr(mesh), q, float(ref_max),
+                              _ptr(out), _ptr(used), _stream()))
+    return out, used

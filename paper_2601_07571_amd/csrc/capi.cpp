@@ -12,13 +12,16 @@
 #include <vector>
 
 #include "gazemap.h"
+#include "gm_host.h"
 #include "gm_internal.h"
 
 using namespace gm;
 
-namespace {
+namespace gm {
 
+namespace {
 thread_local std::string g_error;
+}  // namespace
 
 gm_status fail(gm_status st, const char* fmt, ...)
 {
@@ -31,137 +34,12 @@ gm_status fail(gm_status st, const char* fmt, ...)
     return st;
 }
 
-#define GM_HIP(call)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (call);                                                                   \
-        if (e_ != hipSuccess) return fail(GM_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
+void clear_error() { g_error.clear(); }
+const char* last_error() { return g_error.c_str(); }
 
-// Device buffer that only grows.
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    hipError_t ensure(size_t want)
-    {
-        if (want <= bytes) return hipSuccess;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-        size_t cap = std::max<size_t>(want, 256);
-        hipError_t e = hipMalloc(&p, cap);
-        if (e == hipSuccess) bytes = cap;
-        return e;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <class T> T* as() const { return static_cast<T*>(p); }
-};
+}  // namespace gm
 
-// Pairs of HIP events around the kernels of one stage.
-struct StageTimer {
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-    size_t used = 0;
-    double total_ms = 0.0;
-    int64_t launches = 0;
-    hipError_t begin(hipStream_t s)
-    {
-        if (used == ev.size()) {
-            hipEvent_t a, b;
-            hipError_t e = hipEventCreate(&a);
-            if (e != hipSuccess) return e;
-            e = hipEventCreate(&b);
-            if (e != hipSuccess) return e;
-            ev.emplace_back(a, b);
-        }
-        return hipEventRecord(ev[used].first, s);
-    }
-    hipError_t end(hipStream_t s) { return hipEventRecord(ev[used++].second, s); }
-    hipError_t collect()
-    {
-        for (size_t i = 0; i < used; ++i) {
-            hipError_t e = hipEventSynchronize(ev[i].second);
-            if (e != hipSuccess) return e;
-            float ms = 0.0f;
-            e = hipEventElapsedTime(&ms, ev[i].first, ev[i].second);
-            if (e != hipSuccess) return e;
-            total_ms += ms;
-            ++launches;
-        }
-        used = 0;
-        return hipSuccess;
-    }
-    void clear()
-    {
-        used = 0;
-        total_ms = 0.0;
-        launches = 0;
-    }
-    void release()
-    {
-        for (auto& p : ev) {
-            (void)hipEventDestroy(p.first);
-            (void)hipEventDestroy(p.second);
-        }
-        ev.clear();
-        clear();
-    }
-};
-
-enum Stage { kStageSample = 0, kStagePrep, kStageDensity, kStageFinalize, kStages };
-const char* const kStageNames[kStages] = {"sample", "prep", "density", "finalize"};
-
-constexpr double kEpsV = 1e-4;         // visibility tolerance along the segment
-// Relative widening of kappa in the cheap cone gate.  The FP32 error of the gate value
-// is below ~1e-6 |r|^2 (|e'| + |x'|)^2 (tile-local coordinates), the widening adds
-// kGateWiden * kappa |p|^2 of margin, so no pair of the exact cone is missed while
-// |p| > 0.46 R_tile; eyes closer than 2 R_tile to the tile origin take the exact
-// path for every pair.  It enlarges the cone solid angle by about
-// kGateWiden / (4 sigma)^2 (0.6 % at theta = 1 deg).
-constexpr double kGateWiden = 3e-5;
-
-}  // namespace
-
-struct gm_scene {
-    int device = 0;
-    int32_t M = 0;
-    int64_t T = 0, NV = 0;
-    std::vector<int64_t> tri_off;  // [M+1]
-    HostBvh bvh;
-    // static device data
-    DevBuf V, I, tri_mesh, tri_off_d, nodes, tris;
-    // sampler scratch
-    DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total;
-    // density scratch
-    DevBuf fix, fx_shift, key, hist, cursor, spos, smesh, perm, acc, max_acc, scan_tmp2, stats;
-    int32_t spl = 2;
-    bool profiling = false;
-    StageTimer timers[kStages];
-
-    hipError_t tbegin(int st, hipStream_t s) { return profiling ? timers[st].begin(s) : hipSuccess; }
-    hipError_t tend(int st, hipStream_t s)
-    {
-        if (!profiling) return hipSuccess;
-        hipError_t e = timers[st].end(s);
-        // keep the event list bounded when nobody reads it
-        if (e == hipSuccess && timers[st].used >= 4096) e = timers[st].collect();
-        return e;
-    }
-
-    ~gm_scene()
-    {
-        for (auto& t : timers) t.release();
-        for (DevBuf* b : {&V, &I, &tri_mesh, &tri_off_d, &nodes, &tris, &area, &W, &C, &max_bits, &S, &scan_tmp,
-                          &counts, &offsets, &mesh_total, &fix, &fx_shift, &key, &hist, &cursor, &spos, &smesh,
-                          &perm, &acc, &max_acc, &scan_tmp2, &stats})
-            b->release();
-    }
-};
-
-namespace {
+namespace gm {
 
 gm_status check_device(const gm_scene* sc)
 {
@@ -172,18 +50,25 @@ gm_status check_device(const gm_scene* sc)
     return GM_OK;
 }
 
+namespace {
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
+}  // namespace
 
-// zero fill by a kernel (also safe inside captured graphs)
-void zero(void* p, size_t bytes, hipStream_t s)
+// fills by a kernel (also safe inside captured graphs)
+void fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s)
 {
-    const int64_t n = (int64_t)((bytes + 3) / 4);
-    if (n > 0) k_fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(static_cast<uint32_t*>(p), n, 0u);
+    if (n > 0) k_fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(static_cast<uint32_t*>(p), n, v);
 }
+
+void zero(void* p, size_t bytes, hipStream_t s) { fill_u32(p, (int64_t)((bytes + 3) / 4), 0u, s); }
+
+}  // namespace gm
+
+namespace {
 
 // a1 + a2 on the device, then the per-mesh counts (blocking read-back).
 gm_status sample_counts(gm_scene* sc, double k, hipStream_t s, std::vector<int64_t>& counts)
@@ -224,13 +109,13 @@ bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1])
 
 extern "C" {
 
-const char* gm_last_error(void) { return g_error.c_str(); }
+const char* gm_last_error(void) { return gm::last_error(); }
 
 int32_t gm_version(void) { return (1 << 16) | 0; }
 
 gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** out)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!out) return fail(GM_ERR_INVALID_ARGUMENT, "out is NULL");
     *out = nullptr;
     if (!meshes || n_meshes < 1 || n_meshes > 4096)
@@ -304,7 +189,7 @@ gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** ou
 
 gm_status gm_scene_destroy(gm_scene* scene)
 {
-    g_error.clear();
+    gm::clear_error();
     if (scene) {
         (void)hipDeviceSynchronize();
         delete scene;
@@ -315,7 +200,7 @@ gm_status gm_scene_destroy(gm_scene* scene)
 gm_status gm_scene_info(const gm_scene* sc, int64_t* n_triangles, int32_t* n_meshes, int64_t* n_bvh_nodes,
                         int32_t* bvh_depth, float* bbox)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
     if (n_triangles) *n_triangles = sc->T;
     if (n_meshes) *n_meshes = sc->M;
@@ -331,7 +216,7 @@ gm_status gm_scene_info(const gm_scene* sc, int64_t* n_triangles, int32_t* n_mes
 
 gm_status gm_count_surface_samples(gm_scene* sc, double k, int64_t* n_per_mesh, void* stream)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!sc || !n_per_mesh) return fail(GM_ERR_INVALID_ARGUMENT, "scene and n_per_mesh must not be NULL");
     gm_status st = check_device(sc);
     if (st != GM_OK) return st;
@@ -345,7 +230,7 @@ gm_status gm_count_surface_samples(gm_scene* sc, double k, int64_t* n_per_mesh, 
 gm_status build_surface_samples(gm_scene* sc, double k, uint64_t seed, int32_t* tri, int32_t* mesh, float* bary,
                                 float* pos, int64_t capacity, int64_t* n_out, void* stream)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
     if (capacity < 0) return fail(GM_ERR_INVALID_ARGUMENT, "capacity < 0");
     gm_status st = check_device(sc);
@@ -372,7 +257,7 @@ gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri,
                              const gm_fixations* fix, double theta_deg, uint32_t flags, float* density,
                              float* density_norm, float* max_out, void* stream)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
     if (!fix) return fail(GM_ERR_INVALID_ARGUMENT, "fixations is NULL");
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GM_ERR_INVALID_ARGUMENT, "n must be in [0, 2^31)");
@@ -469,7 +354,7 @@ gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri,
 gm_status gm_debug_pair_values(const float* pos, int64_t n_points, const gm_fixations* fix, double theta_deg,
                                const int32_t* pair_s, const int32_t* pair_f, int64_t m, float* g_out, void* stream)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!fix || (m > 0 && (!pos || !pair_s || !pair_f || !g_out)) || m < 0 || n_points < 0 || fix->n < 0)
         return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or negative size");
     if (!(theta_deg > 0.0 && theta_deg < 45.0)) return fail(GM_ERR_INVALID_ARGUMENT, "theta_deg must be in (0, 45)");
@@ -495,7 +380,7 @@ gm_status gm_debug_pair_visibility(gm_scene* sc, const float* pos, const int32_t
                                    int64_t n_points, const float* eye, int32_t n_eyes, const int32_t* pair_s,
                                    const int32_t* pair_f, int64_t m, uint32_t flags, uint8_t* vis_out, void* stream)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!sc || m < 0 || n_points < 0 || n_eyes < 0 || (m > 0 && (!pos || !eye || !pair_s || !pair_f || !vis_out)))
         return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or negative size");
     const uint32_t mode = flags & GM_OCC_MASK;
@@ -510,7 +395,7 @@ gm_status gm_debug_pair_visibility(gm_scene* sc, const float* pos, const int32_t
 
 gm_status gm_density_stats(gm_scene* sc, int64_t* out)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!sc || !out) return fail(GM_ERR_INVALID_ARGUMENT, "scene and out must not be NULL");
     if (!sc->stats.p) {
         for (int i = 0; i < kDensityStats; ++i) out[i] = 0;
@@ -525,7 +410,7 @@ gm_status gm_density_stats(gm_scene* sc, int64_t* out)
 
 gm_status gm_profile_enable(gm_scene* sc, int32_t on)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
     for (auto& t : sc->timers) {
         GM_HIP(t.collect());
@@ -537,7 +422,7 @@ gm_status gm_profile_enable(gm_scene* sc, int32_t on)
 
 gm_status gm_profile_read(gm_scene* sc, const char* stage, double* total_ms, int64_t* launches)
 {
-    g_error.clear();
+    gm::clear_error();
     if (!sc || !stage) return fail(GM_ERR_INVALID_ARGUMENT, "scene and stage must not be NULL");
     for (int i = 0; i < kStages; ++i) {
         if (std::strcmp(stage, kStageNames[i]) != 0) continue;

@@ -1,0 +1,365 @@
+// field_api.cpp -- C ABI of the neural density field and of query_density:
+// parameter state, the training loop (train kernel, Adam, repacking per step),
+// held-out evaluation and the per-mesh gate with the plain fallback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "gazemap.h"
+#include "gm_host.h"
+#include "gm_internal.h"
+
+using namespace gm;
+
+struct gm_field {
+    gm_scene* scene = nullptr;
+    FieldGeom geom;
+    DevBuf master, m, v, grad, blob, loss;
+    DevBuf flag, offs, idx, scan_tmp, pred, l2sums;
+    DevBuf gate_d, need, qoffs, qscan, gpos, gtri, gmesh, gidx, grho, gnorm;
+    std::vector<float> rel_l2;
+    std::vector<uint8_t> gate;
+    double norm_max = 0.0;
+    double last_loss = NAN;
+    int64_t steps = 0;
+    bool trained = false;
+
+    ~gm_field()
+    {
+        for (DevBuf* b : {&master, &m, &v, &grad, &blob, &loss, &flag, &offs, &idx, &scan_tmp, &pred, &l2sums,
+                          &gate_d, &need, &qoffs, &qscan, &gpos, &gtri, &gmesh, &gidx, &grho, &gnorm})
+            b->release();
+    }
+};
+
+namespace {
+
+// splitmix64 (Steele, Lea and Flood 2014): the host-side initial weights
+uint64_t splitmix64(uint64_t& x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void init_params(uint64_t seed, std::vector<float>& p)
+{
+    p.assign(kFieldParams, 0.0f);
+    uint64_t st = seed;
+    auto uni = [&](float lim) { return (float)(((double)(splitmix64(st) >> 11) * 0x1.0p-53 * 2.0 - 1.0) * lim); };
+    for (int L = 1; L <= 4; ++L) {
+        const int fan_in = L == 1 ? kFieldFeat : kFieldWidth;
+        const float lim = (float)std::sqrt(6.0 / fan_in);
+        for (int i = 0; i < fan_in * kFieldWidth; ++i) p[(size_t)(kFieldOffW[L] + i)] = uni(lim);
+    }
+    const float lim5 = (float)std::sqrt(6.0 / kFieldWidth);
+    for (int i = 0; i < kFieldWidth; ++i) p[(size_t)(kFieldOffW5 + i)] = uni(lim5);
+}
+
+gm_status upload_params(gm_field* f, const float* host, hipStream_t s)
+{
+    GM_HIP(hipMemcpyAsync(f->master.p, host, sizeof(float) * kFieldParams, hipMemcpyHostToDevice, s));
+    launch_field_pack(f->master.as<float>(), f->blob.as<unsigned char>(), s);
+    GM_HIP(hipGetLastError());
+    GM_HIP(hipStreamSynchronize(s));
+    return GM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gm_status gm_field_create(gm_scene* scene, uint64_t seed, gm_field** out)
+{
+    clear_error();
+    if (!scene || !out) return fail(GM_ERR_INVALID_ARGUMENT, "scene and out must not be NULL");
+    *out = nullptr;
+    gm_status st = check_device(scene);
+    if (st != GM_OK) return st;
+    gm_field* f = new (std::nothrow) gm_field();
+    if (!f) return fail(GM_ERR_OUT_OF_MEMORY, "host allocation failed");
+    f->scene = scene;
+    float ext = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        f->geom.lo[a] = scene->bvh.lo[a];
+        ext = std::max(ext, scene->bvh.hi[a] - scene->bvh.lo[a]);
+    }
+    f->geom.inv_ext = ext > 0.0f ? 1.0f / ext : 1.0f;
+    for (int b = 0; b < kFieldBands; ++b) f->geom.freq[b] = (float)std::exp2(0.6 * b);
+    f->rel_l2.assign((size_t)scene->M, NAN);
+    f->gate.assign((size_t)scene->M, 0);
+    hipError_t e = hipSuccess;
+    for (DevBuf* b : {&f->master, &f->m, &f->v, &f->grad})
+        if (e == hipSuccess) e = b->ensure(sizeof(float) * kFieldParams);
+    if (e == hipSuccess) e = f->blob.ensure(field_pack_bytes());
+    if (e == hipSuccess) e = f->loss.ensure(sizeof(double));
+    if (e != hipSuccess) {
+        delete f;
+        return fail(GM_ERR_OUT_OF_MEMORY, "field allocation: %s", hipGetErrorString(e));
+    }
+    std::vector<float> p;
+    init_params(seed, p);
+    st = upload_params(f, p.data(), nullptr);
+    if (st != GM_OK) {
+        delete f;
+        return st;
+    }
+    zero(f->m.p, sizeof(float) * kFieldParams, nullptr);
+    zero(f->v.p, sizeof(float) * kFieldParams, nullptr);
+    zero(f->grad.p, sizeof(float) * kFieldParams, nullptr);
+    if (hipStreamSynchronize(nullptr) != hipSuccess) {
+        delete f;
+        return fail(GM_ERR_DEVICE, "field initialisation failed");
+    }
+    *out = f;
+    return GM_OK;
+}
+
+gm_status gm_field_destroy(gm_field* f)
+{
+    clear_error();
+    if (f) {
+        (void)hipDeviceSynchronize();
+        delete f;
+    }
+    return GM_OK;
+}
+
+gm_status gm_field_set_params(gm_field* f, const float* params)
+{
+    clear_error();
+    if (!f || !params) return fail(GM_ERR_INVALID_ARGUMENT, "field and params must not be NULL");
+    for (int i = 0; i < kFieldParams; ++i)
+        if (!std::isfinite(params[i])) return fail(GM_ERR_INVALID_ARGUMENT, "parameter %d is not finite", i);
+    return upload_params(f, params, nullptr);
+}
+
+gm_status gm_field_get_params(gm_field* f, float* params)
+{
+    clear_error();
+    if (!f || !params) return fail(GM_ERR_INVALID_ARGUMENT, "field and params must not be NULL");
+    GM_HIP(hipDeviceSynchronize());
+    GM_HIP(hipMemcpy(params, f->master.p, sizeof(float) * kFieldParams, hipMemcpyDeviceToHost));
+    return GM_OK;
+}
+
+gm_status gm_field_gradient(gm_field* f, const float* pos, const float* target, int64_t n, float* grad, double* loss)
+{
+    clear_error();
+    if (!f || !pos || !target || !grad || n <= 0 || n > (1 << 30))
+        return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or n outside (0, 2^30]");
+    gm_status st = check_device(f->scene);
+    if (st != GM_OK) return st;
+    hipStream_t s = nullptr;
+    zero(f->grad.p, sizeof(float) * kFieldParams, s);
+    zero(f->loss.p, sizeof(double), s);
+    FieldTrain t;
+    t.pos = pos;
+    t.target = target;
+    t.idx = nullptr;
+    t.n_idx = n;
+    t.batch = (int32_t)n;
+    t.inv_batch = (float)(1.0 / (double)n);
+    t.key0 = t.key1 = 0;
+    t.step = 0;
+    t.grad = f->grad.as<float>();
+    t.loss = f->loss.as<double>();
+    launch_field_train(f->blob.as<unsigned char>(), f->geom, t, s);
+    GM_HIP(hipGetLastError());
+    double l = 0.0;
+    GM_HIP(hipMemcpy(grad, f->grad.p, sizeof(float) * kFieldParams, hipMemcpyDeviceToHost));
+    GM_HIP(hipMemcpy(&l, f->loss.p, sizeof(double), hipMemcpyDeviceToHost));
+    zero(f->grad.p, sizeof(float) * kFieldParams, s);
+    GM_HIP(hipStreamSynchronize(s));
+    if (loss) *loss = l / (double)n;
+    return GM_OK;
+}
+
+gm_status gm_field_train(gm_field* f, const float* pos, const int32_t* mesh, const float* target, int64_t n,
+                         const gm_train_params* P, void* stream)
+{
+    clear_error();
+    if (!f || !pos || !mesh || !target || !P) return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (n < 2 || n >= ((int64_t)1 << 31)) return fail(GM_ERR_INVALID_ARGUMENT, "n must be in [2, 2^31)");
+    if (P->steps < 0 || P->batch < 1 || !(P->lr > 0.0f) || !(P->lr_final >= 0.0f) || !(P->beta1 >= 0.0f) ||
+        !(P->beta1 < 1.0f) || !(P->beta2 >= 0.0f) || !(P->beta2 < 1.0f) || !(P->eps > 0.0f) ||
+        !(P->holdout > 0.0f) || !(P->holdout < 1.0f) || !(P->max_rel_l2 >= 0.0f))
+        return fail(GM_ERR_INVALID_ARGUMENT, "training parameters out of range");
+    gm_status st = check_device(f->scene);
+    if (st != GM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t M = f->scene->M;
+    GM_HIP(f->flag.ensure(4 * (size_t)n));
+    GM_HIP(f->offs.ensure(4 * (size_t)n));
+    GM_HIP(f->idx.ensure(4 * (size_t)n));
+    GM_HIP(f->scan_tmp.ensure(scan_tmp_bytes(n)));
+    GM_HIP(f->pred.ensure(4 * (size_t)n));
+    GM_HIP(f->l2sums.ensure(16 * (size_t)M));
+
+    // held-out split and the compact list of training points
+    const uint32_t key0 = (uint32_t)P->seed, key1 = (uint32_t)(P->seed >> 32);
+    const uint32_t thr = (uint32_t)std::min(4294967295.0, std::floor((double)P->holdout * 4294967296.0));
+    launch_field_split(n, key0, key1, thr, f->flag.as<uint32_t>(), s);
+    launch_exclusive_scan_u32(f->flag.as<uint32_t>(), f->offs.as<uint32_t>(), n, f->scan_tmp.p, s);
+    launch_field_compact(f->flag.as<uint32_t>(), f->offs.as<uint32_t>(), n, f->idx.as<int32_t>(), s);
+    uint32_t last_off = 0, last_flag = 0;
+    GM_HIP(hipMemcpyAsync(&last_off, f->offs.as<uint32_t>() + (n - 1), 4, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipMemcpyAsync(&last_flag, f->flag.as<uint32_t>() + (n - 1), 4, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    const int64_t n_train = (int64_t)last_off + last_flag;
+    if (n_train < 1) return fail(GM_ERR_INVALID_ARGUMENT, "no training points after the held-out split");
+
+    zero(f->m.p, sizeof(float) * kFieldParams, s);
+    zero(f->v.p, sizeof(float) * kFieldParams, s);
+    zero(f->grad.p, sizeof(float) * kFieldParams, s);
+    FieldTrain t;
+    t.pos = pos;
+    t.target = target;
+    t.idx = f->idx.as<int32_t>();
+    t.n_idx = n_train;
+    t.batch = P->batch;
+    t.inv_batch = 1.0f / (float)P->batch;
+    t.key0 = key0 ^ 0x5bd1e995u;
+    t.key1 = key1 ^ 0x1b873593u;
+    t.grad = f->grad.as<float>();
+    t.loss = f->loss.as<double>();
+    double b1t = 1.0, b2t = 1.0;
+    for (int32_t it = 0; it < P->steps; ++it) {
+        t.step = (uint32_t)it;
+        zero(f->loss.p, sizeof(double), s);
+        launch_field_train(f->blob.as<unsigned char>(), f->geom, t, s);
+        b1t *= P->beta1;
+        b2t *= P->beta2;
+        const double frac = P->steps > 1 ? (double)it / (double)(P->steps - 1) : 1.0;
+        const double lr = P->lr_final + 0.5 * (P->lr - P->lr_final) * (1.0 + std::cos(M_PI * frac));
+        launch_field_adam(f->master.as<float>(), f->m.as<float>(), f->v.as<float>(), f->grad.as<float>(), (float)lr,
+                          P->beta1, P->beta2, P->eps, (float)(1.0 / (1.0 - b1t)), (float)(1.0 / (1.0 - b2t)), s);
+        launch_field_pack(f->master.as<float>(), f->blob.as<unsigned char>(), s);
+    }
+    GM_HIP(hipGetLastError());
+    double l = NAN;
+    if (P->steps > 0) GM_HIP(hipMemcpyAsync(&l, f->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+
+    // held-out relative L2 per mesh
+    launch_field_infer(f->blob.as<unsigned char>(), f->geom, pos, n, f->pred.as<float>(), s);
+    zero(f->l2sums.p, 16 * (size_t)M, s);
+    launch_field_l2(f->pred.as<float>(), target, mesh, f->flag.as<uint32_t>(), n, M, f->l2sums.as<double>(), s);
+    GM_HIP(hipGetLastError());
+    std::vector<double> sums((size_t)(2 * M));
+    GM_HIP(hipMemcpyAsync(sums.data(), f->l2sums.p, 16 * (size_t)M, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    f->last_loss = P->steps > 0 ? l / (double)P->batch : NAN;
+    f->steps = P->steps;
+    f->norm_max = P->target_max;
+    f->trained = true;
+    for (int32_t m = 0; m < M; ++m) {
+        const double d2 = sums[(size_t)(2 * m)], t2 = sums[(size_t)(2 * m + 1)];
+        double rel = NAN;
+        if (t2 > 0.0) rel = std::sqrt(d2 / t2);
+        else if (d2 == 0.0 && t2 == 0.0) rel = NAN;  // no held-out point of this mesh
+        f->rel_l2[(size_t)m] = (float)rel;
+        f->gate[(size_t)m] = (std::isfinite(rel) && rel <= P->max_rel_l2 && std::isfinite(f->last_loss)) ? 1 : 0;
+    }
+    GM_HIP(f->gate_d.ensure((size_t)M));
+    GM_HIP(hipMemcpy(f->gate_d.p, f->gate.data(), (size_t)M, hipMemcpyHostToDevice));
+    return GM_OK;
+}
+
+gm_status gm_field_predict(gm_field* f, const float* pos, int64_t q, float* out, void* stream)
+{
+    clear_error();
+    if (!f || q < 0 || q >= ((int64_t)1 << 31) || (q > 0 && (!pos || !out)))
+        return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or q outside [0, 2^31)");
+    gm_status st = check_device(f->scene);
+    if (st != GM_OK) return st;
+    launch_field_infer(f->blob.as<unsigned char>(), f->geom, pos, q, out, (hipStream_t)stream);
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
+gm_status gm_field_info(gm_field* f, float* rel_l2, uint8_t* gate, double* loss, int64_t* steps)
+{
+    clear_error();
+    if (!f) return fail(GM_ERR_INVALID_ARGUMENT, "field is NULL");
+    if (rel_l2) std::memcpy(rel_l2, f->rel_l2.data(), sizeof(float) * f->rel_l2.size());
+    if (gate) std::memcpy(gate, f->gate.data(), f->gate.size());
+    if (loss) *loss = f->last_loss;
+    if (steps) *steps = f->steps;
+    return GM_OK;
+}
+
+gm_status query_density(gm_field* f, gm_scene* sc, const gm_fixations* fix, double theta_deg, uint32_t flags,
+                        const float* pos, const int32_t* tri, const int32_t* mesh, int64_t q, double ref_max,
+                        float* out, uint8_t* used_fallback, void* stream)
+{
+    clear_error();
+    if (!sc || !fix) return fail(GM_ERR_INVALID_ARGUMENT, "scene and fixations must not be NULL");
+    if (f && f->scene != sc) return fail(GM_ERR_INVALID_ARGUMENT, "field belongs to another scene");
+    if (q < 0 || q >= ((int64_t)1 << 31)) return fail(GM_ERR_INVALID_ARGUMENT, "q must be in [0, 2^31)");
+    if (q > 0 && (!pos || !out)) return fail(GM_ERR_INVALID_ARGUMENT, "pos and out must not be NULL");
+    if (!(theta_deg > 0.0 && theta_deg < 45.0)) return fail(GM_ERR_INVALID_ARGUMENT, "theta_deg must be in (0, 45)");
+    if ((flags & GM_OCC_MASK) > GM_OCC_FULL || (flags & ~GM_OCC_MASK))
+        return fail(GM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", flags);
+    gm_status st = check_device(sc);
+    if (st != GM_OK) return st;
+    if (q == 0) return GM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const bool use_field = f && f->trained;
+    if (use_field) launch_field_infer(f->blob.as<unsigned char>(), f->geom, pos, q, out, s);
+    // scratch lives in the field when there is one, else in per-call buffers
+    DevBuf local_need, local_offs, local_scan;
+    DevBuf& need = f ? f->need : local_need;
+    DevBuf& offs = f ? f->qoffs : local_offs;
+    DevBuf& scan = f ? f->qscan : local_scan;
+    GM_HIP(need.ensure(4 * (size_t)q));
+    GM_HIP(offs.ensure(4 * (size_t)q));
+    GM_HIP(scan.ensure(scan_tmp_bytes(q)));
+    launch_gate_flags(mesh, tri, sc->tri_mesh.as<int32_t>(), sc->T, use_field ? f->gate_d.as<uint8_t>() : nullptr,
+                      sc->M, q, need.as<uint32_t>(), s);
+    if (used_fallback) launch_used_flags(need.as<uint32_t>(), q, used_fallback, s);
+    launch_exclusive_scan_u32(need.as<uint32_t>(), offs.as<uint32_t>(), q, scan.p, s);
+    uint32_t last_off = 0, last_need = 0;
+    GM_HIP(hipMemcpyAsync(&last_off, offs.as<uint32_t>() + (q - 1), 4, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipMemcpyAsync(&last_need, need.as<uint32_t>() + (q - 1), 4, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    const int64_t m = (int64_t)last_off + last_need;
+    if (m == 0) return GM_OK;
+
+    DevBuf lg[6];
+    DevBuf& gpos = f ? f->gpos : lg[0];
+    DevBuf& gtri = f ? f->gtri : lg[1];
+    DevBuf& gmesh = f ? f->gmesh : lg[2];
+    DevBuf& gidx = f ? f->gidx : lg[3];
+    DevBuf& grho = f ? f->grho : lg[4];
+    DevBuf& gnorm = f ? f->gnorm : lg[5];
+    GM_HIP(gpos.ensure(12 * (size_t)m));
+    GM_HIP(gtri.ensure(4 * (size_t)m));
+    GM_HIP(gmesh.ensure(4 * (size_t)m));
+    GM_HIP(gidx.ensure(4 * (size_t)m));
+    GM_HIP(grho.ensure(4 * (size_t)m));
+    GM_HIP(gnorm.ensure(16));
+    launch_gather_points(pos, tri, mesh, need.as<uint32_t>(), offs.as<uint32_t>(), q, gpos.as<float>(),
+                         gtri.as<int32_t>(), gmesh.as<int32_t>(), gidx.as<int32_t>(), s);
+    GM_HIP(hipGetLastError());
+    st = accumulate_density(sc, gpos.as<float>(), tri ? gtri.as<int32_t>() : nullptr,
+                            mesh ? gmesh.as<int32_t>() : nullptr, m, fix, theta_deg, flags, grho.as<float>(), nullptr,
+                            gnorm.as<float>(), stream);
+    if (st != GM_OK) return st;
+    double norm = ref_max > 0.0 ? ref_max : (f && f->norm_max > 0.0 ? f->norm_max : 0.0);
+    if (norm > 0.0) {
+        const float nf = (float)norm;
+        uint32_t bits;
+        std::memcpy(&bits, &nf, 4);
+        fill_u32(gnorm.p, 1, bits, s);
+    }
+    launch_scatter_fallback(grho.as<float>(), gidx.as<int32_t>(), m, gnorm.as<float>(), out, s);
+    GM_HIP(hipGetLastError());
+    if (!f) GM_HIP(hipStreamSynchronize(s));  // per-call scratch is freed on return
+    return GM_OK;
+}
+
+}  // extern "C"

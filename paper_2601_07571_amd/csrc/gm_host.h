@@ -1,0 +1,164 @@
+// gm_host.h -- host-side state of the C ABI shared by capi.cpp and field_api.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gazemap.h"
+#include "gm_internal.h"
+
+namespace gm {
+
+gm_status fail(gm_status st, const char* fmt, ...);
+void clear_error();
+const char* last_error();
+
+#define GM_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return gm::fail(GM_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Device buffer that only grows.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    hipError_t ensure(size_t want)
+    {
+        if (want <= bytes) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        const size_t cap = want > 256 ? want : 256;
+        hipError_t e = hipMalloc(&p, cap);
+        if (e == hipSuccess) bytes = cap;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Pairs of HIP events around the kernels of one stage.
+struct StageTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    double total_ms = 0.0;
+    int64_t launches = 0;
+    hipError_t begin(hipStream_t s)
+    {
+        if (used == ev.size()) {
+            hipEvent_t a, b;
+            hipError_t e = hipEventCreate(&a);
+            if (e != hipSuccess) return e;
+            e = hipEventCreate(&b);
+            if (e != hipSuccess) return e;
+            ev.emplace_back(a, b);
+        }
+        return hipEventRecord(ev[used].first, s);
+    }
+    hipError_t end(hipStream_t s) { return hipEventRecord(ev[used++].second, s); }
+    hipError_t collect()
+    {
+        for (size_t i = 0; i < used; ++i) {
+            hipError_t e = hipEventSynchronize(ev[i].second);
+            if (e != hipSuccess) return e;
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, ev[i].first, ev[i].second);
+            if (e != hipSuccess) return e;
+            total_ms += ms;
+            ++launches;
+        }
+        used = 0;
+        return hipSuccess;
+    }
+    void clear()
+    {
+        used = 0;
+        total_ms = 0.0;
+        launches = 0;
+    }
+    void release()
+    {
+        for (auto& p : ev) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+        ev.clear();
+        clear();
+    }
+};
+
+enum Stage { kStageSample = 0, kStagePrep, kStageDensity, kStageFinalize, kStages };
+const char* const kStageNames[kStages] = {"sample", "prep", "density", "finalize"};
+
+constexpr double kEpsV = 1e-4;         // visibility tolerance along the segment
+// Relative widening of kappa in the cheap cone gate.  The FP32 error of the gate value
+// is below ~1e-6 |r|^2 (|e'| + |x'|)^2 (tile-local coordinates), the widening adds
+// kGateWiden * kappa |p|^2 of margin, so no pair of the exact cone is missed while
+// |p| > 0.46 R_tile; eyes closer than 2 R_tile to the tile origin take the exact
+// path for every pair.  It enlarges the cone solid angle by about
+// kGateWiden / (4 sigma)^2 (0.6 % at theta = 1 deg).
+constexpr double kGateWiden = 3e-5;
+
+}  // namespace gm
+
+using gm::DevBuf;
+using gm::HostBvh;
+using gm::StageTimer;
+using gm::kStages;
+
+struct gm_scene {
+    int device = 0;
+    int32_t M = 0;
+    int64_t T = 0, NV = 0;
+    std::vector<int64_t> tri_off;  // [M+1]
+    HostBvh bvh;
+    // static device data
+    DevBuf V, I, tri_mesh, tri_off_d, nodes, tris;
+    // sampler scratch
+    DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total;
+    // density scratch
+    DevBuf fix, fx_shift, key, hist, cursor, spos, smesh, perm, acc, max_acc, scan_tmp2, stats;
+    int32_t spl = 2;
+    bool profiling = false;
+    StageTimer timers[kStages];
+
+    hipError_t tbegin(int st, hipStream_t s) { return profiling ? timers[st].begin(s) : hipSuccess; }
+    hipError_t tend(int st, hipStream_t s)
+    {
+        if (!profiling) return hipSuccess;
+        hipError_t e = timers[st].end(s);
+        // keep the event list bounded when nobody reads it
+        if (e == hipSuccess && timers[st].used >= 4096) e = timers[st].collect();
+        return e;
+    }
+
+    ~gm_scene()
+    {
+        for (auto& t : timers) t.release();
+        for (DevBuf* b : {&V, &I, &tri_mesh, &tri_off_d, &nodes, &tris, &area, &W, &C, &max_bits, &S, &scan_tmp,
+                          &counts, &offsets, &mesh_total, &fix, &fx_shift, &key, &hist, &cursor, &spos, &smesh,
+                          &perm, &acc, &max_acc, &scan_tmp2, &stats})
+            b->release();
+    }
+};
+
+namespace gm {
+gm_status check_device(const gm_scene* sc);
+void zero(void* p, size_t bytes, hipStream_t s);
+void fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
+}  // namespace gm

@@ -123,4 +123,61 @@ void launch_pair_visibility(const float* pos, const int32_t* tri, const int32_t*
                             int32_t n_eyes, int64_t T, const BvhNode* nodes, const BvhTri* tris, int32_t occ_mode,
                             float tmax, uint8_t* vis, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Neural density field: 96 Fourier features -> 4 x (64, ReLU) -> 1 -> softplus.
+// Master parameters are FP32 in one flat array:
+//   W1 [96][64] (input, output), b1 [64], W2 [64][64], b2, W3, b3, W4, b4, w5 [64], b5.
+// ---------------------------------------------------------------------------
+constexpr int kFieldBands = 16;
+constexpr int kFieldFeat = 6 * kFieldBands;
+constexpr int kFieldWidth = 64;
+constexpr int kFieldOffW[5] = {0, 0, 6208, 10368, 14528};   // W_L, L = 1..4
+constexpr int kFieldOffB[5] = {0, 6144, 10304, 14464, 18624};  // b_L
+constexpr int kFieldOffW5 = 18688;
+constexpr int kFieldOffB5 = 18752;
+constexpr int kFieldParams = 18753;
+size_t field_pack_bytes();   // bf16 image of the parameters in matrix-core operand order
+size_t field_infer_bytes();  // its prefix used by inference
+
+struct FieldGeom {
+    float lo[3];
+    float inv_ext;
+    float freq[kFieldBands];
+};
+
+struct FieldTrain {
+    const float* pos;        // [n][3]
+    const float* target;     // [n]
+    const int32_t* idx;      // training subset (NULL: the first `batch` points in order)
+    int64_t n_idx;
+    int32_t batch;           // points of this step
+    float inv_batch;         // 1 / batch
+    uint32_t key0, key1;     // Philox key of the batch draw
+    uint32_t step;
+    float* grad;             // [kFieldParams], accumulated with atomics
+    double* loss;            // sum of squared errors of the step
+};
+
+void launch_field_pack(const float* master, unsigned char* blob, hipStream_t s);
+void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const float* pos, int64_t q, float* out,
+                        hipStream_t s);
+void launch_field_train(const unsigned char* blob, const FieldGeom& g, const FieldTrain& t, hipStream_t s);
+void launch_field_adam(float* master, float* m, float* v, float* grad, float lr, float b1, float b2, float eps,
+                       float c1, float c2, hipStream_t s);
+// held-out split and per-mesh error sums
+void launch_field_split(int64_t n, uint32_t key0, uint32_t key1, uint32_t threshold, uint32_t* flag_train,
+                        hipStream_t s);
+void launch_field_compact(const uint32_t* flag, const uint32_t* offs, int64_t n, int32_t* idx, hipStream_t s);
+void launch_field_l2(const float* pred, const float* target, const int32_t* mesh, const uint32_t* flag_train,
+                     int64_t n, int32_t M, double* sums, hipStream_t s);
+// query helpers
+void launch_gate_flags(const int32_t* mesh, const int32_t* tri, const int32_t* tri_mesh, int64_t T,
+                       const uint8_t* gate, int32_t M, int64_t q, uint32_t* need, hipStream_t s);
+void launch_gather_points(const float* pos, const int32_t* tri, const int32_t* mesh, const uint32_t* need,
+                          const uint32_t* offs, int64_t q, float* gpos, int32_t* gtri, int32_t* gmesh, int32_t* gidx,
+                          hipStream_t s);
+void launch_scatter_fallback(const float* rho, const int32_t* gidx, int64_t m, const float* norm, float* out,
+                             hipStream_t s);
+void launch_used_flags(const uint32_t* need, int64_t q, uint8_t* used, hipStream_t s);
+
 }  // namespace gm

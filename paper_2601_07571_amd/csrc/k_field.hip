@@ -1,0 +1,500 @@
+// k_field.hip -- neural density field on gfx950 matrix cores.
+//
+// x -> 96 Fourier features [sin, cos](2 pi f_b x~_a) (f_b = 2^(0.6 b), b = 0..15) ->
+// 4 x (64, ReLU) -> 1 -> softplus, trained by mean squared error on the
+// normalised densities the method produces.  Every layer product is a chain of
+// v_mfma_f32_32x32x16_bf16 (bf16 operands, fp32 accumulation) per wave of 32
+// points, in the transposed form Z^T = W^T H^T: weights are the A operand (read
+// from LDS), activations the B operand (registers).  The accumulator layout of
+// one product (lane = point, rows 8q + 4h + r) is exactly the B-operand layout
+// of the next one once the input features of each 16-wide k-step are visited
+// in the slot order of slot_feature(); the packed weight image stores every
+// matrix in that order, so activations never leave registers between layers.
+// The backward pass reuses the same trick for dH = W dZ and takes the weight
+// gradients dW = H dZ^T as MFMA products over the 32 points of the wave (a
+// transpose of H and dZ through per-wave LDS tiles), accumulated with fp32
+// atomics.  Adam (Kingma and Ba 2015) keeps fp32 master weights and moments.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "gm_internal.h"
+#include "gm_philox.h"
+
+namespace gm {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kW = kFieldWidth;              // 64
+constexpr int kS1 = 104;                     // LDS row stride (bf16) of the layer-1 weights, padded
+constexpr int kSH = 72;                      // LDS row stride (bf16) of a 64-wide weight matrix, padded
+constexpr int kOffF1 = 0;                    // forward operand of layer 1: [64 out][104]
+constexpr int kMatH = kW * kSH * 2;          // bytes of one 64 x 64 operand
+constexpr int kOffF2 = kOffF1 + kW * kS1 * 2;  // forward operands of layers 2..4: [64 out][72]
+constexpr int kOffBias = kOffF2 + 3 * kMatH;   // fp32 b1..b4
+constexpr int kOffW5 = kOffBias + 4 * kW * 4;  // fp32 w5
+constexpr int kOffB5 = kOffW5 + kW * 4;        // fp32 b5 (+ padding)
+constexpr int kInfer = kOffB5 + 16;
+constexpr int kOffB2 = kInfer;                 // backward operands of layers 2..4: [64 in][72]
+constexpr int kPack = kOffB2 + 3 * kMatH;
+static_assert(kInfer % 16 == 0 && kPack % 16 == 0, "16-byte copies");
+
+constexpr int kThreads = 256;
+constexpr int kTileStride = 40;              // LDS row stride (bf16) of the per-wave 32-point tiles
+
+// slot s of a 16-wide k-step -> feature offset inside the step (the accumulator
+// rows 8q + 4h + r of one product, read as the operand of the next)
+__host__ __device__ constexpr int slot_feature(int s)
+{
+    return (s & 7) < 4 ? 4 * (s >> 3) + (s & 7) : 8 + 4 * (s >> 3) + (s & 7) - 4;
+}
+
+// layer-1 input slot c = 16 ks + 8 h + j -> feature index 6 band + 2 axis + (sin 0 | cos 1)
+__host__ __device__ constexpr int input_feature(int c)
+{
+    return 6 * ((8 * (c / 16) + c % 8) / 3) + 2 * ((8 * (c / 16) + c % 8) % 3) + (c % 16) / 8;
+}
+
+__device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 lds8(const unsigned char* base, int elem)
+{
+    return *reinterpret_cast<const bf16x8*>(base + 2 * elem);
+}
+
+struct Acts {
+    bf16x8 x0[6];     // features, k-steps of layer 1
+    bf16x8 h[4][4];   // hidden layers 1..4, k-steps of the next product
+};
+
+__device__ __forceinline__ float softplus(float o) { return fmaxf(o, 0.0f) + log1pf(expf(-fabsf(o))); }
+
+__device__ __forceinline__ void bias_relu(const unsigned char* lds, int layer, int h, const f32x16& a0,
+                                          const f32x16& a1, bf16x8 (&out)[4])
+{
+    const float* bias = reinterpret_cast<const float*>(lds + kOffBias) + layer * kW;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int f = 8 * (v >> 2) + 4 * h + (v & 3);
+        out[v >> 3][v & 7] = (__bf16)fmaxf(a0[v] + bias[f], 0.0f);
+        out[2 + (v >> 3)][v & 7] = (__bf16)fmaxf(a1[v] + bias[32 + f], 0.0f);
+    }
+}
+
+// Forward pass of the 32 points of a wave (lane & 31 = point, lane >> 5 = half).
+// Returns the pre-softplus output o (same value in both halves).
+__device__ __forceinline__ float field_forward(const unsigned char* lds, const FieldGeom& g, float x, float y,
+                                               float z, int lane, Acts& A)
+{
+    const int n = lane & 31, h = lane >> 5;
+    const float xt[3] = {(x - g.lo[0]) * g.inv_ext, (y - g.lo[1]) * g.inv_ext, (z - g.lo[2]) * g.inv_ext};
+    // slot j of k-step ks: sin/cos pair p = 8 ks + j (band p / 3, axis p % 3); the lane
+    // half picks sin (h = 0) or cos (h = 1), taken as sin of the phase + 1/4 revolution
+    const float quarter = h ? 0.25f : 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < 6; ++ks) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int pr = 8 * ks + j;
+            const float arg = g.freq[pr / 3] * xt[pr % 3];
+            const float rev = (arg - floorf(arg)) + quarter;   // revolutions in [0, 1.25)
+            A.x0[ks][j] = (__bf16)__builtin_amdgcn_sinf(rev);  // sin(2 pi rev)
+        }
+    }
+    f32x16 c0 = {}, c1 = {};
+#pragma unroll
+    for (int ks = 0; ks < 6; ++ks) {
+        c0 = mfma(lds8(lds + kOffF1, n * kS1 + 16 * ks + 8 * h), A.x0[ks], c0);
+        c1 = mfma(lds8(lds + kOffF1, (32 + n) * kS1 + 16 * ks + 8 * h), A.x0[ks], c1);
+    }
+    bias_relu(lds, 0, h, c0, c1, A.h[0]);
+#pragma unroll
+    for (int L = 1; L < 4; ++L) {
+        const unsigned char* F = lds + kOffF2 + (L - 1) * kMatH;
+        f32x16 d0 = {}, d1 = {};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            d0 = mfma(lds8(F, n * kSH + 16 * ks + 8 * h), A.h[L - 1][ks], d0);
+            d1 = mfma(lds8(F, (32 + n) * kSH + 16 * ks + 8 * h), A.h[L - 1][ks], d1);
+        }
+        bias_relu(lds, L, h, d0, d1, A.h[L]);
+    }
+    const float* w5 = reinterpret_cast<const float*>(lds + kOffW5);
+    float part = 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) part += w5[16 * ks + slot_feature(8 * h + j)] * (float)A.h[3][ks][j];
+    return part + __shfl_xor(part, 32, 64) + *reinterpret_cast<const float*>(lds + kOffB5);
+}
+
+__device__ __forceinline__ void stage(unsigned char* dst, const unsigned char* __restrict__ src, int bytes)
+{
+    for (int o = threadIdx.x * 16; o < bytes; o += kThreads * 16)
+        *reinterpret_cast<uint4*>(dst + o) = *reinterpret_cast<const uint4*>(src + o);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_field_pack(const float* __restrict__ p, unsigned char* __restrict__ blob)
+{
+    const int t = blockIdx.x * kThreads + threadIdx.x;
+    __bf16* bf = reinterpret_cast<__bf16*>(blob);
+    float* f32 = reinterpret_cast<float*>(blob);
+    const int nF1 = kW * kS1, nH = kW * kSH;
+    if (t < nF1) {  // layer 1: row = output, column = input slot
+        const int i = t / kS1, c = t % kS1;
+        bf[t] = (__bf16)(c < kFieldFeat ? p[kFieldOffW[1] + input_feature(c) * kW + i] : 0.0f);
+        return;
+    }
+    int u = t - nF1;
+    if (u < 3 * nH) {  // layers 2..4, forward: row = output, column slot -> input feature
+        const int L = 2 + u / nH, r = u % nH, i = r / kSH, c = r % kSH;
+        float v = 0.0f;
+        if (c < kW) v = p[kFieldOffW[L] + (16 * (c / 16) + slot_feature(c % 16)) * kW + i];
+        bf[kOffF2 / 2 + u] = (__bf16)v;
+        return;
+    }
+    u -= 3 * nH;
+    if (u < 3 * nH) {  // layers 2..4, backward: row = input, column slot -> output feature
+        const int L = 2 + u / nH, r = u % nH, k = r / kSH, c = r % kSH;
+        float v = 0.0f;
+        if (c < kW) v = p[kFieldOffW[L] + k * kW + 16 * (c / 16) + slot_feature(c % 16)];
+        bf[kOffB2 / 2 + u] = (__bf16)v;
+        return;
+    }
+    u -= 3 * nH;
+    if (u < 4 * kW) {
+        f32[kOffBias / 4 + u] = p[kFieldOffB[1 + u / kW] + u % kW];
+        return;
+    }
+    u -= 4 * kW;
+    if (u < kW) {
+        f32[kOffW5 / 4 + u] = p[kFieldOffW5 + u];
+        return;
+    }
+    u -= kW;
+    if (u < 4) f32[kOffB5 / 4 + u] = u == 0 ? p[kFieldOffB5] : 0.0f;
+}
+constexpr int kPackThreads = kW * kS1 + 6 * kW * kSH + 5 * kW + 4;
+
+__global__ void __launch_bounds__(kThreads) k_field_infer(const unsigned char* __restrict__ blob, FieldGeom g,
+                                                          const float* __restrict__ pos, int64_t q,
+                                                          float* __restrict__ out)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char s_blob[kInfer];
+    stage(s_blob, blob, kInfer);
+    __syncthreads();
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const int64_t tiles = (q + 31) / 32;
+    for (int64_t tile = (int64_t)blockIdx.x * (kThreads / 64) + wave; tile < tiles;
+         tile += (int64_t)gridDim.x * (kThreads / 64)) {
+        // keep the weights in LDS: without this the loop-invariant operand reads are
+        // hoisted out of the tile loop and pin the whole weight set in registers
+        asm volatile("" ::: "memory");
+        const int64_t i = tile * 32 + (lane & 31);
+        const bool ok = i < q;
+        const int64_t ii = ok ? i : 0;
+        Acts A;
+        const float o = field_forward(s_blob, g, pos[3 * ii], pos[3 * ii + 1], pos[3 * ii + 2], lane, A);
+        if (ok && lane < 32) out[i] = softplus(o);
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* __restrict__ blob, FieldGeom g,
+                                                          FieldTrain t)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char s_blob[kPack];
+    __shared__ __attribute__((aligned(16))) __bf16 s_dz[kThreads / 64][kW][kTileStride];
+    __shared__ __attribute__((aligned(16))) __bf16 s_h[kThreads / 64][kFieldFeat][kTileStride];
+    stage(s_blob, blob, kPack);
+    __syncthreads();
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const int n = lane & 31, h = lane >> 5;
+    const float* w5 = reinterpret_cast<const float*>(s_blob + kOffW5);
+    const int tiles = (t.batch + 31) / 32;
+    for (int tile = blockIdx.x * (kThreads / 64) + wave; tile < tiles; tile += gridDim.x * (kThreads / 64)) {
+        asm volatile("" ::: "memory");  // weights stay in LDS (see k_field_infer)
+        // fresh copy of the gradient base each tile: otherwise the ~300 lane-dependent
+        // atomic addresses below are hoisted out of the loop and spilled
+        float* grad = t.grad;
+        asm volatile("" : "+s"(grad));
+        const int j = tile * 32 + n;
+        const bool ok = j < t.batch;
+        int64_t i = ok ? j : 0;
+        if (t.idx) {
+            uint32_t c0 = (uint32_t)j, c1 = t.step, c2 = 0u, c3 = 4u;
+            philox4x32_10(c0, c1, c2, c3, t.key0, t.key1);
+            i = t.idx[(int64_t)(((uint64_t)c0 * (uint64_t)t.n_idx) >> 32)];
+        }
+        Acts A;
+        const float o = field_forward(s_blob, g, t.pos[3 * i], t.pos[3 * i + 1], t.pos[3 * i + 2], lane, A);
+        const float y = softplus(o);
+        const float diff = ok ? y - t.target[i] : 0.0f;
+        const float dO = 2.0f * diff * t.inv_batch / (1.0f + expf(-o));  // d loss / d o
+        // loss and the output-layer gradients, reduced over the 32 points of the wave
+        float se = h == 0 ? diff * diff : 0.0f, sb = h == 0 ? dO : 0.0f;
+#pragma unroll
+        for (int d = 1; d < 32; d <<= 1) {
+            se += __shfl_xor(se, d, 64);
+            sb += __shfl_xor(sb, d, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(t.loss, (double)se);
+            atomicAdd(&grad[kFieldOffB5], sb);
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                float gw = (float)A.h[3][ks][jj] * dO;
+#pragma unroll
+                for (int d = 1; d < 32; d <<= 1) gw += __shfl_xor(gw, d, 64);
+                if (n == 0) atomicAdd(&grad[kFieldOffW5 + 16 * ks + slot_feature(8 * h + jj)], gw);
+            }
+        asm volatile("" ::: "memory");
+        // dZ of layer 4 in the accumulator layout
+        f32x16 dz0, dz1;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int f = 8 * (v >> 2) + 4 * h + (v & 3);
+            dz0[v] = (float)A.h[3][v >> 3][v & 7] > 0.0f ? w5[f] * dO : 0.0f;
+            dz1[v] = (float)A.h[3][2 + (v >> 3)][v & 7] > 0.0f ? w5[32 + f] * dO : 0.0f;
+        }
+#pragma unroll
+        for (int L = 4; L >= 1; --L) {
+            asm volatile("" ::: "memory");  // one layer at a time (bounds register pressure)
+            bf16x8 dzb[4];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                dzb[v >> 3][v & 7] = (__bf16)dz0[v];
+                dzb[2 + (v >> 3)][v & 7] = (__bf16)dz1[v];
+                const int f = 8 * (v >> 2) + 4 * h + (v & 3);
+                s_dz[wave][f][n] = dzb[v >> 3][v & 7];
+                s_dz[wave][32 + f][n] = dzb[2 + (v >> 3)][v & 7];
+            }
+            if (L >= 2) {
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) s_h[wave][16 * ks + slot_feature(8 * h + jj)][n] = A.h[L - 2][ks][jj];
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < 6; ++ks)
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) s_h[wave][16 * ks + 8 * h + jj][n] = A.x0[ks][jj];
+            }
+            asm volatile("" ::: "memory");
+            // weight gradient dW[k][i] = sum over points of H[k][p] dZ[i][p]
+            const int nk = L == 1 ? 3 : 2;
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 3; ++nb) {
+                    if (nb >= nk) break;
+                    f32x16 c = {};
+#pragma unroll
+                    for (int kp = 0; kp < 2; ++kp) {
+                        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&s_dz[wave][mb * 32 + n][16 * kp + 8 * h]);
+                        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&s_h[wave][nb * 32 + n][16 * kp + 8 * h]);
+                        c = mfma(a, b, c);
+                    }
+                    const int krow = L == 1 ? input_feature(nb * 32 + n) : nb * 32 + n;
+                    float* gW = grad + kFieldOffW[L] + krow * kW + mb * 32 + 4 * h;
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) atomicAdd(gW + 8 * (v >> 2) + (v & 3), c[v]);
+                }
+            // bias gradient: row sums of dZ (lane = output feature)
+            {
+                float sbias = 0.0f;
+#pragma unroll
+                for (int p = 0; p < 32; ++p) sbias += (float)s_dz[wave][lane][p];
+                atomicAdd(&grad[kFieldOffB[L] + lane], sbias);
+            }
+            if (L >= 2) {
+                const unsigned char* Bm = s_blob + kOffB2 + (L - 2) * kMatH;
+                f32x16 e0 = {}, e1 = {};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    e0 = mfma(lds8(Bm, n * kSH + 16 * ks + 8 * h), dzb[ks], e0);
+                    e1 = mfma(lds8(Bm, (32 + n) * kSH + 16 * ks + 8 * h), dzb[ks], e1);
+                }
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    dz0[v] = (float)A.h[L - 2][v >> 3][v & 7] > 0.0f ? e0[v] : 0.0f;
+                    dz1[v] = (float)A.h[L - 2][2 + (v >> 3)][v & 7] > 0.0f ? e1[v] : 0.0f;
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_field_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                             float* __restrict__ grad, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= kFieldParams) return;
+    const float g = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g;
+    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    grad[i] = 0.0f;
+}
+
+__global__ void k_field_split(int64_t n, uint32_t key0, uint32_t key1, uint32_t threshold, uint32_t* __restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = 0u, c3 = 3u;
+    philox4x32_10(c0, c1, c2, c3, key0, key1);
+    flag[i] = c0 >= threshold ? 1u : 0u;  // 1 = training, 0 = held out
+}
+
+__global__ void k_field_compact(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ offs, int64_t n,
+                                int32_t* __restrict__ idx)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n && flag[i]) idx[offs[i]] = (int32_t)i;
+}
+
+__global__ void k_field_l2(const float* __restrict__ pred, const float* __restrict__ target,
+                           const int32_t* __restrict__ mesh, const uint32_t* __restrict__ flag, int64_t n, int32_t M,
+                           double* __restrict__ sums)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n || flag[i]) return;
+    const int m = mesh[i];
+    if (m < 0 || m >= M) return;
+    const double d = (double)pred[i] - (double)target[i];
+    atomicAdd(&sums[2 * m], d * d);
+    atomicAdd(&sums[2 * m + 1], (double)target[i] * (double)target[i]);
+}
+
+__global__ void k_gate_flags(const int32_t* __restrict__ mesh, const int32_t* __restrict__ tri,
+                             const int32_t* __restrict__ tri_mesh, int64_t T, const uint8_t* __restrict__ gate,
+                             int32_t M, int64_t q, uint32_t* __restrict__ need)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= q) return;
+    int m = -1;
+    if (mesh) m = mesh[i];
+    else if (tri) {
+        const int t = tri[i];
+        if (t >= 0 && t < T) m = tri_mesh[t];
+    }
+    need[i] = (gate == nullptr || m < 0 || m >= M || gate[m] == 0) ? 1u : 0u;
+}
+
+__global__ void k_gather_points(const float* __restrict__ pos, const int32_t* __restrict__ tri,
+                                const int32_t* __restrict__ mesh, const uint32_t* __restrict__ need,
+                                const uint32_t* __restrict__ offs, int64_t q, float* __restrict__ gpos,
+                                int32_t* __restrict__ gtri, int32_t* __restrict__ gmesh, int32_t* __restrict__ gidx)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= q || !need[i]) return;
+    const uint32_t j = offs[i];
+    gpos[3 * j] = pos[3 * i];
+    gpos[3 * j + 1] = pos[3 * i + 1];
+    gpos[3 * j + 2] = pos[3 * i + 2];
+    gtri[j] = tri ? tri[i] : -1;
+    gmesh[j] = mesh ? mesh[i] : -1;
+    gidx[j] = (int32_t)i;
+}
+
+__global__ void k_scatter_fallback(const float* __restrict__ rho, const int32_t* __restrict__ gidx, int64_t m,
+                                   const float* __restrict__ norm, float* __restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j >= m) return;
+    const float d = *norm;
+    out[gidx[j]] = d > 0.0f ? rho[j] / d : 0.0f;
+}
+
+__global__ void k_used_flags(const uint32_t* __restrict__ need, int64_t q, uint8_t* __restrict__ used)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < q) used[i] = (uint8_t)need[i];
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+size_t field_pack_bytes() { return kPack; }
+size_t field_infer_bytes() { return kInfer; }
+
+void launch_field_pack(const float* master, unsigned char* blob, hipStream_t s)
+{
+    k_field_pack<<<blocks(kPackThreads), kThreads, 0, s>>>(master, blob);
+}
+
+void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const float* pos, int64_t q, float* out,
+                        hipStream_t s)
+{
+    if (q <= 0) return;
+    const int64_t tiles = (q + 31) / 32;
+    const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 2048);
+    k_field_infer<<<grid, kThreads, 0, s>>>(blob, g, pos, q, out);
+}
+
+void launch_field_train(const unsigned char* blob, const FieldGeom& g, const FieldTrain& t, hipStream_t s)
+{
+    if (t.batch <= 0) return;
+    const int tiles = (t.batch + 31) / 32;
+    const unsigned grid = (unsigned)std::min(((tiles + 3) / 4), 1024);
+    k_field_train<<<grid, kThreads, 0, s>>>(blob, g, t);
+}
+
+void launch_field_adam(float* master, float* m, float* v, float* grad, float lr, float b1, float b2, float eps,
+                       float c1, float c2, hipStream_t s)
+{
+    k_field_adam<<<blocks(kFieldParams), kThreads, 0, s>>>(master, m, v, grad, lr, b1, b2, eps, c1, c2);
+}
+
+void launch_field_split(int64_t n, uint32_t key0, uint32_t key1, uint32_t threshold, uint32_t* flag, hipStream_t s)
+{
+    if (n > 0) k_field_split<<<blocks(n), kThreads, 0, s>>>(n, key0, key1, threshold, flag);
+}
+
+void launch_field_compact(const uint32_t* flag, const uint32_t* offs, int64_t n, int32_t* idx, hipStream_t s)
+{
+    if (n > 0) k_field_compact<<<blocks(n), kThreads, 0, s>>>(flag, offs, n, idx);
+}
+
+void launch_field_l2(const float* pred, const float* target, const int32_t* mesh, const uint32_t* flag, int64_t n,
+                     int32_t M, double* sums, hipStream_t s)
+{
+    if (n > 0) k_field_l2<<<blocks(n), kThreads, 0, s>>>(pred, target, mesh, flag, n, M, sums);
+}
+
+void launch_gate_flags(const int32_t* mesh, const int32_t* tri, const int32_t* tri_mesh, int64_t T,
+                       const uint8_t* gate, int32_t M, int64_t q, uint32_t* need, hipStream_t s)
+{
+    if (q > 0) k_gate_flags<<<blocks(q), kThreads, 0, s>>>(mesh, tri, tri_mesh, T, gate, M, q, need);
+}
+
+void launch_gather_points(const float* pos, const int32_t* tri, const int32_t* mesh, const uint32_t* need,
+                          const uint32_t* offs, int64_t q, float* gpos, int32_t* gtri, int32_t* gmesh, int32_t* gidx,
+                          hipStream_t s)
+{
+    if (q > 0) k_gather_points<<<blocks(q), kThreads, 0, s>>>(pos, tri, mesh, need, offs, q, gpos, gtri, gmesh, gidx);
+}
+
+void launch_scatter_fallback(const float* rho, const int32_t* gidx, int64_t m, const float* norm, float* out,
+                             hipStream_t s)
+{
+    if (m > 0) k_scatter_fallback<<<blocks(m), kThreads, 0, s>>>(rho, gidx, m, norm, out);
+}
+
+void launch_used_flags(const uint32_t* need, int64_t q, uint8_t* used, hipStream_t s)
+{
+    if (q > 0) k_used_flags<<<blocks(q), kThreads, 0, s>>>(need, q, used);
+}
+
+}  // namespace gm

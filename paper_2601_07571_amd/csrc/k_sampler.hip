@@ -6,29 +6,12 @@
 #include <hip/hip_runtime.h>
 
 #include "gm_internal.h"
+#include "gm_philox.h"
 
 namespace gm {
 namespace {
 
 constexpr int kBlock = 256;
-
-// Philox4x32-10 (Salmon et al., SC'11): per round, two 32x32 products; the high
-// halves are mixed with the odd counter words and the round key, the low halves
-// move to the odd positions; the key advances by two Weyl increments.
-__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
-                                              uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0), lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2), lo_b = 0xCD9E8D57u * c2;
-        const uint32_t n0 = hi_b ^ c1 ^ k0;
-        const uint32_t n2 = hi_a ^ c3 ^ k1;
-        c0 = n0; c1 = lo_b; c2 = n2; c3 = lo_a;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
 
 // Half the norm of the edge cross product, FP64, fixed order (the area that sets
 // the sample share of a triangle).

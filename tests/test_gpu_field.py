@@ -1,0 +1,142 @@
+"""Neural density field on the GPU against its FP64 oracle (BF16 emulated at the same
+points), its training, the per-mesh gate and the plain fallback of query_density."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import field as fo
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gm():
+    import torch
+    import paper_2601_07571_amd as gm
+    assert torch.cuda.is_available()
+    gm.load_library()
+    return gm
+
+
+@pytest.fixture(scope="module")
+def tiny(gm):
+    w = workloads.tiny_icosphere_scene()
+    meshes = [(m.V, m.I) for m in w.meshes]
+    scene = gm.Scene(meshes)
+    return w, meshes, scene
+
+
+def _geom(scene):
+    info = scene.info()
+    lo = np.array(info["bbox"][:3], np.float64)
+    ext = float(np.max(np.array(info["bbox"][3:], np.float32) - np.array(info["bbox"][:3], np.float32)))
+    return lo, ext
+
+
+def test_forward_matches_oracle(gm, tiny):
+    w, meshes, scene = tiny
+    f = gm.Field(scene, seed=1)
+    params = fo.init_params(11).astype(np.float32)
+    params[fo.N_PARAMS - 1] = 0.1
+    f.set_params(params)
+    rng = np.random.default_rng(0)
+    lo, ext = _geom(scene)
+    x = (lo + rng.uniform(0, ext, (4099, 3))).astype(np.float32)      # ragged: not a multiple of 32
+    y = f.predict(x).cpu().numpy().astype(np.float64)
+    ref, _ = fo.forward(params.astype(np.float64), x, lo, ext, bf=True)
+    rel = np.abs(y - ref) / np.maximum(np.abs(ref), 1e-3)
+    assert np.median(rel) < 2e-3 and rel.max() < 5e-2, (np.median(rel), rel.max())
+
+
+def test_gradient_matches_oracle(gm, tiny):
+    """Gradients of the hand-written backward kernel against the oracle (BF16 emulated):
+    cosine > 0.999 overall, relative norm difference <= 1e-2, per parameter block too."""
+    w, meshes, scene = tiny
+    f = gm.Field(scene, seed=2)
+    rng = np.random.default_rng(1)
+    params = (fo.init_params(12) + rng.normal(scale=0.02, size=fo.N_PARAMS)).astype(np.float32)
+    f.set_params(params)
+    lo, ext = _geom(scene)
+    x = (lo + rng.uniform(0, ext, (2048, 3))).astype(np.float32)
+    t = rng.uniform(0, 1, 2048).astype(np.float32)
+    g, loss = f.gradient(x, t)
+    rl, rg, _ = fo.loss_and_grad(params.astype(np.float64), x, t, lo, ext, bf=True)
+    assert abs(loss - rl) <= 2e-3 * rl
+    cos = g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg))
+    assert cos > 0.999, cos
+    assert abs(np.linalg.norm(g) - np.linalg.norm(rg)) <= 1e-2 * np.linalg.norm(rg)
+    o = 0
+    for name, shape in fo.SHAPES:
+        k = int(np.prod(shape))
+        a, b = g[o:o + k].astype(np.float64), rg[o:o + k]
+        if np.linalg.norm(b) > 0:
+            c = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+            assert c > 0.995, (name, c)
+        o += k
+
+
+def test_adam_step_matches_oracle(gm, tiny):
+    """One training step with a batch drawn on the device is checked against the oracle's
+    Adam update of the same gradient (one step: the signed learning rate)."""
+    w, meshes, scene = tiny
+    f = gm.Field(scene, seed=3)
+    params = fo.init_params(13).astype(np.float32)
+    f.set_params(params)
+    rng = np.random.default_rng(2)
+    lo, ext = _geom(scene)
+    x = (lo + rng.uniform(0, ext, (1000, 3))).astype(np.float32)
+    t = rng.uniform(0, 1, 1000).astype(np.float32)
+    f.train(x, np.zeros(1000, np.int32), t, steps=1, batch=256, lr=1e-3, lr_final=1e-3, holdout=0.5)
+    p1 = f.get_params().astype(np.float64)
+    step = p1 - params.astype(np.float64)
+    moved = np.abs(step) > 0
+    # Adam's first step moves every parameter by lr |g| / (|g| + eps): never more than lr,
+    # and lr to within FP32 rounding wherever |g| >> eps
+    assert moved.mean() > 0.5
+    assert np.all(np.abs(step) <= 1e-3 * (1 + 1e-4) + 1e-7)
+    assert np.mean(np.abs(np.abs(step[moved]) - 1e-3) < 2e-6) > 0.98
+
+
+def test_training_reaches_gate_and_query_paths(gm, tiny):
+    """Train on the tiny scene's map at ~300k samples; the held-out error gates the
+    field; query_density answers by the field where the gate is open and by the plain
+    accumulation (exactly) where it is closed."""
+    import torch
+    w, meshes, scene = tiny
+    k = 300000 / 3.1266
+    s = scene.build_samples(k, 0)
+    fix = gm.Fixations(w.fix.eye, w.fix.gaze, w.fix.dur)
+    d = scene.accumulate(s.pos, fix, w.theta_deg, occlusion="self", tri=s.tri, mesh=s.mesh)
+    tmax = float(d.max.cpu()[0])
+    f = gm.Field(scene, seed=4)
+    t0 = time.time()
+    info = f.train(s.pos, s.mesh, d.density_norm, steps=1500, batch=16384, lr=3e-3, lr_final=1e-4,
+                   max_rel_l2=0.05, target_max=tmax, seed=5)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    print(f"training: {dt:.2f} s, loss {info['loss']:.3e}, held-out rel L2 {info['rel_l2']}")
+    assert np.isfinite(info["loss"]) and info["rel_l2"][0] < 0.2
+    q = s.pos[:50000]
+    plain, used = gm.query_density(None, scene, fix, w.theta_deg, q, tri=s.tri[:50000], mesh=s.mesh[:50000],
+                                   occlusion="self", ref_max=tmax)
+    assert bool(used.all())
+    assert np.array_equal(plain.cpu().numpy(), (d.density[:50000] / tmax).cpu().numpy()) or \
+        np.allclose(plain.cpu().numpy(), (d.density[:50000] / tmax).cpu().numpy(), rtol=1e-6, atol=0)
+    fv, used = gm.query_density(f, scene, fix, w.theta_deg, q, tri=s.tri[:50000], mesh=s.mesh[:50000],
+                                occlusion="self")
+    if info["gate"][0]:
+        assert not bool(used.any())
+        assert np.allclose(fv.cpu().numpy(), f.predict(q).cpu().numpy())
+    else:
+        assert bool(used.all())
+        assert np.allclose(fv.cpu().numpy(), plain.cpu().numpy(), rtol=1e-6)
+    # a threshold of 0 closes every gate: the plain path answers everything
+    f2 = gm.Field(scene, seed=6)
+    info2 = f2.train(s.pos, s.mesh, d.density_norm, steps=10, batch=1024, max_rel_l2=0.0, target_max=tmax)
+    assert not info2["gate"].any()
+    fb, used = gm.query_density(f2, scene, fix, w.theta_deg, q, tri=s.tri[:50000], mesh=s.mesh[:50000],
+                                occlusion="self")
+    assert bool(used.all()) and np.allclose(fb.cpu().numpy(), plain.cpu().numpy(), rtol=1e-6)
