@@ -238,6 +238,52 @@ gm_status query_density(gm_field* field, gm_scene* scene, const gm_fixations* fi
                         uint32_t flags, const float* pos, const int32_t* tri, const int32_t* mesh, int64_t q,
                         double ref_max, float* out, uint8_t* used_fallback, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batched sessions: many maps (each a scene, its points and its fixations)   */
+/* in one persistent launch.  Not in the paper; the per-map arithmetic is     */
+/* exactly accumulate_density's (fixed-point sums, so each map is bit-equal   */
+/* to its plain call).                                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    gm_scene* scene;
+    const float* pos;        /* device [n][3] */
+    const int32_t* tri;      /* device [n] or NULL */
+    const int32_t* mesh;     /* device [n] or NULL */
+    int64_t n;
+    gm_fixations fix;        /* device */
+    double theta_deg;
+    uint32_t flags;          /* GM_OCC_* */
+    float* density;          /* device outputs [n], [n], [1]; each may be NULL */
+    float* density_norm;
+    float* max_out;
+} gm_session;
+
+typedef struct gm_batch gm_batch;
+
+/*
+ * gm_batch_create -- plan a batch and capture it in a HIP graph.  The work queue
+ * holds one item per (session, tile of 256 * samples-per-lane sorted samples,
+ * chunk of fixations), sorted by estimated cost, largest first; a persistent
+ * kernel pulls items until the queue is empty.  The tile configuration (samples
+ * per lane in {1, 2, 4}, LDS fixation block in {64, 128, 256}, fixations per
+ * chunk) comes from the JSON cache `tune_cache` (NULL: the GM_TUNE_CACHE
+ * environment variable; none: defaults) under a key built from the batch's
+ * shape, or, with tune = 1, from timing candidates on this batch (coordinate
+ * search), the winner being written back to the cache.  Every pointer of every
+ * session must stay valid, with the same sizes, for the life of the batch; their
+ * contents may change between runs.  Blocking (it runs the batch while planning).
+ */
+gm_status gm_batch_create(const gm_session* sessions, int32_t n_sessions, const char* tune_cache, int32_t tune,
+                          gm_batch** out, void* stream);
+/* Replay the captured graph on `stream`: every session's outputs are rewritten. */
+gm_status gm_batch_run(gm_batch* batch, void* stream);
+/* host outputs, each may be NULL: the chosen configuration (fixations per chunk 0 =
+ * automatic per session), the number of work items, the tuned time of the queue kernel
+ * in ms (-1 if not tuned), whether the configuration came from the cache */
+gm_status gm_batch_info(const gm_batch* batch, int32_t* samples_per_lane, int32_t* fix_block,
+                        int32_t* fix_per_chunk, int64_t* work_items, double* tuned_ms, int32_t* from_cache);
+gm_status gm_batch_destroy(gm_batch* batch);
+
 /*
  * gm_density_stats: counters of the last accumulate_density call on this scene,
  * host int64 out[4] = {pairs inside the 4-sigma cone, of those visible, packet

@@ -26,7 +26,8 @@ SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy",
            "gm_count_surface_samples", "build_surface_samples", "accumulate_density",
            "gm_debug_pair_values", "gm_debug_pair_visibility", "gm_profile_enable", "gm_profile_read",
            "gm_density_stats", "gm_field_create", "gm_field_destroy", "gm_field_set_params",
-           "gm_field_get_params", "gm_field_train", "gm_field_info", "gm_field_gradient", "gm_field_predict", "query_density")
+           "gm_field_get_params", "gm_field_train", "gm_field_info", "gm_field_gradient", "gm_field_predict", "query_density",
+           "gm_batch_create", "gm_batch_run", "gm_batch_info", "gm_batch_destroy")
 
 
 class GazemapError(RuntimeError):
@@ -50,6 +51,13 @@ class _TrainParams(ctypes.Structure):
                 ("lr_final", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("holdout", ctypes.c_float), ("max_rel_l2", ctypes.c_float),
                 ("target_max", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class _Session(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("tri", ctypes.c_void_p),
+                ("mesh", ctypes.c_void_p), ("n", ctypes.c_int64), ("fix", _Fix), ("theta_deg", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("density", ctypes.c_void_p), ("density_norm", ctypes.c_void_p),
+                ("max_out", ctypes.c_void_p)]
 
 
 FIELD_PARAMS = 18753
@@ -90,6 +98,11 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.POINTER(i64)]
     lib.gm_field_gradient.argtypes = [vp, vp, vp, i64, f32p, ctypes.POINTER(dbl)]
     lib.gm_field_predict.argtypes = [vp, vp, i64, vp, vp]
+    lib.gm_batch_create.argtypes = [ctypes.POINTER(_Session), i32, ctypes.c_char_p, i32, ctypes.POINTER(vp), vp]
+    lib.gm_batch_run.argtypes = [vp, vp]
+    lib.gm_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(i32)]
+    lib.gm_batch_destroy.argtypes = [vp]
     lib.query_density.argtypes = [vp, vp, ctypes.POINTER(_Fix), dbl, u32, vp, vp, vp, i64, dbl, vp, vp, vp]
     lib.gm_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in SYMBOLS[2:]:
@@ -362,3 +375,56 @@ def query_density(field, scene: Scene, fix: Fixations, theta_deg, pos, tri=None,
                               float(theta_deg), OCC[occlusion], _ptr(pos), _ptr(tri), _ptr(mesh), q, float(ref_max),
                               _ptr(out), _ptr(used), _stream()))
     return out, used
+
+
+class Batch:
+    """Many density maps in one persistent, graph-captured launch.
+
+    sessions: list of dicts with keys scene, pos, fix (Fixations), theta_deg and optional
+    tri, mesh, occlusion.  Output tensors are allocated here and rewritten by run()."""
+
+    def __init__(self, sessions, tune_cache=None, tune=False):
+        torch = _torch()
+        load_library()
+        self._keep = []
+        arr = (_Session * len(sessions))()
+        self.outputs = []
+        for i, ss in enumerate(sessions):
+            pos = _dev(ss["pos"], torch.float32, 3)
+            tri = _dev(ss.get("tri"), torch.int32)
+            mesh = _dev(ss.get("mesh"), torch.int32)
+            n = int(pos.shape[0])
+            out = Density(torch.empty(n, dtype=torch.float32, device="cuda"),
+                          torch.empty(n, dtype=torch.float32, device="cuda"),
+                          torch.empty(1, dtype=torch.float32, device="cuda"))
+            fix = ss["fix"]
+            self._keep += [pos, tri, mesh, fix, ss["scene"]]
+            self.outputs.append(out)
+            arr[i] = _Session(ss["scene"]._h.value, pos.data_ptr(), tri.data_ptr() if tri is not None else None,
+                              mesh.data_ptr() if mesh is not None else None, n, fix._c, float(ss["theta_deg"]),
+                              OCC[ss.get("occlusion", "full")], out.density.data_ptr(), out.density_norm.data_ptr(),
+                              out.max.data_ptr())
+        h = ctypes.c_void_p()
+        _check(_lib.gm_batch_create(arr, len(sessions), tune_cache.encode() if tune_cache else None, 1 if tune else 0,
+                                    ctypes.byref(h), _stream()))
+        self._h = h
+
+    def run(self):
+        _check(_lib.gm_batch_run(self._h, _stream()))
+        return self.outputs
+
+    def info(self):
+        spl = ctypes.c_int32(); fb = ctypes.c_int32(); ch = ctypes.c_int32(); items = ctypes.c_int64()
+        ms = ctypes.c_double(); cached = ctypes.c_int32()
+        _check(_lib.gm_batch_info(self._h, ctypes.byref(spl), ctypes.byref(fb), ctypes.byref(ch), ctypes.byref(items),
+                                  ctypes.byref(ms), ctypes.byref(cached)))
+        return {"samples_per_lane": spl.value, "fix_block": fb.value, "fix_per_chunk": ch.value,
+                "work_items": items.value, "tuned_ms": ms.value, "from_cache": bool(cached.value)}
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.gm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

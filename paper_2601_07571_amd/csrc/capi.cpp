@@ -107,6 +107,114 @@ bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1])
 
 }  // namespace
 
+namespace gm {
+
+gm_status check_density_args(const gm_scene* sc, const float* pos, int64_t n, const gm_fixations* fix,
+                             double theta_deg, uint32_t flags)
+{
+    if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
+    if (!fix) return fail(GM_ERR_INVALID_ARGUMENT, "fixations is NULL");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GM_ERR_INVALID_ARGUMENT, "n must be in [0, 2^31)");
+    if (n > 0 && !pos) return fail(GM_ERR_INVALID_ARGUMENT, "pos is NULL");
+    if (fix->n < 0) return fail(GM_ERR_INVALID_ARGUMENT, "fixation count < 0");
+    if (fix->n > 0 && (!fix->eye || !fix->gaze || !fix->duration))
+        return fail(GM_ERR_INVALID_ARGUMENT, "fixation arrays must not be NULL");
+    if (!(theta_deg > 0.0 && theta_deg < 45.0)) return fail(GM_ERR_INVALID_ARGUMENT, "theta_deg must be in (0, 45)");
+    const uint32_t mode = flags & GM_OCC_MASK;
+    if (mode > GM_OCC_FULL || (flags & ~GM_OCC_MASK)) return fail(GM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", flags);
+    return check_device(sc);
+}
+
+gm_status density_reserve(DensityWork& w, int64_t n, int32_t F)
+{
+    // spatial buckets: about one sample per bucket, at most 2^21
+    int bits = 1;
+    while (bits < 7 && ((int64_t)1 << (3 * bits)) < n) ++bits;
+    w.bits = bits;
+    w.buckets = (int64_t)1 << (3 * bits);
+    const int64_t nn = std::max<int64_t>(n, 1);
+    GM_HIP(w.fix.ensure(sizeof(FixRec) * (size_t)std::max(F, 1)));
+    GM_HIP(w.fx_shift.ensure(16));
+    GM_HIP(w.key.ensure(4 * nn));
+    GM_HIP(w.hist.ensure(4 * w.buckets));
+    GM_HIP(w.cursor.ensure(4 * w.buckets));
+    GM_HIP(w.scan_tmp.ensure(scan_tmp_bytes(w.buckets)));
+    GM_HIP(w.spos.ensure(16 * nn));
+    GM_HIP(w.smesh.ensure(4 * nn));
+    GM_HIP(w.perm.ensure(4 * nn));
+    GM_HIP(w.acc.ensure(8 * nn));
+    GM_HIP(w.max_acc.ensure(8));
+    GM_HIP(w.stats.ensure(8 * kDensityStats));
+    return GM_OK;
+}
+
+gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
+                       int64_t n, const gm_fixations* fix, double theta_deg, uint32_t mode, int spl,
+                       int32_t fix_per_chunk, DensityLaunch& a, hipStream_t s)
+{
+    const int32_t F = fix->n;
+    const double sigma = std::tan(theta_deg * M_PI / 180.0);
+    zero(w.stats.p, 8 * kDensityStats, s);
+    zero(w.fx_shift.p, 16, s);
+    zero(w.max_acc.p, 8, s);
+    launch_fix_prep(fix->eye, fix->gaze, fix->duration, F, sigma, kGateWiden, w.fix.as<FixRec>(), nullptr,
+                    w.fx_shift.as<int32_t>(), s);
+    if (n > 0) {
+        zero(w.acc.p, 8 * (size_t)n, s);
+        zero(w.hist.p, 4 * (size_t)w.buckets, s);
+        float lo[3];
+        float ext = 0.0f;
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = sc->bvh.lo[c];
+            ext = std::max(ext, sc->bvh.hi[c] - sc->bvh.lo[c]);
+        }
+        const int cells = 1 << w.bits;
+        const float inv_cell = ext > 0.0f ? (float)cells / ext : 1.0f;
+        launch_morton(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), n, lo, inv_cell, w.bits, w.key.as<uint32_t>(),
+                      w.hist.as<uint32_t>(), s);
+        launch_exclusive_scan_u32(w.hist.as<uint32_t>(), w.cursor.as<uint32_t>(), w.buckets, w.scan_tmp.p, s);
+        launch_scatter(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), sc->T, n, w.key.as<uint32_t>(),
+                       w.cursor.as<uint32_t>(), w.spos.as<float4>(), w.smesh.as<int32_t>(), w.perm.as<int32_t>(), s);
+    }
+    a.spos = w.spos.as<float4>();
+    a.smesh = w.smesh.as<int32_t>();
+    a.n = n;
+    a.fix = w.fix.as<FixRec>();
+    a.F = F;
+    a.nodes = sc->nodes.as<BvhNode>();
+    a.tris = sc->tris.as<BvhTri>();
+    a.occ_mode = (int32_t)mode;
+    a.tmax = (float)(1.0 - kEpsV);
+    a.cone2 = (float)(16.0 * sigma * sigma);
+    a.kexp = (float)(1.0 / (2.0 * sigma * sigma * std::log(2.0)));
+    a.fx_shift = w.fx_shift.as<int32_t>();
+    a.acc = w.acc.as<unsigned long long>();
+    a.stats = w.stats.as<unsigned long long>();
+    a.spl = spl;
+    if (fix_per_chunk <= 0) {
+        // enough work items to fill the chip: ~4096 (tile, chunk) pairs, chunks of >= 128 fixations
+        const int64_t tiles = std::max<int64_t>(1, (n + 256 * spl - 1) / (256 * spl));
+        const int64_t max_chunks = std::max<int64_t>(1, (F + 127) / 128);
+        const int64_t chunks = std::min<int64_t>(max_chunks, std::max<int64_t>(1, (4096 + tiles - 1) / tiles));
+        fix_per_chunk = (int32_t)std::max<int64_t>(1, (F + chunks - 1) / chunks);
+    }
+    a.fix_per_chunk = fix_per_chunk;
+    a.n_chunks = F > 0 ? (int32_t)((F + fix_per_chunk - 1) / fix_per_chunk) : 0;
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
+gm_status density_finalize(DensityWork& w, int64_t n, float* density, float* density_norm, float* max_out,
+                           hipStream_t s)
+{
+    launch_finalize(w.acc.as<unsigned long long>(), w.perm.as<int32_t>(), n, w.fx_shift.as<int32_t>(),
+                    w.max_acc.as<unsigned long long>(), density, density_norm, max_out, s);
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
+}  // namespace gm
+
 extern "C" {
 
 const char* gm_last_error(void) { return gm::last_error(); }
@@ -258,95 +366,25 @@ gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri,
                              float* density_norm, float* max_out, void* stream)
 {
     gm::clear_error();
-    if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
-    if (!fix) return fail(GM_ERR_INVALID_ARGUMENT, "fixations is NULL");
-    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GM_ERR_INVALID_ARGUMENT, "n must be in [0, 2^31)");
-    if (n > 0 && !pos) return fail(GM_ERR_INVALID_ARGUMENT, "pos is NULL");
-    const int32_t F = fix->n;
-    if (F < 0) return fail(GM_ERR_INVALID_ARGUMENT, "fixation count < 0");
-    if (F > 0 && (!fix->eye || !fix->gaze || !fix->duration))
-        return fail(GM_ERR_INVALID_ARGUMENT, "fixation arrays must not be NULL");
-    if (!(theta_deg > 0.0 && theta_deg < 45.0)) return fail(GM_ERR_INVALID_ARGUMENT, "theta_deg must be in (0, 45)");
-    const uint32_t mode = flags & GM_OCC_MASK;
-    if (mode > GM_OCC_FULL || (flags & ~GM_OCC_MASK)) return fail(GM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", flags);
-    gm_status st = check_device(sc);
+    gm_status st = check_density_args(sc, pos, n, fix, theta_deg, flags);
     if (st != GM_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-
-    const double sigma = std::tan(theta_deg * M_PI / 180.0);
-    // spatial buckets: about one sample per bucket, at most 2^21
-    int bits = 1;
-    while (bits < 7 && ((int64_t)1 << (3 * bits)) < n) ++bits;
-    const int64_t buckets = (int64_t)1 << (3 * bits);
-    const int64_t nn = std::max<int64_t>(n, 1);
-    GM_HIP(sc->fix.ensure(sizeof(FixRec) * (size_t)std::max(F, 1)));
-    GM_HIP(sc->fx_shift.ensure(16));
-    GM_HIP(sc->key.ensure(4 * nn));
-    GM_HIP(sc->hist.ensure(4 * buckets));
-    GM_HIP(sc->cursor.ensure(4 * buckets));
-    GM_HIP(sc->scan_tmp2.ensure(scan_tmp_bytes(buckets)));
-    GM_HIP(sc->spos.ensure(16 * nn));
-    GM_HIP(sc->smesh.ensure(4 * nn));
-    GM_HIP(sc->perm.ensure(4 * nn));
-    GM_HIP(sc->acc.ensure(8 * nn));
-    GM_HIP(sc->max_acc.ensure(8));
-    GM_HIP(sc->stats.ensure(8 * kDensityStats));
-    zero(sc->stats.p, 8 * kDensityStats, s);
-
+    DensityWork& w = sc->work;
+    st = density_reserve(w, n, fix->n);
+    if (st != GM_OK) return st;
+    DensityLaunch a;
     GM_HIP(sc->tbegin(kStagePrep, s));
-    zero(sc->fx_shift.p, 16, s);
-    zero(sc->max_acc.p, 8, s);
-    launch_fix_prep(fix->eye, fix->gaze, fix->duration, F, sigma, kGateWiden, sc->fix.as<FixRec>(), nullptr,
-                    sc->fx_shift.as<int32_t>(), s);
-    if (n > 0) {
-        zero(sc->acc.p, 8 * (size_t)n, s);
-        zero(sc->hist.p, 4 * (size_t)buckets, s);
-        float lo[3];
-        float ext = 0.0f;
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = sc->bvh.lo[a];
-            ext = std::max(ext, sc->bvh.hi[a] - sc->bvh.lo[a]);
-        }
-        const int cells = 1 << bits;
-        const float inv_cell = ext > 0.0f ? (float)cells / ext : 1.0f;
-        launch_morton(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), n, lo, inv_cell, bits, sc->key.as<uint32_t>(),
-                      sc->hist.as<uint32_t>(), s);
-        launch_exclusive_scan_u32(sc->hist.as<uint32_t>(), sc->cursor.as<uint32_t>(), buckets, sc->scan_tmp2.p, s);
-        launch_scatter(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), sc->T, n, sc->key.as<uint32_t>(), sc->cursor.as<uint32_t>(),
-                       sc->spos.as<float4>(), sc->smesh.as<int32_t>(), sc->perm.as<int32_t>(), s);
-        DensityLaunch a;
-        GM_HIP(sc->tend(kStagePrep, s));
-        a.spos = sc->spos.as<float4>();
-        a.smesh = sc->smesh.as<int32_t>();
-        a.n = n;
-        a.fix = sc->fix.as<FixRec>();
-        a.F = F;
-        a.nodes = sc->nodes.as<BvhNode>();
-        a.tris = sc->tris.as<BvhTri>();
-        a.occ_mode = (int32_t)mode;
-        a.tmax = (float)(1.0 - kEpsV);
-        a.cone2 = (float)(16.0 * sigma * sigma);
-        a.kexp = (float)(1.0 / (2.0 * sigma * sigma * std::log(2.0)));
-        a.fx_shift = sc->fx_shift.as<int32_t>();
-        a.acc = sc->acc.as<unsigned long long>();
-        a.stats = sc->stats.as<unsigned long long>();
-        a.spl = sc->spl;
-        const int64_t tiles = (n + 256 * a.spl - 1) / (256 * a.spl);
-        const int64_t max_chunks = std::max<int64_t>(1, (F + 127) / 128);
-        int64_t chunks = std::min<int64_t>(max_chunks, std::max<int64_t>(1, (4096 + tiles - 1) / tiles));
-        a.fix_per_chunk = (int32_t)((F + chunks - 1) / std::max<int64_t>(chunks, 1));
-        if (a.fix_per_chunk < 1) a.fix_per_chunk = 1;
-        a.n_chunks = (int32_t)((F + a.fix_per_chunk - 1) / a.fix_per_chunk);
+    st = density_prep(sc, w, pos, tri, mesh, n, fix, theta_deg, flags & GM_OCC_MASK, sc->spl, 0, a, s);
+    if (st != GM_OK) return st;
+    GM_HIP(sc->tend(kStagePrep, s));
+    if (n > 0 && fix->n > 0) {
         GM_HIP(sc->tbegin(kStageDensity, s));
         launch_density(a, s);
         GM_HIP(sc->tend(kStageDensity, s));
-    } else {
-        GM_HIP(sc->tend(kStagePrep, s));
     }
     GM_HIP(sc->tbegin(kStageFinalize, s));
-    launch_finalize(sc->acc.as<unsigned long long>(), sc->perm.as<int32_t>(), n, sc->fx_shift.as<int32_t>(),
-                    sc->max_acc.as<unsigned long long>(), density, density_norm, max_out, s);
-    GM_HIP(hipGetLastError());
+    st = density_finalize(w, n, density, density_norm, max_out, s);
+    if (st != GM_OK) return st;
     GM_HIP(sc->tend(kStageFinalize, s));
     return GM_OK;
 }
@@ -397,13 +435,13 @@ gm_status gm_density_stats(gm_scene* sc, int64_t* out)
 {
     gm::clear_error();
     if (!sc || !out) return fail(GM_ERR_INVALID_ARGUMENT, "scene and out must not be NULL");
-    if (!sc->stats.p) {
+    if (!sc->work.stats.p) {
         for (int i = 0; i < kDensityStats; ++i) out[i] = 0;
         return GM_OK;
     }
     GM_HIP(hipDeviceSynchronize());
     unsigned long long v[kDensityStats];
-    GM_HIP(hipMemcpy(v, sc->stats.p, sizeof(v), hipMemcpyDeviceToHost));
+    GM_HIP(hipMemcpy(v, sc->work.stats.p, sizeof(v), hipMemcpyDeviceToHost));
     for (int i = 0; i < kDensityStats; ++i) out[i] = (int64_t)v[i];
     return GM_OK;
 }

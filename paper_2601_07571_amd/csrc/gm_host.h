@@ -114,8 +114,16 @@ constexpr double kEpsV = 1e-4;         // visibility tolerance along the segment
 // kGateWiden / (4 sigma)^2 (0.6 % at theta = 1 deg).
 constexpr double kGateWiden = 3e-5;
 
+// Device scratch of one density evaluation (one scene, one set of points and fixations).
+struct DensityWork {
+    DevBuf fix, fx_shift, key, hist, cursor, scan_tmp, spos, smesh, perm, acc, max_acc, stats;
+    int bits = 1;
+    int64_t buckets = 8;
+};
+
 }  // namespace gm
 
+using gm::DensityWork;
 using gm::DevBuf;
 using gm::HostBvh;
 using gm::StageTimer;
@@ -131,8 +139,8 @@ struct gm_scene {
     DevBuf V, I, tri_mesh, tri_off_d, nodes, tris;
     // sampler scratch
     DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total;
-    // density scratch
-    DevBuf fix, fx_shift, key, hist, cursor, spos, smesh, perm, acc, max_acc, scan_tmp2, stats;
+    // density scratch of the plain entry points
+    DensityWork work;
     int32_t spl = 2;
     bool profiling = false;
     StageTimer timers[kStages];
@@ -151,14 +159,26 @@ struct gm_scene {
     {
         for (auto& t : timers) t.release();
         for (DevBuf* b : {&V, &I, &tri_mesh, &tri_off_d, &nodes, &tris, &area, &W, &C, &max_bits, &S, &scan_tmp,
-                          &counts, &offsets, &mesh_total, &fix, &fx_shift, &key, &hist, &cursor, &spos, &smesh,
-                          &perm, &acc, &max_acc, &scan_tmp2, &stats})
+                          &counts, &offsets, &mesh_total})
             b->release();
     }
 };
 
 namespace gm {
 gm_status check_device(const gm_scene* sc);
+// argument checks shared by accumulate_density and the batch planner
+gm_status check_density_args(const gm_scene* sc, const float* pos, int64_t n, const gm_fixations* fix,
+                             double theta_deg, uint32_t flags);
+// allocate the scratch of one evaluation (not allowed while a stream is being captured)
+gm_status density_reserve(DensityWork& w, int64_t n, int32_t F);
+// queue fixation records, spatial sort and zeroed accumulators; fills `a` (chunking by
+// fix_per_chunk, 0 = automatic) for launch_density / launch_density_queue
+gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
+                       int64_t n, const gm_fixations* fix, double theta_deg, uint32_t mode, int spl,
+                       int32_t fix_per_chunk, DensityLaunch& a, hipStream_t s);
+// maximum and outputs
+gm_status density_finalize(DensityWork& w, int64_t n, float* density, float* density_norm, float* max_out,
+                           hipStream_t s);
 void zero(void* p, size_t bytes, hipStream_t s);
 void fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
 }  // namespace gm

@@ -369,23 +369,22 @@ __device__ __forceinline__ unsigned xcd_block(unsigned L, unsigned G)
     return (L & 7u) * q + (L >> 3);
 }
 
-// OCC = 0: no occlusion (no traversal code); OCC = 1: visibility by the BVH.
-template <int SPL, int OCC>
-__global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
+// One work item of the density map: the samples of one tile (256 * SPL consecutive
+// sorted samples) against one chunk of the fixations, by the whole workgroup.
+// OCC = 0: no occlusion (no traversal code); OCC = 1: visibility by the BVH when
+// a.occ_mode != 0.  FB: fixations staged in LDS per round.
+template <int SPL, int OCC, int FB>
+__device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t tile, int chunk)
 {
-    __shared__ float4 s_ra[kFB];  // rx, ry, rz, c0
-    __shared__ float4 s_rb[kFB];  // ax, ay, az, cc
-    __shared__ float s_rc[kFB];   // -kappa
+    __shared__ float4 s_ra[FB];  // rx, ry, rz, c0
+    __shared__ float4 s_rb[FB];  // ax, ay, az, cc
+    __shared__ float s_rc[FB];   // -kappa
     __shared__ unsigned long long s_acc[kThreads * SPL];  // one entry per sample, owned by one lane
     __shared__ float s_rad;
     __shared__ uint32_t s_stats[kDensityStats];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
-    const unsigned G = gridDim.x * gridDim.y;
-    const unsigned L = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, G);
-    const int64_t tile = L % gridDim.x;
-    const int chunk = (int)(L / gridDim.x);
     const int64_t tile_base = tile * (int64_t)(kThreads * SPL);
     const int64_t wave_base = tile_base + wave * (64 * SPL);
     const int64_t n = a.n;
@@ -417,8 +416,8 @@ __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
     const int f_begin = chunk * a.fix_per_chunk;
     const int f_end = min(a.F, f_begin + a.fix_per_chunk);
 
-    for (int fb = f_begin; fb < f_end; fb += kFB) {
-        const int nb = min(kFB, f_end - fb);
+    for (int fb = f_begin; fb < f_end; fb += FB) {
+        const int nb = min(FB, f_end - fb);
         __syncthreads();
         if (threadIdx.x < nb) {
             const FixRec fr = a.fix[fb + threadIdx.x];
@@ -466,7 +465,7 @@ __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
                     g = pair_value(p.x, p.y, p.z, fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w, a.cone2, a.kexp);
                 }
                 bool vis = true;
-                const bool need = OCC != 0 && g > 0.0f;
+                const bool need = OCC != 0 && a.occ_mode != 0 && g > 0.0f;
                 const uint64_t need_mask = ballot(need);
                 if (OCC != 0 && need_mask != 0) {
                     const Seg sg = make_seg(fr.ex, fr.ey, fr.ez, p.x, p.y, p.z);
@@ -495,6 +494,35 @@ __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
     }
     __syncthreads();
     if (threadIdx.x < kDensityStats && s_stats[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], (unsigned long long)s_stats[threadIdx.x]);
+    __syncthreads();  // LDS is reused by the next item of a persistent workgroup
+}
+
+template <int SPL, int OCC>
+__global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
+{
+    const unsigned G = gridDim.x * gridDim.y;
+    const unsigned L = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, G);
+    density_item<SPL, OCC, kFB>(a, (int64_t)(L % gridDim.x), (int)(L / gridDim.x));
+}
+
+// Persistent form for many sessions: every workgroup pulls (session, tile, chunk)
+// items from a queue sorted longest first until the queue is empty.
+template <int SPL, int FB>
+__global__ void __launch_bounds__(kThreads) k_density_queue(const DensityLaunch* __restrict__ sessions,
+                                                            const int4* __restrict__ items, int32_t n_items,
+                                                            unsigned int* __restrict__ head)
+{
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const int4 w = items[it];
+        const DensityLaunch a = sessions[w.x];
+        density_item<SPL, 1, FB>(a, (int64_t)w.y, w.z);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -624,6 +652,41 @@ void launch_density(const DensityLaunch& a, hipStream_t s)
     case 4: occ ? k_density<4, 1><<<grid, kThreads, 0, s>>>(a) : k_density<4, 0><<<grid, kThreads, 0, s>>>(a); break;
     default: occ ? k_density<8, 1><<<grid, kThreads, 0, s>>>(a) : k_density<8, 0><<<grid, kThreads, 0, s>>>(a); break;
     }
+}
+
+void launch_density_queue(const DensityLaunch* sessions, const int4* items, int32_t n_items, unsigned int* head,
+                          int spl, int fb, int grid, hipStream_t s)
+{
+    if (n_items <= 0) return;
+    const dim3 g((unsigned)grid);
+#define GM_Q(S, B) k_density_queue<S, B><<<g, kThreads, 0, s>>>(sessions, items, n_items, head)
+    if (fb <= 64) {
+        if (spl == 1) GM_Q(1, 64); else if (spl == 2) GM_Q(2, 64); else GM_Q(4, 64);
+    } else if (fb <= 128) {
+        if (spl == 1) GM_Q(1, 128); else if (spl == 2) GM_Q(2, 128); else GM_Q(4, 128);
+    } else {
+        if (spl == 1) GM_Q(1, 256); else if (spl == 2) GM_Q(2, 256); else GM_Q(4, 256);
+    }
+#undef GM_Q
+}
+
+int density_queue_grid(int spl, int fb)
+{
+    int dev = 0, cus = 256, per = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = hipSuccess;
+#define GM_OCCQ(S, B) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_density_queue<S, B>, kThreads, 0)
+    if (fb <= 64) {
+        if (spl == 1) GM_OCCQ(1, 64); else if (spl == 2) GM_OCCQ(2, 64); else GM_OCCQ(4, 64);
+    } else if (fb <= 128) {
+        if (spl == 1) GM_OCCQ(1, 128); else if (spl == 2) GM_OCCQ(2, 128); else GM_OCCQ(4, 128);
+    } else {
+        if (spl == 1) GM_OCCQ(1, 256); else if (spl == 2) GM_OCCQ(2, 256); else GM_OCCQ(4, 256);
+    }
+#undef GM_OCCQ
+    if (e != hipSuccess || per < 1) per = 1;
+    return std::max(1, cus) * per;
 }
 
 void launch_finalize(const unsigned long long* acc, const int32_t* perm, int64_t n, const int32_t* fx_shift,
