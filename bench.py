@@ -33,6 +33,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target wall time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-session batched comparison")
+    ap.add_argument("--no-field", action="store_true", help="skip the neural-field comparison")
+    ap.add_argument("--field-steps", type=int, default=20000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the path on a single MI355X "
@@ -90,6 +93,7 @@ def main():
     gate_ms = g_ms / max(1, g_n)
     step()
     torch.cuda.synchronize()
+    counters = scene.density_stats()
 
     achieved = GATE_FLOP_PER_PAIR * pairs / (dens_ms * 1e-3)
     out = {
@@ -117,9 +121,17 @@ def main():
                      "flop_per_pair": GATE_FLOP_PER_PAIR},
         "gate_only": {"kernel_ms": gate_ms, "pairs_per_s": pairs / (gate_ms * 1e-3),
                       "frac_fp32_peak": GATE_FLOP_PER_PAIR * pairs / (gate_ms * 1e-3) / PEAK_FP32_VALU},
+        "visibility": {"in_cone_pairs": counters["in_cone"], "visible_pairs": counters["visible"],
+                       "rays_per_s": counters["in_cone"] / (dens_ms * 1e-3),
+                       "packet_traversals": counters["traversals"], "bvh_node_visits": counters["node_visits"]},
         "paper_context": {"map_time_s": 6.9, "hardware": "NVIDIA GeForce GTX 1060",
                           "workload": "the paper's 800k-triangle scene, 2M samples, 6,000 fixations"},
     }
+
+    if not args.no_batched:
+        out["batched"] = bench_batched(gm, workloads, torch, args)
+    if not args.no_field:
+        out["field"] = bench_field(gm, workloads, torch, np, args, scene, samples, fix, dens, w, k)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -143,6 +155,99 @@ def main():
                                          f"FP64, {dt:.1f} s wall"}
         del d
     print(json.dumps(out))
+
+
+def _time(fn, torch, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def bench_batched(gm, workloads, torch, args):
+    """64 independent sessions of uneven size: one persistent graph-captured launch against
+    64 sequential accumulate_density calls on the same inputs (outputs are bit-equal)."""
+    sessions = []
+    pairs = 0.0
+    for w in workloads.batched_sessions(64):
+        sc = gm.Scene([(m.V, m.I) for m in w.meshes])
+        sm = sc.build_samples(w.k, w.seed)
+        fx = gm.Fixations(w.fix.eye, w.fix.gaze, w.fix.dur)
+        sessions.append({"scene": sc, "pos": sm.pos, "tri": sm.tri, "mesh": sm.mesh, "fix": fx,
+                         "theta_deg": w.theta_deg, "occlusion": "full"})
+        pairs += float(sm.pos.shape[0]) * fx.n
+    outs = []
+    for x in sessions:
+        n = int(x["pos"].shape[0])
+        outs.append(gm.Density(torch.empty(n, device="cuda"), torch.empty(n, device="cuda"),
+                               torch.empty(1, device="cuda")))
+
+    def plain():
+        for x, o in zip(sessions, outs):
+            x["scene"].accumulate(x["pos"], x["fix"], x["theta_deg"], occlusion="full", tri=x["tri"], mesh=x["mesh"],
+                                  out=o)
+    plain()
+    plain_ms = _time(plain, torch, max(1, args.steps // 2))
+    cache = os.environ.get("GM_TUNE_CACHE") or "/tmp/gazemap_tune.json"
+    t0 = time.perf_counter()
+    batch = gm.Batch(sessions, tune_cache=cache, tune=True)
+    tune_s = time.perf_counter() - t0
+    batch.run()
+    batched_ms = _time(batch.run, torch, max(1, args.steps // 2))
+    same = all(bool(torch.equal(a.density, b.density)) for a, b in zip(outs, batch.outputs))
+    return {"sessions": 64, "pairs": pairs, "plain_sequential_ms": plain_ms, "batched_graph_ms": batched_ms,
+            "speedup": plain_ms / batched_ms, "bit_equal_to_plain": same, "plan_and_tune_s": tune_s,
+            "tile_config": batch.info()}
+
+
+def bench_field(gm, workloads, torch, np, args, scene, samples, fix, dens, w, k):
+    """Neural density field trained on the map of the paper-shaped scene (per-mesh gates)
+    and on the tiny scene's geometry resampled to 2M points; time per frame of 2M queries
+    by the field, by the plain accumulation and by query_density (field where the gate is
+    open, plain elsewhere)."""
+    res = {}
+    tmax = float(dens.max.cpu()[0])
+    field = gm.Field(scene, seed=1, max_cycles=32.0)
+    t0 = time.perf_counter()
+    info = field.train(samples.pos, samples.mesh, dens.density_norm, steps=args.field_steps, batch=16384, lr=3e-3,
+                       lr_final=1e-5, max_rel_l2=0.02, target_max=tmax, seed=3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    q = samples.pos
+    pred = torch.empty(q.shape[0], device="cuda")
+    field.predict(q, out=pred)
+    field_ms = _time(lambda: field.predict(q, out=pred), torch, args.steps)
+    tmp = gm.Density(torch.empty(q.shape[0], device="cuda"), None, torch.empty(1, device="cuda"))
+    plain_ms = _time(lambda: scene.accumulate(q, fix, w.theta_deg, occlusion="full", tri=samples.tri,
+                                              mesh=samples.mesh, out=tmp), torch, max(1, args.steps // 2))
+    qout = torch.empty(q.shape[0], device="cuda"); used = torch.empty(q.shape[0], dtype=torch.uint8, device="cuda")
+    query_ms = _time(lambda: gm.query_density(field, scene, fix, w.theta_deg, q, tri=samples.tri, mesh=samples.mesh,
+                                              occlusion="full", out=qout, used=used), torch, max(1, args.steps // 2))
+    res["paper_shaped"] = {"points": int(q.shape[0]), "rel_l2_per_mesh": [float(x) for x in info["rel_l2"]],
+                           "gate_open": [bool(x) for x in info["gate"]], "train_steps": info["steps"],
+                           "train_s": train_s, "field_ms_per_frame": field_ms, "plain_ms_per_frame": plain_ms,
+                           "query_density_ms_per_frame": query_ms,
+                           "fallback_fraction": float(used.float().mean().cpu())}
+    # the tiny scene's geometry and fixations at ~2M samples
+    t = workloads.tiny_icosphere_scene()
+    sc1 = gm.Scene([(m.V, m.I) for m in t.meshes])
+    s1 = sc1.build_samples(2_000_000 / 3.1266231, 0)
+    f1 = gm.Fixations(t.fix.eye, t.fix.gaze, t.fix.dur)
+    d1 = sc1.accumulate(s1.pos, f1, t.theta_deg, occlusion="self", tri=s1.tri, mesh=s1.mesh)
+    fl1 = gm.Field(sc1, seed=1, max_cycles=32.0)
+    i1 = fl1.train(s1.pos, s1.mesh, d1.density_norm, steps=args.field_steps, batch=16384, lr=5e-3, lr_final=1e-5,
+                   max_rel_l2=0.02, target_max=float(d1.max.cpu()[0]), seed=3)
+    p1 = torch.empty(s1.pos.shape[0], device="cuda")
+    fms = _time(lambda: fl1.predict(s1.pos, out=p1), torch, args.steps)
+    tmp1 = gm.Density(torch.empty(s1.pos.shape[0], device="cuda"), None, torch.empty(1, device="cuda"))
+    pms = _time(lambda: sc1.accumulate(s1.pos, f1, t.theta_deg, occlusion="self", tri=s1.tri, mesh=s1.mesh,
+                                       out=tmp1), torch, args.steps)
+    res["tiny_scene_2M"] = {"points": int(s1.pos.shape[0]), "rel_l2": float(i1["rel_l2"][0]),
+                            "gate_open": bool(i1["gate"][0]), "field_ms_per_frame": fms, "plain_ms_per_frame": pms}
+    res["network"] = "96 Fourier features (16 bands to 32 cycles per scene extent) -> 4 x 64 ReLU -> softplus, bf16 MFMA"
+    return res
 
 
 if __name__ == "__main__":

@@ -197,8 +197,10 @@ typedef struct {
 #define GM_FIELD_PARAMS 18753
 
 /* gm_field_create: a field over the scene's bounding cube with He-uniform weights
- * drawn from `seed` (zero biases); every mesh gate closed until trained.  Blocking. */
-gm_status gm_field_create(gm_scene* scene, uint64_t seed, gm_field** out);
+ * drawn from `seed` (zero biases); every mesh gate closed until trained.  The band
+ * frequencies are f_b = max_cycles^(b / 15) cycles per cube edge, b = 0..15
+ * (max_cycles <= 0: 32).  Blocking. */
+gm_status gm_field_create(gm_scene* scene, uint64_t seed, double max_cycles, gm_field** out);
 gm_status gm_field_destroy(gm_field* field);
 /* host float [GM_FIELD_PARAMS] in, out (blocking) */
 gm_status gm_field_set_params(gm_field* field, const float* params);

@@ -10,7 +10,7 @@ pre-activation gradients that feed the matrix cores).  With ``bf16=False`` it is
 the exact FP64 network, which its finite-difference pin checks.
 
 Network: x -> x~ = (x - lo) / ext in [0,1]^3 -> 96 features
-[sin, cos](2 pi f_b x~_a), f_b = 2^(0.6 b), b = 0..15, a = x,y,z, feature
+[sin, cos](2 pi f_b x~_a), f_b = max_cycles^(b/15), b = 0..15, a = x,y,z, feature
 index 6b + 2a + (0 sin | 1 cos) -> 4 x (64, ReLU) -> 1 -> softplus.
 Loss: mean squared error against the normalised density.
 Parity status: pinned (central finite differences in FP64, closed forms of the
@@ -30,8 +30,13 @@ SHAPES = [("W1", (FEAT, WIDTH)), ("b1", (WIDTH,)), ("W2", (WIDTH, WIDTH)), ("b2"
 N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
 
 
-def freqs():
-    return np.exp2(0.6 * np.arange(BANDS, dtype=np.float64)).astype(np.float32).astype(np.float64)
+MAX_CYCLES = 32.0
+
+
+def freqs(max_cycles=None):
+    mc = MAX_CYCLES if max_cycles is None else float(max_cycles)
+    b = np.arange(BANDS, dtype=np.float64)
+    return np.power(mc, b / (BANDS - 1)).astype(np.float32).astype(np.float64)
 
 
 def bf16(x):
@@ -56,11 +61,11 @@ def flatten(p):
     return np.concatenate([np.asarray(p[name], np.float64).reshape(-1) for name, _ in SHAPES])
 
 
-def features(x, lo, ext, bf=True):
+def features(x, lo, ext, bf=True, max_cycles=None):
     """[n][96] features of world points x [n][3] for a field box with corner lo and edge ext."""
     x = np.asarray(x, np.float64).reshape(-1, 3)
     xt = (x - np.asarray(lo, np.float64)) / float(ext)
-    arg = 2.0 * np.pi * xt[:, None, :] * freqs()[None, :, None]        # [n][band][axis]
+    arg = 2.0 * np.pi * xt[:, None, :] * freqs(max_cycles)[None, :, None]        # [n][band][axis]
     phi = np.stack([np.sin(arg), np.cos(arg)], -1).reshape(len(x), FEAT)  # 6b + 2a + c
     return bf16(phi) if bf else phi
 
@@ -69,11 +74,11 @@ def softplus(o):
     return np.logaddexp(0.0, o)
 
 
-def forward(flat, x, lo, ext, bf=True):
+def forward(flat, x, lo, ext, bf=True, max_cycles=None):
     """Returns (y [n], cache)."""
     p = unflatten(flat)
     q = (lambda a: bf16(a)) if bf else (lambda a: a)
-    h = features(x, lo, ext, bf)
+    h = features(x, lo, ext, bf, max_cycles)
     hs, zs = [h], []
     for L in range(1, LAYERS + 1):
         z = h @ q(p[f"W{L}"]) + p[f"b{L}"]
@@ -85,9 +90,9 @@ def forward(flat, x, lo, ext, bf=True):
     return y, {"hs": hs, "zs": zs, "o": o, "p": p, "q": q}
 
 
-def loss_and_grad(flat, x, target, lo, ext, bf=True):
+def loss_and_grad(flat, x, target, lo, ext, bf=True, max_cycles=None):
     """Mean squared error over the batch and its gradient with respect to the flat parameters."""
-    y, c = forward(flat, x, lo, ext, bf)
+    y, c = forward(flat, x, lo, ext, bf, max_cycles)
     t = np.asarray(target, np.float64).reshape(-1)
     B = len(t)
     loss = np.mean((y - t) ** 2)

@@ -89,7 +89,7 @@ def load_library(path: str = LIB_PATH):
     lib.gm_profile_enable.argtypes = [vp, i32]
     lib.gm_density_stats.argtypes = [vp, ctypes.POINTER(i64)]
     f32p = ctypes.POINTER(ctypes.c_float)
-    lib.gm_field_create.argtypes = [vp, u64, ctypes.POINTER(vp)]
+    lib.gm_field_create.argtypes = [vp, u64, dbl, ctypes.POINTER(vp)]
     lib.gm_field_destroy.argtypes = [vp]
     lib.gm_field_set_params.argtypes = [vp, f32p]
     lib.gm_field_get_params.argtypes = [vp, f32p]
@@ -293,10 +293,11 @@ def pair_values(pos, fix: Fixations, theta_deg, pair_s, pair_f):
 class Field:
     """Neural density field over a scene (see include/gazemap.h)."""
 
-    def __init__(self, scene: Scene, seed=0):
+    def __init__(self, scene: Scene, seed=0, max_cycles=32.0):
         lib = load_library()
         h = ctypes.c_void_p()
-        _check(lib.gm_field_create(scene._h, int(seed) & (2 ** 64 - 1), ctypes.byref(h)))
+        _check(lib.gm_field_create(scene._h, int(seed) & (2 ** 64 - 1), float(max_cycles), ctypes.byref(h)))
+        self.max_cycles = float(max_cycles)
         self._h = h
         self.scene = scene
 

@@ -73,7 +73,7 @@ gm_status upload_params(gm_field* f, const float* host, hipStream_t s)
 
 extern "C" {
 
-gm_status gm_field_create(gm_scene* scene, uint64_t seed, gm_field** out)
+gm_status gm_field_create(gm_scene* scene, uint64_t seed, double max_cycles, gm_field** out)
 {
     clear_error();
     if (!scene || !out) return fail(GM_ERR_INVALID_ARGUMENT, "scene and out must not be NULL");
@@ -89,7 +89,9 @@ gm_status gm_field_create(gm_scene* scene, uint64_t seed, gm_field** out)
         ext = std::max(ext, scene->bvh.hi[a] - scene->bvh.lo[a]);
     }
     f->geom.inv_ext = ext > 0.0f ? 1.0f / ext : 1.0f;
-    for (int b = 0; b < kFieldBands; ++b) f->geom.freq[b] = (float)std::exp2(0.6 * b);
+    if (!(max_cycles > 0.0) || !std::isfinite(max_cycles)) max_cycles = 32.0;
+    for (int b = 0; b < kFieldBands; ++b)
+        f->geom.freq[b] = (float)std::pow(max_cycles, (double)b / (double)(kFieldBands - 1));
     f->rel_l2.assign((size_t)scene->M, NAN);
     f->gate.assign((size_t)scene->M, 0);
     hipError_t e = hipSuccess;

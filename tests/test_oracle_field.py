@@ -19,8 +19,9 @@ def test_feature_closed_forms():
     # band 0 (frequency 1): x~ = (0.25, 0.5, 0.75) -> sin(2 pi x~) = (1, 0, -1)
     assert np.allclose(phi[1, [0, 2, 4]], [1.0, 0.0, -1.0], atol=1e-15)
     assert np.allclose(phi[1, [1, 3, 5]], [0.0, -1.0, 0.0], atol=1e-15)
-    # band 5 has frequency 2^3 = 8
-    assert math.isclose(fo.freqs()[5], 8.0)
+    # geometric ladder from 1 to max_cycles: with 32, band 3 has frequency 32^(1/5) = 2
+    assert math.isclose(fo.freqs()[3], 2.0, rel_tol=1e-6) and math.isclose(fo.freqs()[15], 32.0)
+    assert math.isclose(fo.freqs(2.0 ** 15)[5], 32.0, rel_tol=1e-6)
     assert np.allclose(phi[:, 0::2] ** 2 + phi[:, 1::2] ** 2, 1.0)
 
 
