@@ -59,6 +59,7 @@ struct Builder {
     std::vector<int32_t> idx;
     HostBvh* out;
     float pad_abs;
+    int leaf_max = kLeafMax;
 
     Box range_box(int64_t b, int64_t e) const
     {
@@ -110,7 +111,7 @@ struct Builder {
         const bool degenerate = !(cb.hi[axis] > cb.lo[axis]);
         // guarantee depth <= kMaxDepth: object median when the range is too large for the depth left
         const bool force_median =
-            degenerate || (depth >= kMaxDepth - 24 && n > ((int64_t)kLeafMax << std::max(0, kMaxDepth - 1 - depth)));
+            degenerate || (depth >= kMaxDepth - 24 && n > ((int64_t)leaf_max << std::max(0, kMaxDepth - 1 - depth)));
         if (!force_median) {
             double best = std::numeric_limits<double>::infinity();
             int best_axis = -1, best_bin = -1;
@@ -176,7 +177,7 @@ struct Builder {
         return mid;
     }
 
-    // builds an internal node over [b, e) (e - b > kLeafMax) and returns its index
+    // builds an internal node over [b, e) (e - b > leaf_max) and returns its index
     int32_t build(int64_t b, int64_t e, int depth)
     {
         const int32_t id = (int32_t)out->nodes.size();
@@ -191,7 +192,7 @@ struct Builder {
             float lo[3], hi[3];
             padded(bx, lo, hi);
             int32_t child, count;
-            if (re[c] - rb[c] <= kLeafMax) {
+            if (re[c] - rb[c] <= leaf_max) {
                 child = ~emit_leaf(rb[c], re[c]);
                 count = (int32_t)(re[c] - rb[c]);
                 out->depth = std::max(out->depth, depth + 2);
@@ -212,9 +213,10 @@ struct Builder {
 }  // namespace
 
 // V: all vertices [nv][3]; I: triangles with scene-global vertex indices [T][3].
-void build_bvh(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T, HostBvh& out)
+void build_bvh(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T, HostBvh& out, int leaf_max)
 {
     Builder bd;
+    bd.leaf_max = std::min(std::max(leaf_max, 1), kLeafMax);
     bd.V = V; bd.I = I; bd.tri_mesh = tri_mesh; bd.out = &out;
     bd.tbox.resize((size_t)T);
     bd.cent.resize((size_t)T * 3);
@@ -240,7 +242,7 @@ void build_bvh(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_
     out.nodes.clear();
     out.tris.clear();
     out.depth = 0;
-    if (T > kLeafMax) {
+    if (T > bd.leaf_max) {
         bd.build(0, T, 0);
     } else {
         // root with one leaf child and one empty child
@@ -261,6 +263,23 @@ void build_bvh(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_
     pad.id = -2;
     pad.mesh = -2;
     for (int k = 0; k < kLeafMax - 1; ++k) out.tris.push_back(pad);
+}
+
+void permute_tri_copies(const std::vector<BvhTri>& in, std::vector<BvhTri>& out)
+{
+    const size_t n = in.size();
+    out.resize(kTriCopies * n);
+    for (int c = 0; c < kTriCopies; ++c) {
+        const int kz = c, kx = (c + 1) % 3, ky = (c + 2) % 3;
+        for (size_t i = 0; i < n; ++i) {
+            const BvhTri& t = in[i];
+            BvhTri& r = out[c * n + i];
+            r = t;
+            r.v0[0] = t.v0[kx]; r.v0[1] = t.v0[ky]; r.v0[2] = t.v0[kz];
+            r.v1[0] = t.v1[kx]; r.v1[1] = t.v1[ky]; r.v1[2] = t.v1[kz];
+            r.v2[0] = t.v2[kx]; r.v2[1] = t.v2[ky]; r.v2[2] = t.v2[kz];
+        }
+    }
 }
 
 }  // namespace gm

@@ -183,6 +183,7 @@ gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int
     a.F = F;
     a.nodes = sc->nodes.as<BvhNode>();
     a.tris = sc->tris.as<BvhTri>();
+    a.tri_stride = (int64_t)sc->bvh.tris.size();
     a.occ_mode = (int32_t)mode;
     a.tmax = (float)(1.0 - kEpsV);
     a.cone2 = (float)(16.0 * sigma * sigma);
@@ -246,7 +247,7 @@ gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** ou
     if (!sc) return fail(GM_ERR_OUT_OF_MEMORY, "host allocation failed");
     if (const char* e = std::getenv("GM_SAMPLES_PER_LANE")) {
         const int v = std::atoi(e);
-        if (v == 1 || v == 2 || v == 4 || v == 8) sc->spl = v;
+        if (v == 1 || v == 2 || v == 4) sc->spl = v;
     }
     hipError_t he = hipGetDevice(&sc->device);
     if (he != hipSuccess) {
@@ -272,7 +273,12 @@ gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** ou
         tb += g.n_triangles;
     }
     sc->tri_off[(size_t)n_meshes] = tb;
-    build_bvh(V.data(), I.data(), tm.data(), T, sc->bvh);
+    int leaf_max = kLeafMax;
+    if (const char* e = std::getenv("GM_BVH_LEAF")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= kLeafMax) leaf_max = v;
+    }
+    build_bvh(V.data(), I.data(), tm.data(), T, sc->bvh, leaf_max);
 
     auto up = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
         hipError_t e = b.ensure(bytes);
@@ -285,7 +291,9 @@ gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** ou
     if (e == hipSuccess) e = up(sc->tri_mesh, tm.data(), tm.size() * 4);
     if (e == hipSuccess) e = up(sc->tri_off_d, sc->tri_off.data(), sc->tri_off.size() * 8);
     if (e == hipSuccess) e = up(sc->nodes, sc->bvh.nodes.data(), sc->bvh.nodes.size() * sizeof(BvhNode));
-    if (e == hipSuccess) e = up(sc->tris, sc->bvh.tris.data(), sc->bvh.tris.size() * sizeof(BvhTri));
+    std::vector<BvhTri> tri3;
+    permute_tri_copies(sc->bvh.tris, tri3);
+    if (e == hipSuccess) e = up(sc->tris, tri3.data(), tri3.size() * sizeof(BvhTri));
     if (e != hipSuccess) {
         delete sc;
         return fail(e == hipErrorOutOfMemory ? GM_ERR_OUT_OF_MEMORY : GM_ERR_DEVICE, "scene upload: %s",
@@ -374,7 +382,8 @@ gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri,
     if (st != GM_OK) return st;
     DensityLaunch a;
     GM_HIP(sc->tbegin(kStagePrep, s));
-    st = density_prep(sc, w, pos, tri, mesh, n, fix, theta_deg, flags & GM_OCC_MASK, sc->spl, 0, a, s);
+    const int spl = sc->spl ? sc->spl : ((flags & GM_OCC_MASK) != GM_OCC_NONE ? 1 : 2);
+    st = density_prep(sc, w, pos, tri, mesh, n, fix, theta_deg, flags & GM_OCC_MASK, spl, 0, a, s);
     if (st != GM_OK) return st;
     GM_HIP(sc->tend(kStagePrep, s));
     if (n > 0 && fix->n > 0) {
@@ -426,7 +435,7 @@ gm_status gm_debug_pair_visibility(gm_scene* sc, const float* pos, const int32_t
     gm_status st = check_device(sc);
     if (st != GM_OK) return st;
     launch_pair_visibility(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), eye, pair_s, pair_f, m, n_points, n_eyes, sc->T,
-                           sc->nodes.as<BvhNode>(), sc->tris.as<BvhTri>(), (int32_t)mode, (float)(1.0 - kEpsV), vis_out, (hipStream_t)stream);
+                           sc->nodes.as<BvhNode>(), sc->tris.as<BvhTri>() + 2 * sc->bvh.tris.size(), (int32_t)mode, (float)(1.0 - kEpsV), vis_out, (hipStream_t)stream);
     GM_HIP(hipGetLastError());
     return GM_OK;
 }

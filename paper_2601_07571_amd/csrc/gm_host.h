@@ -141,7 +141,9 @@ struct gm_scene {
     DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total;
     // density scratch of the plain entry points
     DensityWork work;
-    int32_t spl = 2;
+    // samples per lane of the plain density kernel; 0 = by occlusion mode (1 with a
+    // visibility test, whose cost is per segment, 2 for the gate-only kernel)
+    int32_t spl = 0;
     bool profiling = false;
     StageTimer timers[kStages];
 

@@ -37,6 +37,13 @@ static_assert(sizeof(BvhTri) == 48, "triangle record is 48 bytes");
 // the end so a leaf's records can always be fetched as one group of kLeafMax.
 constexpr int kLeafMax = 4;
 
+// On the device the record array is stored three times, copy c holding the
+// vertex coordinates in the axis order (kx, ky, kz) = ((c + 1) % 3, (c + 2) % 3, c),
+// so that a wave whose segments share the dominant axis kz = c reads vertices
+// already permuted for the watertight shear.  Copy 2 is the x, y, z order.
+constexpr int kTriCopies = 3;
+void permute_tri_copies(const std::vector<BvhTri>& in, std::vector<BvhTri>& out);
+
 // Per-fixation record written by the prep kernel (32 bytes).
 struct alignas(16) FixRec {
     float ex, ey, ez;  // eye
@@ -52,7 +59,9 @@ struct HostBvh {
     int depth = 0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
 };
-void build_bvh(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T, HostBvh& out);
+// leaf_max (1 .. kLeafMax): most triangles per leaf.
+void build_bvh(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T, HostBvh& out,
+               int leaf_max = kLeafMax);
 
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files).  All asynchronous on `s`.
@@ -91,7 +100,8 @@ struct DensityLaunch {
     const FixRec* fix;
     int32_t F;
     const BvhNode* nodes;
-    const BvhTri* tris;
+    const BvhTri* tris;        // kTriCopies permuted copies
+    int64_t tri_stride;        // records per copy
     int32_t occ_mode;
     float tmax;                // 1 - eps_v
     float cone2;               // 16 sigma^2

@@ -121,11 +121,10 @@ __device__ __forceinline__ float pair_value(float x, float y, float z, float ex,
 // packet visibility: every active lane holds one segment eye -> its point
 // ---------------------------------------------------------------------------
 struct Seg {
-    float ox, oy, oz;  // eye
     float ix, iy, iz;  // 1 / direction (finite)
     float qx, qy, qz;  // -eye / direction
-    float sx, sy, sz;  // watertight shear
-    int kx, ky, kz;
+    float sx, sy, sz;  // watertight shear: d[kx] / d[kz], d[ky] / d[kz], 1 / d[kz]
+    int kx, ky, kz;    // axis order of the shear
 };
 
 __device__ __forceinline__ float safe_inv(float d)
@@ -135,20 +134,31 @@ __device__ __forceinline__ float safe_inv(float d)
 
 __device__ __forceinline__ float pick(int k, float a, float b, float c) { return k == 0 ? a : (k == 1 ? b : c); }
 
-__device__ __forceinline__ Seg make_seg(float ex, float ey, float ez, float px, float py, float pz)
+// Dominant axis kz of d and the other two, swapped when d[kz] < 0 so the shear keeps
+// the triangle's winding.
+__device__ __forceinline__ void axis_order(float dx, float dy, float dz, int& kx, int& ky, int& kz)
+{
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    kx = kz == 2 ? 0 : kz + 1;
+    ky = kx == 2 ? 0 : kx + 1;
+    if (pick(kz, dx, dy, dz) < 0.0f) {
+        const int t = kx;
+        kx = ky;
+        ky = t;
+    }
+}
+
+// Segment eye -> point, sheared along the given axis order.
+__device__ __forceinline__ Seg make_seg(float ex, float ey, float ez, float px, float py, float pz, int kx, int ky,
+                                        int kz)
 {
     Seg s;
-    s.ox = ex; s.oy = ey; s.oz = ez;
     const float dx = px - ex, dy = py - ey, dz = pz - ez;
     s.ix = safe_inv(dx); s.iy = safe_inv(dy); s.iz = safe_inv(dz);
     s.qx = -ex * s.ix; s.qy = -ey * s.iy; s.qz = -ez * s.iz;
-    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
-    int kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
-    int kx = kz == 2 ? 0 : kz + 1;
-    int ky = kx == 2 ? 0 : kx + 1;
-    const float dkz = pick(kz, dx, dy, dz);
-    if (dkz < 0.0f) { const int t = kx; kx = ky; ky = t; }
     s.kx = kx; s.ky = ky; s.kz = kz;
+    const float dkz = pick(kz, dx, dy, dz);
     s.sx = pick(kx, dx, dy, dz) / dkz;
     s.sy = pick(ky, dx, dy, dz) / dkz;
     s.sz = 1.0f / dkz;
@@ -166,73 +176,121 @@ __device__ __forceinline__ bool box_hit(const Seg& s, const float* lo, const flo
     return tn <= tf;
 }
 
+// Triangle vertices relative to the eye, in the axis order of the record copy the
+// wave reads (the eye is passed in that same order).
+struct TriEye {
+    float ax, ay, az, bx, by, bz, cx, cy, cz;
+};
+
+__device__ __forceinline__ TriEye tri_eye(const BvhTri& t, float e0, float e1, float e2)
+{
+    TriEye u;
+    u.ax = t.v0[0] - e0; u.ay = t.v0[1] - e1; u.az = t.v0[2] - e2;
+    u.bx = t.v1[0] - e0; u.by = t.v1[1] - e1; u.bz = t.v1[2] - e2;
+    u.cx = t.v2[0] - e0; u.cy = t.v2[1] - e1; u.cz = t.v2[2] - e2;
+    return u;
+}
+
 // Watertight segment/triangle test (Woop, Benthin and Wald, JCGT 2013): shear the
 // triangle into the segment's frame, three edge functions with inclusive edges,
 // FP64 re-evaluation when an edge function is exactly zero; hit when the
-// parameter tau = T/det lies in (0, tmax).
-__device__ __forceinline__ bool seg_tri(const Seg& s, const BvhTri& t, float tmax)
+// parameter tau = T/det lies in (0, tmax).  Lanes with `active` false get an
+// unspecified answer.  With UNI the vertices are already in
+// the segment's axis order; otherwise they are in x, y, z order and each lane
+// permutes them.  Both windings count, so the order of kx and ky does not matter.
+template <bool UNI>
+__device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, float tmax, bool active)
 {
-    const float ax = t.v0[0] - s.ox, ay = t.v0[1] - s.oy, az = t.v0[2] - s.oz;
-    const float bx = t.v1[0] - s.ox, by = t.v1[1] - s.oy, bz = t.v1[2] - s.oz;
-    const float cx = t.v2[0] - s.ox, cy = t.v2[1] - s.oy, cz = t.v2[2] - s.oz;
-    const float akz = pick(s.kz, ax, ay, az), bkz = pick(s.kz, bx, by, bz), ckz = pick(s.kz, cx, cy, cz);
-    const float Ax = __builtin_fmaf(-s.sx, akz, pick(s.kx, ax, ay, az));
-    const float Ay = __builtin_fmaf(-s.sy, akz, pick(s.ky, ax, ay, az));
-    const float Bx = __builtin_fmaf(-s.sx, bkz, pick(s.kx, bx, by, bz));
-    const float By = __builtin_fmaf(-s.sy, bkz, pick(s.ky, bx, by, bz));
-    const float Cx = __builtin_fmaf(-s.sx, ckz, pick(s.kx, cx, cy, cz));
-    const float Cy = __builtin_fmaf(-s.sy, ckz, pick(s.ky, cx, cy, cz));
+    float akx, aky, akz, bkx, bky, bkz, ckx, cky, ckz;
+    if (UNI) {
+        akx = u.ax; aky = u.ay; akz = u.az;
+        bkx = u.bx; bky = u.by; bkz = u.bz;
+        ckx = u.cx; cky = u.cy; ckz = u.cz;
+    } else {
+        akx = pick(s.kx, u.ax, u.ay, u.az); aky = pick(s.ky, u.ax, u.ay, u.az); akz = pick(s.kz, u.ax, u.ay, u.az);
+        bkx = pick(s.kx, u.bx, u.by, u.bz); bky = pick(s.ky, u.bx, u.by, u.bz); bkz = pick(s.kz, u.bx, u.by, u.bz);
+        ckx = pick(s.kx, u.cx, u.cy, u.cz); cky = pick(s.ky, u.cx, u.cy, u.cz); ckz = pick(s.kz, u.cx, u.cy, u.cz);
+    }
+    const float Ax = __builtin_fmaf(-s.sx, akz, akx);
+    const float Ay = __builtin_fmaf(-s.sy, akz, aky);
+    const float Bx = __builtin_fmaf(-s.sx, bkz, bkx);
+    const float By = __builtin_fmaf(-s.sy, bkz, bky);
+    const float Cx = __builtin_fmaf(-s.sx, ckz, ckx);
+    const float Cy = __builtin_fmaf(-s.sy, ckz, cky);
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
-    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+    if (active && (U == 0.0f || V == 0.0f || W == 0.0f)) {
+        // rare: keep it a real branch (the empty asm stops the compiler from
+        // evaluating the FP64 products for every lane and selecting afterwards)
+        asm volatile("" ::: "memory");
         U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
         W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
     }
-    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
-    float det = U + V + W;
-    if (det == 0.0f) return false;
-    float T = U * (s.sz * akz) + V * (s.sz * bkz) + W * (s.sz * ckz);
-    if (det < 0.0f) { T = -T; det = -det; }
-    return T > 0.0f && T < tmax * det;
+    const bool mixed = (fminf(fminf(U, V), W) < 0.0f) & (fmaxf(fmaxf(U, V), W) > 0.0f);
+    const float det = U + V + W;
+    const float T = U * (s.sz * akz) + V * (s.sz * bkz) + W * (s.sz * ckz);
+    // scale T by sign(det) so the range test reads as for det > 0
+    const float Ts = __uint_as_float(__float_as_uint(T) ^ (__float_as_uint(det) & 0x80000000u));
+    return !mixed & (det != 0.0f) & (Ts > 0.0f) & (Ts < tmax * fabsf(det));
 }
 
-// Returns true for lanes whose segment is blocked.  `active` lanes take part; the
-// eye must be the same for every lane of the wave.  Node and triangle fetches use
-// wave-uniform addresses (scalar loads); the traversal stack lives in one VGPR,
-// lane i holding entry i.
-__device__ bool occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, const Seg& sg,
-                                int own_tri, int own_mesh, int mode, float tmax, bool active, uint32_t& visits)
+// Packet visibility.  Every lane carries up to R segments (R sample slots of the
+// wave), all starting at the wave's eye; `active[r]` marks the segments to test and
+// occ[r] receives the answer.  One traversal serves all R * 64 segments: the node
+// index is wave-uniform (scalar loads), each lane tests its own segments against both
+// child boxes, children are visited near first (entry distance of the first live
+// lane) and the stack is one VGPR, lane i holding entry i.  Per-lane predicates are
+// kept as 64-bit wave masks (scalar registers) rather than per-lane booleans.
+// `tris` is the record copy whose axis order matches (e0, e1, e2), the eye in that
+// order: with UNI the packet's shared order, otherwise copy 2 (x, y, z).
+template <int R, bool UNI>
+__device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, float e0,
+                                float e1, float e2, const Seg (&sg)[R], const int (&own_tri)[R],
+                                const int (&own_mesh)[R], int mode, float tmax, const bool (&active)[R],
+                                bool (&occ)[R], uint32_t& visits)
 {
     const int lane = lane_id();
-    bool occ = false;
-    uint64_t alive = ballot(active);
-    if (alive == 0) return false;
+    uint64_t live[R], hit[R];
+    uint64_t alive = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        live[r] = ballot(active[r]);
+        hit[r] = 0;
+        alive |= live[r];
+    }
     int stack = 0;
     int sp = 0;
     int node = 0;
-    for (;;) {
+    while (alive != 0) {
         const BvhNode nd = load_node(nodes, node);
         ++visits;
-        const bool me = (alive >> lane) & 1ull;
-        float tn0, tn1;
-        const bool h0 = box_hit(sg, nd.lo0, nd.hi0, tmax, tn0) && me;
-        const bool h1 = box_hit(sg, nd.lo1, nd.hi1, tmax, tn1) && me;
-        const uint64_t m0 = ballot(h0), m1 = ballot(h1);
-        // visit order from the first live lane's entry distances
+        uint64_t h0[R], h1[R];
+        uint64_t any0 = 0, any1 = 0;
+        float tn0 = 3.0e38f, tn1 = 3.0e38f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float a, b;
+            h0[r] = ballot(box_hit(sg[r], nd.lo0, nd.hi0, tmax, a)) & live[r];
+            h1[r] = ballot(box_hit(sg[r], nd.lo1, nd.hi1, tmax, b)) & live[r];
+            tn0 = __builtin_amdgcn_inverse_ballot_w64(h0[r]) ? fminf(tn0, a) : tn0;
+            tn1 = __builtin_amdgcn_inverse_ballot_w64(h1[r]) ? fminf(tn1, b) : tn1;
+            any0 |= h0[r];
+            any1 |= h1[r];
+        }
+        // entry distances are >= 0, so their bit patterns order as the floats do
         const int lead = __builtin_ctzll(alive);
-        const float l0 = __shfl(tn0, lead, 64), l1 = __shfl(tn1, lead, 64);
-        const bool swap = uniform(l1 < l0 ? 1 : 0) != 0;
+        const int l0 = __builtin_amdgcn_readlane(__float_as_int(tn0), lead);
+        const int l1 = __builtin_amdgcn_readlane(__float_as_int(tn1), lead);
+        const bool swap = l1 < l0;
         int next = -1;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const bool first = (c == 0) != swap;  // c==0 -> near child
-            const uint64_t mask = first ? m0 : m1;
-            if (mask == 0) continue;
+            const bool first = (c == 0) != swap;  // c == 0: the near child
+            if ((first ? any0 : any1) == 0) continue;
             const int child = first ? nd.child0 : nd.child1;
             const int count = first ? nd.count0 : nd.count1;
-            const bool hit_box = first ? h0 : h1;
             if (child < 0) {
                 // all records of the leaf are fetched together (the array is padded so
                 // that kLeafMax records from any leaf start are in bounds)
@@ -243,12 +301,30 @@ __device__ bool occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
 #pragma unroll
                 for (int k = 0; k < kLeafMax; ++k) {
                     if (k >= count) break;
-                    const bool skip = tr[k].id == own_tri || (mode == 1 && tr[k].mesh != own_mesh);
-                    const bool test = hit_box && !occ && !skip && ((alive >> lane) & 1ull);
-                    if (test && seg_tri(sg, tr[k], tmax)) occ = true;
+                    uint64_t tm[R];
+                    uint64_t tany = 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const bool skip = tr[k].id == own_tri[r] || (mode == 1 && tr[k].mesh != own_mesh[r]);
+                        tm[r] = (first ? h0[r] : h1[r]) & ~hit[r] & ~ballot(skip);
+                        tany |= tm[r];
+                    }
+                    if (tany == 0) continue;
+                    const TriEye u = tri_eye(tr[k], e0, e1, e2);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (tm[r] == 0) continue;
+                        const bool t = __builtin_amdgcn_inverse_ballot_w64(tm[r]);
+                        hit[r] |= ballot(seg_tri<UNI>(sg[r], u, tmax, t)) & tm[r];
+                    }
                 }
-                alive = ballot(((alive >> lane) & 1ull) && !occ);
-                if (alive == 0) return occ;
+                alive = 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    live[r] &= ~hit[r];
+                    alive |= live[r];
+                }
+                if (alive == 0) break;
             } else if (next < 0) {
                 next = child;
             } else {
@@ -256,6 +332,7 @@ __device__ bool occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
                 ++sp;
             }
         }
+        if (alive == 0) break;
         if (next < 0) {
             if (sp == 0) break;
             --sp;
@@ -263,7 +340,8 @@ __device__ bool occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
         }
         node = uniform(next);
     }
-    return occ;
+#pragma unroll
+    for (int r = 0; r < R; ++r) occ[r] = __builtin_amdgcn_inverse_ballot_w64(hit[r]);
 }
 
 __device__ __forceinline__ unsigned long long to_fixed(float g, int shift)
@@ -451,32 +529,76 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
             }
             if (ballot(cand != 0) == 0) continue;
 
-            // exact path for this fixation, one sample slot at a time
+            // exact path for this fixation: values of the passing slots, then one packet
+            // traversal for every slot that needs a visibility answer
             const int f = uniform(fb + j);
             const FixRec fr = load_fix(a.fix, f);
+            float g[SPL];
+            float4 p[SPL];
+            bool need[SPL];
+            bool any_need = false;
+#pragma unroll
             for (int k = 0; k < SPL; ++k) {
                 const int64_t i = wave_base + k * 64 + lane;
                 const bool c = ((cand >> k) & 1u) && i < n;
-                if (ballot(c) == 0) continue;
-                float g = 0.0f;
-                float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (c) {
-                    p = a.spos[i];
-                    g = pair_value(p.x, p.y, p.z, fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w, a.cone2, a.kexp);
+                g[k] = 0.0f;
+                p[k] = make_float4(fr.ex, fr.ey, fr.ez, __int_as_float(-1));
+                if (ballot(c) != 0 && c) {
+                    p[k] = a.spos[i];
+                    g[k] = pair_value(p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w, a.cone2,
+                                      a.kexp);
                 }
-                bool vis = true;
-                const bool need = OCC != 0 && a.occ_mode != 0 && g > 0.0f;
-                const uint64_t need_mask = ballot(need);
-                if (OCC != 0 && need_mask != 0) {
-                    const Seg sg = make_seg(fr.ex, fr.ey, fr.ez, p.x, p.y, p.z);
-                    const int own_mesh = need ? a.smesh[i] : -1;
-                    vis = !occluded_packet(a.nodes, a.tris, sg, __float_as_int(p.w), own_mesh, a.occ_mode,
-                                           a.tmax, need, n_visits);
-                    ++n_trav;
+                need[k] = OCC != 0 && a.occ_mode != 0 && g[k] > 0.0f;
+                any_need = any_need || need[k];
+                n_in += (uint32_t)__popcll(ballot(g[k] > 0.0f));
+            }
+            bool occl[SPL];
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) occl[k] = false;
+            if (OCC != 0 && ballot(any_need) != 0) {
+                // The packet shares the axis order of the gaze's dominant axis when every
+                // segment keeps at least 0.4 of its length along that axis (true for every
+                // in-cone segment while the cone half-angle stays under ~14 degrees); it
+                // then reads the record copy already permuted into that order.
+                const float agx = fabsf(fr.rx), agy = fabsf(fr.ry), agz = fabsf(fr.rz);
+                const int kz = uniform(agx > agy ? (agx > agz ? 0 : 2) : (agy > agz ? 1 : 2));
+                const int kx = kz == 2 ? 0 : kz + 1;
+                const int ky = kx == 2 ? 0 : kx + 1;
+                bool shared = true;
+                int otri[SPL], omesh[SPL];
+#pragma unroll
+                for (int k = 0; k < SPL; ++k) {
+                    const int64_t i = wave_base + k * 64 + lane;
+                    const float dx = p[k].x - fr.ex, dy = p[k].y - fr.ey, dz = p[k].z - fr.ez;
+                    const float dk = pick(kz, dx, dy, dz);
+                    shared = shared && (!need[k] || dk * dk >= 0.16f * (dx * dx + dy * dy + dz * dz));
+                    otri[k] = need[k] ? __float_as_int(p[k].w) : -1;
+                    omesh[k] = need[k] ? a.smesh[i] : -1;
                 }
-                n_in += (uint32_t)__popcll(ballot(g > 0.0f));
-                n_vis += (uint32_t)__popcll(ballot(g > 0.0f && vis));
-                if (g > 0.0f && vis) s_acc[wave * (64 * SPL) + k * 64 + lane] += to_fixed(g, shift);
+                Seg sg[SPL];
+                if (ballot(!shared) == 0) {
+#pragma unroll
+                    for (int k = 0; k < SPL; ++k) sg[k] = make_seg(fr.ex, fr.ey, fr.ez, p[k].x, p[k].y, p[k].z, kx, ky, kz);
+                    occluded_packet<SPL, true>(a.nodes, a.tris + kz * a.tri_stride, pick(kx, fr.ex, fr.ey, fr.ez),
+                                               pick(ky, fr.ex, fr.ey, fr.ez), pick(kz, fr.ex, fr.ey, fr.ez), sg, otri,
+                                               omesh, a.occ_mode, a.tmax, need, occl, n_visits);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < SPL; ++k) {
+                        int lx, ly, lz;
+                        axis_order(p[k].x - fr.ex, p[k].y - fr.ey, p[k].z - fr.ez, lx, ly, lz);
+                        sg[k] = make_seg(fr.ex, fr.ey, fr.ez, p[k].x, p[k].y, p[k].z, lx, ly, lz);
+                    }
+                    occluded_packet<SPL, false>(a.nodes, a.tris + 2 * a.tri_stride, fr.ex, fr.ey, fr.ez, sg, otri,
+                                                omesh, a.occ_mode, a.tmax, need, occl, n_visits);
+                }
+                ++n_trav;
+            }
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) {
+                const bool ok = g[k] > 0.0f && !occl[k];
+                n_vis += (uint32_t)__popcll(ballot(ok));
+                if (ok) s_acc[wave * (64 * SPL) + k * 64 + lane] += to_fixed(g[k], shift);
             }
         }
     }
@@ -602,10 +724,17 @@ __global__ void __launch_bounds__(64) k_pair_visibility(const float* __restrict_
     int t = tri ? tri[s] : -1;
     if (t < 0 || t >= T) t = -1;
     const int me = mesh ? mesh[s] : (t >= 0 ? tri_mesh[t] : -1);
-    const Seg sg = make_seg(eye[3 * f], eye[3 * f + 1], eye[3 * f + 2], pos[3 * s], pos[3 * s + 1], pos[3 * s + 2]);
+    const float ex = eye[3 * f], ey = eye[3 * f + 1], ez = eye[3 * f + 2];
+    const float px = pos[3 * s], py = pos[3 * s + 1], pz = pos[3 * s + 2];
+    int kx, ky, kz;
+    axis_order(px - ex, py - ey, pz - ez, kx, ky, kz);
+    const Seg sgs[1] = {make_seg(ex, ey, ez, px, py, pz, kx, ky, kz)};
     uint32_t visits = 0;
-    const bool occ = mode != 0 && occluded_packet(nodes, tris, sg, t, me, mode, tmax, lane == 0, visits);
-    if (lane == 0) vis[i] = occ ? 0 : 1;
+    const int ot[1] = {t}, om[1] = {me};
+    const bool act[1] = {mode != 0 && lane == 0};
+    bool occ[1] = {false};
+    occluded_packet<1, false>(nodes, tris, ex, ey, ez, sgs, ot, om, mode, tmax, act, occ, visits);
+    if (lane == 0) vis[i] = occ[0] ? 0 : 1;
 }
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -649,8 +778,7 @@ void launch_density(const DensityLaunch& a, hipStream_t s)
     switch (a.spl) {
     case 1: occ ? k_density<1, 1><<<grid, kThreads, 0, s>>>(a) : k_density<1, 0><<<grid, kThreads, 0, s>>>(a); break;
     case 2: occ ? k_density<2, 1><<<grid, kThreads, 0, s>>>(a) : k_density<2, 0><<<grid, kThreads, 0, s>>>(a); break;
-    case 4: occ ? k_density<4, 1><<<grid, kThreads, 0, s>>>(a) : k_density<4, 0><<<grid, kThreads, 0, s>>>(a); break;
-    default: occ ? k_density<8, 1><<<grid, kThreads, 0, s>>>(a) : k_density<8, 0><<<grid, kThreads, 0, s>>>(a); break;
+    default: occ ? k_density<4, 1><<<grid, kThreads, 0, s>>>(a) : k_density<4, 0><<<grid, kThreads, 0, s>>>(a); break;
     }
 }
 
