@@ -13,6 +13,8 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
   triangle_areas .............. pinned (Heron in Kahan's ordering, closed forms)
   mesh_weights / sample_count . pinned (exact integer brute force, k*area)
   sample_scene ................ pinned (chi-square, KS, brute force, invariants)
+  lattice_* ................... pinned (loop enumeration of Eq. (2), the lattice
+                                 set, Eq. (1) and (4) closed forms and bounds)
   pair_value / density ........ pinned (plane closed form, 4-sigma mass,
                                  linearity, rigid motion, hand-computed cases)
   visibility .................. pinned (brute force == BVH, convex sphere ==
@@ -67,6 +69,15 @@ def _load():
     lib.or_sample_count.restype = c_i64
     lib.or_sample_mesh.argtypes = [P(c_f), P(c_i32), P(c_u64), c_i64, c_u32, c_u64, c_i64, c_i64,
                                    P(c_i32), P(c_d), P(c_d), P(c_f), P(c_f)]
+    lib.or_lattice_points.argtypes = [c_i64]
+    lib.or_lattice_points.restype = c_i64
+    lib.or_lattice_resolution.argtypes = [c_d, c_d]
+    lib.or_lattice_resolution.restype = c_i64
+    lib.or_lattice_row_col.argtypes = [c_i64, P(c_i64), P(c_i64)]
+    lib.or_lattice_counts.argtypes = [P(c_f), P(c_i32), c_i64, c_d, P(c_i64), P(c_i64)]
+    lib.or_lattice_counts.restype = c_i64
+    lib.or_lattice_mesh.argtypes = [P(c_f), P(c_i32), c_i64, c_d, c_i64, P(c_i32), P(c_d), P(c_f), P(c_f)]
+    lib.or_lattice_mesh.restype = c_i64
     lib.or_scene_create.argtypes = [P(c_f), P(c_i32), P(c_i32), c_i64]
     lib.or_scene_create.restype = ctypes.c_void_p
     lib.or_scene_destroy.argtypes = [ctypes.c_void_p]
@@ -202,6 +213,71 @@ def sample_scene(meshes, k: float, seed: int) -> OracleSamples:
     return OracleSamples(cat[0].astype(np.int32), cat[1].astype(np.int32), cat[2].astype(np.int32),
                          cat[3], cat[4], cat[5].astype(np.float32), cat[6].astype(np.float32),
                          np.array(counts, np.int64), np.array(Ss, np.int32), np.array(Wms, np.uint64))
+
+
+# ----------------------------------------------------------------------------
+# The paper's lattice sampler (Sec. 3.1.1, 3.1.2)
+# ----------------------------------------------------------------------------
+
+def lattice_points(r: int) -> int:
+    """Eq. (1)."""
+    return int(_load().or_lattice_points(int(r)))
+
+
+def lattice_resolution(k: float, A: float) -> int:
+    """Eq. (4), truncated to a whole resolution, at least 1."""
+    return int(_load().or_lattice_resolution(float(k), float(A)))
+
+
+def lattice_row_col(idx: int):
+    """Eq. (2) with the integer correction."""
+    row, col = ctypes.c_int64(), ctypes.c_int64()
+    _load().or_lattice_row_col(int(idx), ctypes.byref(row), ctypes.byref(col))
+    return row.value, col.value
+
+
+def lattice_counts(V, I, k: float):
+    """Per-triangle (resolution, point count) of one mesh."""
+    V = np.ascontiguousarray(V, dtype=np.float32)
+    I = np.ascontiguousarray(I, dtype=np.int32)
+    r = np.zeros(len(I), np.int64); c = np.zeros(len(I), np.int64)
+    _load().or_lattice_counts(_ptr(V, ctypes.c_float), _ptr(I, ctypes.c_int32), len(I), float(k),
+                              _ptr(r, ctypes.c_int64), _ptr(c, ctypes.c_int64))
+    return r, c
+
+
+@dataclass
+class OracleLattice:
+    tri_local: np.ndarray    # int32 [N], mesh-local triangle index
+    tri: np.ndarray          # int32 [N], scene-global triangle index
+    mesh: np.ndarray         # int32 [N]
+    pos64: np.ndarray        # float64 [N][3]
+    bary32: np.ndarray       # float32 [N][2]  (w2, w3): weights of v1, v2
+    pos32: np.ndarray        # float32 [N][3]
+    counts: np.ndarray       # int64 [M]
+
+
+def lattice_scene(meshes, k: float) -> OracleLattice:
+    """Every lattice point of every mesh: mesh order, triangle order, then idx."""
+    lib = _load()
+    parts, counts = [], []
+    tri_base = 0
+    for m, (V, I) in enumerate(meshes):
+        V = np.ascontiguousarray(V, dtype=np.float32)
+        I = np.ascontiguousarray(I, dtype=np.int32)
+        n = int(lib.or_lattice_counts(_ptr(V, ctypes.c_float), _ptr(I, ctypes.c_int32), len(I), float(k),
+                                      None, None))
+        tri = np.zeros(n, np.int32); p64 = np.zeros((n, 3))
+        b32 = np.zeros((n, 2), np.float32); p32 = np.zeros((n, 3), np.float32)
+        lib.or_lattice_mesh(_ptr(V, ctypes.c_float), _ptr(I, ctypes.c_int32), len(I), float(k), n,
+                            _ptr(tri, ctypes.c_int32), _ptr(p64, ctypes.c_double), _ptr(b32, ctypes.c_float),
+                            _ptr(p32, ctypes.c_float))
+        counts.append(n)
+        parts.append((tri, tri + tri_base, np.full(n, m, np.int32), p64, b32, p32))
+        tri_base += len(I)
+    cat = [np.concatenate([p[i] for p in parts]) for i in range(6)]
+    return OracleLattice(cat[0].astype(np.int32), cat[1].astype(np.int32), cat[2].astype(np.int32), cat[3],
+                         cat[4].astype(np.float32), cat[5].astype(np.float32), np.array(counts, np.int64))
 
 
 # ----------------------------------------------------------------------------

@@ -16,6 +16,9 @@
  *   - area-proportional surface sampling (Sec. 3.1: samples per square metre
  *     independent of mesh resolution) as fixed-point area weights, an exact
  *     integer prefix sum, Philox4x32-10 counters and a square-root warp;
+ *   - the paper's own per-triangle lattice sampler (Sec. 3.1.1 and 3.1.2,
+ *     Eqs. 1-4: point count, index -> row/column, barycentrics, adaptive
+ *     resolution);
  *   - the duration-weighted angular Gaussian of Sec. 3.2.1 (d1, d2, sigma,
  *     d, sigma_k, g), truncated at the 4-sigma cone (Sec. 3.2, Sec. 3.3.2);
  *   - visibility (Sec. 3.2.2) as an exact segment test eye -> sample against
@@ -200,6 +203,111 @@ void or_sample_mesh(const float* V, const int32_t* I, const uint64_t* C, int64_t
             if (pos32_out) pos32_out[3 * s + c] = (float)acc;
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The paper's own sampler: a per-triangle lattice (Sec. 3.1.1, Sec. 3.1.2). */
+/* A triangle subdivided at resolution r holds the points whose barycentric */
+/* coordinates are multiples of 1/r; they are indexed row by row, row 0      */
+/* holding one point and row `row` holding row + 1 points.                   */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. (1): number of lattice points at resolution r, the triangular number */
+/* (r + 1)(r + 2) / 2.                                                      */
+int64_t or_lattice_points(int64_t r)
+{
+    return (r + 1) * (r + 2) / 2;
+}
+
+/*
+ * Eq. (4): resolution giving k points per square metre on a triangle of area A.
+ * Delta = 1 + 8 k A is the discriminant of r^2 + 3r + 2 - 2kA = 0; r = 1 when
+ * Delta < 25, else the positive root (-3 + sqrt(Delta)) / 2.  Reading: the
+ * paper's root is real while a subdivision needs a whole number; the root is
+ * truncated, so a triangle never holds more than k A points (beyond the
+ * three of the r = 1 floor).  Evaluated as Delta = (8 k) A + 1, in FP64.
+ */
+int64_t or_lattice_resolution(double k, double A)
+{
+    double delta = 8.0 * k;
+    delta = delta * A;
+    delta = delta + 1.0;
+    if (!(delta >= 25.0)) return 1;
+    double root = (sqrt(delta) - 3.0) / 2.0;
+    return (int64_t)floor(root);
+}
+
+/*
+ * Eq. (2): row and column of point idx.  row = ceil((-3 + sqrt(8 idx + 9)) / 2)
+ * in FP64, then corrected with integers so that f(row - 1) <= idx < f(row)
+ * holds exactly (f = Eq. (1)); col = idx - f(row - 1).
+ */
+void or_lattice_row_col(int64_t idx, int64_t* row, int64_t* col)
+{
+    int64_t r = (int64_t)ceil((sqrt(8.0 * (double)idx + 9.0) - 3.0) / 2.0);
+    if (r < 0) r = 0;
+    while (or_lattice_points(r) <= idx) ++r;
+    while (r > 0 && or_lattice_points(r - 1) > idx) --r;
+    *row = r;
+    *col = idx - (r > 0 ? or_lattice_points(r - 1) : 0);
+}
+
+/* Per-triangle resolution and point count of a mesh; returns the total. */
+int64_t or_lattice_counts(const float* V, const int32_t* I, int64_t T, double k, int64_t* r_out,
+                          int64_t* count_out)
+{
+    int64_t total = 0;
+    for (int64_t i = 0; i < T; ++i) {
+        double A = tri_area_fp64(V + 3 * (int64_t)I[3 * i], V + 3 * (int64_t)I[3 * i + 1],
+                                 V + 3 * (int64_t)I[3 * i + 2]);
+        int64_t r = or_lattice_resolution(k, A);
+        if (r_out) r_out[i] = r;
+        if (count_out) count_out[i] = or_lattice_points(r);
+        total += or_lattice_points(r);
+    }
+    return total;
+}
+
+/*
+ * Every lattice point of a mesh, triangle by triangle, idx = 0 .. f(r) - 1 in
+ * each.  Eq. (3) as printed, (col/r, 1 - row/r, 1 - (col + row)/r), does not
+ * sum to one; the reading used keeps its first two weights and completes them:
+ *   w1 = col / r, w2 = (r - row) / r, w3 = (row - col) / r
+ * (each an exact integer ratio rounded once), which enumerates exactly the
+ * lattice {(i, j, l) / r : i + j + l = r}.  P = (w1 v0 + w2 v1) + w3 v2 in FP64,
+ * rounded to FP32.  bary32 holds (w2, w3), the weights of v1 and v2.
+ * Writes at most `cap` points; returns the mesh total.
+ */
+int64_t or_lattice_mesh(const float* V, const int32_t* I, int64_t T, double k, int64_t cap,
+                        int32_t* tri_out, double* pos_out, float* bary32_out, float* pos32_out)
+{
+    int64_t s = 0;
+    for (int64_t i = 0; i < T; ++i) {
+        const float* p0 = V + 3 * (int64_t)I[3 * i];
+        const float* p1 = V + 3 * (int64_t)I[3 * i + 1];
+        const float* p2 = V + 3 * (int64_t)I[3 * i + 2];
+        double A = tri_area_fp64(p0, p1, p2);
+        int64_t r = or_lattice_resolution(k, A);
+        int64_t n = or_lattice_points(r);
+        for (int64_t idx = 0; idx < n; ++idx, ++s) {
+            if (s >= cap) continue;
+            int64_t row, col;
+            or_lattice_row_col(idx, &row, &col);
+            double w1 = (double)col / (double)r;
+            double w2 = (double)(r - row) / (double)r;
+            double w3 = (double)(row - col) / (double)r;
+            tri_out[s] = (int32_t)i;
+            if (bary32_out) { bary32_out[2 * s] = (float)w2; bary32_out[2 * s + 1] = (float)w3; }
+            for (int c = 0; c < 3; ++c) {
+                double acc = w1 * (double)p0[c];
+                acc = acc + w2 * (double)p1[c];
+                acc = acc + w3 * (double)p2[c];
+                if (pos_out) pos_out[3 * s + c] = acc;
+                if (pos32_out) pos32_out[3 * s + c] = (float)acc;
+            }
+        }
+    }
+    return s;
 }
 
 /* ------------------------------------------------------------------------ */
