@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU = 157.3e12      # MI355X FP32 vector peak, FLOP/s
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_density_traffic_paper_shaped.md")
+COPY_PROBE_BYTES = 256 << 20   # the calibration copy of --traffic-probe (read and written once each)
 GATE_FLOP_PER_PAIR = 16        # 8 FMA per (sample, fixation) pair in the cone gate
 K_PAPER_SHAPED = 204240.0      # samples/m^2 giving ~2,000,000 samples on the paper-shaped scene
 
@@ -36,6 +38,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-session batched comparison")
     ap.add_argument("--no-field", action="store_true", help="skip the neural-field comparison")
     ap.add_argument("--field-steps", type=int, default=20000)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run one plain copy of known size, then one full-occlusion step, and exit (for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the path on a single MI355X "
@@ -63,6 +67,16 @@ def main():
     def step(occ="full"):
         scene.build_samples(k, w.seed, out=samples)
         scene.accumulate(samples.pos, fix, w.theta_deg, occlusion=occ, tri=samples.tri, mesh=samples.mesh, out=dens)
+
+    if args.traffic_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 4, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)   # one elementwise kernel: reads and writes COPY_PROBE_BYTES
+        torch.cuda.synchronize()
+        step()
+        torch.cuda.synchronize()
+        print("traffic probe done", file=sys.stderr)
+        return
 
     for _ in range(args.warmup):
         step()
@@ -116,7 +130,7 @@ def main():
         "map_time_ms": ms_step,
         "stage_ms": {s: v[0] / args.steps for s, v in stage.items()},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(),
                      "kernel": "k_density (gate + exact value + visibility)", "kernel_ms": dens_ms,
                      "flop_per_pair": GATE_FLOP_PER_PAIR},
         "gate_only": {"kernel_ms": gate_ms, "pairs_per_s": pairs / (gate_ms * 1e-3),
@@ -128,6 +142,7 @@ def main():
                           "workload": "the paper's 800k-triangle scene, 2M samples, 6,000 fixations"},
     }
 
+    out["lattice"] = bench_lattice(gm, torch, args, scene, k)
     if not args.no_batched:
         out["batched"] = bench_batched(gm, workloads, torch, args)
     if not args.no_field:
@@ -157,6 +172,29 @@ def main():
     print(json.dumps(out))
 
 
+def measured_traffic():
+    """HBM bytes per launch of the full-occlusion density kernel from the committed
+    counter summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    src = os.path.join(ROOT, "paper_2601_07571_amd", "csrc", "k_density.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            key, val = line[2:].split(":", 1)
+            fields[key.strip()] = val.strip().strip("`")
+    if fields.get("k_density.hip sha256") != digest:
+        return None
+    try:
+        return float(fields["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _time(fn, torch, reps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -164,6 +202,24 @@ def _time(fn, torch, reps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def bench_lattice(gm, torch, args, scene, k):
+    """The paper's own lattice sampler on the same scene and rate: whole call (counts,
+    blocking read-back, points) and its kernels alone (library stage timer)."""
+    lat = scene.build_lattice(k)
+    n = int(lat.pos.shape[0])
+    call_ms = _time(lambda: scene.build_lattice(k, out=lat), torch, args.steps)
+    scene.profile(True)
+    for _ in range(args.steps):
+        scene.build_lattice(k, out=lat)
+    torch.cuda.synchronize()
+    ms, cnt = scene.profile_read("sample")
+    scene.profile(False)
+    kern_ms = ms / max(1, cnt) * 2   # two timed regions per call: counts, then points
+    written = n * (4 + 4 + 8 + 12)
+    return {"points": n, "call_ms": call_ms, "kernels_ms": kern_ms,
+            "points_per_s": n / (kern_ms * 1e-3), "output_GBps": written / (kern_ms * 1e-3) / 1e9}
 
 
 def bench_batched(gm, workloads, torch, args):

@@ -111,6 +111,31 @@ gm_status build_surface_samples(gm_scene* scene, double samples_per_m2, uint64_t
                                 int32_t* tri, int32_t* mesh, float* bary, float* pos,
                                 int64_t capacity, int64_t* n_out, void* stream);
 
+/*
+ * gm_count_lattice_samples -- per-mesh point counts of the paper's own sampler
+ * (Sec. 3.1.1, 3.1.2): triangle i of area A_i (the same FP64 area as above) is
+ * subdivided at resolution r_i = 1 if Delta_i = 8 k A_i + 1 < 25, else
+ * floor((sqrt(Delta_i) - 3) / 2) (Eq. 4, the real root truncated to a whole
+ * resolution), and holds (r_i + 1)(r_i + 2) / 2 points (Eq. 1).  n_per_mesh: host
+ * int64 [n_meshes].  Blocking.  samples_per_m2 must be in (0, 1e12].
+ */
+gm_status gm_count_lattice_samples(gm_scene* scene, double samples_per_m2, int64_t* n_per_mesh, void* stream);
+
+/*
+ * build_lattice_samples -- every lattice point of the scene, in mesh order, then
+ * triangle order, then index idx within the triangle.  Eq. (2): row =
+ * ceil((sqrt(8 idx + 9) - 3) / 2), made exact with integers (f(row - 1) <= idx <
+ * f(row)), col = idx - f(row - 1).  Eq. (3) as printed does not sum to one; it is
+ * completed to w1 = col / r, w2 = (r - row) / r, w3 = (row - col) / r, which
+ * enumerates the lattice {(i, j, l) / r : i + j + l = r}; P = w1 v0 + w2 v1 + w3 v2
+ * in FP64, rounded to FP32.  Outputs as for build_surface_samples (device,
+ * caller-owned, each may be NULL): tri [N] scene-global, mesh [N], bary [N][2] =
+ * (w2, w3), pos [N][3].  N > capacity gives GM_ERR_CAPACITY with *n_out = N and
+ * nothing written.  Blocking (it reads back the counts).
+ */
+gm_status build_lattice_samples(gm_scene* scene, double samples_per_m2, int32_t* tri, int32_t* mesh, float* bary,
+                                float* pos, int64_t capacity, int64_t* n_out, void* stream);
+
 /* Fixations, device memory: eye [n][3] and gaze [n][3] (direction, any non-zero
  * length) in world space, duration [n] >= 0 (the weight t of Sec. 3.2.1). */
 typedef struct {
@@ -170,13 +195,15 @@ gm_status gm_debug_pair_visibility(gm_scene* scene, const float* pos, const int3
 /* MLP that learns the normalised map from (sample position, rho / max rho)  */
 /* pairs produced by build_surface_samples + accumulate_density, and answers */
 /* density queries at arbitrary surface points.  Network: 96 features        */
-/* [sin, cos](2 pi 2^(0.6 b) x~_a), b = 0..15, x~ = (x - lo) / ext in the     */
+/* [sin, cos](2 pi f_b x~_a), f_b = max_cycles^(b/15), b = 0..15, x~ =        */
+/* (x - lo) / ext in the                                                     */
 /* scene's bounding cube -> 4 x (64, ReLU) -> 1 -> softplus; bf16 matrix-core */
 /* products with fp32 accumulation; Adam on fp32 master weights.  Parameters */
 /* (18,753 floats, host order): W1 [96][64] (input, output), b1 [64], W2, b2, */
 /* W3, b3, W4, b4 (64 x 64, 64), w5 [64], b5; feature index 6 b + 2 a + c   */
 /* (c = 0 sin, 1 cos).  The plain accumulation stays the fallback and the    */
-/* judge: a mesh whose held-out relative L2 error exceeds max_rel_l2 (or a    */
+/* reference for the field's error: a mesh whose held-out relative L2 error   */
+/* exceeds max_rel_l2 (or a                                                  */
 /* field never trained, or with a non-finite error) is answered by           */
 /* accumulate_density at the query points.                                    */
 /* ------------------------------------------------------------------------ */

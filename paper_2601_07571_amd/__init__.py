@@ -23,7 +23,8 @@ OCC = {"none": 0, "self": 1, "full": 2}
 
 # exported symbols of include/gazemap.h
 SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy", "gm_scene_info",
-           "gm_count_surface_samples", "build_surface_samples", "accumulate_density",
+           "gm_count_surface_samples", "build_surface_samples", "gm_count_lattice_samples",
+           "build_lattice_samples", "accumulate_density",
            "gm_debug_pair_values", "gm_debug_pair_visibility", "gm_profile_enable", "gm_profile_read",
            "gm_density_stats", "gm_field_create", "gm_field_destroy", "gm_field_set_params",
            "gm_field_get_params", "gm_field_train", "gm_field_info", "gm_field_gradient", "gm_field_predict", "query_density",
@@ -83,6 +84,8 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
     lib.gm_count_surface_samples.argtypes = [vp, dbl, ctypes.POINTER(i64), vp]
     lib.build_surface_samples.argtypes = [vp, dbl, u64, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
+    lib.gm_count_lattice_samples.argtypes = [vp, dbl, ctypes.POINTER(i64), vp]
+    lib.build_lattice_samples.argtypes = [vp, dbl, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
     lib.accumulate_density.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(_Fix), dbl, u32, vp, vp, vp, vp]
     lib.gm_debug_pair_values.argtypes = [vp, i64, ctypes.POINTER(_Fix), dbl, vp, vp, i64, vp, vp]
     lib.gm_debug_pair_visibility.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, i64, u32, vp, vp]
@@ -247,6 +250,31 @@ class Scene:
         _check(_lib.build_surface_samples(self._h, float(samples_per_m2), int(seed) & (2 ** 64 - 1), _ptr(tri),
                                           _ptr(mesh), _ptr(bary), _ptr(pos), capacity, ctypes.byref(n),
                                           _stream()))
+        N = n.value
+        return Samples(tri[:N], mesh[:N], bary[:N], pos[:N])
+
+    def count_lattice(self, samples_per_m2):
+        """Per-mesh point counts of the paper's lattice sampler (host int64 array)."""
+        out = (ctypes.c_int64 * self.n_meshes)()
+        _check(_lib.gm_count_lattice_samples(self._h, float(samples_per_m2), out, _stream()))
+        return np.array(out[:], np.int64)
+
+    def build_lattice(self, samples_per_m2, capacity=None, out: Samples | None = None):
+        """Every lattice point of the scene (mesh, triangle, then index order)."""
+        torch = _torch()
+        if out is not None:
+            tri, mesh, bary, pos = out.tri, out.mesh, out.bary, out.pos
+            capacity = int(pos.shape[0])
+        else:
+            if capacity is None:
+                capacity = int(self.count_lattice(samples_per_m2).sum())
+            tri = torch.empty(capacity, dtype=torch.int32, device="cuda")
+            mesh = torch.empty(capacity, dtype=torch.int32, device="cuda")
+            bary = torch.empty((capacity, 2), dtype=torch.float32, device="cuda")
+            pos = torch.empty((capacity, 3), dtype=torch.float32, device="cuda")
+        n = ctypes.c_int64(0)
+        _check(_lib.build_lattice_samples(self._h, float(samples_per_m2), _ptr(tri), _ptr(mesh), _ptr(bary),
+                                          _ptr(pos), capacity, ctypes.byref(n), _stream()))
         N = n.value
         return Samples(tri[:N], mesh[:N], bary[:N], pos[:N])
 

@@ -282,4 +282,21 @@ void permute_tri_copies(const std::vector<BvhTri>& in, std::vector<BvhTri>& out)
     }
 }
 
+void octant_node_copies(const std::vector<BvhNode>& in, std::vector<BvhNode>& out)
+{
+    const size_t n = in.size();
+    out.resize(kNodeCopies * n);
+    for (int o = 0; o < kNodeCopies; ++o) {
+        for (size_t i = 0; i < n; ++i) {
+            BvhNode r = in[i];
+            for (int a = 0; a < 3; ++a) {
+                if (!((o >> a) & 1)) continue;
+                std::swap(r.lo0[a], r.hi0[a]);
+                std::swap(r.lo1[a], r.hi1[a]);
+            }
+            out[o * n + i] = r;
+        }
+    }
+}
+
 }  // namespace gm

@@ -103,6 +103,34 @@ gm_status sample_counts(gm_scene* sc, double k, hipStream_t s, std::vector<int64
     return GM_OK;
 }
 
+// Lattice sampler counts: areas (a1's kernel), Eq. (4) resolutions and Eq. (1)
+// counts per triangle, their inclusive scan in sc->C, per-mesh totals (blocking).
+gm_status lattice_counts(gm_scene* sc, double k, hipStream_t s, std::vector<int64_t>& counts)
+{
+    if (!(k > 0.0) || !(k <= 1e12)) return fail(GM_ERR_INVALID_ARGUMENT, "samples_per_m2 must be in (0, 1e12]");
+    const int64_t T = sc->T;
+    const int32_t M = sc->M;
+    GM_HIP(sc->area.ensure(sizeof(double) * T));
+    GM_HIP(sc->W.ensure(8 * T));
+    GM_HIP(sc->C.ensure(8 * T));
+    GM_HIP(sc->max_bits.ensure(8 * M));
+    GM_HIP(sc->scan_tmp.ensure(scan_tmp_bytes(T)));
+    GM_HIP(sc->counts.ensure(8 * M));
+    GM_HIP(sc->tbegin(kStageSample, s));
+    zero(sc->max_bits.p, 8 * (size_t)M, s);
+    launch_tri_area(sc->V.as<float>(), sc->I.as<int32_t>(), sc->tri_mesh.as<int32_t>(), T, sc->area.as<double>(),
+                    sc->max_bits.as<unsigned long long>(), s);
+    launch_lattice_count(sc->area.as<double>(), T, k, sc->W.as<unsigned long long>(), s);
+    launch_inclusive_scan_u64(sc->W.as<unsigned long long>(), sc->C.as<unsigned long long>(), T, sc->scan_tmp.p, s);
+    launch_lattice_mesh_counts(sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), M, sc->counts.as<int64_t>(), s);
+    GM_HIP(hipGetLastError());
+    GM_HIP(sc->tend(kStageSample, s));
+    counts.assign((size_t)M, 0);
+    GM_HIP(hipMemcpyAsync(counts.data(), sc->counts.p, 8 * (size_t)M, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    return GM_OK;
+}
+
 bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
 }  // namespace
@@ -182,6 +210,7 @@ gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int
     a.fix = w.fix.as<FixRec>();
     a.F = F;
     a.nodes = sc->nodes.as<BvhNode>();
+    a.node_stride = (int64_t)sc->bvh.nodes.size();
     a.tris = sc->tris.as<BvhTri>();
     a.tri_stride = (int64_t)sc->bvh.tris.size();
     a.occ_mode = (int32_t)mode;
@@ -290,7 +319,9 @@ gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** ou
     if (e == hipSuccess) e = up(sc->I, I.data(), I.size() * 4);
     if (e == hipSuccess) e = up(sc->tri_mesh, tm.data(), tm.size() * 4);
     if (e == hipSuccess) e = up(sc->tri_off_d, sc->tri_off.data(), sc->tri_off.size() * 8);
-    if (e == hipSuccess) e = up(sc->nodes, sc->bvh.nodes.data(), sc->bvh.nodes.size() * sizeof(BvhNode));
+    std::vector<BvhNode> node8;
+    octant_node_copies(sc->bvh.nodes, node8);
+    if (e == hipSuccess) e = up(sc->nodes, node8.data(), node8.size() * sizeof(BvhNode));
     std::vector<BvhTri> tri3;
     permute_tri_copies(sc->bvh.tris, tri3);
     if (e == hipSuccess) e = up(sc->tris, tri3.data(), tri3.size() * sizeof(BvhTri));
@@ -327,6 +358,44 @@ gm_status gm_scene_info(const gm_scene* sc, int64_t* n_triangles, int32_t* n_mes
             bbox[a] = sc->bvh.lo[a];
             bbox[3 + a] = sc->bvh.hi[a];
         }
+    return GM_OK;
+}
+
+gm_status gm_count_lattice_samples(gm_scene* sc, double k, int64_t* n_per_mesh, void* stream)
+{
+    gm::clear_error();
+    if (!sc || !n_per_mesh) return fail(GM_ERR_INVALID_ARGUMENT, "scene and n_per_mesh must not be NULL");
+    gm_status st = check_device(sc);
+    if (st != GM_OK) return st;
+    std::vector<int64_t> counts;
+    st = lattice_counts(sc, k, (hipStream_t)stream, counts);
+    if (st != GM_OK) return st;
+    std::memcpy(n_per_mesh, counts.data(), 8 * counts.size());
+    return GM_OK;
+}
+
+gm_status build_lattice_samples(gm_scene* sc, double k, int32_t* tri, int32_t* mesh, float* bary, float* pos,
+                                int64_t capacity, int64_t* n_out, void* stream)
+{
+    gm::clear_error();
+    if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
+    if (capacity < 0) return fail(GM_ERR_INVALID_ARGUMENT, "capacity < 0");
+    gm_status st = check_device(sc);
+    if (st != GM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> counts;
+    st = lattice_counts(sc, k, s, counts);
+    if (st != GM_OK) return st;
+    int64_t N = 0;
+    for (int64_t c : counts) N += c;
+    if (n_out) *n_out = N;
+    if (N > capacity) return fail(GM_ERR_CAPACITY, "%lld samples do not fit capacity %lld", (long long)N, (long long)capacity);
+    if (N >= (int64_t)1 << 31) return fail(GM_ERR_INVALID_ARGUMENT, "more than 2^31 - 1 samples");
+    GM_HIP(sc->tbegin(kStageSample, s));
+    launch_lattice_sample(sc->V.as<float>(), sc->I.as<int32_t>(), sc->tri_mesh.as<int32_t>(), sc->area.as<double>(),
+                          sc->C.as<unsigned long long>(), sc->T, N, k, tri, mesh, bary, pos, s);
+    GM_HIP(hipGetLastError());
+    GM_HIP(sc->tend(kStageSample, s));
     return GM_OK;
 }
 

@@ -44,6 +44,13 @@ constexpr int kLeafMax = 4;
 constexpr int kTriCopies = 3;
 void permute_tri_copies(const std::vector<BvhTri>& in, std::vector<BvhTri>& out);
 
+// The node array is stored eight times as well: in copy o, every axis a with bit a
+// of o set has its box bounds swapped (lo holds the upper bound, hi the lower), so a
+// wave whose segments all run towards -a along exactly those axes finds the near
+// plane of each slab in lo and the far plane in hi.  Copy 0 is the plain array.
+constexpr int kNodeCopies = 8;
+void octant_node_copies(const std::vector<BvhNode>& in, std::vector<BvhNode>& out);
+
 // Per-fixation record written by the prep kernel (32 bytes).
 struct alignas(16) FixRec {
     float ex, ey, ez;  // eye
@@ -76,6 +83,15 @@ void launch_mesh_scale(const unsigned long long* max_bits, const int64_t* tri_of
 // a1: fixed-point weights W_i = floor(A_i 2^S_m).
 void launch_tri_weight(const double* area, const int32_t* tri_mesh, const int32_t* S, int64_t T,
                        unsigned long long* W, hipStream_t s);
+// Lattice sampler: per-triangle point counts from the areas, per-mesh totals from
+// their inclusive scan C, and the points themselves.
+void launch_lattice_count(const double* area, int64_t T, double k, unsigned long long* cnt, hipStream_t s);
+void launch_lattice_mesh_counts(const unsigned long long* C, const int64_t* tri_off, int32_t M, int64_t* counts,
+                                hipStream_t s);
+void launch_lattice_sample(const float* V, const int32_t* I, const int32_t* tri_mesh, const double* area,
+                           const unsigned long long* C, int64_t T, int64_t N, double k, int32_t* tri, int32_t* mesh,
+                           float* bary, float* pos, hipStream_t s);
+
 // a2: inclusive prefix sum of uint64 over n (tmp: scan_tmp_bytes(n)).
 size_t scan_tmp_bytes(int64_t n);
 void launch_inclusive_scan_u64(const unsigned long long* in, unsigned long long* out, int64_t n, void* tmp,
@@ -99,7 +115,8 @@ struct DensityLaunch {
     int64_t n;
     const FixRec* fix;
     int32_t F;
-    const BvhNode* nodes;
+    const BvhNode* nodes;      // kNodeCopies octant copies
+    int64_t node_stride;       // nodes per copy
     const BvhTri* tris;        // kTriCopies permuted copies
     int64_t tri_stride;        // records per copy
     int32_t occ_mode;

@@ -123,7 +123,8 @@ __device__ __forceinline__ float pair_value(float x, float y, float z, float ex,
 struct Seg {
     float ix, iy, iz;  // 1 / direction (finite)
     float qx, qy, qz;  // -eye / direction
-    float sx, sy, sz;  // watertight shear: d[kx] / d[kz], d[ky] / d[kz], 1 / d[kz]
+    float sx, sy;      // watertight shear: d[kx] / d[kz], d[ky] / d[kz]
+    float tz;          // tmax * d[kz]
     int kx, ky, kz;    // axis order of the shear
 };
 
@@ -151,7 +152,7 @@ __device__ __forceinline__ void axis_order(float dx, float dy, float dz, int& kx
 
 // Segment eye -> point, sheared along the given axis order.
 __device__ __forceinline__ Seg make_seg(float ex, float ey, float ez, float px, float py, float pz, int kx, int ky,
-                                        int kz)
+                                        int kz, float tmax)
 {
     Seg s;
     const float dx = px - ex, dy = py - ey, dz = pz - ez;
@@ -161,8 +162,23 @@ __device__ __forceinline__ Seg make_seg(float ex, float ey, float ez, float px, 
     const float dkz = pick(kz, dx, dy, dz);
     s.sx = pick(kx, dx, dy, dz) / dkz;
     s.sy = pick(ky, dx, dy, dz) / dkz;
-    s.sz = 1.0f / dkz;
+    s.tz = tmax * dkz;
     return s;
+}
+
+// Slab test when every segment of the packet has the same direction signs: the
+// node copy of that octant stores each axis' near plane first, so no per-lane
+// min/max is needed.
+__device__ __forceinline__ bool box_hit_signed(const Seg& s, const float* near, const float* far, float tmax,
+                                               float& tnear)
+{
+    const float nx = __builtin_fmaf(near[0], s.ix, s.qx), fx = __builtin_fmaf(far[0], s.ix, s.qx);
+    const float ny = __builtin_fmaf(near[1], s.iy, s.qy), fy = __builtin_fmaf(far[1], s.iy, s.qy);
+    const float nz = __builtin_fmaf(near[2], s.iz, s.qz), fz = __builtin_fmaf(far[2], s.iz, s.qz);
+    const float tn = fmaxf(fmaxf(nx, ny), fmaxf(nz, 0.0f));
+    const float tf = fminf(fminf(fx, fy), fminf(fz, tmax));
+    tnear = tn;
+    return tn <= tf;
 }
 
 __device__ __forceinline__ bool box_hit(const Seg& s, const float* lo, const float* hi, float tmax, float& tnear)
@@ -199,7 +215,7 @@ __device__ __forceinline__ TriEye tri_eye(const BvhTri& t, float e0, float e1, f
 // the segment's axis order; otherwise they are in x, y, z order and each lane
 // permutes them.  Both windings count, so the order of kx and ky does not matter.
 template <bool UNI>
-__device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, float tmax, bool active)
+__device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, bool active)
 {
     float akx, aky, akz, bkx, bky, bkz, ckx, cky, ckz;
     if (UNI) {
@@ -230,10 +246,11 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, float tma
     }
     const bool mixed = (fminf(fminf(U, V), W) < 0.0f) & (fmaxf(fmaxf(U, V), W) > 0.0f);
     const float det = U + V + W;
-    const float T = U * (s.sz * akz) + V * (s.sz * bkz) + W * (s.sz * ckz);
-    // scale T by sign(det) so the range test reads as for det > 0
-    const float Ts = __uint_as_float(__float_as_uint(T) ^ (__float_as_uint(det) & 0x80000000u));
-    return !mixed & (det != 0.0f) & (Ts > 0.0f) & (Ts < tmax * fabsf(det));
+    // tau = T' / (det d[kz]) with T' = U akz + V bkz + W ckz: scale T' by the sign of
+    // det d[kz] so the range test reads 0 < T' < tmax |d[kz]| |det|
+    const float Tp = __builtin_fmaf(W, ckz, __builtin_fmaf(V, bkz, U * akz));
+    const float Ts = __uint_as_float(__float_as_uint(Tp) ^ ((__float_as_uint(det) ^ __float_as_uint(s.tz)) & 0x80000000u));
+    return !mixed & (det != 0.0f) & (Ts > 0.0f) & (Ts < fabsf(s.tz) * fabsf(det));
 }
 
 // Packet visibility.  Every lane carries up to R segments (R sample slots of the
@@ -244,12 +261,14 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, float tma
 // lane) and the stack is one VGPR, lane i holding entry i.  Per-lane predicates are
 // kept as 64-bit wave masks (scalar registers) rather than per-lane booleans.
 // `tris` is the record copy whose axis order matches (e0, e1, e2), the eye in that
-// order: with UNI the packet's shared order, otherwise copy 2 (x, y, z).
+// order: with UNI the packet's shared order, otherwise copy 2 (x, y, z).  With UNI
+// the packet's segments also share their direction signs and `nodes` is the node
+// copy of that octant; otherwise the plain copy.
 template <int R, bool UNI>
 __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, float e0,
-                                float e1, float e2, const Seg (&sg)[R], const int (&own_tri)[R],
-                                const int (&own_mesh)[R], int mode, float tmax, const bool (&active)[R],
-                                bool (&occ)[R], uint32_t& visits)
+                                float e1, float e2, const Seg (&sg)[R],
+                                const int (&own_tri)[R], const int (&own_mesh)[R], int mode, float tmax,
+                                const bool (&active)[R], bool (&occ)[R], uint32_t& visits)
 {
     const int lane = lane_id();
     uint64_t live[R], hit[R];
@@ -272,8 +291,13 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             float a, b;
-            h0[r] = ballot(box_hit(sg[r], nd.lo0, nd.hi0, tmax, a)) & live[r];
-            h1[r] = ballot(box_hit(sg[r], nd.lo1, nd.hi1, tmax, b)) & live[r];
+            if (UNI) {
+                h0[r] = ballot(box_hit_signed(sg[r], nd.lo0, nd.hi0, tmax, a)) & live[r];
+                h1[r] = ballot(box_hit_signed(sg[r], nd.lo1, nd.hi1, tmax, b)) & live[r];
+            } else {
+                h0[r] = ballot(box_hit(sg[r], nd.lo0, nd.hi0, tmax, a)) & live[r];
+                h1[r] = ballot(box_hit(sg[r], nd.lo1, nd.hi1, tmax, b)) & live[r];
+            }
             tn0 = __builtin_amdgcn_inverse_ballot_w64(h0[r]) ? fminf(tn0, a) : tn0;
             tn1 = __builtin_amdgcn_inverse_ballot_w64(h1[r]) ? fminf(tn1, b) : tn1;
             any0 |= h0[r];
@@ -294,10 +318,10 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
             if (child < 0) {
                 // all records of the leaf are fetched together (the array is padded so
                 // that kLeafMax records from any leaf start are in bounds)
-                const int t0 = ~child;
+                const BvhTri* leaf = tris + (~child);
                 BvhTri tr[kLeafMax];
 #pragma unroll
-                for (int k = 0; k < kLeafMax; ++k) tr[k] = load_tri(tris, t0 + k);
+                for (int k = 0; k < kLeafMax; ++k) tr[k] = load_tri(leaf, k);
 #pragma unroll
                 for (int k = 0; k < kLeafMax; ++k) {
                     if (k >= count) break;
@@ -305,8 +329,9 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
                     uint64_t tany = 0;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const bool skip = tr[k].id == own_tri[r] || (mode == 1 && tr[k].mesh != own_mesh[r]);
-                        tm[r] = (first ? h0[r] : h1[r]) & ~hit[r] & ~ballot(skip);
+                        uint64_t skip = ballot(tr[k].id == own_tri[r]);
+                        if (mode == 1) skip |= ballot(tr[k].mesh != own_mesh[r]);
+                        tm[r] = (first ? h0[r] : h1[r]) & ~hit[r] & ~skip;
                         tany |= tm[r];
                     }
                     if (tany == 0) continue;
@@ -315,7 +340,7 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
                     for (int r = 0; r < R; ++r) {
                         if (tm[r] == 0) continue;
                         const bool t = __builtin_amdgcn_inverse_ballot_w64(tm[r]);
-                        hit[r] |= ballot(seg_tri<UNI>(sg[r], u, tmax, t)) & tm[r];
+                        hit[r] |= ballot(seg_tri<UNI>(sg[r], u, t)) & tm[r];
                     }
                 }
                 alive = 0;
@@ -565,6 +590,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                 const int kx = kz == 2 ? 0 : kz + 1;
                 const int ky = kx == 2 ? 0 : kx + 1;
                 bool shared = true;
+                uint64_t need_m = 0, nx_m = 0, ny_m = 0, nz_m = 0;
                 int otri[SPL], omesh[SPL];
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
@@ -572,22 +598,32 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                     const float dx = p[k].x - fr.ex, dy = p[k].y - fr.ey, dz = p[k].z - fr.ez;
                     const float dk = pick(kz, dx, dy, dz);
                     shared = shared && (!need[k] || dk * dk >= 0.16f * (dx * dx + dy * dy + dz * dz));
+                    need_m |= ballot(need[k]);
+                    nx_m |= ballot(need[k] && signbit(dx));
+                    ny_m |= ballot(need[k] && signbit(dy));
+                    nz_m |= ballot(need[k] && signbit(dz));
                     otri[k] = need[k] ? __float_as_int(p[k].w) : -1;
                     omesh[k] = need[k] ? a.smesh[i] : -1;
                 }
+                // ... and the same direction signs along every axis
+                shared = ballot(!shared) == 0 && (nx_m == 0 || nx_m == need_m) && (ny_m == 0 || ny_m == need_m) &&
+                         (nz_m == 0 || nz_m == need_m);
                 Seg sg[SPL];
-                if (ballot(!shared) == 0) {
+                if (shared) {
 #pragma unroll
-                    for (int k = 0; k < SPL; ++k) sg[k] = make_seg(fr.ex, fr.ey, fr.ez, p[k].x, p[k].y, p[k].z, kx, ky, kz);
-                    occluded_packet<SPL, true>(a.nodes, a.tris + kz * a.tri_stride, pick(kx, fr.ex, fr.ey, fr.ez),
-                                               pick(ky, fr.ex, fr.ey, fr.ez), pick(kz, fr.ex, fr.ey, fr.ez), sg, otri,
-                                               omesh, a.occ_mode, a.tmax, need, occl, n_visits);
+                    for (int k = 0; k < SPL; ++k)
+                        sg[k] = make_seg(fr.ex, fr.ey, fr.ez, p[k].x, p[k].y, p[k].z, kx, ky, kz, a.tmax);
+                    const int oct = (nx_m != 0 ? 1 : 0) | (ny_m != 0 ? 2 : 0) | (nz_m != 0 ? 4 : 0);
+                    occluded_packet<SPL, true>(a.nodes + oct * a.node_stride, a.tris + kz * a.tri_stride,
+                                               pick(kx, fr.ex, fr.ey, fr.ez), pick(ky, fr.ex, fr.ey, fr.ez),
+                                               pick(kz, fr.ex, fr.ey, fr.ez), sg, otri, omesh, a.occ_mode, a.tmax,
+                                               need, occl, n_visits);
                 } else {
 #pragma unroll
                     for (int k = 0; k < SPL; ++k) {
                         int lx, ly, lz;
                         axis_order(p[k].x - fr.ex, p[k].y - fr.ey, p[k].z - fr.ez, lx, ly, lz);
-                        sg[k] = make_seg(fr.ex, fr.ey, fr.ez, p[k].x, p[k].y, p[k].z, lx, ly, lz);
+                        sg[k] = make_seg(fr.ex, fr.ey, fr.ez, p[k].x, p[k].y, p[k].z, lx, ly, lz, a.tmax);
                     }
                     occluded_packet<SPL, false>(a.nodes, a.tris + 2 * a.tri_stride, fr.ex, fr.ey, fr.ez, sg, otri,
                                                 omesh, a.occ_mode, a.tmax, need, occl, n_visits);
@@ -728,7 +764,7 @@ __global__ void __launch_bounds__(64) k_pair_visibility(const float* __restrict_
     const float px = pos[3 * s], py = pos[3 * s + 1], pz = pos[3 * s + 2];
     int kx, ky, kz;
     axis_order(px - ex, py - ey, pz - ez, kx, ky, kz);
-    const Seg sgs[1] = {make_seg(ex, ey, ez, px, py, pz, kx, ky, kz)};
+    const Seg sgs[1] = {make_seg(ex, ey, ez, px, py, pz, kx, ky, kz, tmax)};
     uint32_t visits = 0;
     const int ot[1] = {t}, om[1] = {me};
     const bool act[1] = {mode != 0 && lane == 0};

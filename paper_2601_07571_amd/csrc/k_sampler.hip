@@ -1,6 +1,6 @@
 // k_sampler.hip -- area weights, per-mesh counts and the area-weighted Philox
 // sampler (Sec. 3.1: sample density in samples per square metre, independent of
-// the triangulation).  Built with -ffp-contract=off: every FP64 expression below
+// the triangulation), and the paper's per-triangle lattice sampler.  Built with -ffp-contract=off: every FP64 expression below
 // is evaluated as written, one IEEE round-to-nearest operation at a time, so the
 // sample positions are reproducible bit for bit from the definition.
 #include <hip/hip_runtime.h>
@@ -152,6 +152,91 @@ k_sample(const float* __restrict__ V, const int32_t* __restrict__ I, const unsig
     }
 }
 
+// ---------------------------------------------------------------------------
+// The paper's lattice sampler (Sec. 3.1.1, Sec. 3.1.2): triangle t subdivided
+// at resolution r_t holds (r_t + 1)(r_t + 2) / 2 points (Eq. 1) whose
+// barycentrics are multiples of 1 / r_t, indexed row by row.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t lattice_points(int64_t r) { return (r + 1) * (r + 2) / 2; }
+
+// Eq. (4): Delta = (8 k) A + 1; r = 1 below Delta = 25, else the positive root
+// (sqrt(Delta) - 3) / 2 truncated to a whole resolution.
+__device__ __forceinline__ int64_t lattice_resolution(double k, double A)
+{
+    double delta = 8.0 * k;
+    delta = delta * A;
+    delta = delta + 1.0;
+    if (!(delta >= 25.0)) return 1;
+    return (int64_t)floor((sqrt(delta) - 3.0) / 2.0);
+}
+
+__global__ void k_lattice_count(const double* __restrict__ area, int64_t T, double k,
+                                unsigned long long* __restrict__ cnt)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= T) return;
+    cnt[t] = (unsigned long long)lattice_points(lattice_resolution(k, area[t]));
+}
+
+// One thread: per-mesh point totals from the inclusive scan of the counts.
+__global__ void k_lattice_mesh_counts(const unsigned long long* __restrict__ C, const int64_t* __restrict__ tri_off,
+                                      int32_t M, int64_t* __restrict__ counts)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int32_t m = 0; m < M; ++m) {
+        const int64_t a = tri_off[m], b = tri_off[m + 1];
+        counts[m] = b > a ? (int64_t)(C[b - 1] - (a > 0 ? C[a - 1] : 0ull)) : 0;
+    }
+}
+
+// Point i of the scene (mesh order, triangle order, then idx in the triangle).
+// Eq. (2): row = ceil((sqrt(8 idx + 9) - 3) / 2), corrected with integers to
+// f(row - 1) <= idx < f(row); col = idx - f(row - 1).  Eq. (3), completed to a
+// partition of unity: w1 = col / r, w2 = (r - row) / r, w3 = (row - col) / r;
+// P = (w1 v0 + w2 v1) + w3 v2 in FP64, rounded to FP32; bary = (w2, w3).
+__global__ void __launch_bounds__(kBlock)
+k_lattice_sample(const float* __restrict__ V, const int32_t* __restrict__ I, const int32_t* __restrict__ tri_mesh,
+                 const double* __restrict__ area, const unsigned long long* __restrict__ C, int64_t T, int64_t N,
+                 double k, int32_t* __restrict__ tri_out, int32_t* __restrict__ mesh_out,
+                 float* __restrict__ bary_out, float* __restrict__ pos_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    // triangle: the first with inclusive point count above i
+    int64_t l = 0, h = T - 1;
+    while (l < h) {
+        const int64_t mid = l + ((h - l) >> 1);
+        if (C[mid] > (unsigned long long)i) h = mid; else l = mid + 1;
+    }
+    const int64_t t = l;
+    const int64_t idx = i - (t > 0 ? (int64_t)C[t - 1] : 0);
+    const int64_t r = lattice_resolution(k, area[t]);
+    int64_t row = (int64_t)ceil((sqrt(8.0 * (double)idx + 9.0) - 3.0) / 2.0);
+    if (row < 0) row = 0;
+    while (lattice_points(row) <= idx) ++row;
+    while (row > 0 && lattice_points(row - 1) > idx) --row;
+    const int64_t col = idx - (row > 0 ? lattice_points(row - 1) : 0);
+    const double w1 = (double)col / (double)r;
+    const double w2 = (double)(r - row) / (double)r;
+    const double w3 = (double)(row - col) / (double)r;
+    const int32_t i0 = I[3 * t], i1 = I[3 * t + 1], i2 = I[3 * t + 2];
+    if (tri_out) tri_out[i] = (int32_t)t;
+    if (mesh_out) mesh_out[i] = tri_mesh[t];
+    if (bary_out) {
+        bary_out[2 * i] = (float)w2;
+        bary_out[2 * i + 1] = (float)w3;
+    }
+    if (pos_out) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double p = w1 * (double)V[3 * i0 + c];
+            p = p + w2 * (double)V[3 * i1 + c];
+            p = p + w3 * (double)V[3 * i2 + c];
+            pos_out[3 * i + c] = (float)p;
+        }
+    }
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -188,6 +273,25 @@ void launch_sample(const float* V, const int32_t* I, const unsigned long long* C
     if (N > 0)
         k_sample<<<grid_for(N), kBlock, 0, s>>>(V, I, C, tri_off, offsets, mesh_total, M, N, (uint32_t)seed,
                                                 (uint32_t)(seed >> 32), tri, mesh, bary, pos);
+}
+
+void launch_lattice_count(const double* area, int64_t T, double k, unsigned long long* cnt, hipStream_t s)
+{
+    if (T > 0) k_lattice_count<<<grid_for(T), kBlock, 0, s>>>(area, T, k, cnt);
+}
+
+void launch_lattice_mesh_counts(const unsigned long long* C, const int64_t* tri_off, int32_t M, int64_t* counts,
+                                hipStream_t s)
+{
+    k_lattice_mesh_counts<<<1, 1, 0, s>>>(C, tri_off, M, counts);
+}
+
+void launch_lattice_sample(const float* V, const int32_t* I, const int32_t* tri_mesh, const double* area,
+                           const unsigned long long* C, int64_t T, int64_t N, double k, int32_t* tri, int32_t* mesh,
+                           float* bary, float* pos, hipStream_t s)
+{
+    if (N > 0 && T > 0)
+        k_lattice_sample<<<grid_for(N), kBlock, 0, s>>>(V, I, tri_mesh, area, C, T, N, k, tri, mesh, bary, pos);
 }
 
 }  // namespace gm
