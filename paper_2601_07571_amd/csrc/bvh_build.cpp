@@ -17,7 +17,7 @@ namespace gm {
 namespace {
 
 constexpr int kBins = 16;
-constexpr int kMaxDepth = 60;
+constexpr int kMaxDepth = 40;  // the traversal stack holds one entry per level, 64 at most
 
 struct Box {
     float lo[3], hi[3];
@@ -98,8 +98,9 @@ struct Builder {
         return first;
     }
 
-    // split [b, e) at the returned index (b < mid < e)
-    int64_t split(int64_t b, int64_t e, int depth)
+    // split [b, e) at the returned index (b < mid < e); `split_axis` receives the axis
+    // along which the first part lies below the second (by centroid)
+    int64_t split(int64_t b, int64_t e, int depth, int& split_axis)
     {
         const int64_t n = e - b;
         Box cb;
@@ -111,7 +112,7 @@ struct Builder {
         const bool degenerate = !(cb.hi[axis] > cb.lo[axis]);
         // guarantee depth <= kMaxDepth: object median when the range is too large for the depth left
         const bool force_median =
-            degenerate || (depth >= kMaxDepth - 24 && n > ((int64_t)leaf_max << std::max(0, kMaxDepth - 1 - depth)));
+            degenerate || n > ((int64_t)leaf_max << std::min(40, std::max(0, kMaxDepth - 1 - depth)));
         if (!force_median) {
             double best = std::numeric_limits<double>::infinity();
             int best_axis = -1, best_bin = -1;
@@ -165,10 +166,14 @@ struct Builder {
                     return k < best_bin;
                 });
                 const int64_t mid = it - idx.begin();
-                if (mid > b && mid < e) return mid;
+                if (mid > b && mid < e) {
+                    split_axis = a;
+                    return mid;
+                }
             }
         }
         const int64_t mid = b + n / 2;
+        split_axis = axis;
         if (!degenerate) {
             std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e, [&](int32_t x, int32_t y) {
                 return cent[3 * (int64_t)x + axis] < cent[3 * (int64_t)y + axis];
@@ -183,7 +188,8 @@ struct Builder {
         const int32_t id = (int32_t)out->nodes.size();
         out->nodes.emplace_back();
         out->depth = std::max(out->depth, depth + 1);
-        const int64_t mid = split(b, e, depth);
+        int split_axis = 0;
+        const int64_t mid = split(b, e, depth, split_axis);
         const int64_t rb[2] = {b, mid}, re[2] = {mid, e};
         BvhNode nd;
         std::memset(&nd, 0, sizeof(nd));
@@ -205,6 +211,7 @@ struct Builder {
             if (c == 0) { nd.child0 = child; nd.count0 = count; }
             else { nd.child1 = child; nd.count1 = count; }
         }
+        nd.count0 |= split_axis << kSplitAxisShift;
         out->nodes[id] = nd;
         return id;
     }

@@ -20,8 +20,12 @@ struct alignas(16) BvhNode {
     float lo0[3], hi0[3];
     float lo1[3], hi1[3];
     int32_t child0, child1;
-    int32_t count0, count1;
+    int32_t count0, count1;  // leaf triangle counts; count0 also carries the split axis
 };
+// count0 = leaf count | split axis << kSplitAxisShift: child 0 holds the triangles
+// whose centroids lie lower along that axis.
+constexpr int kSplitAxisShift = 8;
+constexpr int kCountMask = (1 << kSplitAxisShift) - 1;
 static_assert(sizeof(BvhNode) == 64, "node is one 64-byte line");
 
 // Leaf triangle record, 48 bytes, in leaf order.

@@ -169,26 +169,23 @@ __device__ __forceinline__ Seg make_seg(float ex, float ey, float ez, float px, 
 // Slab test when every segment of the packet has the same direction signs: the
 // node copy of that octant stores each axis' near plane first, so no per-lane
 // min/max is needed.
-__device__ __forceinline__ bool box_hit_signed(const Seg& s, const float* near, const float* far, float tmax,
-                                               float& tnear)
+__device__ __forceinline__ bool box_hit_signed(const Seg& s, const float* near, const float* far, float tmax)
 {
     const float nx = __builtin_fmaf(near[0], s.ix, s.qx), fx = __builtin_fmaf(far[0], s.ix, s.qx);
     const float ny = __builtin_fmaf(near[1], s.iy, s.qy), fy = __builtin_fmaf(far[1], s.iy, s.qy);
     const float nz = __builtin_fmaf(near[2], s.iz, s.qz), fz = __builtin_fmaf(far[2], s.iz, s.qz);
     const float tn = fmaxf(fmaxf(nx, ny), fmaxf(nz, 0.0f));
     const float tf = fminf(fminf(fx, fy), fminf(fz, tmax));
-    tnear = tn;
     return tn <= tf;
 }
 
-__device__ __forceinline__ bool box_hit(const Seg& s, const float* lo, const float* hi, float tmax, float& tnear)
+__device__ __forceinline__ bool box_hit(const Seg& s, const float* lo, const float* hi, float tmax)
 {
     const float t0x = __builtin_fmaf(lo[0], s.ix, s.qx), t1x = __builtin_fmaf(hi[0], s.ix, s.qx);
     const float t0y = __builtin_fmaf(lo[1], s.iy, s.qy), t1y = __builtin_fmaf(hi[1], s.iy, s.qy);
     const float t0z = __builtin_fmaf(lo[2], s.iz, s.qz), t1z = __builtin_fmaf(hi[2], s.iz, s.qz);
     const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
     const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
-    tnear = tn;
     return tn <= tf;
 }
 
@@ -257,8 +254,8 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, bool acti
 // wave), all starting at the wave's eye; `active[r]` marks the segments to test and
 // occ[r] receives the answer.  One traversal serves all R * 64 segments: the node
 // index is wave-uniform (scalar loads), each lane tests its own segments against both
-// child boxes, children are visited near first (entry distance of the first live
-// lane) and the stack is one VGPR, lane i holding entry i.  Per-lane predicates are
+// child boxes, children are visited near first (by the node's split axis and the
+// packet's direction octant `oct`) and the stack is one VGPR, lane i holding entry i.  Per-lane predicates are
 // kept as 64-bit wave masks (scalar registers) rather than per-lane booleans.
 // `tris` is the record copy whose axis order matches (e0, e1, e2), the eye in that
 // order: with UNI the packet's shared order, otherwise copy 2 (x, y, z).  With UNI
@@ -266,7 +263,7 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, bool acti
 // copy of that octant; otherwise the plain copy.
 template <int R, bool UNI>
 __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, float e0,
-                                float e1, float e2, const Seg (&sg)[R],
+                                float e1, float e2, int oct, const Seg (&sg)[R],
                                 const int (&own_tri)[R], const int (&own_mesh)[R], int mode, float tmax,
                                 const bool (&active)[R], bool (&occ)[R], uint32_t& visits)
 {
@@ -287,34 +284,28 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
         ++visits;
         uint64_t h0[R], h1[R];
         uint64_t any0 = 0, any1 = 0;
-        float tn0 = 3.0e38f, tn1 = 3.0e38f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            float a, b;
             if (UNI) {
-                h0[r] = ballot(box_hit_signed(sg[r], nd.lo0, nd.hi0, tmax, a)) & live[r];
-                h1[r] = ballot(box_hit_signed(sg[r], nd.lo1, nd.hi1, tmax, b)) & live[r];
+                h0[r] = ballot(box_hit_signed(sg[r], nd.lo0, nd.hi0, tmax)) & live[r];
+                h1[r] = ballot(box_hit_signed(sg[r], nd.lo1, nd.hi1, tmax)) & live[r];
             } else {
-                h0[r] = ballot(box_hit(sg[r], nd.lo0, nd.hi0, tmax, a)) & live[r];
-                h1[r] = ballot(box_hit(sg[r], nd.lo1, nd.hi1, tmax, b)) & live[r];
+                h0[r] = ballot(box_hit(sg[r], nd.lo0, nd.hi0, tmax)) & live[r];
+                h1[r] = ballot(box_hit(sg[r], nd.lo1, nd.hi1, tmax)) & live[r];
             }
-            tn0 = __builtin_amdgcn_inverse_ballot_w64(h0[r]) ? fminf(tn0, a) : tn0;
-            tn1 = __builtin_amdgcn_inverse_ballot_w64(h1[r]) ? fminf(tn1, b) : tn1;
             any0 |= h0[r];
             any1 |= h1[r];
         }
-        // entry distances are >= 0, so their bit patterns order as the floats do
-        const int lead = __builtin_ctzll(alive);
-        const int l0 = __builtin_amdgcn_readlane(__float_as_int(tn0), lead);
-        const int l1 = __builtin_amdgcn_readlane(__float_as_int(tn1), lead);
-        const bool swap = l1 < l0;
+        // near child first: child 0 lies lower along the node's split axis, so it is
+        // the near one unless the packet runs towards -axis
+        const bool swap = (oct >> ((nd.count0 >> kSplitAxisShift) & 3)) & 1;
         int next = -1;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const bool first = (c == 0) != swap;  // c == 0: the near child
             if ((first ? any0 : any1) == 0) continue;
             const int child = first ? nd.child0 : nd.child1;
-            const int count = first ? nd.count0 : nd.count1;
+            const int count = (first ? nd.count0 : nd.count1) & kCountMask;
             if (child < 0) {
                 // all records of the leaf are fetched together (the array is padded so
                 // that kLeafMax records from any leaf start are in bounds)
@@ -590,7 +581,8 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                 const int kx = kz == 2 ? 0 : kz + 1;
                 const int ky = kx == 2 ? 0 : kx + 1;
                 bool shared = true;
-                uint64_t need_m = 0, nx_m = 0, ny_m = 0, nz_m = 0;
+                // per axis: lanes with a segment (any slot) running towards -axis / +axis
+                uint64_t nx_m = 0, ny_m = 0, nz_m = 0, px_m = 0, py_m = 0, pz_m = 0;
                 int otri[SPL], omesh[SPL];
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
@@ -598,16 +590,18 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                     const float dx = p[k].x - fr.ex, dy = p[k].y - fr.ey, dz = p[k].z - fr.ez;
                     const float dk = pick(kz, dx, dy, dz);
                     shared = shared && (!need[k] || dk * dk >= 0.16f * (dx * dx + dy * dy + dz * dz));
-                    need_m |= ballot(need[k]);
                     nx_m |= ballot(need[k] && signbit(dx));
                     ny_m |= ballot(need[k] && signbit(dy));
                     nz_m |= ballot(need[k] && signbit(dz));
+                    px_m |= ballot(need[k] && !signbit(dx));
+                    py_m |= ballot(need[k] && !signbit(dy));
+                    pz_m |= ballot(need[k] && !signbit(dz));
                     otri[k] = need[k] ? __float_as_int(p[k].w) : -1;
                     omesh[k] = need[k] ? a.smesh[i] : -1;
                 }
-                // ... and the same direction signs along every axis
-                shared = ballot(!shared) == 0 && (nx_m == 0 || nx_m == need_m) && (ny_m == 0 || ny_m == need_m) &&
-                         (nz_m == 0 || nz_m == need_m);
+                // ... and every segment of every slot has the same direction signs
+                shared = ballot(!shared) == 0 && (nx_m == 0 || px_m == 0) && (ny_m == 0 || py_m == 0) &&
+                         (nz_m == 0 || pz_m == 0);
                 Seg sg[SPL];
                 if (shared) {
 #pragma unroll
@@ -616,8 +610,8 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                     const int oct = (nx_m != 0 ? 1 : 0) | (ny_m != 0 ? 2 : 0) | (nz_m != 0 ? 4 : 0);
                     occluded_packet<SPL, true>(a.nodes + oct * a.node_stride, a.tris + kz * a.tri_stride,
                                                pick(kx, fr.ex, fr.ey, fr.ez), pick(ky, fr.ex, fr.ey, fr.ez),
-                                               pick(kz, fr.ex, fr.ey, fr.ez), sg, otri, omesh, a.occ_mode, a.tmax,
-                                               need, occl, n_visits);
+                                               pick(kz, fr.ex, fr.ey, fr.ez), oct, sg, otri, omesh, a.occ_mode,
+                                               a.tmax, need, occl, n_visits);
                 } else {
 #pragma unroll
                     for (int k = 0; k < SPL; ++k) {
@@ -625,8 +619,12 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                         axis_order(p[k].x - fr.ex, p[k].y - fr.ey, p[k].z - fr.ez, lx, ly, lz);
                         sg[k] = make_seg(fr.ex, fr.ey, fr.ez, p[k].x, p[k].y, p[k].z, lx, ly, lz, a.tmax);
                     }
-                    occluded_packet<SPL, false>(a.nodes, a.tris + 2 * a.tri_stride, fr.ex, fr.ey, fr.ez, sg, otri,
-                                                omesh, a.occ_mode, a.tmax, need, occl, n_visits);
+                    // child order from one lane's octant (the order affects speed, not results)
+                    const int lead = __builtin_ctzll(nx_m | px_m);
+                    const int oct = (int)((nx_m >> lead) & 1) | (int)(((ny_m >> lead) & 1) << 1) |
+                                    (int)(((nz_m >> lead) & 1) << 2);
+                    occluded_packet<SPL, false>(a.nodes, a.tris + 2 * a.tri_stride, fr.ex, fr.ey, fr.ez, oct, sg,
+                                                otri, omesh, a.occ_mode, a.tmax, need, occl, n_visits);
                 }
                 ++n_trav;
             }
@@ -769,7 +767,8 @@ __global__ void __launch_bounds__(64) k_pair_visibility(const float* __restrict_
     const int ot[1] = {t}, om[1] = {me};
     const bool act[1] = {mode != 0 && lane == 0};
     bool occ[1] = {false};
-    occluded_packet<1, false>(nodes, tris, ex, ey, ez, sgs, ot, om, mode, tmax, act, occ, visits);
+    const int oct = (signbit(px - ex) ? 1 : 0) | (signbit(py - ey) ? 2 : 0) | (signbit(pz - ez) ? 4 : 0);
+    occluded_packet<1, false>(nodes, tris, ex, ey, ez, oct, sgs, ot, om, mode, tmax, act, occ, visits);
     if (lane == 0) vis[i] = occ[0] ? 0 : 1;
 }
 

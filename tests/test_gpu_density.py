@@ -198,3 +198,37 @@ def test_eyes_close_to_surface(gm):
         assert ok.all(), f"theta {theta}: {(~ok).sum()} samples off"
         assert worst <= REL
         assert (ref.rho > 0).sum() > 1000
+
+
+@pytest.mark.parametrize("spl", [2, 4])
+def test_several_samples_per_lane(gm, tiny, spl, monkeypatch):
+    """Packets of 2 or 4 sample slots per lane: parity on the tiny scene with every
+    occlusion mode, and on the paper-shaped scene the same in-cone and visible pair
+    counts as one slot per lane (the visibility decision of a pair must not depend on
+    which slots share its packet)."""
+    import torch
+    w, meshes, _, s, fix, ref_s = tiny
+    monkeypatch.setenv("GM_SAMPLES_PER_LANE", str(spl))
+    scene = gm.Scene(meshes)
+    sc = oracle.Scene(meshes)
+    for occ, mode in (("none", oracle.OCC_NONE), ("self", oracle.OCC_SELF), ("full", oracle.OCC_FULL)):
+        out = scene.accumulate(s.pos, fix, w.theta_deg, occlusion=occ, tri=s.tri, mesh=s.mesh)
+        torch.cuda.synchronize()
+        ref = oracle.density(sc, ref_s.pos32, ref_s.tri, ref_s.mesh, w.fix.eye, w.fix.gaze, w.fix.dur, w.theta_deg,
+                             mode=mode)
+        ok, worst = _parity(out.density.cpu().numpy(), ref)
+        assert ok.all() and worst <= REL, (occ, int((~ok).sum()))
+
+    wp = workloads.paper_shaped_scene()
+    big = [(m.V, m.I) for m in wp.meshes]
+    fixp = gm.Fixations(wp.fix.eye, wp.fix.gaze, wp.fix.dur)
+    counts = []
+    for n in (1, spl):
+        monkeypatch.setenv("GM_SAMPLES_PER_LANE", str(n))
+        sp = gm.Scene(big)
+        smp = sp.build_samples(204240.0, wp.seed)
+        sp.accumulate(smp.pos, fixp, wp.theta_deg, occlusion="full", tri=smp.tri, mesh=smp.mesh)
+        torch.cuda.synchronize()
+        counts.append(sp.density_stats())
+    assert counts[0]["in_cone"] == counts[1]["in_cone"]
+    assert abs(counts[0]["visible"] - counts[1]["visible"]) <= 1e-5 * counts[0]["in_cone"]
