@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity_util
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -121,7 +122,8 @@ def test_paper_shaped_sampled_parity(gm):
     sc = oracle.Scene(meshes)
     ref = oracle.density(sc, pos, tri, mesh, w.fix.eye, w.fix.gaze, w.fix.dur, w.theta_deg, mode=oracle.OCC_FULL)
     ok, worst = _parity(d[pick], ref)
-    assert ok.all(), f"{(~ok).sum()} of {len(pick)} samples outside tolerance"
+    parity_util.check(gm, scene, meshes, pos, tri, mesh, w.fix.eye, w.fix.gaze, w.fix.dur, w.theta_deg,
+                      oracle.OCC_FULL, d[pick], ref)
     assert worst <= REL
     assert (ref.rho > 0).mean() > 0.2
     dn = out.density_norm.cpu().numpy()
