@@ -223,34 +223,40 @@ typedef struct {
 
 #define GM_FIELD_PARAMS 18753
 
-/* gm_field_create: a field over the scene's bounding cube with He-uniform weights
- * drawn from `seed` (zero biases); every mesh gate closed until trained.  The band
- * frequencies are f_b = max_cycles^(b / 15) cycles per cube edge, b = 0..15
+/* gm_field_create: one network per mesh, network m over mesh m's bounding cube
+ * (corner at the box's lower corner, edge = its largest side), He-uniform weights
+ * drawn from `seed` and m (zero biases); every mesh gate closed until trained.  The
+ * band frequencies are f_b = max_cycles^(b / 15) cycles per cube edge, b = 0..15
  * (max_cycles <= 0: 32).  Blocking. */
 gm_status gm_field_create(gm_scene* scene, uint64_t seed, double max_cycles, gm_field** out);
 gm_status gm_field_destroy(gm_field* field);
-/* host float [GM_FIELD_PARAMS] in, out (blocking) */
+/* host float [n_meshes][GM_FIELD_PARAMS] in, out (blocking) */
 gm_status gm_field_set_params(gm_field* field, const float* params);
 gm_status gm_field_get_params(gm_field* field, float* params);
 /*
  * gm_field_train: pos [n][3], mesh [n] (mesh of each point, device) and target [n]
- * (device, the normalised density in [0, 1]).  Runs `steps` Adam steps of mean
- * squared error on the training split, then evaluates every mesh's relative L2
- * error sqrt(sum (y - t)^2 / sum t^2) on its held-out points and opens the gate of
- * the meshes at or below max_rel_l2.  Blocking.
+ * (device, the normalised density in [0, 1]).  For every mesh, runs `steps` Adam
+ * steps of mean squared error of its network on its points of the training split,
+ * then evaluates the mesh's relative L2 error sqrt(sum (y - t)^2 / sum t^2) on its
+ * held-out points and opens the gate of the meshes at or below max_rel_l2.
+ * Blocking.
  */
 gm_status gm_field_train(gm_field* field, const float* pos, const int32_t* mesh, const float* target,
                          int64_t n, const gm_train_params* params, void* stream);
 /* host outputs (each may be NULL): rel_l2 [n_meshes] (NaN where a mesh had no held-out
  * point), gate [n_meshes] (1 = field answers), final training loss, steps done. */
 gm_status gm_field_info(gm_field* field, float* rel_l2, uint8_t* gate, double* loss, int64_t* steps);
-/* The field's value (softplus output) at q points, device pos [q][3] -> out [q], whatever
- * the gates say; queued on `stream`. */
-gm_status gm_field_predict(gm_field* field, const float* pos, int64_t q, float* out, void* stream);
-/* One forward and backward pass over all n points (no update): the mean-squared-error
- * gradient (host float [GM_FIELD_PARAMS]) and loss.  Blocking.  For gradient checks. */
-gm_status gm_field_gradient(gm_field* field, const float* pos, const float* target, int64_t n, float* grad,
-                            double* loss);
+/* The field's value (softplus output) at q points, device pos [q][3] -> out [q], each
+ * point by the network of its mesh (device mesh [q]; may be NULL for a one-mesh
+ * scene), whatever the gates say; points of no mesh are left untouched; queued on
+ * `stream`. */
+gm_status gm_field_predict(gm_field* field, const float* pos, const int32_t* mesh, int64_t q, float* out,
+                           void* stream);
+/* One forward and backward pass of network `net` over all n points (no update): the
+ * mean-squared-error gradient (host float [GM_FIELD_PARAMS]) and loss.  Blocking.  For
+ * gradient checks. */
+gm_status gm_field_gradient(gm_field* field, int32_t net, const float* pos, const float* target, int64_t n,
+                            float* grad, double* loss);
 
 /*
  * query_density -- the normalised density at q query points (device pos [q][3];

@@ -99,8 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.gm_field_train.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(_TrainParams), vp]
     lib.gm_field_info.argtypes = [vp, f32p, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(dbl),
                                   ctypes.POINTER(i64)]
-    lib.gm_field_gradient.argtypes = [vp, vp, vp, i64, f32p, ctypes.POINTER(dbl)]
-    lib.gm_field_predict.argtypes = [vp, vp, i64, vp, vp]
+    lib.gm_field_gradient.argtypes = [vp, i32, vp, vp, i64, f32p, ctypes.POINTER(dbl)]
+    lib.gm_field_predict.argtypes = [vp, vp, vp, i64, vp, vp]
     lib.gm_batch_create.argtypes = [ctypes.POINTER(_Session), i32, ctypes.c_char_p, i32, ctypes.POINTER(vp), vp]
     lib.gm_batch_run.argtypes = [vp, vp]
     lib.gm_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -319,7 +319,8 @@ def pair_values(pos, fix: Fixations, theta_deg, pair_s, pair_f):
 
 
 class Field:
-    """Neural density field over a scene (see include/gazemap.h)."""
+    """Neural density field over a scene, one network per mesh (see include/gazemap.h).
+    Parameters are [n_meshes][FIELD_PARAMS] (flat when the scene has one mesh)."""
 
     def __init__(self, scene: Scene, seed=0, max_cycles=32.0):
         lib = load_library()
@@ -338,31 +339,34 @@ class Field:
         self.close()
 
     def set_params(self, params):
-        p = np.ascontiguousarray(params, np.float32)
-        assert p.size == FIELD_PARAMS
+        M = self.scene.n_meshes
+        p = np.ascontiguousarray(params, np.float32).reshape(-1)
+        assert p.size == M * FIELD_PARAMS
         _check(_lib.gm_field_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
 
     def get_params(self):
-        p = np.zeros(FIELD_PARAMS, np.float32)
+        M = self.scene.n_meshes
+        p = np.zeros(M * FIELD_PARAMS, np.float32)
         _check(_lib.gm_field_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
-        return p
+        return p if M == 1 else p.reshape(M, FIELD_PARAMS)
 
-    def predict(self, pos, out=None):
+    def predict(self, pos, mesh=None, out=None):
         torch = _torch()
         pos = _dev(pos, torch.float32, 3)
+        mesh = _dev(mesh, torch.int32)
         q = int(pos.shape[0])
         if out is None:
             out = torch.empty(q, dtype=torch.float32, device="cuda")
-        _check(_lib.gm_field_predict(self._h, _ptr(pos), q, _ptr(out), _stream()))
+        _check(_lib.gm_field_predict(self._h, _ptr(pos), _ptr(mesh), q, _ptr(out), _stream()))
         return out
 
-    def gradient(self, pos, target):
+    def gradient(self, pos, target, net=0):
         torch = _torch()
         pos = _dev(pos, torch.float32, 3)
         target = _dev(target, torch.float32).reshape(-1)
         g = np.zeros(FIELD_PARAMS, np.float32)
         loss = ctypes.c_double(0.0)
-        _check(_lib.gm_field_gradient(self._h, _ptr(pos), _ptr(target), int(pos.shape[0]),
+        _check(_lib.gm_field_gradient(self._h, int(net), _ptr(pos), _ptr(target), int(pos.shape[0]),
                                       g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss)))
         return g, loss.value
 

@@ -14,11 +14,14 @@
 
 using namespace gm;
 
+// One network per mesh, each over its mesh's bounding cube; parameter arrays hold
+// the M networks one after the other.
 struct gm_field {
     gm_scene* scene = nullptr;
-    FieldGeom geom;
+    int32_t M = 0;
+    std::vector<FieldGeom> geom;  // [M]
     DevBuf master, m, v, grad, blob, loss;
-    DevBuf flag, offs, idx, scan_tmp, pred, l2sums;
+    DevBuf flag, sel, offs, idx, scan_tmp, pred, l2sums;
     DevBuf gate_d, need, qoffs, qscan, gpos, gtri, gmesh, gidx, grho, gnorm;
     std::vector<float> rel_l2;
     std::vector<uint8_t> gate;
@@ -29,7 +32,7 @@ struct gm_field {
 
     ~gm_field()
     {
-        for (DevBuf* b : {&master, &m, &v, &grad, &blob, &loss, &flag, &offs, &idx, &scan_tmp, &pred, &l2sums,
+        for (DevBuf* b : {&master, &m, &v, &grad, &blob, &loss, &flag, &sel, &offs, &idx, &scan_tmp, &pred, &l2sums,
                           &gate_d, &need, &qoffs, &qscan, &gpos, &gtri, &gmesh, &gidx, &grho, &gnorm})
             b->release();
     }
@@ -60,14 +63,19 @@ void init_params(uint64_t seed, std::vector<float>& p)
     for (int i = 0; i < kFieldWidth; ++i) p[(size_t)(kFieldOffW5 + i)] = uni(lim5);
 }
 
+float* net_master(gm_field* f, int m) { return f->master.as<float>() + (size_t)m * kFieldParams; }
+unsigned char* net_blob(gm_field* f, int m) { return f->blob.as<unsigned char>() + (size_t)m * field_pack_bytes(); }
+
 gm_status upload_params(gm_field* f, const float* host, hipStream_t s)
 {
-    GM_HIP(hipMemcpyAsync(f->master.p, host, sizeof(float) * kFieldParams, hipMemcpyHostToDevice, s));
-    launch_field_pack(f->master.as<float>(), f->blob.as<unsigned char>(), s);
+    GM_HIP(hipMemcpyAsync(f->master.p, host, sizeof(float) * kFieldParams * (size_t)f->M, hipMemcpyHostToDevice, s));
+    for (int m = 0; m < f->M; ++m) launch_field_pack(net_master(f, m), net_blob(f, m), s);
     GM_HIP(hipGetLastError());
     GM_HIP(hipStreamSynchronize(s));
     return GM_OK;
 }
+
+FieldRoute route_all() { return FieldRoute{nullptr, nullptr, nullptr, 0, -1}; }
 
 }  // namespace
 
@@ -83,36 +91,58 @@ gm_status gm_field_create(gm_scene* scene, uint64_t seed, double max_cycles, gm_
     gm_field* f = new (std::nothrow) gm_field();
     if (!f) return fail(GM_ERR_OUT_OF_MEMORY, "host allocation failed");
     f->scene = scene;
-    float ext = 0.0f;
-    for (int a = 0; a < 3; ++a) {
-        f->geom.lo[a] = scene->bvh.lo[a];
-        ext = std::max(ext, scene->bvh.hi[a] - scene->bvh.lo[a]);
+    f->M = scene->M;
+    // each mesh's bounding box, from the triangle records (vertices in x, y, z order)
+    std::vector<float> blo((size_t)(3 * f->M), INFINITY), bhi((size_t)(3 * f->M), -INFINITY);
+    for (const BvhTri& r : scene->bvh.tris) {
+        if (r.mesh < 0 || r.mesh >= f->M) continue;
+        for (int a = 0; a < 3; ++a) {
+            const float c[3] = {r.v0[a], r.v1[a], r.v2[a]};
+            for (float x : c) {
+                blo[(size_t)(3 * r.mesh + a)] = std::min(blo[(size_t)(3 * r.mesh + a)], x);
+                bhi[(size_t)(3 * r.mesh + a)] = std::max(bhi[(size_t)(3 * r.mesh + a)], x);
+            }
+        }
     }
-    f->geom.inv_ext = ext > 0.0f ? 1.0f / ext : 1.0f;
     if (!(max_cycles > 0.0) || !std::isfinite(max_cycles)) max_cycles = 32.0;
-    for (int b = 0; b < kFieldBands; ++b)
-        f->geom.freq[b] = (float)std::pow(max_cycles, (double)b / (double)(kFieldBands - 1));
+    f->geom.resize((size_t)f->M);
+    for (int m = 0; m < f->M; ++m) {
+        FieldGeom& g = f->geom[(size_t)m];
+        float ext = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            const bool any = blo[(size_t)(3 * m + a)] <= bhi[(size_t)(3 * m + a)];
+            g.lo[a] = any ? blo[(size_t)(3 * m + a)] : 0.0f;
+            if (any) ext = std::max(ext, bhi[(size_t)(3 * m + a)] - blo[(size_t)(3 * m + a)]);
+        }
+        g.inv_ext = ext > 0.0f ? 1.0f / ext : 1.0f;
+        for (int b = 0; b < kFieldBands; ++b)
+            g.freq[b] = (float)std::pow(max_cycles, (double)b / (double)(kFieldBands - 1));
+    }
     f->rel_l2.assign((size_t)scene->M, NAN);
     f->gate.assign((size_t)scene->M, 0);
     hipError_t e = hipSuccess;
+    const size_t np = (size_t)kFieldParams * (size_t)f->M;
     for (DevBuf* b : {&f->master, &f->m, &f->v, &f->grad})
-        if (e == hipSuccess) e = b->ensure(sizeof(float) * kFieldParams);
-    if (e == hipSuccess) e = f->blob.ensure(field_pack_bytes());
+        if (e == hipSuccess) e = b->ensure(sizeof(float) * np);
+    if (e == hipSuccess) e = f->blob.ensure(field_pack_bytes() * (size_t)f->M);
     if (e == hipSuccess) e = f->loss.ensure(sizeof(double));
     if (e != hipSuccess) {
         delete f;
         return fail(GM_ERR_OUT_OF_MEMORY, "field allocation: %s", hipGetErrorString(e));
     }
-    std::vector<float> p;
-    init_params(seed, p);
-    st = upload_params(f, p.data(), nullptr);
+    std::vector<float> p, all;
+    for (int m = 0; m < f->M; ++m) {
+        init_params(seed + 0x9E3779B97F4A7C15ull * (uint64_t)m, p);
+        all.insert(all.end(), p.begin(), p.end());
+    }
+    st = upload_params(f, all.data(), nullptr);
     if (st != GM_OK) {
         delete f;
         return st;
     }
-    zero(f->m.p, sizeof(float) * kFieldParams, nullptr);
-    zero(f->v.p, sizeof(float) * kFieldParams, nullptr);
-    zero(f->grad.p, sizeof(float) * kFieldParams, nullptr);
+    zero(f->m.p, sizeof(float) * np, nullptr);
+    zero(f->v.p, sizeof(float) * np, nullptr);
+    zero(f->grad.p, sizeof(float) * np, nullptr);
     if (hipStreamSynchronize(nullptr) != hipSuccess) {
         delete f;
         return fail(GM_ERR_DEVICE, "field initialisation failed");
@@ -135,8 +165,8 @@ gm_status gm_field_set_params(gm_field* f, const float* params)
 {
     clear_error();
     if (!f || !params) return fail(GM_ERR_INVALID_ARGUMENT, "field and params must not be NULL");
-    for (int i = 0; i < kFieldParams; ++i)
-        if (!std::isfinite(params[i])) return fail(GM_ERR_INVALID_ARGUMENT, "parameter %d is not finite", i);
+    for (int64_t i = 0; i < (int64_t)kFieldParams * f->M; ++i)
+        if (!std::isfinite(params[i])) return fail(GM_ERR_INVALID_ARGUMENT, "parameter %lld is not finite", (long long)i);
     return upload_params(f, params, nullptr);
 }
 
@@ -145,19 +175,22 @@ gm_status gm_field_get_params(gm_field* f, float* params)
     clear_error();
     if (!f || !params) return fail(GM_ERR_INVALID_ARGUMENT, "field and params must not be NULL");
     GM_HIP(hipDeviceSynchronize());
-    GM_HIP(hipMemcpy(params, f->master.p, sizeof(float) * kFieldParams, hipMemcpyDeviceToHost));
+    GM_HIP(hipMemcpy(params, f->master.p, sizeof(float) * kFieldParams * (size_t)f->M, hipMemcpyDeviceToHost));
     return GM_OK;
 }
 
-gm_status gm_field_gradient(gm_field* f, const float* pos, const float* target, int64_t n, float* grad, double* loss)
+gm_status gm_field_gradient(gm_field* f, int32_t net, const float* pos, const float* target, int64_t n, float* grad,
+                            double* loss)
 {
     clear_error();
     if (!f || !pos || !target || !grad || n <= 0 || n > (1 << 30))
         return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or n outside (0, 2^30]");
+    if (net < 0 || net >= f->M) return fail(GM_ERR_INVALID_ARGUMENT, "network %d outside [0, %d)", net, f->M);
     gm_status st = check_device(f->scene);
     if (st != GM_OK) return st;
     hipStream_t s = nullptr;
-    zero(f->grad.p, sizeof(float) * kFieldParams, s);
+    float* gnet = f->grad.as<float>() + (size_t)net * kFieldParams;
+    zero(gnet, sizeof(float) * kFieldParams, s);
     zero(f->loss.p, sizeof(double), s);
     FieldTrain t;
     t.pos = pos;
@@ -168,14 +201,14 @@ gm_status gm_field_gradient(gm_field* f, const float* pos, const float* target, 
     t.inv_batch = (float)(1.0 / (double)n);
     t.key0 = t.key1 = 0;
     t.step = 0;
-    t.grad = f->grad.as<float>();
+    t.grad = gnet;
     t.loss = f->loss.as<double>();
-    launch_field_train(f->blob.as<unsigned char>(), f->geom, t, s);
+    launch_field_train(net_blob(f, net), f->geom[(size_t)net], t, s);
     GM_HIP(hipGetLastError());
     double l = 0.0;
-    GM_HIP(hipMemcpy(grad, f->grad.p, sizeof(float) * kFieldParams, hipMemcpyDeviceToHost));
+    GM_HIP(hipMemcpy(grad, gnet, sizeof(float) * kFieldParams, hipMemcpyDeviceToHost));
     GM_HIP(hipMemcpy(&l, f->loss.p, sizeof(double), hipMemcpyDeviceToHost));
-    zero(f->grad.p, sizeof(float) * kFieldParams, s);
+    zero(gnet, sizeof(float) * kFieldParams, s);
     GM_HIP(hipStreamSynchronize(s));
     if (loss) *loss = l / (double)n;
     return GM_OK;
@@ -196,65 +229,86 @@ gm_status gm_field_train(gm_field* f, const float* pos, const int32_t* mesh, con
     hipStream_t s = (hipStream_t)stream;
     const int32_t M = f->scene->M;
     GM_HIP(f->flag.ensure(4 * (size_t)n));
+    GM_HIP(f->sel.ensure(4 * (size_t)n));
     GM_HIP(f->offs.ensure(4 * (size_t)n));
     GM_HIP(f->idx.ensure(4 * (size_t)n));
     GM_HIP(f->scan_tmp.ensure(scan_tmp_bytes(n)));
     GM_HIP(f->pred.ensure(4 * (size_t)n));
     GM_HIP(f->l2sums.ensure(16 * (size_t)M));
 
-    // held-out split and the compact list of training points
+    // held-out split (one Philox draw per point, for every network)
     const uint32_t key0 = (uint32_t)P->seed, key1 = (uint32_t)(P->seed >> 32);
     const uint32_t thr = (uint32_t)std::min(4294967295.0, std::floor((double)P->holdout * 4294967296.0));
     launch_field_split(n, key0, key1, thr, f->flag.as<uint32_t>(), s);
-    launch_exclusive_scan_u32(f->flag.as<uint32_t>(), f->offs.as<uint32_t>(), n, f->scan_tmp.p, s);
-    launch_field_compact(f->flag.as<uint32_t>(), f->offs.as<uint32_t>(), n, f->idx.as<int32_t>(), s);
-    uint32_t last_off = 0, last_flag = 0;
-    GM_HIP(hipMemcpyAsync(&last_off, f->offs.as<uint32_t>() + (n - 1), 4, hipMemcpyDeviceToHost, s));
-    GM_HIP(hipMemcpyAsync(&last_flag, f->flag.as<uint32_t>() + (n - 1), 4, hipMemcpyDeviceToHost, s));
-    GM_HIP(hipStreamSynchronize(s));
-    const int64_t n_train = (int64_t)last_off + last_flag;
-    if (n_train < 1) return fail(GM_ERR_INVALID_ARGUMENT, "no training points after the held-out split");
+    const size_t np = (size_t)kFieldParams * (size_t)M;
+    zero(f->m.p, sizeof(float) * np, s);
+    zero(f->v.p, sizeof(float) * np, s);
+    zero(f->grad.p, sizeof(float) * np, s);
+    zero(f->pred.p, 4 * (size_t)n, s);
+    double last = NAN;
+    std::vector<uint8_t> has_train((size_t)M, 0);
+    for (int32_t net = 0; net < M; ++net) {
+        // this mesh's training points, compacted
+        launch_field_select(f->flag.as<uint32_t>(), mesh, net, n, f->sel.as<uint32_t>(), s);
+        launch_exclusive_scan_u32(f->sel.as<uint32_t>(), f->offs.as<uint32_t>(), n, f->scan_tmp.p, s);
+        launch_field_compact(f->sel.as<uint32_t>(), f->offs.as<uint32_t>(), n, f->idx.as<int32_t>(), s);
+        uint32_t last_off = 0, last_sel = 0;
+        GM_HIP(hipMemcpyAsync(&last_off, f->offs.as<uint32_t>() + (n - 1), 4, hipMemcpyDeviceToHost, s));
+        GM_HIP(hipMemcpyAsync(&last_sel, f->sel.as<uint32_t>() + (n - 1), 4, hipMemcpyDeviceToHost, s));
+        GM_HIP(hipStreamSynchronize(s));
+        const int64_t n_train = (int64_t)last_off + last_sel;
+        if (n_train < 1) continue;  // a mesh without training points keeps its gate closed
+        has_train[(size_t)net] = 1;
 
-    zero(f->m.p, sizeof(float) * kFieldParams, s);
-    zero(f->v.p, sizeof(float) * kFieldParams, s);
-    zero(f->grad.p, sizeof(float) * kFieldParams, s);
-    FieldTrain t;
-    t.pos = pos;
-    t.target = target;
-    t.idx = f->idx.as<int32_t>();
-    t.n_idx = n_train;
-    t.batch = P->batch;
-    t.inv_batch = 1.0f / (float)P->batch;
-    t.key0 = key0 ^ 0x5bd1e995u;
-    t.key1 = key1 ^ 0x1b873593u;
-    t.grad = f->grad.as<float>();
-    t.loss = f->loss.as<double>();
-    double b1t = 1.0, b2t = 1.0;
-    for (int32_t it = 0; it < P->steps; ++it) {
-        t.step = (uint32_t)it;
-        zero(f->loss.p, sizeof(double), s);
-        launch_field_train(f->blob.as<unsigned char>(), f->geom, t, s);
-        b1t *= P->beta1;
-        b2t *= P->beta2;
-        const double frac = P->steps > 1 ? (double)it / (double)(P->steps - 1) : 1.0;
-        const double lr = P->lr_final + 0.5 * (P->lr - P->lr_final) * (1.0 + std::cos(M_PI * frac));
-        launch_field_adam(f->master.as<float>(), f->m.as<float>(), f->v.as<float>(), f->grad.as<float>(), (float)lr,
-                          P->beta1, P->beta2, P->eps, (float)(1.0 / (1.0 - b1t)), (float)(1.0 / (1.0 - b2t)), s);
-        launch_field_pack(f->master.as<float>(), f->blob.as<unsigned char>(), s);
+        float* master = net_master(f, net);
+        float* mom = f->m.as<float>() + (size_t)net * kFieldParams;
+        float* vel = f->v.as<float>() + (size_t)net * kFieldParams;
+        float* gr = f->grad.as<float>() + (size_t)net * kFieldParams;
+        unsigned char* blob = net_blob(f, net);
+        FieldTrain t;
+        t.pos = pos;
+        t.target = target;
+        t.idx = f->idx.as<int32_t>();
+        t.n_idx = n_train;
+        t.batch = P->batch;
+        t.inv_batch = 1.0f / (float)P->batch;
+        t.key0 = key0 ^ 0x5bd1e995u ^ (uint32_t)net;
+        t.key1 = key1 ^ 0x1b873593u;
+        t.grad = gr;
+        t.loss = f->loss.as<double>();
+        double b1t = 1.0, b2t = 1.0;
+        for (int32_t it = 0; it < P->steps; ++it) {
+            t.step = (uint32_t)it;
+            zero(f->loss.p, sizeof(double), s);
+            launch_field_train(blob, f->geom[(size_t)net], t, s);
+            b1t *= P->beta1;
+            b2t *= P->beta2;
+            const double frac = P->steps > 1 ? (double)it / (double)(P->steps - 1) : 1.0;
+            const double lr = P->lr_final + 0.5 * (P->lr - P->lr_final) * (1.0 + std::cos(M_PI * frac));
+            launch_field_adam(master, mom, vel, gr, (float)lr, P->beta1, P->beta2, P->eps, (float)(1.0 / (1.0 - b1t)),
+                              (float)(1.0 / (1.0 - b2t)), s);
+            launch_field_pack(master, blob, s);
+        }
+        GM_HIP(hipGetLastError());
+        if (P->steps > 0) {
+            double l = NAN;
+            GM_HIP(hipMemcpyAsync(&l, f->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+            GM_HIP(hipStreamSynchronize(s));
+            last = std::isnan(last) ? l : std::max(last, l);
+        }
+        // this network's values at its mesh's points, for the held-out error
+        launch_field_infer(blob, f->geom[(size_t)net], pos, n, f->pred.as<float>(),
+                           FieldRoute{mesh, nullptr, nullptr, 0, net}, s);
     }
-    GM_HIP(hipGetLastError());
-    double l = NAN;
-    if (P->steps > 0) GM_HIP(hipMemcpyAsync(&l, f->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
 
     // held-out relative L2 per mesh
-    launch_field_infer(f->blob.as<unsigned char>(), f->geom, pos, n, f->pred.as<float>(), s);
     zero(f->l2sums.p, 16 * (size_t)M, s);
     launch_field_l2(f->pred.as<float>(), target, mesh, f->flag.as<uint32_t>(), n, M, f->l2sums.as<double>(), s);
     GM_HIP(hipGetLastError());
     std::vector<double> sums((size_t)(2 * M));
     GM_HIP(hipMemcpyAsync(sums.data(), f->l2sums.p, 16 * (size_t)M, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
-    f->last_loss = P->steps > 0 ? l / (double)P->batch : NAN;
+    f->last_loss = P->steps > 0 ? last / (double)P->batch : NAN;
     f->steps = P->steps;
     f->norm_max = P->target_max;
     f->trained = true;
@@ -264,21 +318,30 @@ gm_status gm_field_train(gm_field* f, const float* pos, const int32_t* mesh, con
         if (t2 > 0.0) rel = std::sqrt(d2 / t2);
         else if (d2 == 0.0 && t2 == 0.0) rel = NAN;  // no held-out point of this mesh
         f->rel_l2[(size_t)m] = (float)rel;
-        f->gate[(size_t)m] = (std::isfinite(rel) && rel <= P->max_rel_l2 && std::isfinite(f->last_loss)) ? 1 : 0;
+        f->gate[(size_t)m] =
+            (has_train[(size_t)m] && std::isfinite(rel) && rel <= P->max_rel_l2 && std::isfinite(f->last_loss)) ? 1 : 0;
     }
     GM_HIP(f->gate_d.ensure((size_t)M));
     GM_HIP(hipMemcpy(f->gate_d.p, f->gate.data(), (size_t)M, hipMemcpyHostToDevice));
     return GM_OK;
 }
 
-gm_status gm_field_predict(gm_field* f, const float* pos, int64_t q, float* out, void* stream)
+gm_status gm_field_predict(gm_field* f, const float* pos, const int32_t* mesh, int64_t q, float* out, void* stream)
 {
     clear_error();
     if (!f || q < 0 || q >= ((int64_t)1 << 31) || (q > 0 && (!pos || !out)))
         return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or q outside [0, 2^31)");
+    if (!mesh && f->M > 1) return fail(GM_ERR_INVALID_ARGUMENT, "mesh is required with more than one mesh");
     gm_status st = check_device(f->scene);
     if (st != GM_OK) return st;
-    launch_field_infer(f->blob.as<unsigned char>(), f->geom, pos, q, out, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    if (!mesh) {
+        launch_field_infer(net_blob(f, 0), f->geom[0], pos, q, out, route_all(), s);
+    } else {
+        for (int32_t m = 0; m < f->M; ++m)
+            launch_field_infer(net_blob(f, m), f->geom[(size_t)m], pos, q, out, FieldRoute{mesh, nullptr, nullptr, 0, m},
+                               s);
+    }
     GM_HIP(hipGetLastError());
     return GM_OK;
 }
@@ -311,7 +374,12 @@ gm_status query_density(gm_field* f, gm_scene* sc, const gm_fixations* fix, doub
     if (q == 0) return GM_OK;
     hipStream_t s = (hipStream_t)stream;
     const bool use_field = f && f->trained;
-    if (use_field) launch_field_infer(f->blob.as<unsigned char>(), f->geom, pos, q, out, s);
+    if (use_field && (mesh || tri)) {
+        for (int32_t m = 0; m < f->M; ++m)
+            if (f->gate[(size_t)m])
+                launch_field_infer(net_blob(f, m), f->geom[(size_t)m], pos, q, out,
+                                   FieldRoute{mesh, tri, sc->tri_mesh.as<int32_t>(), sc->T, m}, s);
+    }
     // scratch lives in the field when there is one, else in per-call buffers
     DevBuf local_need, local_offs, local_scan;
     DevBuf& need = f ? f->need : local_need;

@@ -195,8 +195,19 @@ struct FieldTrain {
 };
 
 void launch_field_pack(const float* master, unsigned char* blob, hipStream_t s);
+// Points whose mesh (mesh[i], else tri_mesh[tri[i]] for 0 <= tri[i] < T) is `m` get the
+// network's value; m < 0 writes every point.
+struct FieldRoute {
+    const int32_t* mesh;
+    const int32_t* tri;
+    const int32_t* tri_mesh;
+    int64_t T;
+    int32_t m;
+};
 void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const float* pos, int64_t q, float* out,
-                        hipStream_t s);
+                        const FieldRoute& route, hipStream_t s);
+// sel[i] = flag[i] && mesh[i] == m
+void launch_field_select(const uint32_t* flag, const int32_t* mesh, int32_t m, int64_t n, uint32_t* sel, hipStream_t s);
 void launch_field_train(const unsigned char* blob, const FieldGeom& g, const FieldTrain& t, hipStream_t s);
 void launch_field_adam(float* master, float* m, float* v, float* grad, float lr, float b1, float b2, float eps,
                        float c1, float c2, hipStream_t s);

@@ -241,13 +241,13 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, bool acti
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
         W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
     }
-    const bool mixed = (fminf(fminf(U, V), W) < 0.0f) & (fmaxf(fmaxf(U, V), W) > 0.0f);
+    const int mixed = (int)(fminf(fminf(U, V), W) < 0.0f) & (int)(fmaxf(fmaxf(U, V), W) > 0.0f);
     const float det = U + V + W;
     // tau = T' / (det d[kz]) with T' = U akz + V bkz + W ckz: scale T' by the sign of
     // det d[kz] so the range test reads 0 < T' < tmax |d[kz]| |det|
     const float Tp = __builtin_fmaf(W, ckz, __builtin_fmaf(V, bkz, U * akz));
     const float Ts = __uint_as_float(__float_as_uint(Tp) ^ ((__float_as_uint(det) ^ __float_as_uint(s.tz)) & 0x80000000u));
-    return !mixed & (det != 0.0f) & (Ts > 0.0f) & (Ts < fabsf(s.tz) * fabsf(det));
+    return ((mixed ^ 1) & (int)(det != 0.0f) & (int)(Ts > 0.0f) & (int)(Ts < fabsf(s.tz) * fabsf(det))) != 0;
 }
 
 // Packet visibility.  Every lane carries up to R segments (R sample slots of the
@@ -255,8 +255,9 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, bool acti
 // occ[r] receives the answer.  One traversal serves all R * 64 segments: the node
 // index is wave-uniform (scalar loads), each lane tests its own segments against both
 // child boxes, children are visited near first (by the node's split axis and the
-// packet's direction octant `oct`) and the stack is one VGPR, lane i holding entry i.  Per-lane predicates are
-// kept as 64-bit wave masks (scalar registers) rather than per-lane booleans.
+// packet's direction octant `oct`) and the stack is one VGPR, lane i holding entry i.
+// Per-lane predicates are kept as 64-bit wave masks (scalar registers) rather than
+// per-lane booleans.
 // `tris` is the record copy whose axis order matches (e0, e1, e2), the eye in that
 // order: with UNI the packet's shared order, otherwise copy 2 (x, y, z).  With UNI
 // the packet's segments also share their direction signs and `nodes` is the node

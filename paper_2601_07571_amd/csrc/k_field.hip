@@ -184,7 +184,7 @@ constexpr int kPackThreads = kW * kS1 + 6 * kW * kSH + 5 * kW + 4;
 
 __global__ void __launch_bounds__(kThreads) k_field_infer(const unsigned char* __restrict__ blob, FieldGeom g,
                                                           const float* __restrict__ pos, int64_t q,
-                                                          float* __restrict__ out)
+                                                          float* __restrict__ out, FieldRoute route)
 {
     __shared__ __attribute__((aligned(16))) unsigned char s_blob[kInfer];
     stage(s_blob, blob, kInfer);
@@ -201,7 +201,20 @@ __global__ void __launch_bounds__(kThreads) k_field_infer(const unsigned char* _
         const int64_t ii = ok ? i : 0;
         Acts A;
         const float o = field_forward(s_blob, g, pos[3 * ii], pos[3 * ii + 1], pos[3 * ii + 2], lane, A);
-        if (ok && lane < 32) out[i] = softplus(o);
+        if (ok && lane < 32) {
+            bool mine = route.m < 0;
+            if (!mine) {
+                int pm = -1;
+                if (route.mesh) {
+                    pm = route.mesh[i];
+                } else if (route.tri) {
+                    const int t = route.tri[i];
+                    pm = t >= 0 && t < route.T ? route.tri_mesh[t] : -1;
+                }
+                mine = pm == route.m;
+            }
+            if (mine) out[i] = softplus(o);
+        }
     }
 }
 
@@ -356,6 +369,13 @@ __global__ void k_field_split(int64_t n, uint32_t key0, uint32_t key1, uint32_t 
     flag[i] = c0 >= threshold ? 1u : 0u;  // 1 = training, 0 = held out
 }
 
+__global__ void k_field_select(const uint32_t* __restrict__ flag, const int32_t* __restrict__ mesh, int32_t m,
+                               int64_t n, uint32_t* __restrict__ sel)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) sel[i] = flag[i] && mesh[i] == m ? 1u : 0u;
+}
+
 __global__ void k_field_compact(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ offs, int64_t n,
                                 int32_t* __restrict__ idx)
 {
@@ -435,12 +455,17 @@ void launch_field_pack(const float* master, unsigned char* blob, hipStream_t s)
 }
 
 void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const float* pos, int64_t q, float* out,
-                        hipStream_t s)
+                        const FieldRoute& route, hipStream_t s)
 {
     if (q <= 0) return;
     const int64_t tiles = (q + 31) / 32;
     const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 2048);
-    k_field_infer<<<grid, kThreads, 0, s>>>(blob, g, pos, q, out);
+    k_field_infer<<<grid, kThreads, 0, s>>>(blob, g, pos, q, out, route);
+}
+
+void launch_field_select(const uint32_t* flag, const int32_t* mesh, int32_t m, int64_t n, uint32_t* sel, hipStream_t s)
+{
+    if (n > 0) k_field_select<<<blocks(n), kThreads, 0, s>>>(flag, mesh, m, n, sel);
 }
 
 void launch_field_train(const unsigned char* blob, const FieldGeom& g, const FieldTrain& t, hipStream_t s)

@@ -140,3 +140,47 @@ def test_training_reaches_gate_and_query_paths(gm, tiny):
     fb, used = gm.query_density(f2, scene, fix, w.theta_deg, q, tri=s.tri[:50000], mesh=s.mesh[:50000],
                                 occlusion="self")
     assert bool(used.all()) and np.allclose(fb.cpu().numpy(), plain.cpu().numpy(), rtol=1e-6)
+
+
+def test_one_network_per_mesh(gm):
+    """Two meshes, two networks: each point is answered by its mesh's network over that
+    mesh's bounding cube, through predict (mesh ids) and query_density (triangle ids)."""
+    import torch
+    sph = workloads.sphere_mesh(level=2, radius=0.3, displace=0.05, seed=2)
+    cube = workloads.cube_mesh(0.5)
+    Vc = (cube.V + np.array([1.5, 0.2, -0.4], np.float32)).astype(np.float32)
+    meshes = [(sph.V, sph.I), (Vc, cube.I)]
+    scene = gm.Scene(meshes)
+    f = gm.Field(scene, seed=7)
+    rng = np.random.default_rng(3)
+    params = np.stack([fo.init_params(21), fo.init_params(22) + rng.normal(scale=0.02, size=fo.N_PARAMS)])
+    params[:, fo.N_PARAMS - 1] = [0.1, -0.2]
+    params = params.astype(np.float32)
+    f.set_params(params)
+    assert np.array_equal(f.get_params(), params)
+    xs, ids, refs = [], [], []
+    for m, (V, _) in enumerate(meshes):
+        lo32 = V.min(axis=0).astype(np.float32)
+        ext = float(np.max(V.max(axis=0).astype(np.float32) - lo32))
+        x = (lo32 + rng.uniform(0, ext, (2051 + m, 3))).astype(np.float32)
+        ref, _ = fo.forward(params[m].astype(np.float64), x, lo32.astype(np.float64), ext, bf=True)
+        xs.append(x); ids.append(np.full(len(x), m, np.int32)); refs.append(ref)
+    x = np.concatenate(xs); ids = np.concatenate(ids); ref = np.concatenate(refs)
+    perm = rng.permutation(len(x))
+    x, ids, ref = x[perm], ids[perm], ref[perm]
+    y = f.predict(x, mesh=ids).cpu().numpy().astype(np.float64)
+    rel = np.abs(y - ref) / np.maximum(np.abs(ref), 1e-3)
+    assert np.median(rel) < 2e-3 and rel.max() < 5e-2, (np.median(rel), rel.max())
+    with pytest.raises(gm.GazemapError):
+        f.predict(x)          # two meshes: mesh ids are required
+    # query_density routes by triangle when no mesh ids are given: train so both gates open
+    s = scene.build_samples(20000.0, 1)
+    tgt = torch.full((s.pos.shape[0],), 0.5, device="cuda")
+    info = f.train(s.pos, s.mesh, tgt, steps=800, batch=4096, lr=3e-3, lr_final=1e-4, max_rel_l2=0.1,
+                   target_max=1.0, seed=9)
+    assert info["gate"].all(), info
+    fix = gm.Fixations(np.array([[0, 0, 3.0]], np.float32), np.array([[0, 0, -1.0]], np.float32),
+                       np.array([1.0], np.float32))
+    out, used = gm.query_density(f, scene, fix, 1.0, s.pos, tri=s.tri, occlusion="full")
+    assert not bool(used.any())
+    assert np.allclose(out.cpu().numpy(), f.predict(s.pos, mesh=s.mesh).cpu().numpy())
