@@ -143,6 +143,7 @@ def main():
     }
 
     out["lattice"] = bench_lattice(gm, torch, args, scene, k)
+    out["incremental"] = bench_incremental(gm, workloads, torch, np, args, scene, samples, fix, w, ms_step)
     if not args.no_batched:
         out["batched"] = bench_batched(gm, workloads, torch, args)
     if not args.no_field:
@@ -220,6 +221,39 @@ def bench_lattice(gm, torch, args, scene, k):
     written = n * (4 + 4 + 8 + 12)
     return {"points": n, "call_ms": call_ms, "kernels_ms": kern_ms,
             "points_per_s": n / (kern_ms * 1e-3), "output_GBps": written / (kern_ms * 1e-3) / 1e9}
+
+
+def bench_incremental(gm, workloads, torch, np, args, scene, samples, fix, w, plain_ms):
+    """The same map fed as a growing recording (blocks of 500 fixations, each added as it
+    arrives, then read), and one 300 s analysis window of the recording (start times of the
+    fixations played back to back, 30 ms saccades), on an incremental map."""
+    t = workloads.start_times(w.fix.dur)
+    tt = torch.as_tensor(t, dtype=torch.float64, device="cuda")
+    m = gm.DensityMap(scene, samples.pos, w.theta_deg, occlusion="full", tri=samples.tri, mesh=samples.mesh)
+    blocks = [fix.subset(lo, min(fix.n, lo + 500)) for lo in range(0, fix.n, 500)]
+    res = m.read()
+
+    def feed():
+        m.reset()
+        for b in blocks:
+            m.add(b)
+        m.read(out=res)
+
+    feed()
+    feed_ms = _time(feed, torch, max(1, args.steps // 2))
+    mid = float(t[len(t) // 2])
+    win = (mid, mid + 300.0)
+
+    def window():
+        m.reset()
+        m.add(fix, time=tt, window=win)
+        m.read(out=res)
+
+    window()
+    win_ms = _time(window, torch, max(1, args.steps // 2))
+    return {"blocks": len(blocks), "fixations_per_block": 500, "feed_ms": feed_ms, "plain_call_ms": plain_ms,
+            "window_s": 300.0, "window_fixations": int(((t >= win[0]) & (t < win[1])).sum()),
+            "recording_s": float(t[-1] + w.fix.dur[-1]), "window_ms": win_ms}
 
 
 def bench_batched(gm, workloads, torch, args):

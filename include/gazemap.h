@@ -191,6 +191,70 @@ gm_status gm_debug_pair_visibility(gm_scene* scene, const float* pos, const int3
                                    int64_t m, uint32_t flags, uint8_t* vis_out, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Incremental maps and time windows.  rho is a sum over fixations, so a map */
+/* over a fixed set of points can take its fixations in blocks (a recording  */
+/* that grows, or several recordings) and any subset of them, such as those  */
+/* whose start time falls in an analysis window (the time interval among    */
+/* the generation parameters of Sec. 3.3.4; Sec. 2.3.3 asks for it).  A     */
+/* gm_map holds the points in                                                */
+/* their spatial order and one 64-bit fixed-point accumulator per point; the */
+/* scale 2^S is fixed at creation from a budget D on the total duration of   */
+/* the fixations it will take (S = 62 - e, 2^(e-1) <= 2 D / (sigma sqrt(2pi)) */
+/* < 2^e), so every block is added exactly: a map fed blocks A then B holds  */
+/* the same bits as one fed A u B in one call, in any order and split.        */
+/* Values match accumulate_density's to the fixed-point quantum 2^-S (the two */
+/* scales differ); visibility and cone decisions are the same code.           */
+/* ------------------------------------------------------------------------ */
+typedef struct gm_map gm_map;
+
+/*
+ * gm_map_create -- a map over n points with fixed theta and occlusion mode.
+ * pos / tri / mesh: device, as in accumulate_density; read during the call (the
+ * map keeps its own sorted copy).  theta_deg in (0, 45); flags one GM_OCC_* mode.
+ * max_total_duration: D in seconds, (0, 1e9]; fixations beyond it are refused
+ * (see gm_map_add).  The map starts empty (all zero).  Allocates device memory
+ * for about 40 bytes per point.  Queued on `stream`, then returns.  The scene
+ * must outlive the map (its BVH answers the visibility of every block).
+ */
+gm_status gm_map_create(gm_scene* scene, const float* pos, const int32_t* tri, const int32_t* mesh,
+                        int64_t n, double theta_deg, uint32_t flags, double max_total_duration,
+                        gm_map** out, void* stream);
+
+/*
+ * gm_map_add -- accumulate a block of fixations.  time: device float64 [fix->n]
+ * start time of each fixation (any clock), or NULL to take every fixation; with
+ * time, fixation f is taken iff t_begin <= time[f] < t_end (NaN is never taken).
+ * A taken fixation that is invalid (non-finite eye or gaze, zero gaze, duration
+ * negative, non-finite or above 1e6 s) contributes nothing, as in
+ * accumulate_density, and is counted as invalid.  Durations are charged to the
+ * budget D rounded up to units of 2^-10 s; a fixation that does not fit in what
+ * is left is not added and is counted as over budget (which ones, when a block
+ * overruns the budget, is unspecified).  Queued on `stream`; the fixation arrays
+ * must stay valid until the work completes.  Adds on one map are serialised by
+ * the stream: calls on different streams for one map race.
+ */
+gm_status gm_map_add(gm_map* map, const gm_fixations* fix, const double* time, double t_begin,
+                     double t_end, void* stream);
+
+/*
+ * gm_map_read -- the map as accumulate_density's outputs (device, each may be
+ * NULL): density [n] = rho in the caller's point order, density_norm [n] =
+ * rho / max rho (all zero when the map is empty), max_out [1].  Queued.
+ */
+gm_status gm_map_read(gm_map* map, float* density, float* density_norm, float* max_out, void* stream);
+
+/* gm_map_reset -- back to empty, with the whole budget.  Queued. */
+gm_status gm_map_reset(gm_map* map, void* stream);
+
+/*
+ * gm_map_info -- host int64 out[4] = {fixations added, taken but invalid,
+ * taken but over budget, budget used in units of 2^-10 s} since creation or the
+ * last reset.  Blocking (synchronises the device).
+ */
+gm_status gm_map_info(gm_map* map, int64_t* out);
+gm_status gm_map_destroy(gm_map* map);
+
+/* ------------------------------------------------------------------------ */
 /* Neural density field.  Not part of the paper's method: a Fourier-feature   */
 /* MLP that learns the normalised map from (sample position, rho / max rho)  */
 /* pairs produced by build_surface_samples + accumulate_density, and answers */

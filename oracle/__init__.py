@@ -20,6 +20,9 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
   visibility .................. pinned (brute force == BVH, convex sphere ==
                                  front-facing, hand-placed occluders)
   normalize ................... pinned (max == 1, range)
+  in_window / density_window .. pinned (partition of a recording into back-to-back
+                                 windows sums to the whole, boundary and NaN
+                                 times, empty window)
 """
 from __future__ import annotations
 
@@ -385,6 +388,26 @@ def density(scene: Scene | None, pos, tri, mesh, eye, gaze, dur, theta_deg, mode
                    float(theta_deg), mode, eps, int(brute), int(nthreads), _ptr(rho, ctypes.c_double),
                    _ptr(budget, ctypes.c_double), _ptr(stats, ctypes.c_int64))
     return OracleDensity(rho, budget, stats)
+
+
+def in_window(time, t_begin, t_end):
+    """Fixations whose start time lies in the analysis interval [t_begin, t_end)
+    (the time interval among the generation parameters, Sec. 3.3.4): half open, so
+    back-to-back windows split a recording without counting a fixation twice; a NaN
+    time is in no window."""
+    t = np.asarray(time, np.float64).reshape(-1)
+    return (t >= t_begin) & (t < t_end)
+
+
+def density_window(scene: Scene | None, pos, tri, mesh, eye, gaze, dur, time, window, theta_deg, mode=OCC_FULL,
+                   **kw) -> OracleDensity:
+    """rho of Sec. 3.2 over the fixations in the window only: the per-fixation sum of
+    Sec. 3.2.1 restricted to that subset."""
+    sel = in_window(time, window[0], window[1])
+    eye = np.asarray(eye, np.float32).reshape(-1, 3)[sel]
+    gaze = np.asarray(gaze, np.float32).reshape(-1, 3)[sel]
+    dur = np.asarray(dur, np.float32).reshape(-1)[sel]
+    return density(scene, pos, tri, mesh, eye, gaze, dur, theta_deg, mode, **kw)
 
 
 def normalize(rho):

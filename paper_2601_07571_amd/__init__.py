@@ -8,6 +8,7 @@ paper_2601_07571_amd.build``); importing this module fails loudly otherwise.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 
@@ -28,7 +29,8 @@ SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy",
            "gm_debug_pair_values", "gm_debug_pair_visibility", "gm_profile_enable", "gm_profile_read",
            "gm_density_stats", "gm_field_create", "gm_field_destroy", "gm_field_set_params",
            "gm_field_get_params", "gm_field_train", "gm_field_info", "gm_field_gradient", "gm_field_predict", "query_density",
-           "gm_batch_create", "gm_batch_run", "gm_batch_info", "gm_batch_destroy")
+           "gm_batch_create", "gm_batch_run", "gm_batch_info", "gm_batch_destroy",
+           "gm_map_create", "gm_map_add", "gm_map_read", "gm_map_reset", "gm_map_info", "gm_map_destroy")
 
 
 class GazemapError(RuntimeError):
@@ -108,6 +110,12 @@ def load_library(path: str = LIB_PATH):
     lib.gm_batch_destroy.argtypes = [vp]
     lib.query_density.argtypes = [vp, vp, ctypes.POINTER(_Fix), dbl, u32, vp, vp, vp, i64, dbl, vp, vp, vp]
     lib.gm_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    lib.gm_map_create.argtypes = [vp, vp, vp, vp, i64, dbl, u32, dbl, ctypes.POINTER(vp), vp]
+    lib.gm_map_add.argtypes = [vp, ctypes.POINTER(_Fix), vp, dbl, dbl, vp]
+    lib.gm_map_read.argtypes = [vp, vp, vp, vp, vp]
+    lib.gm_map_reset.argtypes = [vp, vp]
+    lib.gm_map_info.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.gm_map_destroy.argtypes = [vp]
     for name in SYMBOLS[2:]:
         getattr(lib, name).restype = i32
     _lib = lib
@@ -304,6 +312,66 @@ class Scene:
                                              _ptr(eye), int(eye.shape[0]), _ptr(ps), _ptr(pf), int(ps.shape[0]),
                                              OCC[occlusion], _ptr(vis), _stream()))
         return vis
+
+
+class DensityMap:
+    """Incremental map over a fixed set of points (gm_map_* in include/gazemap.h):
+    fixations are added in blocks, optionally filtered by a start-time window
+    [t_begin, t_end); `read()` gives the map of everything added so far."""
+
+    def __init__(self, scene: Scene, pos, theta_deg, occlusion="full", tri=None, mesh=None,
+                 max_total_duration=86400.0):
+        lib = load_library()
+        torch = _torch()
+        pos = _dev(pos, torch.float32, 3)
+        tri = _dev(tri, torch.int32)
+        mesh = _dev(mesh, torch.int32)
+        self.n = int(pos.shape[0])
+        self.scene = scene  # the scene must outlive the map
+        h = ctypes.c_void_p()
+        _check(lib.gm_map_create(scene._h, _ptr(pos), _ptr(tri), _ptr(mesh), self.n, float(theta_deg),
+                                 OCC[occlusion] if isinstance(occlusion, str) else occlusion,
+                                 float(max_total_duration), ctypes.byref(h), _stream()))
+        self._h = h
+
+    def add(self, fix: Fixations, time=None, window=None):
+        """Accumulate `fix`; with `time` (float64 [F], start times) only fixations with
+        window[0] <= time < window[1] are taken."""
+        torch = _torch()
+        t = _dev(time, torch.float64)
+        if t is not None:
+            t = t.reshape(-1)
+            if t.shape[0] != fix.n:
+                raise ValueError("time must hold one start time per fixation")
+        t0, t1 = window if window is not None else (-math.inf, math.inf)
+        _check(_lib.gm_map_add(self._h, ctypes.byref(fix._c), _ptr(t), float(t0), float(t1), _stream()))
+        self._keep = (fix, t)  # alive until the next call on this map's stream
+        return self
+
+    def read(self, out: Density | None = None):
+        torch = _torch()
+        if out is None:
+            out = Density(torch.empty(self.n, dtype=torch.float32, device="cuda"),
+                          torch.empty(self.n, dtype=torch.float32, device="cuda"),
+                          torch.empty(1, dtype=torch.float32, device="cuda"))
+        _check(_lib.gm_map_read(self._h, _ptr(out.density), _ptr(out.density_norm), _ptr(out.max), _stream()))
+        return out
+
+    def reset(self):
+        _check(_lib.gm_map_reset(self._h, _stream()))
+
+    def info(self):
+        out = (ctypes.c_int64 * 4)()
+        _check(_lib.gm_map_info(self._h, out))
+        return {"added": out[0], "invalid": out[1], "over_budget": out[2], "budget_used_s": out[3] / 1024.0}
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.gm_map_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def pair_values(pos, fix: Fixations, theta_deg, pair_s, pair_f):

@@ -176,34 +176,30 @@ gm_status density_reserve(DensityWork& w, int64_t n, int32_t F)
     return GM_OK;
 }
 
-gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
-                       int64_t n, const gm_fixations* fix, double theta_deg, uint32_t mode, int spl,
-                       int32_t fix_per_chunk, DensityLaunch& a, hipStream_t s)
+void density_sort(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
+                  int64_t n, hipStream_t s)
 {
-    const int32_t F = fix->n;
-    const double sigma = std::tan(theta_deg * M_PI / 180.0);
-    zero(w.stats.p, 8 * kDensityStats, s);
-    zero(w.fx_shift.p, 16, s);
-    zero(w.max_acc.p, 8, s);
-    launch_fix_prep(fix->eye, fix->gaze, fix->duration, F, sigma, kGateWiden, w.fix.as<FixRec>(), nullptr,
-                    w.fx_shift.as<int32_t>(), s);
-    if (n > 0) {
-        zero(w.acc.p, 8 * (size_t)n, s);
-        zero(w.hist.p, 4 * (size_t)w.buckets, s);
-        float lo[3];
-        float ext = 0.0f;
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = sc->bvh.lo[c];
-            ext = std::max(ext, sc->bvh.hi[c] - sc->bvh.lo[c]);
-        }
-        const int cells = 1 << w.bits;
-        const float inv_cell = ext > 0.0f ? (float)cells / ext : 1.0f;
-        launch_morton(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), n, lo, inv_cell, w.bits, w.key.as<uint32_t>(),
-                      w.hist.as<uint32_t>(), s);
-        launch_exclusive_scan_u32(w.hist.as<uint32_t>(), w.cursor.as<uint32_t>(), w.buckets, w.scan_tmp.p, s);
-        launch_scatter(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), sc->T, n, w.key.as<uint32_t>(),
-                       w.cursor.as<uint32_t>(), w.spos.as<float4>(), w.smesh.as<int32_t>(), w.perm.as<int32_t>(), s);
+    if (n <= 0) return;
+    zero(w.acc.p, 8 * (size_t)n, s);
+    zero(w.hist.p, 4 * (size_t)w.buckets, s);
+    float lo[3];
+    float ext = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = sc->bvh.lo[c];
+        ext = std::max(ext, sc->bvh.hi[c] - sc->bvh.lo[c]);
     }
+    const int cells = 1 << w.bits;
+    const float inv_cell = ext > 0.0f ? (float)cells / ext : 1.0f;
+    launch_morton(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), n, lo, inv_cell, w.bits, w.key.as<uint32_t>(),
+                  w.hist.as<uint32_t>(), s);
+    launch_exclusive_scan_u32(w.hist.as<uint32_t>(), w.cursor.as<uint32_t>(), w.buckets, w.scan_tmp.p, s);
+    launch_scatter(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), sc->T, n, w.key.as<uint32_t>(),
+                   w.cursor.as<uint32_t>(), w.spos.as<float4>(), w.smesh.as<int32_t>(), w.perm.as<int32_t>(), s);
+}
+
+void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F, double sigma, uint32_t mode,
+                  int spl, int32_t fix_per_chunk, DensityLaunch& a)
+{
     a.spos = w.spos.as<float4>();
     a.smesh = w.smesh.as<int32_t>();
     a.n = n;
@@ -230,6 +226,22 @@ gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int
     }
     a.fix_per_chunk = fix_per_chunk;
     a.n_chunks = F > 0 ? (int32_t)((F + fix_per_chunk - 1) / fix_per_chunk) : 0;
+    a.F_live = nullptr;
+}
+
+gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
+                       int64_t n, const gm_fixations* fix, double theta_deg, uint32_t mode, int spl,
+                       int32_t fix_per_chunk, DensityLaunch& a, hipStream_t s)
+{
+    const int32_t F = fix->n;
+    const double sigma = std::tan(theta_deg * M_PI / 180.0);
+    zero(w.stats.p, 8 * kDensityStats, s);
+    zero(w.fx_shift.p, 16, s);
+    zero(w.max_acc.p, 8, s);
+    launch_fix_prep(fix->eye, fix->gaze, fix->duration, F, sigma, kGateWiden, w.fix.as<FixRec>(), nullptr,
+                    w.fx_shift.as<int32_t>(), s);
+    density_sort(sc, w, pos, tri, mesh, n, s);
+    density_args(sc, w, n, F, sigma, mode, spl, fix_per_chunk, a);
     GM_HIP(hipGetLastError());
     return GM_OK;
 }

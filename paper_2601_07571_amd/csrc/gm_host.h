@@ -178,6 +178,12 @@ gm_status density_reserve(DensityWork& w, int64_t n, int32_t F);
 gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
                        int64_t n, const gm_fixations* fix, double theta_deg, uint32_t mode, int spl,
                        int32_t fix_per_chunk, DensityLaunch& a, hipStream_t s);
+// the two halves of density_prep's point side: zeroed accumulators and the spatial sort
+// of the points into w; the launch descriptor for F records in w.fix
+void density_sort(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
+                  int64_t n, hipStream_t s);
+void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F, double sigma, uint32_t mode,
+                  int spl, int32_t fix_per_chunk, DensityLaunch& a);
 // maximum and outputs
 gm_status density_finalize(DensityWork& w, int64_t n, float* density, float* density_norm, float* max_out,
                            hipStream_t s);

@@ -133,10 +133,15 @@ struct DensityLaunch {
     int32_t fix_per_chunk;
     int32_t n_chunks;
     int32_t spl;               // samples per lane
+    const unsigned int* F_live = nullptr;  // device count of valid records (<= F), or NULL: all F
 };
 
 void launch_fix_prep(const float* eye, const float* gaze, const float* dur, int32_t F, double sigma,
                      double widen, FixRec* rec, double* wsum, int32_t* fx_shift, hipStream_t s);
+// incremental maps: records of the fixations of one block that fall in a time window
+void launch_fix_select(const float* eye, const float* gaze, const float* dur, const double* time, int32_t F,
+                       double t0, double t1, double sigma, double widen, FixRec* rec, unsigned int* kept,
+                       unsigned long long* budget, unsigned long long* totals, hipStream_t s);
 void launch_morton(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
                    int64_t n, const float* bbox_lo, float inv_cell, int bits, uint32_t* key, uint32_t* hist,
                    hipStream_t s);

@@ -369,6 +369,31 @@ __device__ __forceinline__ unsigned long long to_fixed(float g, int shift)
 // ---------------------------------------------------------------------------
 // a4: fixation records and the fixed-point scale
 // ---------------------------------------------------------------------------
+// a4: the record of fixation f; false (and a record that contributes nothing: zero
+// gaze makes the gate s <= 0) for a non-finite eye or gaze, a zero gaze, or a
+// duration that is negative, non-finite or above t_cap.
+__device__ __forceinline__ bool fix_record(const float* __restrict__ eye, const float* __restrict__ gaze,
+                                           const float* __restrict__ dur, int f, double inv_norm,
+                                           double kappa_scale, float t_cap, FixRec& r)
+{
+    r.ex = eye[3 * f]; r.ey = eye[3 * f + 1]; r.ez = eye[3 * f + 2];
+    r.rx = gaze[3 * f]; r.ry = gaze[3 * f + 1]; r.rz = gaze[3 * f + 2];
+    const float t = dur[f];
+    const double r2 = (double)r.rx * r.rx + (double)r.ry * r.ry + (double)r.rz * r.rz;
+    const bool ok = isfinite(r.ex) && isfinite(r.ey) && isfinite(r.ez) && isfinite(r2) && r2 > 0.0 &&
+                    isfinite(t) && t >= 0.0f && t <= t_cap;
+    if (ok) {
+        r.w = (float)((double)t * inv_norm);
+        r.kappa = (float)(r2 * kappa_scale);
+    } else {
+        r.ex = r.ey = r.ez = 0.0f;
+        r.rx = r.ry = r.rz = 0.0f;
+        r.w = 0.0f;
+        r.kappa = 1.0f;
+    }
+    return ok;
+}
+
 __global__ void k_fix_prep(const float* __restrict__ eye, const float* __restrict__ gaze,
                            const float* __restrict__ dur, int32_t F, double inv_norm, double kappa_scale,
                            FixRec* __restrict__ rec, unsigned int* __restrict__ wmax_bits)
@@ -376,27 +401,48 @@ __global__ void k_fix_prep(const float* __restrict__ eye, const float* __restric
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
     FixRec r;
-    r.ex = eye[3 * f]; r.ey = eye[3 * f + 1]; r.ez = eye[3 * f + 2];
-    r.rx = gaze[3 * f]; r.ry = gaze[3 * f + 1]; r.rz = gaze[3 * f + 2];
-    const float t = dur[f];
-    const double r2 = (double)r.rx * r.rx + (double)r.ry * r.ry + (double)r.rz * r.rz;
-    const bool ok = isfinite(r.ex) && isfinite(r.ey) && isfinite(r.ez) && isfinite(r2) && r2 > 0.0 &&
-                    isfinite(t) && t >= 0.0f;
-    if (ok) {
-        r.w = (float)((double)t * inv_norm);
-        r.kappa = (float)(r2 * kappa_scale);
-    } else {
-        // an invalid fixation contributes nothing: zero gaze makes the gate s <= 0
-        r.ex = r.ey = r.ez = 0.0f;
-        r.rx = r.ry = r.rz = 0.0f;
-        r.w = 0.0f;
-        r.kappa = 1.0f;
-    }
+    (void)fix_record(eye, gaze, dur, f, inv_norm, kappa_scale, INFINITY, r);
     rec[f] = r;
     atomicMax(wmax_bits, __float_as_uint(r.w));
 }
 
-// shift such that F * max w * 2^shift <= 2^62: no sample total can overflow 63 bits
+// Records of one block of fixations added to an incremental map: the fixations whose
+// start time lies in [t0, t1) (every fixation when `time` is NULL) are kept and
+// written to rec[0 .. *kept) in no particular order (the map's sums are exact
+// integers, so the order cannot change them).  A fixation is kept only if it is
+// valid (a duration of at most 1e6 s) and its duration, rounded up to whole units of
+// 2^-10 s, fits in what is left of the map's duration budget (budget[0] used,
+// budget[1] total, in those units; a reservation that does not fit is returned, and
+// 2^31 in-flight reservations of 2^30 units cannot wrap 64 bits); the others are counted
+// in totals[1] (invalid) and totals[2] (over budget); totals[0] counts kept ones.
+__global__ void k_fix_select(const float* __restrict__ eye, const float* __restrict__ gaze,
+                             const float* __restrict__ dur, const double* __restrict__ time, int32_t F, double t0,
+                             double t1, double inv_norm, double kappa_scale, FixRec* __restrict__ rec,
+                             unsigned int* __restrict__ kept, unsigned long long* __restrict__ budget,
+                             unsigned long long* __restrict__ totals)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    if (time) {
+        const double t = time[f];
+        if (!(t >= t0 && t < t1)) return;  // NaN times are outside every window
+    }
+    FixRec r;
+    if (!fix_record(eye, gaze, dur, f, inv_norm, kappa_scale, 1.0e6f, r)) {
+        atomicAdd(&totals[1], 1ull);
+        return;
+    }
+    const unsigned long long units = (unsigned long long)ceil((double)dur[f] * 1024.0);
+    const unsigned long long used = atomicAdd(&budget[0], units);
+    if (used + units > budget[1]) {
+        atomicAdd(&budget[0], 0ull - units);
+        atomicAdd(&totals[2], 1ull);
+        return;
+    }
+    rec[atomicAdd(kept, 1u)] = r;
+    atomicAdd(&totals[0], 1ull);
+}
+
 __global__ void k_fix_shift(const unsigned int* __restrict__ wmax_bits, int32_t F, int32_t* __restrict__ shift)
 {
     const float wmax = __uint_as_float(*wmax_bits);
@@ -509,7 +555,8 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
 
     const int shift = *a.fx_shift;
     const int f_begin = chunk * a.fix_per_chunk;
-    const int f_end = min(a.F, f_begin + a.fix_per_chunk);
+    const int F = a.F_live ? min(a.F, (int)*a.F_live) : a.F;
+    const int f_end = min(F, f_begin + a.fix_per_chunk);
 
     for (int fb = f_begin; fb < f_end; fb += FB) {
         const int nb = min(FB, f_end - fb);
@@ -786,6 +833,17 @@ void launch_fix_prep(const float* eye, const float* gaze, const float* dur, int3
     unsigned int* wmax = reinterpret_cast<unsigned int*>(fx_shift + 1);
     if (F > 0) k_fix_prep<<<blocks(F, 256), 256, 0, s>>>(eye, gaze, dur, F, inv_norm, kappa_scale, rec, wmax);
     k_fix_shift<<<1, 1, 0, s>>>(wmax, F, fx_shift);
+}
+
+void launch_fix_select(const float* eye, const float* gaze, const float* dur, const double* time, int32_t F,
+                       double t0, double t1, double sigma, double widen, FixRec* rec, unsigned int* kept,
+                       unsigned long long* budget, unsigned long long* totals, hipStream_t s)
+{
+    const double inv_norm = 1.0 / (sigma * std::sqrt(2.0 * M_PI));
+    const double kappa_scale = (1.0 - widen) / (1.0 + 16.0 * sigma * sigma);
+    if (F > 0)
+        k_fix_select<<<blocks(F, 256), 256, 0, s>>>(eye, gaze, dur, time, F, t0, t1, inv_norm, kappa_scale, rec,
+                                                    kept, budget, totals);
 }
 
 void launch_morton(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh, int64_t n,

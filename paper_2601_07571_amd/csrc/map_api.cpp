@@ -1,0 +1,202 @@
+// map_api.cpp -- incremental density maps (include/gazemap.h, gm_map_*): a fixed set
+// of points, sorted once, whose fixed-point accumulators take fixations in blocks,
+// each block filtered by a start-time window and charged to a duration budget.
+// rho is linear in the fixations (Sec. 3.2.1 sums one term per fixation), so
+// adding blocks one after the other gives exactly the map of their union.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "gazemap.h"
+#include "gm_host.h"
+#include "gm_internal.h"
+
+using namespace gm;
+
+namespace {
+
+// counters[]: budget used, budget total (units of 2^-10 s), fixations added,
+// invalid, over budget
+constexpr int kMapCounters = 5;
+constexpr double kBudgetUnit = 1024.0;  // units per second
+
+}  // namespace
+
+struct gm_map {
+    gm_scene* scene = nullptr;
+    int device = 0;
+    int64_t n = 0;
+    double sigma = 0.0;
+    uint32_t mode = 0;
+    int spl = 1;
+    int32_t shift = 0;
+    unsigned long long budget_units = 0;
+    DensityWork w;     // sorted points, accumulators, records of the last block
+    DevBuf live;       // records of the block being added
+    DevBuf counters;   // [kMapCounters] uint64
+};
+
+namespace {
+
+gm_status check_map(const gm_map* m)
+{
+    if (!m) return fail(GM_ERR_INVALID_ARGUMENT, "map is NULL");
+    int dev = -1;
+    GM_HIP(hipGetDevice(&dev));
+    if (dev != m->device)
+        return fail(GM_ERR_INVALID_ARGUMENT, "map lives on device %d but device %d is current", m->device, dev);
+    return GM_OK;
+}
+
+// accumulators, maximum and counters back to zero; the budget total set again
+gm_status map_clear(gm_map* m, hipStream_t s)
+{
+    if (m->n > 0) zero(m->w.acc.p, 8 * (size_t)m->n, s);
+    zero(m->counters.p, 8 * kMapCounters, s);
+    const unsigned long long b = m->budget_units;  // counters[1], as two little-endian words
+    fill_u32(static_cast<uint32_t*>(m->counters.p) + 2, 1, (uint32_t)(b & 0xFFFFFFFFull), s);
+    fill_u32(static_cast<uint32_t*>(m->counters.p) + 3, 1, (uint32_t)(b >> 32), s);
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gm_status gm_map_create(gm_scene* sc, const float* pos, const int32_t* tri, const int32_t* mesh, int64_t n,
+                        double theta_deg, uint32_t flags, double max_total_duration, gm_map** out, void* stream)
+{
+    clear_error();
+    if (!out) return fail(GM_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GM_ERR_INVALID_ARGUMENT, "n must be in [0, 2^31)");
+    if (n > 0 && !pos) return fail(GM_ERR_INVALID_ARGUMENT, "pos is NULL");
+    if (!(theta_deg > 0.0 && theta_deg < 45.0)) return fail(GM_ERR_INVALID_ARGUMENT, "theta_deg must be in (0, 45)");
+    const uint32_t mode = flags & GM_OCC_MASK;
+    if (mode > GM_OCC_FULL || (flags & ~GM_OCC_MASK)) return fail(GM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", flags);
+    if (!(max_total_duration > 0.0 && max_total_duration <= 1e9))
+        return fail(GM_ERR_INVALID_ARGUMENT, "max_total_duration must be in (0, 1e9] seconds");
+    gm_status st = check_device(sc);
+    if (st != GM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+
+    gm_map* m = new gm_map;
+    m->scene = sc;
+    m->device = sc->device;
+    m->n = n;
+    m->sigma = std::tan(theta_deg * M_PI / 180.0);
+    m->mode = mode;
+    m->spl = sc->spl ? sc->spl : (mode != GM_OCC_NONE ? 1 : 2);
+    m->budget_units = (unsigned long long)std::floor(max_total_duration * kBudgetUnit);
+    // rho_s <= sum of the weights t / (sigma sqrt(2 pi)) of the fixations taken <= D / (sigma sqrt(2 pi))
+    int e = 0;
+    (void)std::frexp(2.0 * max_total_duration / (m->sigma * std::sqrt(2.0 * M_PI)), &e);
+    m->shift = 62 - e;
+    st = density_reserve(m->w, n, 1);
+    if (st == GM_OK && m->live.ensure(16) != hipSuccess) st = fail(GM_ERR_OUT_OF_MEMORY, "map counters");
+    if (st == GM_OK && m->counters.ensure(8 * kMapCounters) != hipSuccess)
+        st = fail(GM_ERR_OUT_OF_MEMORY, "map counters");
+    if (st != GM_OK) {
+        delete m;
+        return st;
+    }
+    fill_u32(m->w.fx_shift.p, 1, (uint32_t)m->shift, s);
+    density_sort(sc, m->w, pos, tri, mesh, n, s);
+    st = map_clear(m, s);
+    if (st == GM_OK) {
+        const hipError_t e2 = hipGetLastError();
+        if (e2 != hipSuccess) st = fail(GM_ERR_DEVICE, "map create: %s", hipGetErrorString(e2));
+    }
+    if (st != GM_OK) {
+        delete m;
+        return st;
+    }
+    *out = m;
+    return GM_OK;
+}
+
+gm_status gm_map_add(gm_map* m, const gm_fixations* fix, const double* time, double t_begin, double t_end,
+                     void* stream)
+{
+    clear_error();
+    gm_status st = check_map(m);
+    if (st != GM_OK) return st;
+    if (!fix) return fail(GM_ERR_INVALID_ARGUMENT, "fixations is NULL");
+    if (fix->n < 0) return fail(GM_ERR_INVALID_ARGUMENT, "fixation count < 0");
+    if (fix->n > 0 && (!fix->eye || !fix->gaze || !fix->duration))
+        return fail(GM_ERR_INVALID_ARGUMENT, "fixation arrays must not be NULL");
+    if (time && (std::isnan(t_begin) || std::isnan(t_end)))
+        return fail(GM_ERR_INVALID_ARGUMENT, "the time window bounds must not be NaN");
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t F = fix->n;
+    if (F == 0) return GM_OK;
+    GM_HIP(m->w.fix.ensure(sizeof(FixRec) * (size_t)F));
+    unsigned long long* c = m->counters.as<unsigned long long>();
+    zero(m->live.p, 4, s);
+    launch_fix_select(fix->eye, fix->gaze, fix->duration, time, F, t_begin, t_end, m->sigma, kGateWiden,
+                      m->w.fix.as<FixRec>(), m->live.as<unsigned int>(), c, c + 2, s);
+    if (m->n > 0) {
+        DensityLaunch a;
+        density_args(m->scene, m->w, m->n, F, m->sigma, m->mode, m->spl, 0, a);
+        a.F_live = m->live.as<unsigned int>();
+        zero(m->w.stats.p, 8 * kDensityStats, s);
+        launch_density(a, s);
+    }
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
+gm_status gm_map_read(gm_map* m, float* density, float* density_norm, float* max_out, void* stream)
+{
+    clear_error();
+    gm_status st = check_map(m);
+    if (st != GM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    zero(m->w.max_acc.p, 8, s);
+    return density_finalize(m->w, m->n, density, density_norm, max_out, s);
+}
+
+gm_status gm_map_reset(gm_map* m, void* stream)
+{
+    clear_error();
+    gm_status st = check_map(m);
+    if (st != GM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    return map_clear(m, s);
+}
+
+gm_status gm_map_info(gm_map* m, int64_t* out)
+{
+    clear_error();
+    gm_status st = check_map(m);
+    if (st != GM_OK) return st;
+    if (!out) return fail(GM_ERR_INVALID_ARGUMENT, "out is NULL");
+    unsigned long long v[kMapCounters];
+    GM_HIP(hipDeviceSynchronize());
+    GM_HIP(hipMemcpy(v, m->counters.p, sizeof(v), hipMemcpyDeviceToHost));
+    out[0] = (int64_t)v[2];
+    out[1] = (int64_t)v[3];
+    out[2] = (int64_t)v[4];
+    out[3] = (int64_t)v[0];
+    return GM_OK;
+}
+
+gm_status gm_map_destroy(gm_map* m)
+{
+    clear_error();
+    if (!m) return GM_OK;
+    const int dev = m->device;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    delete m;
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+    return GM_OK;
+}
+
+}  // extern "C"

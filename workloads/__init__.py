@@ -346,6 +346,14 @@ def walk_fixations(rng, meshes, F, weights, r_in, r_out, height=1.6, step=0.05, 
 # the workloads
 # ----------------------------------------------------------------------------
 
+def start_times(dur, gap=0.03):
+    """Start time (s, float64) of each fixation of a recording that plays them in order,
+    each followed by a saccade of `gap` seconds: t_0 = 0, t_f = sum over j < f of
+    (dur_j + gap)."""
+    d = np.asarray(dur, np.float64).reshape(-1) + gap
+    return np.concatenate([[0.0], np.cumsum(d)[:-1]]) if len(d) else np.zeros(0)
+
+
 def tiny_icosphere_scene(seed=0):
     """Icosphere level 3 (1,280 triangles), R = 0.5 m at the origin, 2,000 samples/m^2,
     Philox seed 0; 100 fixations, eyes uniform in the 1.5-2.5 m shell, gaze at uniform
