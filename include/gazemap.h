@@ -207,10 +207,19 @@ gm_status gm_debug_pair_visibility(gm_scene* scene, const float* pos, const int3
 /* ------------------------------------------------------------------------ */
 typedef struct gm_map gm_map;
 
+/* Flag of gm_map_create: the meshes move; every fixation comes with each mesh's
+ * pose at its time (gm_map_add_posed). */
+#define GM_MAP_POSED 4u
+
 /*
  * gm_map_create -- a map over n points with fixed theta and occlusion mode.
  * pos / tri / mesh: device, as in accumulate_density; read during the call (the
- * map keeps its own sorted copy).  theta_deg in (0, 45); flags one GM_OCC_* mode.
+ * map keeps its own sorted copy).  theta_deg in (0, 45); flags: one GM_OCC_* mode,
+ * optionally | GM_MAP_POSED.  A posed map holds points in their mesh's own frame
+ * (the scene's coordinates are each mesh's own), needs mesh [n] with the points
+ * grouped by mesh in mesh order (as the samplers write them; checked, blocking),
+ * and with occlusion builds one BVH per mesh on the host on first use per scene
+ * (blocking, kept by the scene).
  * max_total_duration: D in seconds, (0, 1e9]; fixations beyond it are refused
  * (see gm_map_add).  The map starts empty (all zero).  Allocates device memory
  * for about 40 bytes per point.  Queued on `stream`, then returns.  The scene
@@ -237,6 +246,25 @@ gm_status gm_map_add(gm_map* map, const gm_fixations* fix, const double* time, d
                      double t_end, void* stream);
 
 /*
+ * gm_map_add_posed -- accumulate a block of fixations on a posed map (dynamic
+ * objects: the values stay bound to each object, Sec. 2.1 and Sec. 3.3.3).
+ * pose: device float32 [fix->n][n_meshes][12], row-major 3x4 (A | b) taking mesh
+ * m's own frame to the world at fixation f's time; A must be a similarity (a
+ * rotation, possibly with a reflection, times a uniform scale): with s2 =
+ * trace(A^T A) / 3 every entry of A^T A - s2 I must be within 1e-5 s2, else the
+ * fixation is invalid.  Seen from mesh m, fixation f has eye A^-1 (e - b) and
+ * gaze A^-1 r (A^-1 = A^T / s2), each evaluated in FP64 as ((A_0i v_0 +
+ * A_1i v_1) + A_2i v_2) / s2 and rounded to FP32; the pair value of Sec. 3.2.1 is
+ * computed in that frame (a similarity keeps angles, so g is the world's).
+ * Visibility: GM_OCC_SELF tests the point's own mesh in its own frame;
+ * GM_OCC_FULL also every other mesh, with the segment taken into that mesh's frame
+ * (its parameter tau does not change).  time / window / budget / invalid
+ * fixations as in gm_map_add.  Queued on `stream`.
+ */
+gm_status gm_map_add_posed(gm_map* map, const gm_fixations* fix, const float* pose, const double* time,
+                           double t_begin, double t_end, void* stream);
+
+/*
  * gm_map_read -- the map as accumulate_density's outputs (device, each may be
  * NULL): density [n] = rho in the caller's point order, density_norm [n] =
  * rho / max rho (all zero when the map is empty), max_out [1].  Queued.
@@ -253,6 +281,32 @@ gm_status gm_map_reset(gm_map* map, void* stream);
  */
 gm_status gm_map_info(gm_map* map, int64_t* out);
 gm_status gm_map_destroy(gm_map* map);
+
+/*
+ * Export format (Sec. 3.3.3): one record per sample, ready for external analysis.
+ * 48 bytes, little-endian, no padding.
+ */
+typedef struct {
+    float value;       /* rho */
+    float value_norm;  /* rho / max rho (NaN when not given) */
+    int32_t mesh;      /* object (-1: unknown) */
+    int32_t triangle;  /* triangle index within its mesh (-1: unknown) */
+    float bary[2];     /* barycentric coordinates (b1, b2) of vertices 1 and 2; b0 = 1 - b1 - b2 */
+    float local[3];    /* position in the mesh's own frame (the scene's coordinates) */
+    float world[3];    /* position in the world: the mesh's pose applied to `local` */
+} gm_export_record;
+
+/*
+ * gm_export_samples -- pack n samples into records.  Device inputs: tri [n]
+ * scene-global triangle, mesh [n] or NULL (then from tri), bary [n][2], pos [n][3]
+ * (as the samplers write them), density [n], density_norm [n] or NULL; pose:
+ * device float32 [n_meshes][12] row-major 3x4 (A | b), the frame of each mesh in
+ * the world at the time of interest, or NULL (world = local).  world = A local + b
+ * in FP64, rounded.  out: device gm_export_record [n].  Queued on `stream`.
+ */
+gm_status gm_export_samples(gm_scene* scene, const int32_t* tri, const int32_t* mesh, const float* bary,
+                            const float* pos, const float* density, const float* density_norm,
+                            const float* pose, int64_t n, gm_export_record* out, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Neural density field.  Not part of the paper's method: a Fourier-feature   */

@@ -20,6 +20,11 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
   visibility .................. pinned (brute force == BVH, convex sphere ==
                                  front-facing, hand-placed occluders)
   normalize ................... pinned (max == 1, range)
+  local_fixation / posed_density  pinned (identity poses give the static map,
+                                 exact quarter turns give the static map, a mesh
+                                 carried along with its eye repeats one fixation,
+                                 a moving occluder equals the static maps of each
+                                 instant, shears are refused)
   in_window / density_window .. pinned (partition of a recording into back-to-back
                                  windows sums to the whole, boundary and NaN
                                  times, empty window)
@@ -408,6 +413,107 @@ def density_window(scene: Scene | None, pos, tri, mesh, eye, gaze, dur, time, wi
     gaze = np.asarray(gaze, np.float32).reshape(-1, 3)[sel]
     dur = np.asarray(dur, np.float32).reshape(-1)[sel]
     return density(scene, pos, tri, mesh, eye, gaze, dur, theta_deg, mode, **kw)
+
+
+SIMILARITY_TOL = 1e-5
+
+
+def local_fixation(pose, e, r):
+    """A fixation seen from a mesh placed in the world by `pose` (3x4 row-major, mesh frame
+    -> world): eye A^-1 (e - b) and gaze A^-1 r with A^-1 = A^T / s2, s2 = trace(A^T A) / 3,
+    each in FP64 as ((A_0i v_0 + A_1i v_1) + A_2i v_2) / s2 and rounded to FP32 (the
+    fixation's inputs in that frame; the paper likewise expresses p and r in a local
+    space, Sec. 3.2.1).  Returns (eye, gaze, ok); ok is False unless A is a similarity
+    (every entry of A^T A - s2 I within 1e-5 s2), the only maps that keep angles."""
+    P = np.asarray(pose, np.float32).reshape(12).astype(np.float64)
+    A = [[P[0], P[1], P[2]], [P[4], P[5], P[6]], [P[8], P[9], P[10]]]
+    b = [P[3], P[7], P[11]]
+    G = [[(A[0][i] * A[0][j] + A[1][i] * A[1][j]) + A[2][i] * A[2][j] for j in range(3)] for i in range(3)]
+    s2 = ((G[0][0] + G[1][1]) + G[2][2]) / 3.0
+    ok = bool(np.all(np.isfinite(P))) and s2 > 0.0 and math.isfinite(s2)
+    if ok:
+        ok = all(abs(G[i][j] - (s2 if i == j else 0.0)) <= SIMILARITY_TOL * s2 for i in range(3) for j in range(3))
+    e = np.asarray(e, np.float32).astype(np.float64); r = np.asarray(r, np.float32).astype(np.float64)
+    d = [e[0] - b[0], e[1] - b[1], e[2] - b[2]]
+
+    def frame(v):
+        return np.array([((A[0][i] * v[0] + A[1][i] * v[1]) + A[2][i] * v[2]) / s2 if s2 > 0 else 0.0
+                         for i in range(3)], np.float32)
+
+    return frame(d), frame(r), ok
+
+
+def posed_world(V, pose):
+    """Vertices of a mesh placed by `pose` (3x4, FP64 arithmetic, rounded to FP32)."""
+    P = np.asarray(pose, np.float32).astype(np.float64).reshape(3, 4)
+    V = np.asarray(V, np.float32).astype(np.float64)
+    W = np.stack([((P[k, 0] * V[:, 0] + P[k, 1] * V[:, 1]) + P[k, 2] * V[:, 2]) + P[k, 3] for k in range(3)], 1)
+    return W.astype(np.float32)
+
+
+def posed_density(meshes, pos, tri, mesh, eye, gaze, dur, pose, theta_deg, mode=OCC_FULL,
+                  eps=EPS_V) -> OracleDensity:
+    """rho of Sec. 3.2 when the meshes move: at fixation f mesh m stands where pose[f, m]
+    (3x4, mesh frame -> world) puts it and the points move with their mesh (values
+    bound to objects, Sec. 2.2, Sec. 3.3.3).  The pair value is taken in the point's
+    mesh frame from local_fixation's FP32 eye and gaze; visibility is taken in the world
+    at the fixation's time: with mode self against the point's own mesh (in its own
+    frame, the same thing), with mode full against every mesh as posed, the point moved
+    to the world in FP64.  A fixation whose duration, eye or gaze is invalid or whose
+    any pose is not a similarity contributes nothing.  Same bookkeeping (budget, stats)
+    as density()."""
+    pos = np.asarray(pos, np.float32).reshape(-1, 3)
+    tri = np.asarray(tri, np.int32); mesh = np.asarray(mesh, np.int32)
+    eye = np.asarray(eye, np.float32).reshape(-1, 3); gaze = np.asarray(gaze, np.float32).reshape(-1, 3)
+    dur = np.asarray(dur, np.float32).reshape(-1)
+    pose = np.asarray(pose, np.float32).reshape(len(eye), len(meshes), 12)
+    n = len(pos); M = len(meshes)
+    rho = np.zeros(n); budget = np.zeros(n); stats = np.zeros((n, 4), np.int64)
+    own = Scene(meshes)
+    groups = [np.nonzero(mesh == m)[0] for m in range(M)]
+    for f in range(len(eye)):
+        t = float(dur[f])
+        if not (np.all(np.isfinite(eye[f])) and np.all(np.isfinite(gaze[f])) and np.dot(gaze[f].astype(np.float64),
+                gaze[f].astype(np.float64)) > 0 and math.isfinite(t) and 0.0 <= t <= 1e6):
+            continue
+        loc = [local_fixation(pose[f, m], eye[f], gaze[f]) for m in range(M)]
+        if not all(ok for _, _, ok in loc):
+            continue
+        world = Scene([(posed_world(V, pose[f, m]), I) for m, (V, I) in enumerate(meshes)]) \
+            if mode == OCC_FULL else None
+        for m in range(M):
+            idx = groups[m]
+            if len(idx) == 0:
+                continue
+            el, rl, _ = loc[m]
+            g, mg, inc = pair_values(pos[idx], el[None], rl[None], dur[f:f + 1], np.arange(len(idx)),
+                                     np.zeros(len(idx), np.int64), theta_deg)
+            amb = np.abs(mg) < 1e-5
+            P = pose[f, m].astype(np.float64).reshape(3, 4)
+            for j in np.nonzero(inc | amb)[0]:
+                s = idx[j]
+                if mode == OCC_NONE:
+                    vis, frag = True, False
+                elif mode == OCC_SELF:
+                    vis, frag = own.visible(el.astype(np.float64), pos[s].astype(np.float64), int(tri[s]), m,
+                                            OCC_SELF, eps)
+                else:
+                    x = pos[s].astype(np.float64)
+                    xw = np.array([((P[k, 0] * x[0] + P[k, 1] * x[1]) + P[k, 2] * x[2]) + P[k, 3]
+                                   for k in range(3)])
+                    vis, frag = world.visible(eye[f].astype(np.float64), xw, int(tri[s]), m, OCC_FULL, eps)
+                if inc[j]:
+                    stats[s, 0] += 1
+                    if vis:
+                        stats[s, 1] += 1
+                        rho[s] += g[j]
+                if amb[j]:
+                    stats[s, 2] += 1
+                if frag and inc[j]:
+                    stats[s, 3] += 1
+                if amb[j] or (frag and inc[j]):
+                    budget[s] += g[j]
+    return OracleDensity(rho, budget, stats)
 
 
 def normalize(rho):

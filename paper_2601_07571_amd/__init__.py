@@ -30,7 +30,13 @@ SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy",
            "gm_density_stats", "gm_field_create", "gm_field_destroy", "gm_field_set_params",
            "gm_field_get_params", "gm_field_train", "gm_field_info", "gm_field_gradient", "gm_field_predict", "query_density",
            "gm_batch_create", "gm_batch_run", "gm_batch_info", "gm_batch_destroy",
-           "gm_map_create", "gm_map_add", "gm_map_read", "gm_map_reset", "gm_map_info", "gm_map_destroy")
+           "gm_map_create", "gm_map_add", "gm_map_add_posed", "gm_map_read", "gm_map_reset", "gm_map_info",
+           "gm_map_destroy", "gm_export_samples")
+GM_MAP_POSED = 4
+
+# one exported sample (gm_export_record), 48 bytes
+EXPORT_DTYPE = np.dtype([("value", "<f4"), ("value_norm", "<f4"), ("mesh", "<i4"), ("triangle", "<i4"),
+                         ("bary", "<f4", (2,)), ("local", "<f4", (3,)), ("world", "<f4", (3,))])
 
 
 class GazemapError(RuntimeError):
@@ -112,7 +118,9 @@ def load_library(path: str = LIB_PATH):
     lib.gm_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     lib.gm_map_create.argtypes = [vp, vp, vp, vp, i64, dbl, u32, dbl, ctypes.POINTER(vp), vp]
     lib.gm_map_add.argtypes = [vp, ctypes.POINTER(_Fix), vp, dbl, dbl, vp]
+    lib.gm_map_add_posed.argtypes = [vp, ctypes.POINTER(_Fix), vp, vp, dbl, dbl, vp]
     lib.gm_map_read.argtypes = [vp, vp, vp, vp, vp]
+    lib.gm_export_samples.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp]
     lib.gm_map_reset.argtypes = [vp, vp]
     lib.gm_map_info.argtypes = [vp, ctypes.POINTER(i64)]
     lib.gm_map_destroy.argtypes = [vp]
@@ -320,7 +328,7 @@ class DensityMap:
     [t_begin, t_end); `read()` gives the map of everything added so far."""
 
     def __init__(self, scene: Scene, pos, theta_deg, occlusion="full", tri=None, mesh=None,
-                 max_total_duration=86400.0):
+                 max_total_duration=86400.0, posed=False):
         lib = load_library()
         torch = _torch()
         pos = _dev(pos, torch.float32, 3)
@@ -328,11 +336,31 @@ class DensityMap:
         mesh = _dev(mesh, torch.int32)
         self.n = int(pos.shape[0])
         self.scene = scene  # the scene must outlive the map
+        flags = OCC[occlusion] if isinstance(occlusion, str) else occlusion
+        if posed:
+            flags |= GM_MAP_POSED
         h = ctypes.c_void_p()
-        _check(lib.gm_map_create(scene._h, _ptr(pos), _ptr(tri), _ptr(mesh), self.n, float(theta_deg),
-                                 OCC[occlusion] if isinstance(occlusion, str) else occlusion,
+        _check(lib.gm_map_create(scene._h, _ptr(pos), _ptr(tri), _ptr(mesh), self.n, float(theta_deg), flags,
                                  float(max_total_duration), ctypes.byref(h), _stream()))
         self._h = h
+
+    def add_posed(self, fix: Fixations, pose, time=None, window=None):
+        """Accumulate `fix` with the meshes placed by `pose` (float32 [F][n_meshes][12],
+        row-major 3x4 mesh frame -> world at each fixation's time)."""
+        torch = _torch()
+        pose = _dev(pose, torch.float32)
+        if pose.numel() != fix.n * self.scene.n_meshes * 12:
+            raise ValueError("pose must be [F][n_meshes][12]")
+        t = _dev(time, torch.float64)
+        if t is not None:
+            t = t.reshape(-1)
+            if t.shape[0] != fix.n:
+                raise ValueError("time must hold one start time per fixation")
+        t0, t1 = window if window is not None else (-math.inf, math.inf)
+        _check(_lib.gm_map_add_posed(self._h, ctypes.byref(fix._c), _ptr(pose), _ptr(t), float(t0), float(t1),
+                                     _stream()))
+        self._keep = (fix, pose, t)
+        return self
 
     def add(self, fix: Fixations, time=None, window=None):
         """Accumulate `fix`; with `time` (float64 [F], start times) only fixations with
@@ -372,6 +400,35 @@ class DensityMap:
 
     def __del__(self):
         self.close()
+
+
+def export_samples(scene: Scene, samples: Samples, density: Density, pose=None):
+    """The export format of Sec. 3.3.3 on the device: uint8 [n][48] records
+    (gm_export_record); `pose` float32 [n_meshes][12] places each mesh in the world
+    (None: world = local).  `records_to_numpy` gives the host structured array."""
+    torch = _torch()
+    n = int(samples.pos.shape[0])
+    out = torch.empty((n, EXPORT_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+    pose = _dev(pose, torch.float32)
+    _check(_lib.gm_export_samples(scene._h, _ptr(samples.tri), _ptr(samples.mesh), _ptr(samples.bary),
+                                  _ptr(samples.pos), _ptr(density.density), _ptr(density.density_norm), _ptr(pose),
+                                  n, _ptr(out), _stream()))
+    return out
+
+
+def records_to_numpy(records):
+    return records.cpu().numpy().reshape(-1).view(EXPORT_DTYPE)
+
+
+def write_csv(path, records):
+    """One line per sample: value, value_norm, mesh, triangle, b1, b2, local xyz, world xyz."""
+    r = records_to_numpy(records) if not isinstance(records, np.ndarray) else records
+    cols = np.column_stack([r["value"], r["value_norm"], r["mesh"], r["triangle"], r["bary"], r["local"],
+                            r["world"]])
+    fmt = ["%.9g", "%.9g", "%d", "%d"] + ["%.9g"] * 8
+    np.savetxt(path, cols, fmt=fmt, delimiter=",",
+               header="value,value_norm,mesh,triangle,b1,b2,local_x,local_y,local_z,world_x,world_y,world_z",
+               comments="")
 
 
 def pair_values(pos, fix: Fixations, theta_deg, pair_s, pair_f):

@@ -177,10 +177,10 @@ gm_status density_reserve(DensityWork& w, int64_t n, int32_t F)
 }
 
 void density_sort(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
-                  int64_t n, hipStream_t s)
+                  int64_t n, hipStream_t s, int64_t off)
 {
     if (n <= 0) return;
-    zero(w.acc.p, 8 * (size_t)n, s);
+    zero(w.acc.as<unsigned long long>() + off, 8 * (size_t)n, s);
     zero(w.hist.p, 4 * (size_t)w.buckets, s);
     float lo[3];
     float ext = 0.0f;
@@ -194,7 +194,8 @@ void density_sort(gm_scene* sc, DensityWork& w, const float* pos, const int32_t*
                   w.hist.as<uint32_t>(), s);
     launch_exclusive_scan_u32(w.hist.as<uint32_t>(), w.cursor.as<uint32_t>(), w.buckets, w.scan_tmp.p, s);
     launch_scatter(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), sc->T, n, w.key.as<uint32_t>(),
-                   w.cursor.as<uint32_t>(), w.spos.as<float4>(), w.smesh.as<int32_t>(), w.perm.as<int32_t>(), s);
+                   w.cursor.as<uint32_t>(), w.spos.as<float4>() + off, w.smesh.as<int32_t>() + off,
+                   w.perm.as<int32_t>() + off, (int32_t)off, s);
 }
 
 void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F, double sigma, uint32_t mode,

@@ -125,6 +125,7 @@ struct DensityWork {
 
 using gm::DensityWork;
 using gm::DevBuf;
+using gm::BlasDesc;
 using gm::HostBvh;
 using gm::StageTimer;
 using gm::kStages;
@@ -141,6 +142,10 @@ struct gm_scene {
     DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total;
     // density scratch of the plain entry points
     DensityWork work;
+    // one BVH per mesh in the mesh's own frame (posed maps), built on first use:
+    // BlasDesc per mesh into the concatenated node and record arrays (with copies)
+    std::vector<BlasDesc> blas;
+    DevBuf blas_nodes, blas_tris, blas_desc;
     // samples per lane of the plain density kernel; 0 = by occlusion mode (1 with a
     // visibility test, whose cost is per segment, 2 for the gate-only kernel)
     int32_t spl = 0;
@@ -161,7 +166,7 @@ struct gm_scene {
     {
         for (auto& t : timers) t.release();
         for (DevBuf* b : {&V, &I, &tri_mesh, &tri_off_d, &nodes, &tris, &area, &W, &C, &max_bits, &S, &scan_tmp,
-                          &counts, &offsets, &mesh_total})
+                          &counts, &offsets, &mesh_total, &blas_nodes, &blas_tris, &blas_desc})
             b->release();
     }
 };
@@ -179,9 +184,10 @@ gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int
                        int64_t n, const gm_fixations* fix, double theta_deg, uint32_t mode, int spl,
                        int32_t fix_per_chunk, DensityLaunch& a, hipStream_t s);
 // the two halves of density_prep's point side: zeroed accumulators and the spatial sort
-// of the points into w; the launch descriptor for F records in w.fix
+// of the points into w (into entries [off, off + n), caller indices off + i); the
+// launch descriptor for F records in w.fix
 void density_sort(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
-                  int64_t n, hipStream_t s);
+                  int64_t n, hipStream_t s, int64_t off = 0);
 void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F, double sigma, uint32_t mode,
                   int spl, int32_t fix_per_chunk, DensityLaunch& a);
 // maximum and outputs

@@ -112,6 +112,12 @@ void launch_sample(const float* V, const int32_t* I, const unsigned long long* C
 
 // density path
 constexpr int kDensityStats = 4;  // in-cone pairs, visible pairs, packet traversals, BVH node visits
+// One mesh's BVH inside the concatenated per-mesh arrays: kNodeCopies copies of
+// node_count nodes from node_base, kTriCopies copies of tri_count records from tri_base.
+struct BlasDesc {
+    int64_t node_base, node_count, tri_base, tri_count;
+};
+
 struct DensityLaunch {
     // sorted samples
     const float4* spos;        // xyz, w = own triangle (int bits, -1 = none)
@@ -134,10 +140,28 @@ struct DensityLaunch {
     int32_t n_chunks;
     int32_t spl;               // samples per lane
     const unsigned int* F_live = nullptr;  // device count of valid records (<= F), or NULL: all F
+    // Posed scenes (meshes that move between fixations): one BVH per mesh in its own
+    // frame, fixation records per mesh (fix = fix_all + self_mesh * fix_stride) and
+    // per (mesh, fixation) 24 floats: the 3x4 pose (mesh -> world), then its inverse.
+    // blas == NULL: the static scene BVH above.
+    const BlasDesc* blas = nullptr;
+    const BvhNode* blas_nodes = nullptr;
+    const BvhTri* blas_tris = nullptr;
+    const FixRec* fix_all = nullptr;
+    const float* xf = nullptr;
+    int64_t fix_stride = 0;
+    int32_t n_inst = 0;
+    int32_t self_mesh = 0;
 };
+
 
 void launch_fix_prep(const float* eye, const float* gaze, const float* dur, int32_t F, double sigma,
                      double widen, FixRec* rec, double* wsum, int32_t* fx_shift, hipStream_t s);
+// posed maps: per fixation taken, one record and one pose pair (forward, inverse) per mesh
+void launch_fix_posed(const float* eye, const float* gaze, const float* dur, const double* time, const float* pose,
+                      int32_t F, int32_t M, int64_t stride, double t0, double t1, double sigma, double widen,
+                      FixRec* rec, float* xf, unsigned int* kept, unsigned long long* budget,
+                      unsigned long long* totals, hipStream_t s);
 // incremental maps: records of the fixations of one block that fall in a time window
 void launch_fix_select(const float* eye, const float* gaze, const float* dur, const double* time, int32_t F,
                        double t0, double t1, double sigma, double widen, FixRec* rec, unsigned int* kept,
@@ -147,7 +171,7 @@ void launch_morton(const float* pos, const int32_t* tri, const int32_t* mesh, co
                    hipStream_t s);
 void launch_scatter(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
                     int64_t T, int64_t n, const uint32_t* key, uint32_t* cursor, float4* spos, int32_t* smesh,
-                    int32_t* perm, hipStream_t s);
+                    int32_t* perm, int32_t base, hipStream_t s);
 void launch_density(const DensityLaunch& a, hipStream_t s);
 // persistent multi-session form: items are (session, tile, chunk, 0); head is zeroed by the caller
 void launch_density_queue(const DensityLaunch* sessions, const int4* items, int32_t n_items, unsigned int* head,

@@ -372,13 +372,11 @@ __device__ __forceinline__ unsigned long long to_fixed(float g, int shift)
 // a4: the record of fixation f; false (and a record that contributes nothing: zero
 // gaze makes the gate s <= 0) for a non-finite eye or gaze, a zero gaze, or a
 // duration that is negative, non-finite or above t_cap.
-__device__ __forceinline__ bool fix_record(const float* __restrict__ eye, const float* __restrict__ gaze,
-                                           const float* __restrict__ dur, int f, double inv_norm,
-                                           double kappa_scale, float t_cap, FixRec& r)
+__device__ __forceinline__ bool fix_record_v(float ex, float ey, float ez, float rx, float ry, float rz, float t,
+                                             double inv_norm, double kappa_scale, float t_cap, FixRec& r)
 {
-    r.ex = eye[3 * f]; r.ey = eye[3 * f + 1]; r.ez = eye[3 * f + 2];
-    r.rx = gaze[3 * f]; r.ry = gaze[3 * f + 1]; r.rz = gaze[3 * f + 2];
-    const float t = dur[f];
+    r.ex = ex; r.ey = ey; r.ez = ez;
+    r.rx = rx; r.ry = ry; r.rz = rz;
     const double r2 = (double)r.rx * r.rx + (double)r.ry * r.ry + (double)r.rz * r.rz;
     const bool ok = isfinite(r.ex) && isfinite(r.ey) && isfinite(r.ez) && isfinite(r2) && r2 > 0.0 &&
                     isfinite(t) && t >= 0.0f && t <= t_cap;
@@ -392,6 +390,14 @@ __device__ __forceinline__ bool fix_record(const float* __restrict__ eye, const 
         r.kappa = 1.0f;
     }
     return ok;
+}
+
+__device__ __forceinline__ bool fix_record(const float* __restrict__ eye, const float* __restrict__ gaze,
+                                           const float* __restrict__ dur, int f, double inv_norm,
+                                           double kappa_scale, float t_cap, FixRec& r)
+{
+    return fix_record_v(eye[3 * f], eye[3 * f + 1], eye[3 * f + 2], gaze[3 * f], gaze[3 * f + 1], gaze[3 * f + 2],
+                        dur[f], inv_norm, kappa_scale, t_cap, r);
 }
 
 __global__ void k_fix_prep(const float* __restrict__ eye, const float* __restrict__ gaze,
@@ -455,6 +461,98 @@ __global__ void k_fix_shift(const unsigned int* __restrict__ wmax_bits, int32_t 
     }
 }
 
+// Posed scenes.  pose [F][M][12]: row-major 3x4 (A | b) taking mesh m's own frame to
+// the world at fixation f's time; A must be a similarity (rotation, optionally a
+// reflection, times a uniform scale): s2 = trace(A^T A) / 3 and every entry of
+// A^T A - s2 I within 1e-5 s2.  Seen from mesh m the fixation has eye
+// A^-1 (e - b) and gaze A^-1 r (A^-1 = A^T / s2), each evaluated in FP64 in a fixed
+// order and rounded to FP32: these are the inputs of the pair value in that frame,
+// where angles, and so g, are those of the world.
+__device__ __forceinline__ bool similarity(const float* __restrict__ P, double& s2)
+{
+    double G[3][3];
+    bool ok = true;
+    for (int k = 0; k < 12; ++k) ok = ok && isfinite(P[k]);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            G[i][j] = ((double)P[i] * (double)P[j] + (double)P[4 + i] * (double)P[4 + j]) +
+                      (double)P[8 + i] * (double)P[8 + j];
+    s2 = ((G[0][0] + G[1][1]) + G[2][2]) / 3.0;
+    ok = ok && s2 > 0.0 && isfinite(s2);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) ok = ok && fabs(G[i][j] - (i == j ? s2 : 0.0)) <= 1e-5 * s2;
+    return ok;
+}
+
+// (A^T v) / s2 with the columns of A taken in order
+__device__ __forceinline__ void to_frame(const float* __restrict__ P, double s2, double v0, double v1, double v2,
+                                         float& o0, float& o1, float& o2)
+{
+    o0 = (float)((((double)P[0] * v0 + (double)P[4] * v1) + (double)P[8] * v2) / s2);
+    o1 = (float)((((double)P[1] * v0 + (double)P[5] * v1) + (double)P[9] * v2) / s2);
+    o2 = (float)((((double)P[2] * v0 + (double)P[6] * v1) + (double)P[10] * v2) / s2);
+}
+
+// One thread per fixation: window, validity (the fixation's own and every mesh's
+// pose), duration budget, then one record and one pose pair per mesh at the
+// fixation's compacted index.
+__global__ void k_fix_posed(const float* __restrict__ eye, const float* __restrict__ gaze,
+                            const float* __restrict__ dur, const double* __restrict__ time,
+                            const float* __restrict__ pose, int32_t F, int32_t M, int64_t stride, double t0,
+                            double t1, double inv_norm, double kappa_scale, FixRec* __restrict__ rec,
+                            float* __restrict__ xf, unsigned int* __restrict__ kept,
+                            unsigned long long* __restrict__ budget, unsigned long long* __restrict__ totals)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    if (time) {
+        const double t = time[f];
+        if (!(t >= t0 && t < t1)) return;
+    }
+    FixRec r;
+    bool ok = fix_record(eye, gaze, dur, f, inv_norm, kappa_scale, 1.0e6f, r);
+    for (int m = 0; m < M && ok; ++m) {
+        double s2;
+        ok = similarity(pose + ((int64_t)f * M + m) * 12, s2);
+    }
+    if (!ok) {
+        atomicAdd(&totals[1], 1ull);
+        return;
+    }
+    const unsigned long long units = (unsigned long long)ceil((double)dur[f] * 1024.0);
+    const unsigned long long used = atomicAdd(&budget[0], units);
+    if (used + units > budget[1]) {
+        atomicAdd(&budget[0], 0ull - units);
+        atomicAdd(&totals[2], 1ull);
+        return;
+    }
+    const unsigned idx = atomicAdd(kept, 1u);
+    atomicAdd(&totals[0], 1ull);
+    for (int m = 0; m < M; ++m) {
+        const float* P = pose + ((int64_t)f * M + m) * 12;
+        double s2;
+        (void)similarity(P, s2);
+        float ex, ey, ez, rx, ry, rz;
+        to_frame(P, s2, (double)r.ex - (double)P[3], (double)r.ey - (double)P[7], (double)r.ez - (double)P[11], ex,
+                 ey, ez);
+        to_frame(P, s2, (double)r.rx, (double)r.ry, (double)r.rz, rx, ry, rz);
+        FixRec rm;
+        (void)fix_record_v(ex, ey, ez, rx, ry, rz, dur[f], inv_norm, kappa_scale, 1.0e6f, rm);
+        rec[(int64_t)m * stride + idx] = rm;
+        float* o = xf + ((int64_t)m * stride + idx) * 24;
+        for (int k = 0; k < 12; ++k) o[k] = P[k];
+        // inverse: A^T / s2 and -(A^T b) / s2
+        for (int i = 0; i < 3; ++i) {
+            o[12 + 4 * i + 0] = (float)((double)P[i] / s2);
+            o[12 + 4 * i + 1] = (float)((double)P[4 + i] / s2);
+            o[12 + 4 * i + 2] = (float)((double)P[8 + i] / s2);
+        }
+        float c0, c1, c2;
+        to_frame(P, s2, (double)P[3], (double)P[7], (double)P[11], c0, c1, c2);
+        o[15] = -c0; o[19] = -c1; o[23] = -c2;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // spatial order: 7-bit-per-axis Morton buckets, counting sort
 // ---------------------------------------------------------------------------
@@ -486,7 +584,7 @@ __global__ void k_morton(const float* __restrict__ pos, int64_t n, float lox, fl
 __global__ void k_scatter(const float* __restrict__ pos, const int32_t* __restrict__ tri,
                           const int32_t* __restrict__ mesh, const int32_t* __restrict__ tri_mesh, int64_t T, int64_t n,
                           const uint32_t* __restrict__ key, uint32_t* __restrict__ cursor, float4* __restrict__ spos,
-                          int32_t* __restrict__ smesh, int32_t* __restrict__ perm)
+                          int32_t* __restrict__ smesh, int32_t* __restrict__ perm, int32_t base)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -496,7 +594,7 @@ __global__ void k_scatter(const float* __restrict__ pos, const int32_t* __restri
     const int32_t m = mesh ? mesh[i] : (t >= 0 ? tri_mesh[t] : -1);
     spos[dst] = make_float4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], __int_as_float(t));
     smesh[dst] = m;
-    perm[dst] = (int32_t)i;
+    perm[dst] = base + (int32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -514,7 +612,69 @@ __device__ __forceinline__ unsigned xcd_block(unsigned L, unsigned G)
 // sorted samples) against one chunk of the fixations, by the whole workgroup.
 // OCC = 0: no occlusion (no traversal code); OCC = 1: visibility by the BVH when
 // a.occ_mode != 0.  FB: fixations staged in LDS per round.
-template <int SPL, int OCC, int FB>
+// Visibility of the wave's slots that need it, for one fixation, in one frame: the
+// segments run from the eye (ex, ey, ez) to the points p[k], both in the frame of the
+// BVH whose octant node copies start at `nodes` (node_stride nodes apart) and whose
+// axis-permuted record copies start at `tris` (tri_stride records apart); only the
+// gaze's dominant axis is used.
+template <int SPL>
+__device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ nodes, int64_t node_stride,
+                                                  const BvhTri* __restrict__ tris, int64_t tri_stride, float ex,
+                                                  float ey, float ez, float rx, float ry, float rz,
+                                                  const float4 (&p)[SPL], const int (&otri)[SPL],
+                                                  const int (&omesh)[SPL], int mode, float tmax,
+                                                  const bool (&need)[SPL], bool (&occl)[SPL], uint32_t& n_visits)
+{
+    // The packet shares the axis order of the gaze's dominant axis when every
+    // segment keeps at least 0.4 of its length along that axis (true for every
+    // in-cone segment while the cone half-angle stays under ~14 degrees); it
+    // then reads the record copy already permuted into that order.
+    const float agx = fabsf(rx), agy = fabsf(ry), agz = fabsf(rz);
+    const int kz = uniform(agx > agy ? (agx > agz ? 0 : 2) : (agy > agz ? 1 : 2));
+    const int kx = kz == 2 ? 0 : kz + 1;
+    const int ky = kx == 2 ? 0 : kx + 1;
+    bool shared = true;
+    // per axis: lanes with a segment (any slot) running towards -axis / +axis
+    uint64_t nx_m = 0, ny_m = 0, nz_m = 0, px_m = 0, py_m = 0, pz_m = 0;
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+        const float dx = p[k].x - ex, dy = p[k].y - ey, dz = p[k].z - ez;
+        const float dk = pick(kz, dx, dy, dz);
+        shared = shared && (!need[k] || dk * dk >= 0.16f * (dx * dx + dy * dy + dz * dz));
+        nx_m |= ballot(need[k] && signbit(dx));
+        ny_m |= ballot(need[k] && signbit(dy));
+        nz_m |= ballot(need[k] && signbit(dz));
+        px_m |= ballot(need[k] && !signbit(dx));
+        py_m |= ballot(need[k] && !signbit(dy));
+        pz_m |= ballot(need[k] && !signbit(dz));
+    }
+    // ... and every segment of every slot has the same direction signs
+    shared = ballot(!shared) == 0 && (nx_m == 0 || px_m == 0) && (ny_m == 0 || py_m == 0) &&
+             (nz_m == 0 || pz_m == 0);
+    Seg sg[SPL];
+    if (shared) {
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) sg[k] = make_seg(ex, ey, ez, p[k].x, p[k].y, p[k].z, kx, ky, kz, tmax);
+        const int oct = (nx_m != 0 ? 1 : 0) | (ny_m != 0 ? 2 : 0) | (nz_m != 0 ? 4 : 0);
+        occluded_packet<SPL, true>(nodes + oct * node_stride, tris + kz * tri_stride, pick(kx, ex, ey, ez),
+                                   pick(ky, ex, ey, ez), pick(kz, ex, ey, ez), oct, sg, otri, omesh, mode, tmax, need,
+                                   occl, n_visits);
+    } else {
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+            int lx, ly, lz;
+            axis_order(p[k].x - ex, p[k].y - ey, p[k].z - ez, lx, ly, lz);
+            sg[k] = make_seg(ex, ey, ez, p[k].x, p[k].y, p[k].z, lx, ly, lz, tmax);
+        }
+        // child order from one lane's octant (the order affects speed, not results)
+        const int lead = __builtin_ctzll(nx_m | px_m);
+        const int oct = (int)((nx_m >> lead) & 1) | (int)(((ny_m >> lead) & 1) << 1) | (int)(((nz_m >> lead) & 1) << 2);
+        occluded_packet<SPL, false>(nodes, tris + 2 * tri_stride, ex, ey, ez, oct, sg, otri, omesh, mode, tmax, need,
+                                    occl, n_visits);
+    }
+}
+
+template <int SPL, int OCC, int FB, bool POSED = false>
 __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t tile, int chunk)
 {
     __shared__ float4 s_ra[FB];  // rx, ry, rz, c0
@@ -620,61 +780,63 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
 #pragma unroll
             for (int k = 0; k < SPL; ++k) occl[k] = false;
             if (OCC != 0 && ballot(any_need) != 0) {
-                // The packet shares the axis order of the gaze's dominant axis when every
-                // segment keeps at least 0.4 of its length along that axis (true for every
-                // in-cone segment while the cone half-angle stays under ~14 degrees); it
-                // then reads the record copy already permuted into that order.
-                const float agx = fabsf(fr.rx), agy = fabsf(fr.ry), agz = fabsf(fr.rz);
-                const int kz = uniform(agx > agy ? (agx > agz ? 0 : 2) : (agy > agz ? 1 : 2));
-                const int kx = kz == 2 ? 0 : kz + 1;
-                const int ky = kx == 2 ? 0 : kx + 1;
-                bool shared = true;
-                // per axis: lanes with a segment (any slot) running towards -axis / +axis
-                uint64_t nx_m = 0, ny_m = 0, nz_m = 0, px_m = 0, py_m = 0, pz_m = 0;
                 int otri[SPL], omesh[SPL];
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
                     const int64_t i = wave_base + k * 64 + lane;
-                    const float dx = p[k].x - fr.ex, dy = p[k].y - fr.ey, dz = p[k].z - fr.ez;
-                    const float dk = pick(kz, dx, dy, dz);
-                    shared = shared && (!need[k] || dk * dk >= 0.16f * (dx * dx + dy * dy + dz * dz));
-                    nx_m |= ballot(need[k] && signbit(dx));
-                    ny_m |= ballot(need[k] && signbit(dy));
-                    nz_m |= ballot(need[k] && signbit(dz));
-                    px_m |= ballot(need[k] && !signbit(dx));
-                    py_m |= ballot(need[k] && !signbit(dy));
-                    pz_m |= ballot(need[k] && !signbit(dz));
                     otri[k] = need[k] ? __float_as_int(p[k].w) : -1;
                     omesh[k] = need[k] ? a.smesh[i] : -1;
                 }
-                // ... and every segment of every slot has the same direction signs
-                shared = ballot(!shared) == 0 && (nx_m == 0 || px_m == 0) && (ny_m == 0 || py_m == 0) &&
-                         (nz_m == 0 || pz_m == 0);
-                Seg sg[SPL];
-                if (shared) {
-#pragma unroll
-                    for (int k = 0; k < SPL; ++k)
-                        sg[k] = make_seg(fr.ex, fr.ey, fr.ez, p[k].x, p[k].y, p[k].z, kx, ky, kz, a.tmax);
-                    const int oct = (nx_m != 0 ? 1 : 0) | (ny_m != 0 ? 2 : 0) | (nz_m != 0 ? 4 : 0);
-                    occluded_packet<SPL, true>(a.nodes + oct * a.node_stride, a.tris + kz * a.tri_stride,
-                                               pick(kx, fr.ex, fr.ey, fr.ez), pick(ky, fr.ex, fr.ey, fr.ez),
-                                               pick(kz, fr.ex, fr.ey, fr.ez), oct, sg, otri, omesh, a.occ_mode,
-                                               a.tmax, need, occl, n_visits);
+                if (!POSED) {
+                    packet_visibility<SPL>(a.nodes, a.node_stride, a.tris, a.tri_stride, fr.ex, fr.ey, fr.ez, fr.rx,
+                                           fr.ry, fr.rz, p, otri, omesh, a.occ_mode, a.tmax, need, occl, n_visits);
+                    ++n_trav;
                 } else {
+                    // every mesh in its own frame at this fixation's time: the points move
+                    // with their mesh (forward pose of this launch's mesh), then into the
+                    // occluding mesh's frame (its inverse pose); the eye and gaze of that
+                    // frame are that mesh's fixation record.  tau is unchanged by the
+                    // (affine) change of frame.
+                    const float* fw = a.xf + ((int64_t)a.self_mesh * a.fix_stride + f) * 24;
+                    const int m_lo = a.occ_mode == 1 ? a.self_mesh : 0;
+                    const int m_hi = a.occ_mode == 1 ? a.self_mesh + 1 : a.n_inst;
+                    for (int mi = m_lo; mi < m_hi; ++mi) {
+                        bool rest[SPL];
+                        bool any = false;
 #pragma unroll
-                    for (int k = 0; k < SPL; ++k) {
-                        int lx, ly, lz;
-                        axis_order(p[k].x - fr.ex, p[k].y - fr.ey, p[k].z - fr.ez, lx, ly, lz);
-                        sg[k] = make_seg(fr.ex, fr.ey, fr.ez, p[k].x, p[k].y, p[k].z, lx, ly, lz, a.tmax);
+                        for (int k = 0; k < SPL; ++k) {
+                            rest[k] = need[k] && !occl[k];
+                            any = any || rest[k];
+                        }
+                        if (ballot(any) == 0) break;
+                        const BlasDesc b = a.blas[mi];
+                        const FixRec fo = load_fix(a.fix_all + (int64_t)mi * a.fix_stride, f);
+                        float4 q[SPL];
+                        if (mi == a.self_mesh) {
+#pragma unroll
+                            for (int k = 0; k < SPL; ++k) q[k] = p[k];
+                        } else {
+                            const float* iv = a.xf + ((int64_t)mi * a.fix_stride + f) * 24 + 12;
+#pragma unroll
+                            for (int k = 0; k < SPL; ++k) {
+                                const float wx = __builtin_fmaf(fw[0], p[k].x, __builtin_fmaf(fw[1], p[k].y, __builtin_fmaf(fw[2], p[k].z, fw[3])));
+                                const float wy = __builtin_fmaf(fw[4], p[k].x, __builtin_fmaf(fw[5], p[k].y, __builtin_fmaf(fw[6], p[k].z, fw[7])));
+                                const float wz = __builtin_fmaf(fw[8], p[k].x, __builtin_fmaf(fw[9], p[k].y, __builtin_fmaf(fw[10], p[k].z, fw[11])));
+                                q[k].x = __builtin_fmaf(iv[0], wx, __builtin_fmaf(iv[1], wy, __builtin_fmaf(iv[2], wz, iv[3])));
+                                q[k].y = __builtin_fmaf(iv[4], wx, __builtin_fmaf(iv[5], wy, __builtin_fmaf(iv[6], wz, iv[7])));
+                                q[k].z = __builtin_fmaf(iv[8], wx, __builtin_fmaf(iv[9], wy, __builtin_fmaf(iv[10], wz, iv[11])));
+                                q[k].w = p[k].w;
+                            }
+                        }
+                        bool o2[SPL];
+                        packet_visibility<SPL>(a.blas_nodes + b.node_base, b.node_count, a.blas_tris + b.tri_base,
+                                               b.tri_count, fo.ex, fo.ey, fo.ez, fo.rx, fo.ry, fo.rz, q, otri, omesh,
+                                               2, a.tmax, rest, o2, n_visits);
+#pragma unroll
+                        for (int k = 0; k < SPL; ++k) occl[k] = occl[k] || o2[k];
+                        ++n_trav;
                     }
-                    // child order from one lane's octant (the order affects speed, not results)
-                    const int lead = __builtin_ctzll(nx_m | px_m);
-                    const int oct = (int)((nx_m >> lead) & 1) | (int)(((ny_m >> lead) & 1) << 1) |
-                                    (int)(((nz_m >> lead) & 1) << 2);
-                    occluded_packet<SPL, false>(a.nodes, a.tris + 2 * a.tri_stride, fr.ex, fr.ey, fr.ez, oct, sg,
-                                                otri, omesh, a.occ_mode, a.tmax, need, occl, n_visits);
                 }
-                ++n_trav;
             }
 #pragma unroll
             for (int k = 0; k < SPL; ++k) {
@@ -701,12 +863,12 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
     __syncthreads();  // LDS is reused by the next item of a persistent workgroup
 }
 
-template <int SPL, int OCC>
+template <int SPL, int OCC, bool POSED = false>
 __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
 {
     const unsigned G = gridDim.x * gridDim.y;
     const unsigned L = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, G);
-    density_item<SPL, OCC, kFB>(a, (int64_t)(L % gridDim.x), (int)(L / gridDim.x));
+    density_item<SPL, OCC, kFB, POSED>(a, (int64_t)(L % gridDim.x), (int)(L / gridDim.x));
 }
 
 // Persistent form for many sessions: every workgroup pulls (session, tile, chunk)
@@ -835,6 +997,18 @@ void launch_fix_prep(const float* eye, const float* gaze, const float* dur, int3
     k_fix_shift<<<1, 1, 0, s>>>(wmax, F, fx_shift);
 }
 
+void launch_fix_posed(const float* eye, const float* gaze, const float* dur, const double* time, const float* pose,
+                      int32_t F, int32_t M, int64_t stride, double t0, double t1, double sigma, double widen,
+                      FixRec* rec, float* xf, unsigned int* kept, unsigned long long* budget,
+                      unsigned long long* totals, hipStream_t s)
+{
+    const double inv_norm = 1.0 / (sigma * std::sqrt(2.0 * M_PI));
+    const double kappa_scale = (1.0 - widen) / (1.0 + 16.0 * sigma * sigma);
+    if (F > 0)
+        k_fix_posed<<<blocks(F, 256), 256, 0, s>>>(eye, gaze, dur, time, pose, F, M, stride, t0, t1, inv_norm,
+                                                   kappa_scale, rec, xf, kept, budget, totals);
+}
+
 void launch_fix_select(const float* eye, const float* gaze, const float* dur, const double* time, int32_t F,
                        double t0, double t1, double sigma, double widen, FixRec* rec, unsigned int* kept,
                        unsigned long long* budget, unsigned long long* totals, hipStream_t s)
@@ -857,10 +1031,11 @@ void launch_morton(const float* pos, const int32_t* tri, const int32_t* mesh, co
 
 void launch_scatter(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh, int64_t T,
                     int64_t n, const uint32_t* key, uint32_t* cursor, float4* spos, int32_t* smesh, int32_t* perm,
-                    hipStream_t s)
+                    int32_t base, hipStream_t s)
 {
     if (n > 0)
-        k_scatter<<<blocks(n, 256), 256, 0, s>>>(pos, tri, mesh, tri_mesh, T, n, key, cursor, spos, smesh, perm);
+        k_scatter<<<blocks(n, 256), 256, 0, s>>>(pos, tri, mesh, tri_mesh, T, n, key, cursor, spos, smesh, perm,
+                                                 base);
 }
 
 void launch_density(const DensityLaunch& a, hipStream_t s)
@@ -869,6 +1044,14 @@ void launch_density(const DensityLaunch& a, hipStream_t s)
     const int64_t per_tile = (int64_t)kThreads * a.spl;
     const dim3 grid(blocks(a.n, (int)per_tile), (unsigned)a.n_chunks);
     const bool occ = a.occ_mode != 0;
+    if (occ && a.blas) {
+        switch (a.spl) {
+        case 1: k_density<1, 1, true><<<grid, kThreads, 0, s>>>(a); break;
+        case 2: k_density<2, 1, true><<<grid, kThreads, 0, s>>>(a); break;
+        default: k_density<4, 1, true><<<grid, kThreads, 0, s>>>(a); break;
+        }
+        return;
+    }
     switch (a.spl) {
     case 1: occ ? k_density<1, 1><<<grid, kThreads, 0, s>>>(a) : k_density<1, 0><<<grid, kThreads, 0, s>>>(a); break;
     case 2: occ ? k_density<2, 1><<<grid, kThreads, 0, s>>>(a) : k_density<2, 0><<<grid, kThreads, 0, s>>>(a); break;

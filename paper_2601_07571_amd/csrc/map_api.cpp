@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "gazemap.h"
 #include "gm_host.h"
@@ -36,6 +37,11 @@ struct gm_map {
     DensityWork w;     // sorted points, accumulators, records of the last block
     DevBuf live;       // records of the block being added
     DevBuf counters;   // [kMapCounters] uint64
+    // posed maps: points grouped by mesh, mesh m at sorted entries [moff[m], moff[m + 1]);
+    // per block, records [M][stride] and pose pairs [M][stride][24]
+    bool posed = false;
+    std::vector<int64_t> moff;
+    DevBuf recs, xf;
 };
 
 namespace {
@@ -62,6 +68,78 @@ gm_status map_clear(gm_map* m, hipStream_t s)
     return GM_OK;
 }
 
+// One BVH per mesh in the mesh's own frame, from the scene's triangle records (the
+// same FP32 vertices), with the octant node copies and axis-permuted record copies of
+// the scene BVH; record ids stay scene-global.
+gm_status ensure_blas(gm_scene* sc)
+{
+    if (!sc->blas.empty()) return GM_OK;
+    const int32_t M = sc->M;
+    std::vector<std::vector<int64_t>> per((size_t)M);
+    for (size_t i = 0; i < sc->bvh.tris.size(); ++i) {
+        const BvhTri& r = sc->bvh.tris[i];
+        if (r.id >= 0 && r.mesh >= 0 && r.mesh < M) per[(size_t)r.mesh].push_back((int64_t)i);
+    }
+    std::vector<BvhNode> all_nodes;
+    std::vector<BvhTri> all_tris;
+    std::vector<BlasDesc> desc((size_t)M);
+    for (int32_t m = 0; m < M; ++m) {
+        const std::vector<int64_t>& ids = per[(size_t)m];
+        const int64_t Tm = (int64_t)ids.size();
+        std::vector<float> V((size_t)(9 * std::max<int64_t>(Tm, 1)));
+        std::vector<int32_t> I((size_t)(3 * std::max<int64_t>(Tm, 1))), tm((size_t)std::max<int64_t>(Tm, 1), m),
+            gid((size_t)std::max<int64_t>(Tm, 1));
+        for (int64_t j = 0; j < Tm; ++j) {
+            const BvhTri& r = sc->bvh.tris[(size_t)ids[(size_t)j]];
+            for (int k = 0; k < 3; ++k) {
+                V[(size_t)(9 * j + k)] = r.v0[k];
+                V[(size_t)(9 * j + 3 + k)] = r.v1[k];
+                V[(size_t)(9 * j + 6 + k)] = r.v2[k];
+                I[(size_t)(3 * j + k)] = (int32_t)(3 * j + k);
+            }
+            gid[(size_t)j] = r.id;
+        }
+        HostBvh hb;
+        build_bvh(V.data(), I.data(), tm.data(), Tm, hb);
+        for (BvhTri& r : hb.tris)
+            if (r.id >= 0) r.id = gid[(size_t)r.id];
+        std::vector<BvhNode> n8;
+        octant_node_copies(hb.nodes, n8);
+        std::vector<BvhTri> t3;
+        permute_tri_copies(hb.tris, t3);
+        desc[(size_t)m] = BlasDesc{(int64_t)all_nodes.size(), (int64_t)hb.nodes.size(), (int64_t)all_tris.size(),
+                                   (int64_t)hb.tris.size()};
+        all_nodes.insert(all_nodes.end(), n8.begin(), n8.end());
+        all_tris.insert(all_tris.end(), t3.begin(), t3.end());
+    }
+    auto up = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
+        hipError_t e = b.ensure(bytes);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e = up(sc->blas_nodes, all_nodes.data(), all_nodes.size() * sizeof(BvhNode));
+    if (e == hipSuccess) e = up(sc->blas_tris, all_tris.data(), all_tris.size() * sizeof(BvhTri));
+    if (e == hipSuccess) e = up(sc->blas_desc, desc.data(), desc.size() * sizeof(BlasDesc));
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? GM_ERR_OUT_OF_MEMORY : GM_ERR_DEVICE, "per-mesh BVH upload: %s",
+                    hipGetErrorString(e));
+    sc->blas = desc;
+    return GM_OK;
+}
+
+gm_status check_block(const gm_map* m, const gm_fixations* fix, const double* time, double t_begin, double t_end)
+{
+    gm_status st = check_map(m);
+    if (st != GM_OK) return st;
+    if (!fix) return fail(GM_ERR_INVALID_ARGUMENT, "fixations is NULL");
+    if (fix->n < 0) return fail(GM_ERR_INVALID_ARGUMENT, "fixation count < 0");
+    if (fix->n > 0 && (!fix->eye || !fix->gaze || !fix->duration))
+        return fail(GM_ERR_INVALID_ARGUMENT, "fixation arrays must not be NULL");
+    if (time && (std::isnan(t_begin) || std::isnan(t_end)))
+        return fail(GM_ERR_INVALID_ARGUMENT, "the time window bounds must not be NaN");
+    return GM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -77,14 +155,41 @@ gm_status gm_map_create(gm_scene* sc, const float* pos, const int32_t* tri, cons
     if (n > 0 && !pos) return fail(GM_ERR_INVALID_ARGUMENT, "pos is NULL");
     if (!(theta_deg > 0.0 && theta_deg < 45.0)) return fail(GM_ERR_INVALID_ARGUMENT, "theta_deg must be in (0, 45)");
     const uint32_t mode = flags & GM_OCC_MASK;
-    if (mode > GM_OCC_FULL || (flags & ~GM_OCC_MASK)) return fail(GM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", flags);
+    const bool posed = (flags & GM_MAP_POSED) != 0;
+    if (mode > GM_OCC_FULL || (flags & ~(GM_OCC_MASK | GM_MAP_POSED)))
+        return fail(GM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", flags);
+    if (posed && n > 0 && !mesh) return fail(GM_ERR_INVALID_ARGUMENT, "a posed map needs the points' mesh ids");
     if (!(max_total_duration > 0.0 && max_total_duration <= 1e9))
         return fail(GM_ERR_INVALID_ARGUMENT, "max_total_duration must be in (0, 1e9] seconds");
     gm_status st = check_device(sc);
     if (st != GM_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> moff;
+    if (posed) {
+        // points must come grouped by mesh (as the samplers write them)
+        std::vector<int32_t> hm((size_t)std::max<int64_t>(n, 1));
+        if (n > 0) {
+            GM_HIP(hipStreamSynchronize(s));
+            GM_HIP(hipMemcpy(hm.data(), mesh, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost));
+        }
+        moff.assign((size_t)sc->M + 1, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t v = hm[(size_t)i];
+            if (v < 0 || v >= sc->M) return fail(GM_ERR_INVALID_ARGUMENT, "point %lld: mesh %d out of range", (long long)i, v);
+            if (i > 0 && v < hm[(size_t)i - 1])
+                return fail(GM_ERR_INVALID_ARGUMENT, "a posed map needs its points grouped by mesh, in mesh order");
+            ++moff[(size_t)v + 1];
+        }
+        for (int32_t k = 0; k < sc->M; ++k) moff[(size_t)k + 1] += moff[(size_t)k];
+        if (mode != GM_OCC_NONE) {
+            st = ensure_blas(sc);
+            if (st != GM_OK) return st;
+        }
+    }
 
     gm_map* m = new gm_map;
+    m->posed = posed;
+    m->moff = moff;
     m->scene = sc;
     m->device = sc->device;
     m->n = n;
@@ -105,7 +210,14 @@ gm_status gm_map_create(gm_scene* sc, const float* pos, const int32_t* tri, cons
         return st;
     }
     fill_u32(m->w.fx_shift.p, 1, (uint32_t)m->shift, s);
-    density_sort(sc, m->w, pos, tri, mesh, n, s);
+    if (!posed) {
+        density_sort(sc, m->w, pos, tri, mesh, n, s);
+    } else {
+        for (int32_t k = 0; k < sc->M; ++k) {
+            const int64_t off = moff[(size_t)k], nk = moff[(size_t)k + 1] - off;
+            density_sort(sc, m->w, pos + 3 * off, tri ? tri + off : nullptr, mesh + off, nk, s, off);
+        }
+    }
     st = map_clear(m, s);
     if (st == GM_OK) {
         const hipError_t e2 = hipGetLastError();
@@ -123,14 +235,9 @@ gm_status gm_map_add(gm_map* m, const gm_fixations* fix, const double* time, dou
                      void* stream)
 {
     clear_error();
-    gm_status st = check_map(m);
+    gm_status st = check_block(m, fix, time, t_begin, t_end);
     if (st != GM_OK) return st;
-    if (!fix) return fail(GM_ERR_INVALID_ARGUMENT, "fixations is NULL");
-    if (fix->n < 0) return fail(GM_ERR_INVALID_ARGUMENT, "fixation count < 0");
-    if (fix->n > 0 && (!fix->eye || !fix->gaze || !fix->duration))
-        return fail(GM_ERR_INVALID_ARGUMENT, "fixation arrays must not be NULL");
-    if (time && (std::isnan(t_begin) || std::isnan(t_end)))
-        return fail(GM_ERR_INVALID_ARGUMENT, "the time window bounds must not be NaN");
+    if (m->posed) return fail(GM_ERR_INVALID_ARGUMENT, "a posed map takes its fixations with gm_map_add_posed");
     hipStream_t s = (hipStream_t)stream;
     const int32_t F = fix->n;
     if (F == 0) return GM_OK;
@@ -144,6 +251,53 @@ gm_status gm_map_add(gm_map* m, const gm_fixations* fix, const double* time, dou
         density_args(m->scene, m->w, m->n, F, m->sigma, m->mode, m->spl, 0, a);
         a.F_live = m->live.as<unsigned int>();
         zero(m->w.stats.p, 8 * kDensityStats, s);
+        launch_density(a, s);
+    }
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
+gm_status gm_map_add_posed(gm_map* m, const gm_fixations* fix, const float* pose, const double* time,
+                           double t_begin, double t_end, void* stream)
+{
+    clear_error();
+    gm_status st = check_block(m, fix, time, t_begin, t_end);
+    if (st != GM_OK) return st;
+    if (!m->posed) return fail(GM_ERR_INVALID_ARGUMENT, "the map was not created with GM_MAP_POSED");
+    const int32_t F = fix->n;
+    if (F > 0 && !pose) return fail(GM_ERR_INVALID_ARGUMENT, "pose is NULL");
+    if (F == 0) return GM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    gm_scene* sc = m->scene;
+    const int32_t M = sc->M;
+    const int64_t stride = F;
+    GM_HIP(m->recs.ensure(sizeof(FixRec) * (size_t)M * (size_t)stride));
+    GM_HIP(m->xf.ensure(sizeof(float) * 24 * (size_t)M * (size_t)stride));
+    unsigned long long* c = m->counters.as<unsigned long long>();
+    zero(m->live.p, 4, s);
+    launch_fix_posed(fix->eye, fix->gaze, fix->duration, time, pose, F, M, stride, t_begin, t_end, m->sigma,
+                     kGateWiden, m->recs.as<FixRec>(), m->xf.as<float>(), m->live.as<unsigned int>(), c, c + 2, s);
+    zero(m->w.stats.p, 8 * kDensityStats, s);
+    for (int32_t k = 0; k < M; ++k) {
+        const int64_t off = m->moff[(size_t)k], nk = m->moff[(size_t)k + 1] - off;
+        if (nk <= 0) continue;
+        DensityLaunch a;
+        density_args(sc, m->w, nk, F, m->sigma, m->mode, m->spl, 0, a);
+        a.spos += off;
+        a.smesh += off;
+        a.acc += off;
+        a.fix = m->recs.as<FixRec>() + (int64_t)k * stride;
+        a.F_live = m->live.as<unsigned int>();
+        if (m->mode != GM_OCC_NONE) {
+            a.blas = sc->blas_desc.as<BlasDesc>();
+            a.blas_nodes = sc->blas_nodes.as<BvhNode>();
+            a.blas_tris = sc->blas_tris.as<BvhTri>();
+            a.fix_all = m->recs.as<FixRec>();
+            a.xf = m->xf.as<float>();
+            a.fix_stride = stride;
+            a.n_inst = M;
+            a.self_mesh = k;
+        }
         launch_density(a, s);
     }
     GM_HIP(hipGetLastError());

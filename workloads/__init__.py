@@ -354,6 +354,68 @@ def start_times(dur, gap=0.03):
     return np.concatenate([[0.0], np.cumsum(d)[:-1]]) if len(d) else np.zeros(0)
 
 
+def plate_mesh(size=0.8, cells=8, name="plate"):
+    """Square grid of cells x cells quads in the local x-y plane, centred at the origin."""
+    h = size / 2.0
+    g = np.linspace(-h, h, cells + 1)
+    V = np.array([[x, y, 0.0] for y in g for x in g])
+    F = []
+    for j in range(cells):
+        for i in range(cells):
+            a = j * (cells + 1) + i
+            F += [(a, a + 1, a + cells + 2), (a, a + cells + 2, a + cells + 1)]
+
+    def aim(rng, n):
+        P = np.zeros((n, 3)); P[:, :2] = rng.uniform(-h, h, (n, 2))
+        N = np.zeros((n, 3)); N[:, 2] = 1.0
+        return P, N
+    return Mesh(V.astype(np.float32), np.array(F, np.int32), name, aim)
+
+
+def _rot(axis, ang):
+    a = np.asarray(axis, np.float64); a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * (K @ K)
+
+
+def posed_scene(seed=0, F=40, k=6000.0):
+    """Objects that move during a recording: a sphere (R 0.4 m, 1,280 triangles) sliding and
+    turning, a cube (0.4 m, scaled by 1.25) orbiting and tumbling, and a 0.8 m plate that
+    slides back and forth in front of the sphere; each mesh in its own frame, centred at its
+    origin.  pose [F][3][12]: row-major 3x4 (A | b), mesh frame -> world at each fixation's
+    start time.  Eyes in the 1.8-2.6 m shell on the -y side, gaze at a surface point of a
+    posed object with 1 degree jitter, t ~ U[0.1, 0.5] s; theta = 1 degree."""
+    rng = np.random.default_rng(seed)
+    meshes = [sphere_mesh(level=3, radius=0.4, name="sphere"), cube_mesh(0.4, name="cube"),
+              plate_mesh(0.8, 8, name="plate")]
+    dur = rng.uniform(0.1, 0.5, F)
+    t = start_times(dur)
+    pose = np.zeros((F, 3, 3, 4))
+    for f in range(F):
+        tau = t[f]
+        pose[f, 0, :, :3] = _rot((0, 0, 1), 0.2 * tau)
+        pose[f, 0, :, 3] = (0.6 * math.sin(0.3 * tau), 0.3, 0.0)
+        pose[f, 1, :, :3] = 1.25 * _rot((1, 1, 0), 0.5 * tau)
+        pose[f, 1, :, 3] = (0.9 * math.cos(0.4 * tau), 0.9 * math.sin(0.4 * tau), 0.5)
+        pose[f, 2, :, :3] = _rot((1, 0, 0), math.pi / 2)
+        pose[f, 2, :, 3] = (-0.2 + 0.8 * math.sin(0.9 * tau), -0.45, 0.0)
+    u = rng.uniform(1.8 ** 3, 2.6 ** 3, F) ** (1.0 / 3.0)
+    d = rng.normal(size=(F, 3)); d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d[:, 1] = -np.abs(d[:, 1]) - 0.5
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    eye = u[:, None] * d
+    obj = rng.integers(0, 3, F)
+    tgt = np.zeros((F, 3))
+    for f in range(F):
+        P, _ = meshes[obj[f]].aim(rng, 1)
+        A = pose[f, obj[f], :, :3]; b = pose[f, obj[f], :, 3]
+        tgt[f] = A @ P[0] + b
+    gaze = _jitter(rng, tgt - eye, 1.0)
+    fix = Fixations(eye.astype(np.float32), gaze.astype(np.float32), dur.astype(np.float32))
+    return Workload("posed", meshes, fix, 1.0, k, seed, "full",
+                    {"pose": pose.reshape(F, 3, 12).astype(np.float32), "time": t})
+
+
 def tiny_icosphere_scene(seed=0):
     """Icosphere level 3 (1,280 triangles), R = 0.5 m at the origin, 2,000 samples/m^2,
     Philox seed 0; 100 fixations, eyes uniform in the 1.5-2.5 m shell, gaze at uniform
