@@ -13,6 +13,7 @@ events that the library records on its launch stream; `cpu_baseline` is the FP64
 oracle timed on this host on a bounded sample of the same workload.
 """
 import argparse
+import math
 import json
 import os
 import sys
@@ -38,6 +39,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-session batched comparison")
     ap.add_argument("--no-field", action="store_true", help="skip the neural-field comparison")
     ap.add_argument("--field-steps", type=int, default=20000)
+    ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-map and time-window timing")
+    ap.add_argument("--no-posed", action="store_true", help="skip the moving-objects timing")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one plain copy of known size, then one full-occlusion step, and exit (for HBM counters)")
     args = ap.parse_args()
@@ -143,7 +146,10 @@ def main():
     }
 
     out["lattice"] = bench_lattice(gm, torch, args, scene, k)
-    out["incremental"] = bench_incremental(gm, workloads, torch, np, args, scene, samples, fix, w, ms_step)
+    if not args.no_incremental:
+        out["incremental"] = bench_incremental(gm, workloads, torch, np, args, scene, samples, fix, w, ms_step)
+    if not args.no_posed:
+        out["posed"] = bench_posed(gm, workloads, torch, np, args, scene, samples, fix, w, ms_step)
     if not args.no_batched:
         out["batched"] = bench_batched(gm, workloads, torch, args)
     if not args.no_field:
@@ -254,6 +260,50 @@ def bench_incremental(gm, workloads, torch, np, args, scene, samples, fix, w, pl
     return {"blocks": len(blocks), "fixations_per_block": 500, "feed_ms": feed_ms, "plain_call_ms": plain_ms,
             "window_s": 300.0, "window_fixations": int(((t >= win[0]) & (t < win[1])).sum()),
             "recording_s": float(t[-1] + w.fix.dur[-1]), "window_ms": win_ms}
+
+
+def bench_posed(gm, workloads, torch, np, args, scene, samples, fix, w, plain_ms):
+    """The same recording with moving objects: each object of the paper-shaped scene turns
+    about the vertical axis through its centre (0.05, 0.10, 0.15 rad/s; the heightfield
+    stays), one pose per mesh per fixation at its start time; full occlusion between the
+    moving objects.  Also the same map with identity poses (the static scene through the
+    posed path) and the number of samples where it differs from the plain map."""
+    t = workloads.start_times(w.fix.dur)
+    M = len(w.meshes)
+    pose = np.zeros((fix.n, M, 3, 4))
+    for m, mesh in enumerate(w.meshes):
+        c = 0.5 * (mesh.V.min(0).astype(np.float64) + mesh.V.max(0))
+        rate = 0.05 * (m + 1) if m < M - 1 else 0.0
+        for f in range(fix.n):
+            a = rate * t[f]
+            R = np.array([[math.cos(a), 0, math.sin(a)], [0, 1, 0], [-math.sin(a), 0, math.cos(a)]])
+            pose[f, m, :, :3] = R
+            pose[f, m, :, 3] = c - R @ c
+    pose_d = torch.as_tensor(pose.reshape(fix.n, M, 12).astype(np.float32), device="cuda")
+    ident = torch.zeros_like(pose_d)
+    ident[:, :, 0] = ident[:, :, 5] = ident[:, :, 10] = 1.0
+    m = gm.DensityMap(scene, samples.pos, w.theta_deg, occlusion="full", tri=samples.tri, mesh=samples.mesh,
+                      posed=True)
+    res = m.read()
+
+    def run(p):
+        m.reset()
+        m.add_posed(fix, p)
+        m.read(out=res)
+
+    run(pose_d)
+    moving_ms = _time(lambda: run(pose_d), torch, max(1, args.steps // 2))
+    moving = res.density.clone()
+    run(ident)
+    ident_ms = _time(lambda: run(ident), torch, max(1, args.steps // 2))
+    plain = scene.accumulate(samples.pos, fix, w.theta_deg, occlusion="full", tri=samples.tri, mesh=samples.mesh)
+    torch.cuda.synchronize()
+    d, p = res.density, plain.density
+    differ = int(((d - p).abs() > 1e-6 * p + 1e-8).sum())
+    return {"map_ms_moving": moving_ms, "map_ms_identity_poses": ident_ms, "plain_map_ms": plain_ms,
+            "samples_moved_by_motion": int(((moving - p).abs() > 1e-6 * p + 1e-8).sum()),
+            "identity_vs_plain_samples_differing": differ, "samples": int(samples.pos.shape[0]),
+            "meshes": M, "fixations": fix.n}
 
 
 def bench_batched(gm, workloads, torch, args):

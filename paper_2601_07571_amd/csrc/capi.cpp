@@ -219,10 +219,15 @@ void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F
     a.stats = w.stats.as<unsigned long long>();
     a.spl = spl;
     if (fix_per_chunk <= 0) {
-        // enough work items to fill the chip: ~4096 (tile, chunk) pairs, chunks of >= 128 fixations
+        // The cost of a (tile, chunk) item varies a lot (how many of its fixations see
+        // the tile), so the grid holds many small items: at least ~64k of them and at
+        // most 1024 fixations each, but chunks of no fewer than 128 fixations.
         const int64_t tiles = std::max<int64_t>(1, (n + 256 * spl - 1) / (256 * spl));
         const int64_t max_chunks = std::max<int64_t>(1, (F + 127) / 128);
-        const int64_t chunks = std::min<int64_t>(max_chunks, std::max<int64_t>(1, (4096 + tiles - 1) / tiles));
+        const int64_t want = std::max<int64_t>((65536 + tiles - 1) / tiles, (F + 1023) / 1024);
+        // the grid is tiles x chunks: chunks <= 65535 (grid y) and tiles x chunks < 2^31
+        const int64_t cap = std::min<int64_t>(65535, std::max<int64_t>(1, INT32_MAX / tiles));
+        const int64_t chunks = std::min<int64_t>(std::min(max_chunks, cap), std::max<int64_t>(1, want));
         fix_per_chunk = (int32_t)std::max<int64_t>(1, (F + chunks - 1) / chunks);
     }
     a.fix_per_chunk = fix_per_chunk;
@@ -467,6 +472,7 @@ gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri,
     const int spl = sc->spl ? sc->spl : ((flags & GM_OCC_MASK) != GM_OCC_NONE ? 1 : 2);
     st = density_prep(sc, w, pos, tri, mesh, n, fix, theta_deg, flags & GM_OCC_MASK, spl, 0, a, s);
     if (st != GM_OK) return st;
+
     GM_HIP(sc->tend(kStagePrep, s));
     if (n > 0 && fix->n > 0) {
         GM_HIP(sc->tbegin(kStageDensity, s));

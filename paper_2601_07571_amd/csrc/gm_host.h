@@ -193,6 +193,8 @@ void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F
 // maximum and outputs
 gm_status density_finalize(DensityWork& w, int64_t n, float* density, float* density_norm, float* max_out,
                            hipStream_t s);
+// the scene's per-mesh BVHs (gm_scene::blas), built and uploaded once
+gm_status ensure_blas(gm_scene* sc);
 void zero(void* p, size_t bytes, hipStream_t s);
 void fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
 }  // namespace gm

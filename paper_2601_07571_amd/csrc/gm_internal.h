@@ -140,10 +140,11 @@ struct DensityLaunch {
     int32_t n_chunks;
     int32_t spl;               // samples per lane
     const unsigned int* F_live = nullptr;  // device count of valid records (<= F), or NULL: all F
-    // Posed scenes (meshes that move between fixations): one BVH per mesh in its own
-    // frame, fixation records per mesh (fix = fix_all + self_mesh * fix_stride) and
-    // per (mesh, fixation) 24 floats: the 3x4 pose (mesh -> world), then its inverse.
-    // blas == NULL: the static scene BVH above.
+    // One BVH per mesh (blas, n_inst of them; NULL: the scene BVH above).  Static
+    // scenes: xf and fix_all NULL, every mesh in the world frame.  Posed launches
+    // (meshes that move between fixations, one launch per mesh self_mesh): fixation
+    // records per mesh (fix = fix_all + self_mesh * fix_stride) and per (mesh,
+    // fixation) 24 floats, the 3x4 pose (mesh -> world) and then its inverse.
     const BlasDesc* blas = nullptr;
     const BvhNode* blas_nodes = nullptr;
     const BvhTri* blas_tris = nullptr;

@@ -600,18 +600,6 @@ __global__ void k_scatter(const float* __restrict__ pos, const int32_t* __restri
 // ---------------------------------------------------------------------------
 // a5 + a6: gate, exact value, visibility, fixed-point accumulation
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned xcd_block(unsigned L, unsigned G)
-{
-    // consecutive tiles on the same XCD (workgroups go round-robin over 8 XCDs)
-    const unsigned q = G >> 3;
-    if (L >= (q << 3)) return L;
-    return (L & 7u) * q + (L >> 3);
-}
-
-// One work item of the density map: the samples of one tile (256 * SPL consecutive
-// sorted samples) against one chunk of the fixations, by the whole workgroup.
-// OCC = 0: no occlusion (no traversal code); OCC = 1: visibility by the BVH when
-// a.occ_mode != 0.  FB: fixations staged in LDS per round.
 // Visibility of the wave's slots that need it, for one fixation, in one frame: the
 // segments run from the eye (ex, ey, ez) to the points p[k], both in the frame of the
 // BVH whose octant node copies start at `nodes` (node_stride nodes apart) and whose
@@ -674,8 +662,12 @@ __device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ no
     }
 }
 
-template <int SPL, int OCC, int FB, bool POSED = false>
-__device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t tile, int chunk)
+// One work item of the density map: the samples of one tile (256 * SPL consecutive
+// sorted samples) against one chunk of the fixations, by the whole workgroup.
+// OCC = 0: no occlusion (no traversal code); OCC = 1: visibility by the BVH when
+// a.occ_mode != 0.  FB: fixations staged in LDS per round.
+template <int SPL, int OCC, int FB, bool INST = false>
+__device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t tile, int chunk, int F)
 {
     __shared__ float4 s_ra[FB];  // rx, ry, rz, c0
     __shared__ float4 s_rb[FB];  // ax, ay, az, cc
@@ -715,7 +707,6 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
 
     const int shift = *a.fx_shift;
     const int f_begin = chunk * a.fix_per_chunk;
-    const int F = a.F_live ? min(a.F, (int)*a.F_live) : a.F;
     const int f_end = min(F, f_begin + a.fix_per_chunk);
 
     for (int fb = f_begin; fb < f_end; fb += FB) {
@@ -787,45 +778,50 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                     otri[k] = need[k] ? __float_as_int(p[k].w) : -1;
                     omesh[k] = need[k] ? a.smesh[i] : -1;
                 }
-                if (!POSED) {
+                if (!INST) {
                     packet_visibility<SPL>(a.nodes, a.node_stride, a.tris, a.tri_stride, fr.ex, fr.ey, fr.ez, fr.rx,
                                            fr.ry, fr.rz, p, otri, omesh, a.occ_mode, a.tmax, need, occl, n_visits);
                     ++n_trav;
                 } else {
-                    // every mesh in its own frame at this fixation's time: the points move
-                    // with their mesh (forward pose of this launch's mesh), then into the
-                    // occluding mesh's frame (its inverse pose); the eye and gaze of that
-                    // frame are that mesh's fixation record.  tau is unchanged by the
-                    // (affine) change of frame.
-                    const float* fw = a.xf + ((int64_t)a.self_mesh * a.fix_stride + f) * 24;
-                    const int m_lo = a.occ_mode == 1 ? a.self_mesh : 0;
-                    const int m_hi = a.occ_mode == 1 ? a.self_mesh + 1 : a.n_inst;
-                    for (int mi = m_lo; mi < m_hi; ++mi) {
+                    // One BVH per mesh.  Static scenes (xf NULL): every mesh in the world
+                    // frame, the segments as they are.  Posed launches: every mesh in its
+                    // own frame at this fixation's time; the points move with their mesh
+                    // (forward pose of this launch's mesh), then into the occluding mesh's
+                    // frame (its inverse pose), whose eye and gaze are that mesh's fixation
+                    // record; tau is unchanged by the (affine) change of frame.  With
+                    // GM_OCC_SELF a lane takes part only in its own mesh.
+                    const bool moving = a.xf != nullptr;
+                    const float* fw = moving ? a.xf + ((int64_t)a.self_mesh * a.fix_stride + f) * 24 : nullptr;
+                    for (int mi = 0; mi < a.n_inst; ++mi) {
                         bool rest[SPL];
-                        bool any = false;
+                        bool left = false, any = false;
 #pragma unroll
                         for (int k = 0; k < SPL; ++k) {
-                            rest[k] = need[k] && !occl[k];
+                            const bool r = need[k] && !occl[k];
+                            left = left || r;
+                            rest[k] = r && (a.occ_mode != 1 || omesh[k] == mi);
                             any = any || rest[k];
                         }
-                        if (ballot(any) == 0) break;
+                        if (ballot(left) == 0) break;
+                        if (ballot(any) == 0) continue;
                         const BlasDesc b = a.blas[mi];
-                        const FixRec fo = load_fix(a.fix_all + (int64_t)mi * a.fix_stride, f);
+                        FixRec fo = fr;
                         float4 q[SPL];
-                        if (mi == a.self_mesh) {
 #pragma unroll
-                            for (int k = 0; k < SPL; ++k) q[k] = p[k];
-                        } else {
-                            const float* iv = a.xf + ((int64_t)mi * a.fix_stride + f) * 24 + 12;
+                        for (int k = 0; k < SPL; ++k) q[k] = p[k];
+                        if (moving) {
+                            fo = load_fix(a.fix_all + (int64_t)mi * a.fix_stride, f);
+                            if (mi != a.self_mesh) {
+                                const float* iv = a.xf + ((int64_t)mi * a.fix_stride + f) * 24 + 12;
 #pragma unroll
-                            for (int k = 0; k < SPL; ++k) {
-                                const float wx = __builtin_fmaf(fw[0], p[k].x, __builtin_fmaf(fw[1], p[k].y, __builtin_fmaf(fw[2], p[k].z, fw[3])));
-                                const float wy = __builtin_fmaf(fw[4], p[k].x, __builtin_fmaf(fw[5], p[k].y, __builtin_fmaf(fw[6], p[k].z, fw[7])));
-                                const float wz = __builtin_fmaf(fw[8], p[k].x, __builtin_fmaf(fw[9], p[k].y, __builtin_fmaf(fw[10], p[k].z, fw[11])));
-                                q[k].x = __builtin_fmaf(iv[0], wx, __builtin_fmaf(iv[1], wy, __builtin_fmaf(iv[2], wz, iv[3])));
-                                q[k].y = __builtin_fmaf(iv[4], wx, __builtin_fmaf(iv[5], wy, __builtin_fmaf(iv[6], wz, iv[7])));
-                                q[k].z = __builtin_fmaf(iv[8], wx, __builtin_fmaf(iv[9], wy, __builtin_fmaf(iv[10], wz, iv[11])));
-                                q[k].w = p[k].w;
+                                for (int k = 0; k < SPL; ++k) {
+                                    const float wx = __builtin_fmaf(fw[0], p[k].x, __builtin_fmaf(fw[1], p[k].y, __builtin_fmaf(fw[2], p[k].z, fw[3])));
+                                    const float wy = __builtin_fmaf(fw[4], p[k].x, __builtin_fmaf(fw[5], p[k].y, __builtin_fmaf(fw[6], p[k].z, fw[7])));
+                                    const float wz = __builtin_fmaf(fw[8], p[k].x, __builtin_fmaf(fw[9], p[k].y, __builtin_fmaf(fw[10], p[k].z, fw[11])));
+                                    q[k].x = __builtin_fmaf(iv[0], wx, __builtin_fmaf(iv[1], wy, __builtin_fmaf(iv[2], wz, iv[3])));
+                                    q[k].y = __builtin_fmaf(iv[4], wx, __builtin_fmaf(iv[5], wy, __builtin_fmaf(iv[6], wz, iv[7])));
+                                    q[k].z = __builtin_fmaf(iv[8], wx, __builtin_fmaf(iv[9], wy, __builtin_fmaf(iv[10], wz, iv[11])));
+                                }
                             }
                         }
                         bool o2[SPL];
@@ -863,12 +859,17 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
     __syncthreads();  // LDS is reused by the next item of a persistent workgroup
 }
 
-template <int SPL, int OCC, bool POSED = false>
+// INST: visibility over one BVH per mesh (DensityLaunch::blas), else the scene BVH.
+// Items in dispatch order go tile by tile, the chunks of one tile next to each other:
+// workgroups are handed out round-robin over the XCDs, so the chunks of a tile run at
+// once on different XCDs and every XCD sees every part of the scene; when only the
+// first chunks hold fixations (a time window), the work still spreads over all XCDs.
+template <int SPL, int OCC, bool INST = false>
 __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
 {
-    const unsigned G = gridDim.x * gridDim.y;
-    const unsigned L = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, G);
-    density_item<SPL, OCC, kFB, POSED>(a, (int64_t)(L % gridDim.x), (int)(L / gridDim.x));
+    const unsigned L = blockIdx.x + blockIdx.y * gridDim.x;  // < 2^31 (tiles x chunks)
+    const int F = a.F_live ? min(a.F, (int)*a.F_live) : a.F;
+    density_item<SPL, OCC, kFB, INST>(a, (int64_t)(L / gridDim.y), (int)(L % gridDim.y), F);
 }
 
 // Persistent form for many sessions: every workgroup pulls (session, tile, chunk)
@@ -886,8 +887,9 @@ __global__ void __launch_bounds__(kThreads) k_density_queue(const DensityLaunch*
         __syncthreads();
         if (it >= n_items) break;
         const int4 w = items[it];
-        const DensityLaunch a = sessions[w.x];
-        density_item<SPL, 1, FB>(a, (int64_t)w.y, w.z);
+        // the session's descriptor stays in memory: its fields are read where they are
+        // used (wave-uniform loads) rather than copied into registers
+        density_item<SPL, 1, FB>(sessions[w.x], (int64_t)w.y, w.z, sessions[w.x].F);
     }
 }
 

@@ -44,29 +44,7 @@ struct gm_map {
     DevBuf recs, xf;
 };
 
-namespace {
-
-gm_status check_map(const gm_map* m)
-{
-    if (!m) return fail(GM_ERR_INVALID_ARGUMENT, "map is NULL");
-    int dev = -1;
-    GM_HIP(hipGetDevice(&dev));
-    if (dev != m->device)
-        return fail(GM_ERR_INVALID_ARGUMENT, "map lives on device %d but device %d is current", m->device, dev);
-    return GM_OK;
-}
-
-// accumulators, maximum and counters back to zero; the budget total set again
-gm_status map_clear(gm_map* m, hipStream_t s)
-{
-    if (m->n > 0) zero(m->w.acc.p, 8 * (size_t)m->n, s);
-    zero(m->counters.p, 8 * kMapCounters, s);
-    const unsigned long long b = m->budget_units;  // counters[1], as two little-endian words
-    fill_u32(static_cast<uint32_t*>(m->counters.p) + 2, 1, (uint32_t)(b & 0xFFFFFFFFull), s);
-    fill_u32(static_cast<uint32_t*>(m->counters.p) + 3, 1, (uint32_t)(b >> 32), s);
-    GM_HIP(hipGetLastError());
-    return GM_OK;
-}
+namespace gm {
 
 // One BVH per mesh in the mesh's own frame, from the scene's triangle records (the
 // same FP32 vertices), with the octant node copies and axis-permuted record copies of
@@ -124,6 +102,32 @@ gm_status ensure_blas(gm_scene* sc)
         return fail(e == hipErrorOutOfMemory ? GM_ERR_OUT_OF_MEMORY : GM_ERR_DEVICE, "per-mesh BVH upload: %s",
                     hipGetErrorString(e));
     sc->blas = desc;
+    return GM_OK;
+}
+
+}  // namespace gm
+
+namespace {
+
+gm_status check_map(const gm_map* m)
+{
+    if (!m) return fail(GM_ERR_INVALID_ARGUMENT, "map is NULL");
+    int dev = -1;
+    GM_HIP(hipGetDevice(&dev));
+    if (dev != m->device)
+        return fail(GM_ERR_INVALID_ARGUMENT, "map lives on device %d but device %d is current", m->device, dev);
+    return GM_OK;
+}
+
+// accumulators, maximum and counters back to zero; the budget total set again
+gm_status map_clear(gm_map* m, hipStream_t s)
+{
+    if (m->n > 0) zero(m->w.acc.p, 8 * (size_t)m->n, s);
+    zero(m->counters.p, 8 * kMapCounters, s);
+    const unsigned long long b = m->budget_units;  // counters[1], as two little-endian words
+    fill_u32(static_cast<uint32_t*>(m->counters.p) + 2, 1, (uint32_t)(b & 0xFFFFFFFFull), s);
+    fill_u32(static_cast<uint32_t*>(m->counters.p) + 3, 1, (uint32_t)(b >> 32), s);
+    GM_HIP(hipGetLastError());
     return GM_OK;
 }
 
