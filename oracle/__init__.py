@@ -25,6 +25,14 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
                                  carried along with its eye repeats one fixation,
                                  a moving occluder equals the static maps of each
                                  instant, shears are refused)
+  camera_basis / crop_bounds /
+  density_zbuffer ............. pinned (centred gaze: the square of half-width
+                                 n tan(phi); oblique gaze: A0, A1, B0, B1 on the
+                                 cone and inside the bounds, mirror symmetry;
+                                 z-buffer depths of planes and spheres in closed
+                                 form, an occluder's shadow, eps widening;
+                                 a fine z-buffer agrees with the exact test
+                                 away from silhouettes)
   in_window / density_window .. pinned (partition of a recording into back-to-back
                                  windows sums to the whole, boundary and NaN
                                  times, empty window)
@@ -97,6 +105,12 @@ def _load():
     lib.or_density.argtypes = [ctypes.c_void_p, P(c_f), P(c_i32), P(c_i32), c_i64, P(c_f), P(c_f),
                                P(c_f), c_i64, c_d, ctypes.c_int, c_d, ctypes.c_int, ctypes.c_int,
                                P(c_d), P(c_d), P(c_i64)]
+    lib.or_closest.argtypes = [ctypes.c_void_p, P(c_d), P(c_d), c_d, c_d, P(ctypes.c_int)]
+    lib.or_closest.restype = c_d
+    lib.or_zbuffer.argtypes = [ctypes.c_void_p, P(c_d), P(c_d), c_d, c_d, ctypes.c_int, P(c_d), P(c_u8)]
+    lib.or_density_zbuffer.argtypes = [ctypes.c_void_p, P(c_f), c_i64, P(c_f), P(c_f), P(c_f), P(c_d), c_i64,
+                                       c_d, ctypes.c_int, c_d, c_d, c_d, ctypes.c_int, P(c_d), P(c_u8), P(c_d),
+                                       P(c_d), P(c_i64)]
     lib.or_pair_visibility.argtypes = [ctypes.c_void_p, P(c_f), P(c_i32), P(c_i32), P(c_f),
                                        P(c_i64), P(c_i64), c_i64, ctypes.c_int, c_d, ctypes.c_int,
                                        P(c_u8), P(c_u8)]
@@ -514,6 +528,114 @@ def posed_density(meshes, pos, tri, mesh, eye, gaze, dur, pose, theta_deg, mode=
                 if amb[j] or (frag and inc[j]):
                     budget[s] += g[j]
     return OracleDensity(rho, budget, stats)
+
+
+WORLD_UP = np.array([0.0, 1.0, 0.0])
+
+
+def camera_basis(head):
+    """Camera frame of a fixation, FP64: forward f = head / |head| (the head's view direction;
+    without head tracking the gaze itself), right = f x up / |f x up| with the world's up
+    (0, 1, 0), or (0, 0, 1) when the view is within 1e-6 of vertical; up' = right x f."""
+    f = np.asarray(head, np.float32).astype(np.float64)
+    f = f / math.sqrt(f @ f)
+    up = WORLD_UP if abs(f @ WORLD_UP) < 1 - 1e-6 else np.array([0.0, 0.0, 1.0])
+    x = np.cross(f, up); x /= math.sqrt(x @ x)
+    y = np.cross(x, f)
+    return x, y, f
+
+
+def _quat_rotate(v, axis, ang):
+    # q v q^-1 with q = cos(ang/2) + axis sin(ang/2), axis a unit vector (Appendix A)
+    w, s_ = math.cos(ang / 2), math.sin(ang / 2)
+    qv = s_ * np.asarray(axis, np.float64)
+    t = 2.0 * np.cross(qv, v)
+    return v + w * t + np.cross(qv, t)
+
+
+def crop_bounds(r_cam, theta_deg, near):
+    """Appendix A: the bounds l', r', b', t' on the near plane z = -n (camera coordinates:
+    right x, up y, looking along -z) of the ellipse where the 4-sigma cone around the gaze
+    r_cam meets that plane.  phi = atan(4 sigma); a0, a1 = r rotated by -+phi about
+    u1 = r x i (i the camera's forward (0, 0, -1)), b0, b1 about u2 = r x u1; their hits
+    A0, A1, B0, B1 with the plane give a = |A1 - A0| / 2, b = |B1 - B0| / 2; E = the gaze's
+    hit, alpha = acos(j . ME / |ME|) (j the right vector, M the plane's centre); l', r' =
+    E_x -+ sqrt(a^2 cos^2 alpha + b^2 sin^2 alpha), b', t' = E_y -+ sqrt(a^2 sin^2 alpha +
+    b^2 cos^2 alpha).  When the gaze runs along i, u1 is taken along r x j instead (the
+    ellipse is then a circle and alpha does not matter)."""
+    r = np.asarray(r_cam, np.float64); r = r / math.sqrt(r @ r)
+    sigma = math.tan(math.radians(theta_deg))
+    phi = math.atan(4.0 * sigma)
+    i_fwd = np.array([0.0, 0.0, -1.0]); j_right = np.array([1.0, 0.0, 0.0])
+    u1 = np.cross(r, i_fwd)
+    if math.sqrt(u1 @ u1) < 1e-12:
+        u1 = np.cross(r, j_right)
+    u1 /= math.sqrt(u1 @ u1)
+    u2 = np.cross(r, u1); u2 /= math.sqrt(u2 @ u2)
+
+    def hit(v):
+        return -near / v[2] * v[:2]
+    A0, A1 = hit(_quat_rotate(r, u1, -phi)), hit(_quat_rotate(r, u1, phi))
+    B0, B1 = hit(_quat_rotate(r, u2, -phi)), hit(_quat_rotate(r, u2, phi))
+    E = hit(r)
+    a = math.sqrt((A1 - A0) @ (A1 - A0)) / 2.0
+    b = math.sqrt((B1 - B0) @ (B1 - B0)) / 2.0
+    me = math.sqrt(E @ E)
+    alpha = math.acos(max(-1.0, min(1.0, E[0] / me))) if me > 0 else 0.0
+    hx = math.sqrt(a * a * math.cos(alpha) ** 2 + b * b * math.sin(alpha) ** 2)
+    hy = math.sqrt(a * a * math.sin(alpha) ** 2 + b * b * math.cos(alpha) ** 2)
+    return E[0] - hx, E[0] + hx, E[1] - hy, E[1] + hy
+
+
+def crop_cameras(gaze, head, theta_deg, near):
+    """Per fixation [F][13]: right, up, forward (FP64) and l', r', b', t' of its crop."""
+    gaze = np.asarray(gaze, np.float32).reshape(-1, 3)
+    head = gaze if head is None else np.asarray(head, np.float32).reshape(-1, 3)
+    out = np.zeros((len(gaze), 13))
+    for k in range(len(gaze)):
+        x, y, f = camera_basis(head[k])
+        g = gaze[k].astype(np.float64)
+        rc = np.array([g @ x, g @ y, -(g @ f)])
+        out[k, :3], out[k, 3:6], out[k, 6:9] = x, y, f
+        out[k, 9:] = crop_bounds(rc, theta_deg, near)
+    return out
+
+
+@dataclass
+class OracleZDensity:
+    rho: np.ndarray      # float64 [n]
+    budget: np.ndarray   # float64 [n]
+    stats: np.ndarray    # int64 [n][4]: in the frustum, visible, ambiguous, 0
+    zbuf: np.ndarray     # float64 [F][R][R] depth of the nearest surface per pixel (inf: none)
+    zamb: np.ndarray     # bool [F][R][R] pixels a rasteriser could fill from another triangle
+    cams: np.ndarray     # [F][13]
+
+
+def density_zbuffer(scene: Scene, pos, eye, gaze, dur, theta_deg, resolution=128, eps_depth=1e-2, near=0.05,
+                    far=1000.0, head=None, nthreads=None) -> OracleZDensity:
+    """The paper's own approximation (Sec. 3.2.2, 3.3.2, Appendix A): per fixation a camera
+    at the eye looking along the head direction (the gaze without head tracking), cropped to
+    the 4-sigma cone's bounds on the near plane (crop_bounds), a resolution x resolution
+    z-buffer of the whole scene (depth of the nearest surface through each pixel centre,
+    depths in [near, far]); a sample inside the cropped frustum (the NDC cube) gets the
+    angular Gaussian of Sec. 3.2.1 (not cut at 4 sigma) when its depth D satisfies
+    D - zbuf(pixel) <= eps_depth D.  Sums in FP64."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, np.float32).reshape(-1, 3)
+    eye = np.ascontiguousarray(eye, np.float32).reshape(-1, 3)
+    gaze = np.ascontiguousarray(gaze, np.float32).reshape(-1, 3)
+    dur = np.ascontiguousarray(dur, np.float32).reshape(-1)
+    F, n, R = len(eye), len(pos), int(resolution)
+    cams = np.ascontiguousarray(crop_cameras(gaze, head, theta_deg, near))
+    zbuf = np.zeros((F, R, R)); zamb = np.zeros((F, R, R), np.uint8)
+    rho = np.zeros(n); budget = np.zeros(n); stats = np.zeros((n, 4), np.int64)
+    lib.or_density_zbuffer(scene._h, _ptr(pos, ctypes.c_float), n, _ptr(eye, ctypes.c_float),
+                           _ptr(gaze, ctypes.c_float), _ptr(dur, ctypes.c_float), _ptr(cams, ctypes.c_double), F,
+                           float(theta_deg), R, float(eps_depth), float(near), float(far),
+                           int(nthreads or os.cpu_count() or 1), _ptr(zbuf, ctypes.c_double),
+                           _ptr(zamb, ctypes.c_uint8), _ptr(rho, ctypes.c_double), _ptr(budget, ctypes.c_double),
+                           _ptr(stats, ctypes.c_int64))
+    return OracleZDensity(rho, budget, stats, zbuf, zamb.astype(bool), cams)
 
 
 def normalize(rho):

@@ -686,3 +686,217 @@ void or_pair_values(const float* pos, const float* eye, const float* gaze, const
         if (in_out) in_out[i] = (uint8_t)in;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* The paper's own visibility approximation (Sec. 3.2.2, Sec. 3.3.2,        */
+/* Appendix A): per fixation, a z-buffer of the scene seen through a camera */
+/* cropped to the 4-sigma cone; a sample inside the cropped frustum is      */
+/* visible when its depth is within eps of the depth stored at its pixel.   */
+/* The buffer holds, per pixel, the depth of the nearest surface met by the */
+/* ray through the pixel centre (what rasterisation stores there).  Camera */
+/* cam[13] = right (3), up (3), forward (3) unit vectors, then l', r', b',  */
+/* t' of the crop on the near plane (Appendix A).  Depth = distance along   */
+/* forward; the frustum keeps depths in [near, far].                        */
+/* ------------------------------------------------------------------------ */
+
+/* Nearest hit of o + t d with tmin <= t <= tmax over all triangles (MT in  */
+/* FP64, inclusive edges); INFINITY when none.  *ambiguous = a triangle     */
+/* within the bookkeeping band of a hit (its edges, or tmin / tmax) lies in */
+/* front of or at the nearest hit, so a rasteriser could store its depth.   */
+double or_closest(const or_scene* sc, const double o[3], const double d[3], double tmin, double tmax,
+                  int* ambiguous)
+{
+    double best = INFINITY, best_band = INFINITY;
+    int32_t stack[256];
+    int sp = 0;
+    if (sc->T > 0) stack[sp++] = 0;
+    while (sp > 0) {
+        const or_node* nd = &sc->nodes[stack[--sp]];
+        /* box test on [0, min(tmax, best) (1 + band)] with the ray's own parameter */
+        if (!seg_box(o, d, nd->lo, nd->hi, fmin(tmax, best) * (1.0 + FRAG_TAU))) continue;
+        if (nd->left >= 0) {
+            stack[sp++] = nd->left;
+            stack[sp++] = nd->right;
+            continue;
+        }
+        for (int32_t i = nd->first; i < nd->first + nd->count; ++i) {
+            const double* t = sc->v + 9 * (int64_t)sc->order[i];
+            double e1[3] = {t[3] - t[0], t[4] - t[1], t[5] - t[2]};
+            double e2[3] = {t[6] - t[0], t[7] - t[1], t[8] - t[2]};
+            double pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+            double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+            if (det == 0.0) continue;
+            double inv = 1.0 / det;
+            double tv[3] = {o[0] - t[0], o[1] - t[1], o[2] - t[2]};
+            double u = (tv[0] * pv[0] + tv[1] * pv[1] + tv[2] * pv[2]) * inv;
+            double qv[3] = {tv[1] * e1[2] - tv[2] * e1[1], tv[2] * e1[0] - tv[0] * e1[2], tv[0] * e1[1] - tv[1] * e1[0]};
+            double v = (d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2]) * inv;
+            double tt = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * inv;
+            double w = 1.0 - u - v;
+            if (u >= 0.0 && v >= 0.0 && w >= 0.0 && tt >= tmin && tt <= tmax && tt < best) best = tt;
+            int loose = u >= -FRAG_BARY && v >= -FRAG_BARY && w >= -FRAG_BARY && tt >= tmin * (1.0 - FRAG_TAU) &&
+                        tt <= tmax * (1.0 + FRAG_TAU);
+            int tight = u >= FRAG_BARY && v >= FRAG_BARY && w >= FRAG_BARY && tt >= tmin * (1.0 + FRAG_TAU) &&
+                        tt <= tmax * (1.0 - FRAG_TAU);
+            if (loose && !tight && tt < best_band) best_band = tt;
+        }
+    }
+    if (ambiguous) *ambiguous = best_band <= best * (1.0 + FRAG_TAU);
+    return best;
+}
+
+/* z-buffer of one fixation: zbuf[j * R + i] for pixel column i (along the */
+/* right vector) and row j (along up), centre at NDC (-1 + (2i + 1) / R,   */
+/* -1 + (2j + 1) / R).  The ray through it has direction x' right + y' up + */
+/* forward (depth = its parameter) with x' = (ndc_x + ox) / sx, sx = 2n /  */
+/* (r' - l'), ox = (r' + l') / (r' - l'), the inverse of the crop matrix.  */
+void or_zbuffer(const or_scene* sc, const double e[3], const double cam[13], double near_, double far_, int R,
+                double* zbuf, uint8_t* amb)
+{
+    double sx = 2.0 * near_ / (cam[10] - cam[9]), ox = (cam[10] + cam[9]) / (cam[10] - cam[9]);
+    double sy = 2.0 * near_ / (cam[12] - cam[11]), oy = (cam[12] + cam[11]) / (cam[12] - cam[11]);
+    for (int j = 0; j < R; ++j)
+        for (int i = 0; i < R; ++i) {
+            double nx = -1.0 + (2.0 * i + 1.0) / R, ny = -1.0 + (2.0 * j + 1.0) / R;
+            double xc = (nx + ox) / sx, yc = (ny + oy) / sy;
+            double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = xc * cam[a] + yc * cam[3 + a] + cam[6 + a];
+            int am = 0;
+            zbuf[(int64_t)j * R + i] = or_closest(sc, e, d, near_, far_, &am);
+            if (amb) amb[(int64_t)j * R + i] = (uint8_t)am;
+        }
+}
+
+typedef struct {
+    const or_scene* sc;
+    const float *pos, *eye, *gaze, *dur;
+    const double* cams;
+    int64_t n, F, begin, end;
+    double sigma, eps_depth, near_, far_;
+    int R;
+    const double* zbuf;    /* [F][R][R] */
+    const uint8_t* zamb;
+    double *rho, *budget;
+    int64_t* stats;
+} zdensity_job;
+
+static const double ZB_NDC_BAND = 1e-5, ZB_PIX_BAND = 1e-4, ZB_DEPTH_BAND = 1e-5;
+
+static void* zdensity_worker(void* arg)
+{
+    zdensity_job* jb = (zdensity_job*)arg;
+    const int R = jb->R;
+    for (int64_t s = jb->begin; s < jb->end; ++s) {
+        double x[3] = {jb->pos[3 * s], jb->pos[3 * s + 1], jb->pos[3 * s + 2]};
+        double rho = 0.0, budget = 0.0;
+        int64_t n_in = 0, n_vis = 0, n_amb = 0;
+        for (int64_t f = 0; f < jb->F; ++f) {
+            const double* cam = jb->cams + 13 * f;
+            double e[3] = {jb->eye[3 * f], jb->eye[3 * f + 1], jb->eye[3 * f + 2]};
+            double r[3] = {jb->gaze[3 * f], jb->gaze[3 * f + 1], jb->gaze[3 * f + 2]};
+            double p[3] = {x[0] - e[0], x[1] - e[1], x[2] - e[2]};
+            double xc = p[0] * cam[0] + p[1] * cam[1] + p[2] * cam[2];
+            double yc = p[0] * cam[3] + p[1] * cam[4] + p[2] * cam[5];
+            double D = p[0] * cam[6] + p[1] * cam[7] + p[2] * cam[8];
+            if (!(D > 0.0)) continue;
+            double sx = 2.0 * jb->near_ / (cam[10] - cam[9]), ox = (cam[10] + cam[9]) / (cam[10] - cam[9]);
+            double sy = 2.0 * jb->near_ / (cam[12] - cam[11]), oy = (cam[12] + cam[11]) / (cam[12] - cam[11]);
+            double nx = sx * xc / D - ox, ny = sy * yc / D - oy;
+            int in = D >= jb->near_ && D <= jb->far_ && fabs(nx) <= 1.0 && fabs(ny) <= 1.0;
+            int amb_in = fabs(fabs(nx) - 1.0) <= ZB_NDC_BAND || fabs(fabs(ny) - 1.0) <= ZB_NDC_BAND ||
+                         fabs(D - jb->near_) <= ZB_NDC_BAND * D || fabs(D - jb->far_) <= ZB_NDC_BAND * D;
+            if (!in && !amb_in) continue;
+            double g, margin;
+            (void)or_pair_value(x, e, r, (double)jb->dur[f], jb->sigma, &g, &margin);
+            if (!in) {
+                budget += g;
+                ++n_amb;
+                continue;
+            }
+            double fx = (nx + 1.0) * 0.5 * R, fy = (ny + 1.0) * 0.5 * R;
+            int i = (int)floor(fx), j = (int)floor(fy);
+            if (i < 0) i = 0;
+            if (i > R - 1) i = R - 1;
+            if (j < 0) j = 0;
+            if (j > R - 1) j = R - 1;
+            double frx = fx - floor(fx), fry = fy - floor(fy);
+            int amb_pix = (frx <= ZB_PIX_BAND || frx >= 1.0 - ZB_PIX_BAND || fry <= ZB_PIX_BAND ||
+                           fry >= 1.0 - ZB_PIX_BAND) && fx > ZB_PIX_BAND && fx < R - ZB_PIX_BAND &&
+                          fy > ZB_PIX_BAND && fy < R - ZB_PIX_BAND;
+            int64_t px = ((int64_t)f * R + j) * R + i;
+            double zb = jb->zbuf[px];
+            double m = jb->eps_depth * D - (D - zb);
+            int vis = isinf(zb) || m >= 0.0;
+            int amb_d = (!isinf(zb) && fabs(m) <= ZB_DEPTH_BAND * D) || jb->zamb[px];
+            ++n_in;
+            if (vis) { ++n_vis; rho += g; }
+            if (amb_in || amb_pix || amb_d) { budget += g; ++n_amb; }
+        }
+        jb->rho[s] = rho;
+        jb->budget[s] = budget;
+        if (jb->stats) {
+            jb->stats[4 * s] = n_in; jb->stats[4 * s + 1] = n_vis;
+            jb->stats[4 * s + 2] = n_amb; jb->stats[4 * s + 3] = 0;
+        }
+    }
+    return NULL;
+}
+
+typedef struct {
+    const or_scene* sc;
+    const float* eye;
+    const double* cams;
+    double near_, far_;
+    int R;
+    int64_t f0, f1;
+    double* zbuf;
+    uint8_t* zamb;
+} zbuf_job;
+
+static void* zbuf_worker(void* arg)
+{
+    zbuf_job* jb = (zbuf_job*)arg;
+    const int64_t RR = (int64_t)jb->R * jb->R;
+    for (int64_t f = jb->f0; f < jb->f1; ++f) {
+        double e[3] = {jb->eye[3 * f], jb->eye[3 * f + 1], jb->eye[3 * f + 2]};
+        or_zbuffer(jb->sc, e, jb->cams + 13 * f, jb->near_, jb->far_, jb->R, jb->zbuf + f * RR, jb->zamb + f * RR);
+    }
+    return NULL;
+}
+
+/* Density with the z-buffer test: rho_s = sum over fixations whose cropped */
+/* frustum holds s and whose z-buffer sees s of the Gaussian g (not cut at   */
+/* 4 sigma: the frustum does the cutting).  zbuf / zamb: caller-owned       */
+/* [F][R][R] (filled here).  budget = sum of g over pairs whose frustum,    */
+/* pixel or depth decision sits within the bookkeeping bands.               */
+int or_density_zbuffer(const or_scene* sc, const float* pos, int64_t n, const float* eye, const float* gaze,
+                       const float* dur, const double* cams, int64_t F, double theta_deg, int R, double eps_depth,
+                       double near_, double far_, int nthreads, double* zbuf, uint8_t* zamb, double* rho,
+                       double* budget, int64_t* stats)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    zbuf_job zj[256];
+    int64_t fc = (F + nthreads - 1) / nthreads;
+    for (int i = 0; i < nthreads; ++i) {
+        zj[i] = (zbuf_job){sc, eye, cams, near_, far_, R, i * fc, (i + 1) * fc < F ? (i + 1) * fc : F, zbuf, zamb};
+        if (zj[i].f0 < zj[i].f1) pthread_create(&th[i], NULL, zbuf_worker, &zj[i]);
+    }
+    for (int i = 0; i < nthreads; ++i)
+        if (zj[i].f0 < zj[i].f1) pthread_join(th[i], NULL);
+    double sigma = tan(theta_deg * M_PI / 180.0);
+    zdensity_job jobs[256];
+    int64_t chunk = (n + nthreads - 1) / nthreads;
+    for (int i = 0; i < nthreads; ++i) {
+        zdensity_job* jb = &jobs[i];
+        jb->sc = sc; jb->pos = pos; jb->eye = eye; jb->gaze = gaze; jb->dur = dur; jb->cams = cams;
+        jb->n = n; jb->F = F; jb->begin = i * chunk; jb->end = (i + 1) * chunk < n ? (i + 1) * chunk : n;
+        jb->sigma = sigma; jb->eps_depth = eps_depth; jb->near_ = near_; jb->far_ = far_; jb->R = R;
+        jb->zbuf = zbuf; jb->zamb = zamb; jb->rho = rho; jb->budget = budget; jb->stats = stats;
+        if (jb->begin < jb->end) pthread_create(&th[i], NULL, zdensity_worker, jb);
+    }
+    for (int i = 0; i < nthreads; ++i)
+        if (jobs[i].begin < jobs[i].end) pthread_join(th[i], NULL);
+    return 0;
+}
