@@ -282,6 +282,49 @@ gm_status gm_map_reset(gm_map* map, void* stream);
 gm_status gm_map_info(gm_map* map, int64_t* out);
 gm_status gm_map_destroy(gm_map* map);
 
+/* ------------------------------------------------------------------------ */
+/* The paper's own visibility approximation (Sec. 3.2.2, Sec. 3.3.2,        */
+/* Appendix A), to measure it against the exact test of accumulate_density.  */
+/* Per fixation: a camera at the eye looking along the head direction (the  */
+/* gaze when none is given), with the world's up (0, 1, 0) ((0, 0, 1) for a */
+/* vertical view); its view cropped to the bounds of the ellipse where the  */
+/* 4-sigma cone meets the near plane (Appendix A: the gaze turned by -+phi, */
+/* phi = atan(4 sigma), about u1 = r x i and u2 = r x u1 gives A0, A1, B0,  */
+/* B1; E the gaze's hit; a = |A1 - A0| / 2, b = |B1 - B0| / 2, alpha the    */
+/* angle of ME to the right vector; l', r' = E_x -+ sqrt(a^2 cos^2 alpha +  */
+/* b^2 sin^2 alpha), b', t' = E_y -+ sqrt(a^2 sin^2 alpha + b^2 cos^2       */
+/* alpha)); a resolution x resolution z-buffer holding, per pixel, the depth */
+/* (distance along the forward axis) of the nearest surface of the whole    */
+/* scene met by the ray through the pixel centre within [near, far] (+inf: */
+/* none); CDNA4 has no raster hardware, so each pixel is one ray over the   */
+/* scene BVH.  A sample inside the cropped frustum (the NDC cube) whose     */
+/* depth D satisfies D - zbuf(its pixel) <= depth_eps D adds the angular   */
+/* Gaussian of Sec. 3.2.1 (not cut at 4 sigma).  A fixation whose crop is  */
+/* undefined (the cone reaches behind the camera) or whose crop corners lie */
+/* 80 degrees or more off its gaze contributes nothing.  theta_deg must be */
+/* in (0, 10].                                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t resolution;  /* pixels per side, a multiple of 8 in [8, 1024] */
+    float depth_eps;     /* relative depth tolerance, in [0, 1] */
+    float near_plane;    /* metres, > 0 */
+    float far_plane;     /* metres, > near_plane, finite */
+    const float* head;   /* device [n][3] head view direction per fixation, or NULL (the gaze) */
+} gm_zbuffer_params;
+
+/* gm_render_zbuffers -- the z-buffers alone: zbuf device float [fix->n][R][R],
+ * row j (along up) then column i (along right), pixel centre at NDC
+ * (-1 + (2i + 1) / R, -1 + (2j + 1) / R).  Queued on `stream`. */
+gm_status gm_render_zbuffers(gm_scene* scene, const gm_fixations* fix, double theta_deg,
+                             const gm_zbuffer_params* params, float* zbuf, void* stream);
+
+/* accumulate_density_zbuffer -- the density map with the approximation above in
+ * place of the exact cone and segment test; outputs as accumulate_density.  The
+ * scene holds the z-buffers meanwhile (4 R^2 bytes per fixation).  Queued. */
+gm_status accumulate_density_zbuffer(gm_scene* scene, const float* pos, int64_t n, const gm_fixations* fix,
+                                     double theta_deg, const gm_zbuffer_params* params, float* density,
+                                     float* density_norm, float* max_out, void* stream);
+
 /*
  * Export format (Sec. 3.3.3): one record per sample, ready for external analysis.
  * 48 bytes, little-endian, no padding.

@@ -562,7 +562,8 @@ def crop_bounds(r_cam, theta_deg, near):
     hit, alpha = acos(j . ME / |ME|) (j the right vector, M the plane's centre); l', r' =
     E_x -+ sqrt(a^2 cos^2 alpha + b^2 sin^2 alpha), b', t' = E_y -+ sqrt(a^2 sin^2 alpha +
     b^2 cos^2 alpha).  When the gaze runs along i, u1 is taken along r x j instead (the
-    ellipse is then a circle and alpha does not matter)."""
+    ellipse is then a circle and alpha does not matter).  None when the cone reaches
+    behind the camera (the crop is undefined)."""
     r = np.asarray(r_cam, np.float64); r = r / math.sqrt(r @ r)
     sigma = math.tan(math.radians(theta_deg))
     phi = math.atan(4.0 * sigma)
@@ -575,8 +576,10 @@ def crop_bounds(r_cam, theta_deg, near):
 
     def hit(v):
         return -near / v[2] * v[:2]
-    A0, A1 = hit(_quat_rotate(r, u1, -phi)), hit(_quat_rotate(r, u1, phi))
-    B0, B1 = hit(_quat_rotate(r, u2, -phi)), hit(_quat_rotate(r, u2, phi))
+    rays = [_quat_rotate(r, u1, -phi), _quat_rotate(r, u1, phi), _quat_rotate(r, u2, -phi), _quat_rotate(r, u2, phi)]
+    if r[2] >= 0 or any(v[2] >= 0 for v in rays):
+        return None   # the cone reaches behind the camera: no crop
+    A0, A1, B0, B1 = (hit(v) for v in rays)
     E = hit(r)
     a = math.sqrt((A1 - A0) @ (A1 - A0)) / 2.0
     b = math.sqrt((B1 - B0) @ (B1 - B0)) / 2.0
@@ -588,17 +591,26 @@ def crop_bounds(r_cam, theta_deg, near):
 
 
 def crop_cameras(gaze, head, theta_deg, near):
-    """Per fixation [F][13]: right, up, forward (FP64) and l', r', b', t' of its crop."""
+    """Per fixation [F][13]: right, up, forward (FP64) and l', r', b', t' of its crop; and
+    whether the fixation is usable: a defined crop whose four corners lie less than 80
+    degrees off the gaze (wider crops are refused rather than cut)."""
     gaze = np.asarray(gaze, np.float32).reshape(-1, 3)
     head = gaze if head is None else np.asarray(head, np.float32).reshape(-1, 3)
-    out = np.zeros((len(gaze), 13))
+    out = np.zeros((len(gaze), 13)); out[:, 10] = out[:, 12] = 1.0
+    ok = np.zeros(len(gaze), bool)
     for k in range(len(gaze)):
         x, y, f = camera_basis(head[k])
         g = gaze[k].astype(np.float64)
         rc = np.array([g @ x, g @ y, -(g @ f)])
         out[k, :3], out[k, 3:6], out[k, 6:9] = x, y, f
-        out[k, 9:] = crop_bounds(rc, theta_deg, near)
-    return out
+        cb = crop_bounds(rc, theta_deg, near)
+        if cb is None:
+            continue
+        out[k, 9:] = cb
+        rn = rc / math.sqrt(rc @ rc)
+        corners = [np.array([cx, cy, -near]) for cx in cb[:2] for cy in cb[2:]]
+        ok[k] = min(c @ rn / math.sqrt(c @ c) for c in corners) > math.cos(math.radians(80.0))
+    return out, ok
 
 
 @dataclass
@@ -609,6 +621,7 @@ class OracleZDensity:
     zbuf: np.ndarray     # float64 [F][R][R] depth of the nearest surface per pixel (inf: none)
     zamb: np.ndarray     # bool [F][R][R] pixels a rasteriser could fill from another triangle
     cams: np.ndarray     # [F][13]
+    ok: np.ndarray       # bool [F] fixations with a usable crop
 
 
 def density_zbuffer(scene: Scene, pos, eye, gaze, dur, theta_deg, resolution=128, eps_depth=1e-2, near=0.05,
@@ -626,7 +639,9 @@ def density_zbuffer(scene: Scene, pos, eye, gaze, dur, theta_deg, resolution=128
     gaze = np.ascontiguousarray(gaze, np.float32).reshape(-1, 3)
     dur = np.ascontiguousarray(dur, np.float32).reshape(-1)
     F, n, R = len(eye), len(pos), int(resolution)
-    cams = np.ascontiguousarray(crop_cameras(gaze, head, theta_deg, near))
+    cams, ok = crop_cameras(gaze, head, theta_deg, near)
+    cams = np.ascontiguousarray(cams)
+    dur = np.ascontiguousarray(np.where(ok, dur, np.float32(0)).astype(np.float32))   # refused: nothing
     zbuf = np.zeros((F, R, R)); zamb = np.zeros((F, R, R), np.uint8)
     rho = np.zeros(n); budget = np.zeros(n); stats = np.zeros((n, 4), np.int64)
     lib.or_density_zbuffer(scene._h, _ptr(pos, ctypes.c_float), n, _ptr(eye, ctypes.c_float),
@@ -635,7 +650,8 @@ def density_zbuffer(scene: Scene, pos, eye, gaze, dur, theta_deg, resolution=128
                            int(nthreads or os.cpu_count() or 1), _ptr(zbuf, ctypes.c_double),
                            _ptr(zamb, ctypes.c_uint8), _ptr(rho, ctypes.c_double), _ptr(budget, ctypes.c_double),
                            _ptr(stats, ctypes.c_int64))
-    return OracleZDensity(rho, budget, stats, zbuf, zamb.astype(bool), cams)
+    zbuf[~ok] = np.inf
+    return OracleZDensity(rho, budget, stats, zbuf, zamb.astype(bool), cams, ok)
 
 
 def normalize(rho):

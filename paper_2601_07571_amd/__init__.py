@@ -31,7 +31,7 @@ SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy",
            "gm_field_get_params", "gm_field_train", "gm_field_info", "gm_field_gradient", "gm_field_predict", "query_density",
            "gm_batch_create", "gm_batch_run", "gm_batch_info", "gm_batch_destroy",
            "gm_map_create", "gm_map_add", "gm_map_add_posed", "gm_map_read", "gm_map_reset", "gm_map_info",
-           "gm_map_destroy", "gm_export_samples")
+           "gm_map_destroy", "gm_export_samples", "gm_render_zbuffers", "accumulate_density_zbuffer")
 GM_MAP_POSED = 4
 
 # one exported sample (gm_export_record), 48 bytes
@@ -60,6 +60,11 @@ class _TrainParams(ctypes.Structure):
                 ("lr_final", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("holdout", ctypes.c_float), ("max_rel_l2", ctypes.c_float),
                 ("target_max", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class _ZParams(ctypes.Structure):
+    _fields_ = [("resolution", ctypes.c_int32), ("depth_eps", ctypes.c_float), ("near_plane", ctypes.c_float),
+                ("far_plane", ctypes.c_float), ("head", ctypes.c_void_p)]
 
 
 class _Session(ctypes.Structure):
@@ -121,6 +126,9 @@ def load_library(path: str = LIB_PATH):
     lib.gm_map_add_posed.argtypes = [vp, ctypes.POINTER(_Fix), vp, vp, dbl, dbl, vp]
     lib.gm_map_read.argtypes = [vp, vp, vp, vp, vp]
     lib.gm_export_samples.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp]
+    lib.gm_render_zbuffers.argtypes = [vp, ctypes.POINTER(_Fix), dbl, ctypes.POINTER(_ZParams), vp, vp]
+    lib.accumulate_density_zbuffer.argtypes = [vp, vp, i64, ctypes.POINTER(_Fix), dbl, ctypes.POINTER(_ZParams),
+                                               vp, vp, vp, vp]
     lib.gm_map_reset.argtypes = [vp, vp]
     lib.gm_map_info.argtypes = [vp, ctypes.POINTER(i64)]
     lib.gm_map_destroy.argtypes = [vp]
@@ -307,6 +315,40 @@ class Scene:
         _check(_lib.accumulate_density(self._h, _ptr(pos), _ptr(tri), _ptr(mesh), n, ctypes.byref(fix._c),
                                        float(theta_deg), OCC[occlusion] if isinstance(occlusion, str) else occlusion,
                                        _ptr(out.density), _ptr(out.density_norm), _ptr(out.max), _stream()))
+        return out
+
+    def _zparams(self, resolution, depth_eps, near, far, head, n):
+        torch = _torch()
+        head = _dev(head, torch.float32, 3)
+        if head is not None and int(head.shape[0]) != n:
+            raise ValueError("head must hold one direction per fixation")
+        return _ZParams(int(resolution), float(depth_eps), float(near), float(far),
+                        None if head is None else head.data_ptr()), head
+
+    def render_zbuffers(self, fix: Fixations, theta_deg, resolution=128, depth_eps=1e-2, near=0.05, far=1000.0,
+                        head=None):
+        """The paper's per-fixation z-buffers: float32 [F][R][R] nearest depths (+inf: none)."""
+        torch = _torch()
+        zp, keep = self._zparams(resolution, depth_eps, near, far, head, fix.n)
+        out = torch.empty((fix.n, resolution, resolution), dtype=torch.float32, device="cuda")
+        _check(_lib.gm_render_zbuffers(self._h, ctypes.byref(fix._c), float(theta_deg), ctypes.byref(zp), _ptr(out),
+                                       _stream()))
+        return out
+
+    def accumulate_zbuffer(self, pos, fix: Fixations, theta_deg, resolution=128, depth_eps=1e-2, near=0.05,
+                           far=1000.0, head=None, out=None):
+        """The map under the paper's approximation (crop frustum + z-buffer test)."""
+        torch = _torch()
+        pos = _dev(pos, torch.float32, 3)
+        n = int(pos.shape[0])
+        zp, keep = self._zparams(resolution, depth_eps, near, far, head, fix.n)
+        if out is None:
+            out = Density(torch.empty(n, dtype=torch.float32, device="cuda"),
+                          torch.empty(n, dtype=torch.float32, device="cuda"),
+                          torch.empty(1, dtype=torch.float32, device="cuda"))
+        _check(_lib.accumulate_density_zbuffer(self._h, _ptr(pos), n, ctypes.byref(fix._c), float(theta_deg),
+                                               ctypes.byref(zp), _ptr(out.density), _ptr(out.density_norm),
+                                               _ptr(out.max), _stream()))
         return out
 
     def pair_visibility(self, pos, eye, pair_s, pair_f, occlusion="full", tri=None, mesh=None):

@@ -116,7 +116,7 @@ constexpr double kGateWiden = 3e-5;
 
 // Device scratch of one density evaluation (one scene, one set of points and fixations).
 struct DensityWork {
-    DevBuf fix, fx_shift, key, hist, cursor, scan_tmp, spos, smesh, perm, acc, max_acc, stats;
+    DevBuf fix, fx_shift, key, hist, cursor, scan_tmp, spos, smesh, perm, acc, max_acc, stats, zcam, zbuf;
     int bits = 1;
     int64_t buckets = 8;
 };

@@ -153,11 +153,37 @@ struct DensityLaunch {
     int64_t fix_stride = 0;
     int32_t n_inst = 0;
     int32_t self_mesh = 0;
+    // The paper's z-buffer visibility (zbuf != NULL): per fixation a camera record
+    // (ZCam, 16 floats) and a zres x zres buffer of nearest depths; a pair counts
+    // when the point lies in the cropped frustum and its depth D has D - zbuf <= zeps D.
+    const float* zcam = nullptr;
+    const float* zbuf = nullptr;
+    int32_t zres = 0;
+    float zeps = 0.0f;
 };
+
+// Camera of one fixation for the z-buffer test: right, up, forward unit vectors, the
+// crop's NDC scale and offset (x_ndc = sx x / D - ox, y likewise, D the depth along
+// forward), the near and far depths.
+struct alignas(16) ZCam {
+    float x[3], y[3], f[3];
+    float sx, ox, sy, oy;
+    float near_, far_;
+    float pad;
+};
+static_assert(sizeof(ZCam) == 64, "camera record is 64 bytes");
 
 
 void launch_fix_prep(const float* eye, const float* gaze, const float* dur, int32_t F, double sigma,
                      double widen, FixRec* rec, double* wsum, int32_t* fx_shift, hipStream_t s);
+// z-buffer visibility: per fixation the camera, its crop to the 4-sigma cone (Appendix A)
+// and a gate record whose cone holds the crop (rec.w = 0 for a fixation whose crop is
+// undefined); then one nearest-depth ray per pixel centre
+void launch_zcam_prep(const float* eye, const float* gaze, const float* dur, const float* head, int32_t F,
+                      double sigma, double widen, double near_, double far_, FixRec* rec, ZCam* cam,
+                      int32_t* fx_shift, hipStream_t s);
+void launch_zbuffer(const BvhNode* nodes, const BvhTri* tris, const FixRec* rec, const ZCam* cam, int32_t F,
+                    int32_t R, float* zbuf, hipStream_t s);
 // posed maps: per fixation taken, one record and one pose pair (forward, inverse) per mesh
 void launch_fix_posed(const float* eye, const float* gaze, const float* dur, const double* time, const float* pose,
                       int32_t F, int32_t M, int64_t stride, double t0, double t1, double sigma, double widen,

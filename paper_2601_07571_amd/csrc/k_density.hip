@@ -96,10 +96,10 @@ __device__ __forceinline__ float diff_of_products(float a, float b, float c, flo
     return f + e;
 }
 
-// Returns g (0 outside the 4-sigma cone).  tan^2(phi) = |p x r|^2 / (p.r)^2 with the
-// gaze left unnormalised (its length cancels).
-__device__ __forceinline__ float pair_value(float x, float y, float z, float ex, float ey, float ez, float rx,
-                                            float ry, float rz, float w, float cone2, float kexp)
+// |p x r|^2 and p.r for p = x - e, with p carried as a TwoSum pair (hi + lo) and the
+// cross product's differences of products with one rounding each
+__device__ __forceinline__ void pair_terms(float x, float y, float z, float ex, float ey, float ez, float rx,
+                                           float ry, float rz, float& q, float& d1)
 {
     float phx, plx, phy, ply, phz, plz;
     two_sum(x, -ex, phx, plx);
@@ -108,9 +108,18 @@ __device__ __forceinline__ float pair_value(float x, float y, float z, float ex,
     const float cx = diff_of_products(phy, rz, phz, ry) + (ply * rz - plz * ry);
     const float cy = diff_of_products(phz, rx, phx, rz) + (plz * rx - plx * rz);
     const float cz = diff_of_products(phx, ry, phy, rx) + (plx * ry - ply * rx);
-    const float q = __builtin_fmaf(cx, cx, __builtin_fmaf(cy, cy, cz * cz));
+    q = __builtin_fmaf(cx, cx, __builtin_fmaf(cy, cy, cz * cz));
     const float lo = __builtin_fmaf(plx, rx, __builtin_fmaf(ply, ry, plz * rz));
-    const float d1 = __builtin_fmaf(phx, rx, __builtin_fmaf(phy, ry, __builtin_fmaf(phz, rz, lo)));
+    d1 = __builtin_fmaf(phx, rx, __builtin_fmaf(phy, ry, __builtin_fmaf(phz, rz, lo)));
+}
+
+// Returns g (0 outside the 4-sigma cone).  tan^2(phi) = |p x r|^2 / (p.r)^2 with the
+// gaze left unnormalised (its length cancels).
+__device__ __forceinline__ float pair_value(float x, float y, float z, float ex, float ey, float ez, float rx,
+                                            float ry, float rz, float w, float cone2, float kexp)
+{
+    float q, d1;
+    pair_terms(x, y, z, ex, ey, ez, rx, ry, rz, q, d1);
     const float d12 = d1 * d1;
     if (!(d1 > 0.0f) || !(q <= cone2 * d12)) return 0.0f;
     const float t2 = q / d12;
@@ -361,6 +370,101 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
     for (int r = 0; r < R; ++r) occ[r] = __builtin_amdgcn_inverse_ballot_w64(hit[r]);
 }
 
+// Ray e + t d in the same sheared form as a segment with tmax = 1 (so s.tz = d[kz]).
+__device__ __forceinline__ Seg make_ray(float ex, float ey, float ez, float dx, float dy, float dz, int kx, int ky,
+                                        int kz)
+{
+    Seg s;
+    s.ix = safe_inv(dx); s.iy = safe_inv(dy); s.iz = safe_inv(dz);
+    s.qx = -ex * s.ix; s.qy = -ey * s.iy; s.qz = -ez * s.iz;
+    s.kx = kx; s.ky = ky; s.kz = kz;
+    const float dkz = pick(kz, dx, dy, dz);
+    s.sx = pick(kx, dx, dy, dz) / dkz;
+    s.sy = pick(ky, dx, dy, dz) / dkz;
+    s.tz = dkz;
+    return s;
+}
+
+// The watertight test of seg_tri (per-lane axis order) returning the ray parameter of
+// the hit, T' / (det d[kz]), or +inf when the ray misses the triangle's plane region.
+__device__ __forceinline__ float ray_tri_t(const Seg& s, const TriEye& u, bool active)
+{
+    const float akx = pick(s.kx, u.ax, u.ay, u.az), aky = pick(s.ky, u.ax, u.ay, u.az), akz = pick(s.kz, u.ax, u.ay, u.az);
+    const float bkx = pick(s.kx, u.bx, u.by, u.bz), bky = pick(s.ky, u.bx, u.by, u.bz), bkz = pick(s.kz, u.bx, u.by, u.bz);
+    const float ckx = pick(s.kx, u.cx, u.cy, u.cz), cky = pick(s.ky, u.cx, u.cy, u.cz), ckz = pick(s.kz, u.cx, u.cy, u.cz);
+    const float Ax = __builtin_fmaf(-s.sx, akz, akx), Ay = __builtin_fmaf(-s.sy, akz, aky);
+    const float Bx = __builtin_fmaf(-s.sx, bkz, bkx), By = __builtin_fmaf(-s.sy, bkz, bky);
+    const float Cx = __builtin_fmaf(-s.sx, ckz, ckx), Cy = __builtin_fmaf(-s.sy, ckz, cky);
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (active && (U == 0.0f || V == 0.0f || W == 0.0f)) {
+        asm volatile("" ::: "memory");
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    const bool mixed = (fminf(fminf(U, V), W) < 0.0f) && (fmaxf(fmaxf(U, V), W) > 0.0f);
+    const float det = U + V + W;
+    if (mixed || det == 0.0f) return INFINITY;
+    const float Tp = __builtin_fmaf(W, ckz, __builtin_fmaf(V, bkz, U * akz));
+    return Tp / (det * s.tz);
+}
+
+// Nearest surface along every lane's ray (lanes with `active`), tmin <= t < tbest on
+// entry: the packet walk of occluded_packet over the plain node copy and the x, y, z
+// record copy, except that no lane stops early: each keeps its nearest hit and clips
+// its box tests to it.
+__device__ void closest_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, float ex,
+                               float ey, float ez, int oct, const Seg& sg, float tmin, bool active, float& tbest)
+{
+    const int lane = lane_id();
+    const uint64_t live = ballot(active);
+    if (live == 0) return;
+    int stack = 0;
+    int sp = 0;
+    int node = 0;
+    for (;;) {
+        const BvhNode nd = load_node(nodes, node);
+        const uint64_t h0 = ballot(box_hit(sg, nd.lo0, nd.hi0, tbest)) & live;
+        const uint64_t h1 = ballot(box_hit(sg, nd.lo1, nd.hi1, tbest)) & live;
+        const bool swap = (oct >> ((nd.count0 >> kSplitAxisShift) & 3)) & 1;
+        int next = -1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const bool first = (c == 0) != swap;
+            const uint64_t m = first ? h0 : h1;
+            if (m == 0) continue;
+            const int child = first ? nd.child0 : nd.child1;
+            const int count = (first ? nd.count0 : nd.count1) & kCountMask;
+            if (child < 0) {
+                const BvhTri* leaf = tris + (~child);
+                BvhTri tr[kLeafMax];
+#pragma unroll
+                for (int k = 0; k < kLeafMax; ++k) tr[k] = load_tri(leaf, k);
+                const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
+#pragma unroll
+                for (int k = 0; k < kLeafMax; ++k) {
+                    if (k >= count) break;
+                    const float t = ray_tri_t(sg, tri_eye(tr[k], ex, ey, ez), in);
+                    if (in && t >= tmin && t < tbest) tbest = t;
+                }
+            } else if (next < 0) {
+                next = child;
+            } else {
+                stack = lane == sp ? child : stack;
+                ++sp;
+            }
+        }
+        if (next < 0) {
+            if (sp == 0) break;
+            --sp;
+            next = __builtin_amdgcn_readlane(stack, sp);
+        }
+        node = uniform(next);
+    }
+}
+
 __device__ __forceinline__ unsigned long long to_fixed(float g, int shift)
 {
     return (unsigned long long)ldexp((double)g, shift);
@@ -554,6 +658,173 @@ __global__ void k_fix_posed(const float* __restrict__ eye, const float* __restri
 }
 
 // ---------------------------------------------------------------------------
+// The paper's visibility approximation (Sec. 3.2.2, Sec. 3.3.2, Appendix A)
+// ---------------------------------------------------------------------------
+// q v q^-1 for q = cos(a/2) + u sin(a/2), u a unit vector
+__device__ __forceinline__ void quat_rotate(const double v[3], const double u[3], double a, double o[3])
+{
+    const double w = cos(0.5 * a), sn = sin(0.5 * a);
+    const double q[3] = {sn * u[0], sn * u[1], sn * u[2]};
+    const double t[3] = {2.0 * (q[1] * v[2] - q[2] * v[1]), 2.0 * (q[2] * v[0] - q[0] * v[2]),
+                         2.0 * (q[0] * v[1] - q[1] * v[0])};
+    o[0] = v[0] + w * t[0] + (q[1] * t[2] - q[2] * t[1]);
+    o[1] = v[1] + w * t[1] + (q[2] * t[0] - q[0] * t[2]);
+    o[2] = v[2] + w * t[2] + (q[0] * t[1] - q[1] * t[0]);
+}
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// One thread per fixation, in FP64: the camera at the eye looking along the head
+// direction (the gaze when no head direction is given) with the world's up (0, 1, 0)
+// (or (0, 0, 1) for a vertical view); the crop of Appendix A on the near plane:
+// the gaze turned by -+phi = -+atan(4 sigma) about u1 = r x i and u2 = r x u1 meets
+// the plane at A0, A1, B0, B1, E is the gaze's own hit, a = |A1 - A0| / 2,
+// b = |B1 - B0| / 2, alpha = angle of ME to the right vector, bounds E -+
+// (sqrt(a^2 cos^2 + b^2 sin^2), sqrt(a^2 sin^2 + b^2 cos^2)).  The gate record keeps the
+// eye, gaze and weight, with a cone (tan psi, psi the widest angle from the gaze to
+// the crop's corners) that holds the whole cropped frustum.  A fixation whose crop
+// is undefined (the cone reaches behind the camera) or whose corners lie 80 degrees
+// or more off the gaze gets w = 0.
+__global__ void k_zcam_prep(const float* __restrict__ eye, const float* __restrict__ gaze,
+                            const float* __restrict__ dur, const float* __restrict__ head, int32_t F, double sigma,
+                            double inv_norm, double widen, double near_, double far_, FixRec* __restrict__ rec,
+                            ZCam* __restrict__ cam, unsigned int* __restrict__ wmax_bits)
+{
+    const int fi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (fi >= F) return;
+    FixRec r;
+    bool ok = fix_record(eye, gaze, dur, fi, inv_norm, 1.0, INFINITY, r);
+    ZCam c;
+    for (int k = 0; k < 3; ++k) c.x[k] = c.y[k] = c.f[k] = 0.0f;
+    c.sx = c.sy = 1.0f; c.ox = c.oy = 0.0f; c.near_ = (float)near_; c.far_ = (float)far_; c.pad = 0.0f;
+    double f[3] = {head ? head[3 * fi] : gaze[3 * fi], head ? head[3 * fi + 1] : gaze[3 * fi + 1],
+                   head ? head[3 * fi + 2] : gaze[3 * fi + 2]};
+    const double fn = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    ok = ok && isfinite(fn) && fn > 0.0;
+    double tanpsi = 0.0;
+    if (ok) {
+        for (int k = 0; k < 3; ++k) f[k] /= fn;
+        const double up0[3] = {0.0, 1.0, 0.0}, up1[3] = {0.0, 0.0, 1.0};
+        const double* up = fabs(f[1]) < 1.0 - 1e-6 ? up0 : up1;
+        double x[3], y[3];
+        cross3(f, up, x);
+        const double xn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        for (int k = 0; k < 3; ++k) x[k] /= xn;
+        cross3(x, f, y);
+        const double g[3] = {r.rx, r.ry, r.rz};
+        double rc[3] = {g[0] * x[0] + g[1] * x[1] + g[2] * x[2], g[0] * y[0] + g[1] * y[1] + g[2] * y[2],
+                        -(g[0] * f[0] + g[1] * f[1] + g[2] * f[2])};
+        const double rn = sqrt(rc[0] * rc[0] + rc[1] * rc[1] + rc[2] * rc[2]);
+        for (int k = 0; k < 3; ++k) rc[k] /= rn;
+        const double phi = atan(4.0 * sigma);
+        const double ifw[3] = {0.0, 0.0, -1.0}, jr[3] = {1.0, 0.0, 0.0};
+        double u1[3], u2[3];
+        cross3(rc, ifw, u1);
+        double n1 = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+        if (n1 < 1e-12) {
+            cross3(rc, jr, u1);
+            n1 = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+        }
+        for (int k = 0; k < 3; ++k) u1[k] /= n1;
+        cross3(rc, u1, u2);
+        const double n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+        for (int k = 0; k < 3; ++k) u2[k] /= n2;
+        double a0[3], a1[3], b0[3], b1[3];
+        quat_rotate(rc, u1, -phi, a0); quat_rotate(rc, u1, phi, a1);
+        quat_rotate(rc, u2, -phi, b0); quat_rotate(rc, u2, phi, b1);
+        ok = rc[2] < 0.0 && a0[2] < 0.0 && a1[2] < 0.0 && b0[2] < 0.0 && b1[2] < 0.0;
+        if (ok) {
+            const double A0x = -near_ / a0[2] * a0[0], A0y = -near_ / a0[2] * a0[1];
+            const double A1x = -near_ / a1[2] * a1[0], A1y = -near_ / a1[2] * a1[1];
+            const double B0x = -near_ / b0[2] * b0[0], B0y = -near_ / b0[2] * b0[1];
+            const double B1x = -near_ / b1[2] * b1[0], B1y = -near_ / b1[2] * b1[1];
+            const double Ex = -near_ / rc[2] * rc[0], Ey = -near_ / rc[2] * rc[1];
+            const double a = sqrt((A1x - A0x) * (A1x - A0x) + (A1y - A0y) * (A1y - A0y)) / 2.0;
+            const double b = sqrt((B1x - B0x) * (B1x - B0x) + (B1y - B0y) * (B1y - B0y)) / 2.0;
+            const double me = sqrt(Ex * Ex + Ey * Ey);
+            const double al = me > 0.0 ? acos(fmax(-1.0, fmin(1.0, Ex / me))) : 0.0;
+            const double ca = cos(al), sa = sin(al);
+            const double hx = sqrt(a * a * ca * ca + b * b * sa * sa), hy = sqrt(a * a * sa * sa + b * b * ca * ca);
+            const double l = Ex - hx, rr = Ex + hx, bt = Ey - hy, tp = Ey + hy;
+            // the widest angle from the gaze to a corner of the crop
+            double cmin = 1.0;
+            for (int k = 0; k < 4; ++k) {
+                const double cx = (k & 1) ? rr : l, cy = (k & 2) ? tp : bt;
+                const double cl = sqrt(cx * cx + cy * cy + near_ * near_);
+                cmin = fmin(cmin, (cx * rc[0] + cy * rc[1] - near_ * rc[2]) / cl);
+            }
+            ok = cmin > 0.17364817766693033;  // cos 80 degrees
+            tanpsi = ok ? sqrt(1.0 - cmin * cmin) / cmin : 0.0;
+            for (int k = 0; k < 3; ++k) {
+                c.x[k] = (float)x[k]; c.y[k] = (float)y[k]; c.f[k] = (float)f[k];
+            }
+            c.sx = (float)(2.0 * near_ / (rr - l));
+            c.ox = (float)((rr + l) / (rr - l));
+            c.sy = (float)(2.0 * near_ / (tp - bt));
+            c.oy = (float)((tp + bt) / (tp - bt));
+        }
+    }
+    if (ok) {
+        const double r2 = (double)r.rx * r.rx + (double)r.ry * r.ry + (double)r.rz * r.rz;
+        r.kappa = (float)(r2 * (1.0 - widen) / (1.0 + tanpsi * tanpsi));
+    } else {
+        r.ex = r.ey = r.ez = 0.0f;
+        r.rx = r.ry = r.rz = 0.0f;
+        r.w = 0.0f;
+        r.kappa = 1.0f;
+    }
+    rec[fi] = r;
+    cam[fi] = c;
+    atomicMax(wmax_bits, __float_as_uint(r.w));
+}
+
+// One wave per 8 x 8 block of pixels of one fixation's z-buffer: the ray through
+// each pixel centre, direction x' right + y' up + forward (so the ray parameter is
+// the depth), x' = (x_ndc + ox) / sx; the buffer keeps the nearest hit with depth in
+// [near, far], +inf where there is none.  Fixations with w = 0 get +inf everywhere.
+__global__ void __launch_bounds__(256) k_zbuffer(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris,
+                                                 const FixRec* __restrict__ rec, const ZCam* __restrict__ cams,
+                                                 int32_t F, int32_t R, float* __restrict__ zbuf)
+{
+    const int lane = lane_id();
+    const int64_t blocks_per_fix = (int64_t)(R / 8) * (R / 8);
+    const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= blocks_per_fix * F) return;
+    const int f = (int)(item / blocks_per_fix);
+    const int blk = (int)(item % blocks_per_fix);
+    const int i = (blk % (R / 8)) * 8 + (lane & 7);
+    const int j = (blk / (R / 8)) * 8 + (lane >> 3);
+    const FixRec fr = load_fix(rec, f);
+    const ZCam c = cams[f];
+    float tbest = c.far_;
+    const bool active = fr.w > 0.0f;
+    if (uniform(active ? 1 : 0)) {
+        const float nx = -1.0f + (2.0f * i + 1.0f) / (float)R, ny = -1.0f + (2.0f * j + 1.0f) / (float)R;
+        const float xc = (nx + c.ox) / c.sx, yc = (ny + c.oy) / c.sy;
+        const float dx = __builtin_fmaf(xc, c.x[0], __builtin_fmaf(yc, c.y[0], c.f[0]));
+        const float dy = __builtin_fmaf(xc, c.x[1], __builtin_fmaf(yc, c.y[1], c.f[1]));
+        const float dz = __builtin_fmaf(xc, c.x[2], __builtin_fmaf(yc, c.y[2], c.f[2]));
+        int kx, ky, kz;
+        axis_order(dx, dy, dz, kx, ky, kz);
+        const Seg sg = make_ray(fr.ex, fr.ey, fr.ez, dx, dy, dz, kx, ky, kz);
+        const int lead = 0;
+        const int oct = (int)(__shfl(dx, lead) < 0.0f) | ((int)(__shfl(dy, lead) < 0.0f) << 1) |
+                        ((int)(__shfl(dz, lead) < 0.0f) << 2);
+        tbest = nextafterf(c.far_, INFINITY);
+        closest_packet(nodes, tris, fr.ex, fr.ey, fr.ez, uniform(oct), sg, c.near_, true, tbest);
+        if (!(tbest <= c.far_)) tbest = INFINITY;
+    } else {
+        tbest = INFINITY;
+    }
+    zbuf[((int64_t)f * R + j) * R + i] = tbest;
+}
+
+// ---------------------------------------------------------------------------
 // spatial order: 7-bit-per-axis Morton buckets, counting sort
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t spread3(uint32_t v)
@@ -662,11 +933,48 @@ __device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ no
     }
 }
 
+// The pair under the paper's approximation: inside the fixation's cropped frustum
+// (n <= D <= f, |x_ndc| <= 1, |y_ndc| <= 1, D the depth along the camera's forward
+// axis) and passing the depth test D - zbuf(pixel) <= eps D, the angular Gaussian
+// of Sec. 3.2.1 (not cut at 4 sigma: the frustum does the cutting); else 0.
+// `in` reports whether the point lies in the frustum.
+__device__ __forceinline__ float zb_value(float x, float y, float z, const FixRec& fr, const ZCam& c,
+                                          const float* __restrict__ zb, int R, float eps, float kexp, bool& in)
+{
+    float phx, plx, phy, ply, phz, plz;
+    two_sum(x, -fr.ex, phx, plx);
+    two_sum(y, -fr.ey, phy, ply);
+    two_sum(z, -fr.ez, phz, plz);
+    const float xc = __builtin_fmaf(phx, c.x[0], __builtin_fmaf(phy, c.x[1], __builtin_fmaf(phz, c.x[2],
+                     __builtin_fmaf(plx, c.x[0], __builtin_fmaf(ply, c.x[1], plz * c.x[2])))));
+    const float yc = __builtin_fmaf(phx, c.y[0], __builtin_fmaf(phy, c.y[1], __builtin_fmaf(phz, c.y[2],
+                     __builtin_fmaf(plx, c.y[0], __builtin_fmaf(ply, c.y[1], plz * c.y[2])))));
+    const float D = __builtin_fmaf(phx, c.f[0], __builtin_fmaf(phy, c.f[1], __builtin_fmaf(phz, c.f[2],
+                    __builtin_fmaf(plx, c.f[0], __builtin_fmaf(ply, c.f[1], plz * c.f[2])))));
+    in = false;
+    if (!(D >= c.near_ && D <= c.far_)) return 0.0f;
+    const float nx = c.sx * xc / D - c.ox, ny = c.sy * yc / D - c.oy;
+    if (!(fabsf(nx) <= 1.0f && fabsf(ny) <= 1.0f)) return 0.0f;
+    in = true;
+    const int i = min(R - 1, max(0, (int)floorf((nx + 1.0f) * 0.5f * (float)R)));
+    const int j = min(R - 1, max(0, (int)floorf((ny + 1.0f) * 0.5f * (float)R)));
+    const float depth = zb[(int64_t)j * R + i];
+    if (D - depth > eps * D) return 0.0f;
+    const float cx = diff_of_products(phy, fr.rz, phz, fr.ry) + (ply * fr.rz - plz * fr.ry);
+    const float cy = diff_of_products(phz, fr.rx, phx, fr.rz) + (plz * fr.rx - plx * fr.rz);
+    const float cz = diff_of_products(phx, fr.ry, phy, fr.rx) + (plx * fr.ry - ply * fr.rx);
+    const float q = __builtin_fmaf(cx, cx, __builtin_fmaf(cy, cy, cz * cz));
+    const float lo = __builtin_fmaf(plx, fr.rx, __builtin_fmaf(ply, fr.ry, plz * fr.rz));
+    const float d1 = __builtin_fmaf(phx, fr.rx, __builtin_fmaf(phy, fr.ry, __builtin_fmaf(phz, fr.rz, lo)));
+    if (!(d1 > 0.0f)) return 0.0f;
+    return fr.w * exp2f(-(q / (d1 * d1)) * kexp);
+}
+
 // One work item of the density map: the samples of one tile (256 * SPL consecutive
 // sorted samples) against one chunk of the fixations, by the whole workgroup.
 // OCC = 0: no occlusion (no traversal code); OCC = 1: visibility by the BVH when
 // a.occ_mode != 0.  FB: fixations staged in LDS per round.
-template <int SPL, int OCC, int FB, bool INST = false>
+template <int SPL, int OCC, int FB, bool INST = false, bool ZB = false>
 __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t tile, int chunk, int F)
 {
     __shared__ float4 s_ra[FB];  // rx, ry, rz, c0
@@ -752,20 +1060,27 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
             float4 p[SPL];
             bool need[SPL];
             bool any_need = false;
+            ZCam zc;
+            if (ZB) zc = reinterpret_cast<const ZCam*>(a.zcam)[f];
 #pragma unroll
             for (int k = 0; k < SPL; ++k) {
                 const int64_t i = wave_base + k * 64 + lane;
                 const bool c = ((cand >> k) & 1u) && i < n;
                 g[k] = 0.0f;
                 p[k] = make_float4(fr.ex, fr.ey, fr.ez, __int_as_float(-1));
+                bool in = false;
                 if (ballot(c) != 0 && c) {
                     p[k] = a.spos[i];
-                    g[k] = pair_value(p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w, a.cone2,
-                                      a.kexp);
+                    if (ZB)
+                        g[k] = zb_value(p[k].x, p[k].y, p[k].z, fr, zc, a.zbuf + (int64_t)f * a.zres * a.zres, a.zres,
+                                        a.zeps, a.kexp, in);
+                    else
+                        g[k] = pair_value(p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w,
+                                          a.cone2, a.kexp);
                 }
                 need[k] = OCC != 0 && a.occ_mode != 0 && g[k] > 0.0f;
                 any_need = any_need || need[k];
-                n_in += (uint32_t)__popcll(ballot(g[k] > 0.0f));
+                n_in += (uint32_t)__popcll(ballot(ZB ? in : g[k] > 0.0f));
             }
             bool occl[SPL];
 #pragma unroll
@@ -864,12 +1179,13 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
 // workgroups are handed out round-robin over the XCDs, so the chunks of a tile run at
 // once on different XCDs and every XCD sees every part of the scene; when only the
 // first chunks hold fixations (a time window), the work still spreads over all XCDs.
-template <int SPL, int OCC, bool INST = false>
+// ZB: the paper's z-buffer visibility instead of the exact segment test.
+template <int SPL, int OCC, bool INST = false, bool ZB = false>
 __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
 {
     const unsigned L = blockIdx.x + blockIdx.y * gridDim.x;  // < 2^31 (tiles x chunks)
     const int F = a.F_live ? min(a.F, (int)*a.F_live) : a.F;
-    density_item<SPL, OCC, kFB, INST>(a, (int64_t)(L / gridDim.y), (int)(L % gridDim.y), F);
+    density_item<SPL, OCC, kFB, INST, ZB>(a, (int64_t)(L / gridDim.y), (int)(L % gridDim.y), F);
 }
 
 // Persistent form for many sessions: every workgroup pulls (session, tile, chunk)
@@ -999,6 +1315,25 @@ void launch_fix_prep(const float* eye, const float* gaze, const float* dur, int3
     k_fix_shift<<<1, 1, 0, s>>>(wmax, F, fx_shift);
 }
 
+void launch_zcam_prep(const float* eye, const float* gaze, const float* dur, const float* head, int32_t F,
+                      double sigma, double widen, double near_, double far_, FixRec* rec, ZCam* cam,
+                      int32_t* fx_shift, hipStream_t s)
+{
+    const double inv_norm = 1.0 / (sigma * std::sqrt(2.0 * M_PI));
+    unsigned int* wmax = reinterpret_cast<unsigned int*>(fx_shift + 1);
+    if (F > 0)
+        k_zcam_prep<<<blocks(F, 128), 128, 0, s>>>(eye, gaze, dur, head, F, sigma, inv_norm, widen, near_, far_, rec,
+                                                   cam, wmax);
+    k_fix_shift<<<1, 1, 0, s>>>(wmax, F, fx_shift);
+}
+
+void launch_zbuffer(const BvhNode* nodes, const BvhTri* tris, const FixRec* rec, const ZCam* cam, int32_t F,
+                    int32_t R, float* zbuf, hipStream_t s)
+{
+    const int64_t waves = (int64_t)F * (R / 8) * (R / 8);
+    if (waves > 0) k_zbuffer<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(nodes, tris, rec, cam, F, R, zbuf);
+}
+
 void launch_fix_posed(const float* eye, const float* gaze, const float* dur, const double* time, const float* pose,
                       int32_t F, int32_t M, int64_t stride, double t0, double t1, double sigma, double widen,
                       FixRec* rec, float* xf, unsigned int* kept, unsigned long long* budget,
@@ -1046,6 +1381,11 @@ void launch_density(const DensityLaunch& a, hipStream_t s)
     const int64_t per_tile = (int64_t)kThreads * a.spl;
     const dim3 grid(blocks(a.n, (int)per_tile), (unsigned)a.n_chunks);
     const bool occ = a.occ_mode != 0;
+    if (a.zbuf) {
+        if (a.spl == 1) k_density<1, 0, false, true><<<grid, kThreads, 0, s>>>(a);
+        else k_density<2, 0, false, true><<<grid, kThreads, 0, s>>>(a);
+        return;
+    }
     if (occ && a.blas) {
         switch (a.spl) {
         case 1: k_density<1, 1, true><<<grid, kThreads, 0, s>>>(a); break;

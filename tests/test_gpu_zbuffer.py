@@ -1,0 +1,129 @@
+"""The paper's own visibility approximation on the GPU (crop frustum of Appendix A,
+per-fixation z-buffer, depth test with tolerance) against the oracle: the z-buffers
+pixel by pixel, and the density per sample within the density tolerance."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gm():
+    import torch
+    import paper_2601_07571_amd as gm
+    assert torch.cuda.is_available()
+    gm.load_library()
+    return gm
+
+
+def _tilted_heads(gaze, seed, max_deg=12.0):
+    """Head directions a few degrees off each gaze (eye-in-head eccentricity)."""
+    rng = np.random.default_rng(seed)
+    g = gaze.astype(np.float64); g /= np.linalg.norm(g, axis=1, keepdims=True)
+    a = np.where(np.abs(g[:, :1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+    u = np.cross(g, a); u /= np.linalg.norm(u, axis=1, keepdims=True)
+    v = np.cross(g, u)
+    ang = np.radians(rng.uniform(0, max_deg, len(g))); rot = rng.uniform(0, 2 * np.pi, len(g))
+    return (g + np.tan(ang)[:, None] * (np.cos(rot)[:, None] * u + np.sin(rot)[:, None] * v)).astype(np.float32)
+
+
+def _static_posed_scene():
+    """The moving-objects scene frozen at its first fixation: sphere, cube and a plate in
+    front of them, with the recording's eyes and gazes."""
+    w = workloads.posed_scene()
+    pose = w.extra["pose"][0]
+    meshes = [(oracle.posed_world(m.V, pose[k]), m.I) for k, m in enumerate(w.meshes)]
+    return w, meshes
+
+
+def _compare_zbuffers(got, ref):
+    amb = ref.zamb
+    fin = np.isfinite(ref.zbuf)
+    same_kind = np.isfinite(got) == fin
+    assert np.all(same_kind | amb), f"{(~same_kind & ~amb).sum()} pixels hit on one side only"
+    both = fin & np.isfinite(got) & ~amb
+    rel = np.abs(got[both] - ref.zbuf[both]) / ref.zbuf[both]
+    assert both.sum() > 1000 and rel.max() < 2e-5, rel.max()
+
+
+def test_zbuffers_match_the_oracle(gm):
+    import torch
+    w = workloads.tiny_icosphere_scene()
+    meshes = [(m.V, m.I) for m in w.meshes]
+    scene = gm.Scene(meshes)
+    F = 24
+    fix = gm.Fixations(w.fix.eye[:F], w.fix.gaze[:F], w.fix.dur[:F])
+    got = scene.render_zbuffers(fix, w.theta_deg, resolution=64).cpu().numpy()
+    torch.cuda.synchronize()
+    ref = oracle.density_zbuffer(oracle.Scene(meshes), np.zeros((0, 3), np.float32), w.fix.eye[:F],
+                                 w.fix.gaze[:F], w.fix.dur[:F], w.theta_deg, resolution=64)
+    _compare_zbuffers(got, ref)
+    # oblique crops (head directions off the gaze) on a scene with occluders
+    w2, meshes2 = _static_posed_scene()
+    scene2 = gm.Scene(meshes2)
+    heads = _tilted_heads(w2.fix.gaze, 1)
+    fix2 = gm.Fixations(w2.fix.eye, w2.fix.gaze, w2.fix.dur)
+    got2 = scene2.render_zbuffers(fix2, w2.theta_deg, resolution=32, head=heads).cpu().numpy()
+    ref2 = oracle.density_zbuffer(oracle.Scene(meshes2), np.zeros((0, 3), np.float32), w2.fix.eye, w2.fix.gaze,
+                                  w2.fix.dur, w2.theta_deg, resolution=32, head=heads)
+    assert ref2.ok.all()
+    _compare_zbuffers(got2, ref2)
+
+
+@pytest.mark.parametrize("case", ["tiny", "occluders", "oblique"])
+def test_density_matches_the_oracle(gm, case):
+    import torch
+    if case == "tiny":
+        w = workloads.tiny_icosphere_scene()
+        meshes = [(m.V, m.I) for m in w.meshes]
+        heads, R, eps, F = None, 64, 1e-2, 40
+    else:
+        w, meshes = _static_posed_scene()
+        heads = _tilted_heads(w.fix.gaze, 2) if case == "oblique" else None
+        R, eps, F = 48, 5e-3, len(w.fix.eye)
+    scene = gm.Scene(meshes)
+    s = scene.build_samples(w.k, seed=w.seed)
+    fix = gm.Fixations(w.fix.eye[:F], w.fix.gaze[:F], w.fix.dur[:F])
+    got = scene.accumulate_zbuffer(s.pos, fix, w.theta_deg, resolution=R, depth_eps=eps,
+                                   head=None if heads is None else heads[:F])
+    torch.cuda.synchronize()
+    pos = s.pos.cpu().numpy()
+    ref = oracle.density_zbuffer(oracle.Scene(meshes), pos, w.fix.eye[:F], w.fix.gaze[:F], w.fix.dur[:F],
+                                 w.theta_deg, resolution=R, eps_depth=eps,
+                                 head=None if heads is None else heads[:F])
+    d = got.density.cpu().numpy().astype(np.float64)
+    ok = np.abs(d - ref.rho) <= 1e-5 * ref.rho + ref.budget + 1e-30
+    assert ok.all(), f"{(~ok).sum()} samples off"
+    assert (ref.rho > 0).mean() > 0.03
+    st = scene.density_stats()
+    assert st["in_cone"] > 0 and 0 < st["visible"] <= st["in_cone"]
+
+
+def test_refused_fixations_and_arguments(gm):
+    import torch
+    w = workloads.tiny_icosphere_scene()
+    meshes = [(m.V, m.I) for m in w.meshes]
+    scene = gm.Scene(meshes)
+    s = scene.build_samples(w.k, seed=w.seed)
+    F = 10
+    heads = w.fix.gaze[:F].copy()
+    heads[3] = -heads[3]                  # looking away from the gaze: no crop
+    fix = gm.Fixations(w.fix.eye[:F], w.fix.gaze[:F], w.fix.dur[:F])
+    got = scene.accumulate_zbuffer(s.pos, fix, w.theta_deg, resolution=32, head=heads).density.cpu().numpy()
+    keep = np.ones(F, bool); keep[3] = False
+    fix_k = gm.Fixations(w.fix.eye[:F][keep], w.fix.gaze[:F][keep], w.fix.dur[:F][keep])
+    ref = scene.accumulate_zbuffer(s.pos, fix_k, w.theta_deg, resolution=32, head=heads[keep]).density.cpu().numpy()
+    assert np.array_equal(got, ref)
+    zb = scene.render_zbuffers(fix, w.theta_deg, resolution=32, head=heads).cpu().numpy()
+    assert np.all(np.isinf(zb[3])) and np.isfinite(zb[0]).any()
+    for kw in ({"resolution": 12}, {"resolution": 2048}, {"depth_eps": -1.0}, {"near": 0.0}, {"far": 0.01}):
+        with pytest.raises(gm.GazemapError):
+            scene.accumulate_zbuffer(s.pos, fix, w.theta_deg, **kw)
+    with pytest.raises(gm.GazemapError):
+        scene.accumulate_zbuffer(s.pos, fix, 20.0)
+    torch.cuda.synchronize()
