@@ -41,6 +41,7 @@ def main():
     ap.add_argument("--field-steps", type=int, default=20000)
     ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-map and time-window timing")
     ap.add_argument("--no-posed", action="store_true", help="skip the moving-objects timing")
+    ap.add_argument("--no-zbuffer", action="store_true", help="skip the paper's z-buffer approximation")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one plain copy of known size, then one full-occlusion step, and exit (for HBM counters)")
     args = ap.parse_args()
@@ -150,6 +151,8 @@ def main():
         out["incremental"] = bench_incremental(gm, workloads, torch, np, args, scene, samples, fix, w, ms_step)
     if not args.no_posed:
         out["posed"] = bench_posed(gm, workloads, torch, np, args, scene, samples, fix, w, ms_step)
+    if not args.no_zbuffer:
+        out["zbuffer"] = bench_zbuffer(gm, torch, np, args, scene, samples, fix, w, dens, ms_step)
     if not args.no_batched:
         out["batched"] = bench_batched(gm, workloads, torch, args)
     if not args.no_field:
@@ -304,6 +307,33 @@ def bench_posed(gm, workloads, torch, np, args, scene, samples, fix, w, plain_ms
             "samples_moved_by_motion": int(((moving - p).abs() > 1e-6 * p + 1e-8).sum()),
             "identity_vs_plain_samples_differing": differ, "samples": int(samples.pos.shape[0]),
             "meshes": M, "fixations": fix.n}
+
+
+def bench_zbuffer(gm, torch, np, args, scene, samples, fix, w, dens, plain_ms):
+    """The paper's own approximation on the same map (camera along the gaze, cropped to
+    the 4-sigma cone, per-fixation z-buffer, depth tolerance 1 %): map time, and how far
+    its normalised map lies from the exact one (relative L2, samples off by more than 10 %
+    of the maximum)."""
+    exact = dens.density.double().clone()
+    emax = float(exact.max())
+    res = {}
+    for R, eps in ((64, 1e-2), (128, 1e-2), (256, 1e-2), (256, 1e-3)):
+        out = scene.accumulate_zbuffer(samples.pos, fix, w.theta_deg, resolution=R, depth_eps=eps)
+        ms = _time(lambda: scene.accumulate_zbuffer(samples.pos, fix, w.theta_deg, resolution=R, depth_eps=eps,
+                                                    out=out), torch, max(1, args.steps // 2))
+        scene.profile(True)
+        scene.accumulate_zbuffer(samples.pos, fix, w.theta_deg, resolution=R, depth_eps=eps, out=out)
+        torch.cuda.synchronize()
+        prep_ms = scene.profile_read("prep")[0]
+        dens_ms = scene.profile_read("density")[0]
+        scene.profile(False)
+        diff = out.density.double() - exact
+        res[f"R{R}_eps{eps:g}"] = {"map_ms": ms, "zbuffer_render_ms": prep_ms, "density_ms": dens_ms,
+                                   "rel_l2_vs_exact": float(diff.norm() / exact.norm()),
+                                   "samples_off_by_10pct_of_max": int((diff.abs() > 0.1 * emax).sum()),
+                                   "samples_gaining": int((diff > 1e-3 * emax).sum()),
+                                   "samples_losing": int((diff < -1e-3 * emax).sum())}
+    return {"near_m": 0.05, "far_m": 1000.0, "exact_map_ms": plain_ms, "runs": res}
 
 
 def bench_batched(gm, workloads, torch, args):
