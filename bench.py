@@ -182,22 +182,31 @@ def main():
     print(json.dumps(out))
 
 
+TRAFFIC_SOURCES = ("k_density.hip", "capi.cpp")   # the kernel and its launch configuration
+
+
+def traffic_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2601_07571_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the full-occlusion density kernel from the committed
-    counter summary, or None when the kernel source changed since it was taken."""
-    import hashlib
+    counter summary, or None when the kernel or its launch configuration changed since
+    it was taken."""
     try:
         text = open(TRAFFIC_SUMMARY).read()
     except OSError:
         return None
-    src = os.path.join(ROOT, "paper_2601_07571_amd", "csrc", "k_density.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     fields = {}
     for line in text.splitlines():
         if line.startswith("- ") and ":" in line:
             key, val = line[2:].split(":", 1)
             fields[key.strip()] = val.strip().strip("`")
-    if fields.get("k_density.hip sha256") != digest:
+    if fields.get("k_density.hip + capi.cpp sha256") != traffic_sources_digest():
         return None
     try:
         return float(fields["traffic bytes per launch"])
