@@ -23,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU = 157.3e12      # MI355X FP32 vector peak, FLOP/s
+PEAK_HBM = 8.0e12              # MI355X HBM3E peak, bytes/s
+NODE_BYTES, TRI_BYTES = 64, 48 # BVH node and triangle record sizes
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_density_traffic_paper_shaped.md")
 COPY_PROBE_BYTES = 256 << 20   # the calibration copy of --traffic-probe (read and written once each)
 GATE_FLOP_PER_PAIR = 16        # 8 FMA per (sample, fixation) pair in the cone gate
@@ -141,7 +143,15 @@ def main():
                       "frac_fp32_peak": GATE_FLOP_PER_PAIR * pairs / (gate_ms * 1e-3) / PEAK_FP32_VALU},
         "visibility": {"in_cone_pairs": counters["in_cone"], "visible_pairs": counters["visible"],
                        "rays_per_s": counters["in_cone"] / (dens_ms * 1e-3),
-                       "packet_traversals": counters["traversals"], "bvh_node_visits": counters["node_visits"]},
+                       "packet_traversals": counters["traversals"], "bvh_node_visits": counters["node_visits"],
+                       "triangle_tests": counters["triangle_tests"],
+                       # the traversal's own memory work: one 64-byte node and one 48-byte record
+                       # per wave-level visit / test, against the HBM peak
+                       "traversal_bytes": NODE_BYTES * counters["node_visits"] + TRI_BYTES * counters["triangle_tests"],
+                       "traversal_GBps": (NODE_BYTES * counters["node_visits"] + TRI_BYTES * counters["triangle_tests"])
+                       / (dens_ms * 1e-3) / 1e9,
+                       "traversal_frac_hbm_peak": (NODE_BYTES * counters["node_visits"] +
+                                                   TRI_BYTES * counters["triangle_tests"]) / (dens_ms * 1e-3) / PEAK_HBM},
         "paper_context": {"map_time_s": 6.9, "hardware": "NVIDIA GeForce GTX 1060",
                           "workload": "the paper's 800k-triangle scene, 2M samples, 6,000 fixations"},
     }

@@ -488,6 +488,11 @@ gm_status gm_batch_destroy(gm_batch* batch);
  */
 gm_status gm_density_stats(gm_scene* scene, int64_t* out);
 
+/* gm_density_counters: the same counters and more, host int64 out[n_out] = {the four
+ * above, triangle tests (one per triangle tested by a packet for at least one of its
+ * segments)}; entries past the known counters are set to 0.  Blocking. */
+gm_status gm_density_counters(gm_scene* scene, int64_t* out, int32_t n_out);
+
 /*
  * Stage timing with HIP events recorded on the caller's stream around the
  * kernels of each stage (for measurement; off by default).

@@ -31,7 +31,8 @@ SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy",
            "gm_field_get_params", "gm_field_train", "gm_field_info", "gm_field_gradient", "gm_field_predict", "query_density",
            "gm_batch_create", "gm_batch_run", "gm_batch_info", "gm_batch_destroy",
            "gm_map_create", "gm_map_add", "gm_map_add_posed", "gm_map_read", "gm_map_reset", "gm_map_info",
-           "gm_map_destroy", "gm_export_samples", "gm_render_zbuffers", "accumulate_density_zbuffer")
+           "gm_map_destroy", "gm_export_samples", "gm_render_zbuffers", "accumulate_density_zbuffer",
+           "gm_density_counters")
 GM_MAP_POSED = 4
 
 # one exported sample (gm_export_record), 48 bytes
@@ -104,6 +105,7 @@ def load_library(path: str = LIB_PATH):
     lib.gm_debug_pair_visibility.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, i64, u32, vp, vp]
     lib.gm_profile_enable.argtypes = [vp, i32]
     lib.gm_density_stats.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.gm_density_counters.argtypes = [vp, ctypes.POINTER(i64), i32]
     f32p = ctypes.POINTER(ctypes.c_float)
     lib.gm_field_create.argtypes = [vp, u64, dbl, ctypes.POINTER(vp)]
     lib.gm_field_destroy.argtypes = [vp]
@@ -239,10 +241,11 @@ class Scene:
                 "bvh_depth": depth.value, "bbox": list(bbox)}
 
     def density_stats(self):
-        """Counters of the last accumulate call: in-cone pairs, visible pairs, traversals, node visits."""
-        out = (ctypes.c_int64 * 4)()
-        _check(_lib.gm_density_stats(self._h, out))
-        return dict(zip(("in_cone", "visible", "traversals", "node_visits"), out[:]))
+        """Counters of the last accumulate call: in-cone pairs, visible pairs, traversals,
+        node visits, triangle tests (wave level)."""
+        out = (ctypes.c_int64 * 5)()
+        _check(_lib.gm_density_counters(self._h, out, 5))
+        return dict(zip(("in_cone", "visible", "traversals", "node_visits", "triangle_tests"), out[:]))
 
     def profile(self, on=True):
         _check(_lib.gm_profile_enable(self._h, 1 if on else 0))

@@ -528,20 +528,22 @@ gm_status gm_debug_pair_visibility(gm_scene* sc, const float* pos, const int32_t
     return GM_OK;
 }
 
-gm_status gm_density_stats(gm_scene* sc, int64_t* out)
+gm_status gm_density_counters(gm_scene* sc, int64_t* out, int32_t n_out)
 {
     gm::clear_error();
     if (!sc || !out) return fail(GM_ERR_INVALID_ARGUMENT, "scene and out must not be NULL");
-    if (!sc->work.stats.p) {
-        for (int i = 0; i < kDensityStats; ++i) out[i] = 0;
-        return GM_OK;
-    }
+    if (n_out < 0) return fail(GM_ERR_INVALID_ARGUMENT, "n_out < 0");
+    const int n = std::min<int32_t>(n_out, kDensityStats);
+    for (int i = 0; i < n_out; ++i) out[i] = 0;
+    if (!sc->work.stats.p) return GM_OK;
     GM_HIP(hipDeviceSynchronize());
     unsigned long long v[kDensityStats];
     GM_HIP(hipMemcpy(v, sc->work.stats.p, sizeof(v), hipMemcpyDeviceToHost));
-    for (int i = 0; i < kDensityStats; ++i) out[i] = (int64_t)v[i];
+    for (int i = 0; i < n; ++i) out[i] = (int64_t)v[i];
     return GM_OK;
 }
+
+gm_status gm_density_stats(gm_scene* sc, int64_t* out) { return gm_density_counters(sc, out, 4); }
 
 gm_status gm_profile_enable(gm_scene* sc, int32_t on)
 {

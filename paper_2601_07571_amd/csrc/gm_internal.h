@@ -111,7 +111,8 @@ void launch_sample(const float* V, const int32_t* I, const unsigned long long* C
                    uint64_t seed, int32_t* tri, int32_t* mesh, float* bary, float* pos, hipStream_t s);
 
 // density path
-constexpr int kDensityStats = 4;  // in-cone pairs, visible pairs, packet traversals, BVH node visits
+// in-cone pairs, visible pairs, packet traversals, BVH node visits, triangle tests (wave level)
+constexpr int kDensityStats = 5;
 // One mesh's BVH inside the concatenated per-mesh arrays: kNodeCopies copies of
 // node_count nodes from node_base, kTriCopies copies of tri_count records from tri_base.
 struct BlasDesc {

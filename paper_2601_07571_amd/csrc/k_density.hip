@@ -259,6 +259,12 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, bool acti
     return ((mixed ^ 1) & (int)(det != 0.0f) & (int)(Ts > 0.0f) & (int)(Ts < fabsf(s.tz) * fabsf(det))) != 0;
 }
 
+// Work of packet traversals (wave level): node visits, triangle tests (one per
+// triangle tested by at least one lane).
+struct TravCount {
+    uint32_t nodes = 0, tests = 0;
+};
+
 // Packet visibility.  Every lane carries up to R segments (R sample slots of the
 // wave), all starting at the wave's eye; `active[r]` marks the segments to test and
 // occ[r] receives the answer.  One traversal serves all R * 64 segments: the node
@@ -275,7 +281,7 @@ template <int R, bool UNI>
 __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, float e0,
                                 float e1, float e2, int oct, const Seg (&sg)[R],
                                 const int (&own_tri)[R], const int (&own_mesh)[R], int mode, float tmax,
-                                const bool (&active)[R], bool (&occ)[R], uint32_t& visits)
+                                const bool (&active)[R], bool (&occ)[R], TravCount& visits)
 {
     const int lane = lane_id();
     uint64_t live[R], hit[R];
@@ -291,7 +297,7 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
     int node = 0;
     while (alive != 0) {
         const BvhNode nd = load_node(nodes, node);
-        ++visits;
+        ++visits.nodes;
         uint64_t h0[R], h1[R];
         uint64_t any0 = 0, any1 = 0;
 #pragma unroll
@@ -336,6 +342,7 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
                         tany |= tm[r];
                     }
                     if (tany == 0) continue;
+                    ++visits.tests;
                     const TriEye u = tri_eye(tr[k], e0, e1, e2);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
@@ -882,7 +889,7 @@ __device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ no
                                                   float ey, float ez, float rx, float ry, float rz,
                                                   const float4 (&p)[SPL], const int (&otri)[SPL],
                                                   const int (&omesh)[SPL], int mode, float tmax,
-                                                  const bool (&need)[SPL], bool (&occl)[SPL], uint32_t& n_visits)
+                                                  const bool (&need)[SPL], bool (&occl)[SPL], TravCount& n_visits)
 {
     // The packet shares the axis order of the gaze's dominant axis when every
     // segment keeps at least 0.4 of its length along that axis (true for every
@@ -995,7 +1002,8 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
     if (threadIdx.x == 0) s_rad = 0.0f;
     if (threadIdx.x < kDensityStats) s_stats[threadIdx.x] = 0u;
     __syncthreads();
-    uint32_t n_in = 0, n_vis = 0, n_trav = 0, n_visits = 0;  // wave-uniform counters
+    uint32_t n_in = 0, n_vis = 0, n_trav = 0;  // wave-uniform counters
+    TravCount n_visits;
 
     float px[SPL], py[SPL], pz[SPL], pq[SPL];
     float rad = 0.0f;
@@ -1167,7 +1175,8 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
         atomicAdd(&s_stats[0], n_in);
         atomicAdd(&s_stats[1], n_vis);
         atomicAdd(&s_stats[2], n_trav);
-        atomicAdd(&s_stats[3], n_visits);
+        atomicAdd(&s_stats[3], n_visits.nodes);
+        atomicAdd(&s_stats[4], n_visits.tests);
     }
     __syncthreads();
     if (threadIdx.x < kDensityStats && s_stats[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], (unsigned long long)s_stats[threadIdx.x]);
@@ -1291,7 +1300,7 @@ __global__ void __launch_bounds__(64) k_pair_visibility(const float* __restrict_
     int kx, ky, kz;
     axis_order(px - ex, py - ey, pz - ez, kx, ky, kz);
     const Seg sgs[1] = {make_seg(ex, ey, ez, px, py, pz, kx, ky, kz, tmax)};
-    uint32_t visits = 0;
+    TravCount visits;
     const int ot[1] = {t}, om[1] = {me};
     const bool act[1] = {mode != 0 && lane == 0};
     bool occ[1] = {false};

@@ -234,3 +234,31 @@ def test_several_samples_per_lane(gm, tiny, spl, monkeypatch):
         counts.append(sp.density_stats())
     assert counts[0]["in_cone"] == counts[1]["in_cone"]
     assert abs(counts[0]["visible"] - counts[1]["visible"]) <= 1e-5 * counts[0]["in_cone"]
+
+
+def test_counters(gm):
+    """gm_density_stats and gm_density_counters agree; visible <= in-cone; no traversal
+    work without occlusion; a packet tests at most kLeafMax triangles per node visit
+    and both children's leaves."""
+    import ctypes
+    import torch
+    w = workloads.tiny_icosphere_scene()
+    scene = gm.Scene([(m.V, m.I) for m in w.meshes])
+    s = scene.build_samples(w.k, seed=w.seed)
+    fix = gm.Fixations(w.fix.eye, w.fix.gaze, w.fix.dur)
+    scene.accumulate(s.pos, fix, w.theta_deg, occlusion="self", tri=s.tri, mesh=s.mesh)
+    torch.cuda.synchronize()
+    c = scene.density_stats()
+    four = (ctypes.c_int64 * 4)()
+    assert gm._lib.gm_density_stats(scene._h, four) == 0
+    seven = (ctypes.c_int64 * 7)()
+    assert gm._lib.gm_density_counters(scene._h, seven, 7) == 0
+    assert list(four) == [c["in_cone"], c["visible"], c["traversals"], c["node_visits"]]
+    assert list(seven)[:5] == list(c.values()) and seven[5] == 0 and seven[6] == 0
+    assert 0 < c["visible"] < c["in_cone"] and c["traversals"] > 0
+    assert 0 < c["triangle_tests"] <= 2 * 4 * c["node_visits"]
+    scene.accumulate(s.pos, fix, w.theta_deg, occlusion="none", tri=s.tri, mesh=s.mesh)
+    torch.cuda.synchronize()
+    c0 = scene.density_stats()
+    assert c0["in_cone"] == c["in_cone"] and c0["visible"] == c0["in_cone"]
+    assert c0["traversals"] == c0["node_visits"] == c0["triangle_tests"] == 0
