@@ -242,6 +242,12 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, bool acti
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
+    {
+        // most tests miss for every lane: edge functions of both signs and none zero
+        const bool z = ((int)(U == 0.0f) | (int)(V == 0.0f) | (int)(W == 0.0f)) != 0;
+        const bool mx = ((int)(fminf(fminf(U, V), W) < 0.0f) & (int)(fmaxf(fmaxf(U, V), W) > 0.0f)) != 0;
+        if (ballot(active && (z || !mx)) == 0) return false;
+    }
     if (active && (U == 0.0f || V == 0.0f || W == 0.0f)) {
         // rare: keep it a real branch (the empty asm stops the compiler from
         // evaluating the FP64 products for every lane and selecting afterwards)
