@@ -21,7 +21,7 @@ struct gm_field {
     int32_t M = 0;
     std::vector<FieldGeom> geom;  // [M]
     DevBuf master, m, v, grad, blob, loss;
-    DevBuf flag, sel, offs, idx, scan_tmp, pred, l2sums;
+    DevBuf flag, sel, offs, idx, scan_tmp, pred, l2sums, geom_d, net_off, net_cnt;
     DevBuf gate_d, need, qoffs, qscan, gpos, gtri, gmesh, gidx, grho, gnorm;
     std::vector<float> rel_l2;
     std::vector<uint8_t> gate;
@@ -33,7 +33,8 @@ struct gm_field {
     ~gm_field()
     {
         for (DevBuf* b : {&master, &m, &v, &grad, &blob, &loss, &flag, &sel, &offs, &idx, &scan_tmp, &pred, &l2sums,
-                          &gate_d, &need, &qoffs, &qscan, &gpos, &gtri, &gmesh, &gidx, &grho, &gnorm})
+                          &geom_d, &net_off, &net_cnt, &gate_d, &need, &qoffs, &qscan, &gpos, &gtri, &gmesh, &gidx,
+                          &grho, &gnorm})
             b->release();
     }
 };
@@ -63,13 +64,12 @@ void init_params(uint64_t seed, std::vector<float>& p)
     for (int i = 0; i < kFieldWidth; ++i) p[(size_t)(kFieldOffW5 + i)] = uni(lim5);
 }
 
-float* net_master(gm_field* f, int m) { return f->master.as<float>() + (size_t)m * kFieldParams; }
 unsigned char* net_blob(gm_field* f, int m) { return f->blob.as<unsigned char>() + (size_t)m * field_pack_bytes(); }
 
 gm_status upload_params(gm_field* f, const float* host, hipStream_t s)
 {
     GM_HIP(hipMemcpyAsync(f->master.p, host, sizeof(float) * kFieldParams * (size_t)f->M, hipMemcpyHostToDevice, s));
-    for (int m = 0; m < f->M; ++m) launch_field_pack(net_master(f, m), net_blob(f, m), s);
+    launch_field_pack_nets(f->master.as<float>(), f->blob.as<unsigned char>(), f->M, s);
     GM_HIP(hipGetLastError());
     GM_HIP(hipStreamSynchronize(s));
     return GM_OK;
@@ -125,7 +125,10 @@ gm_status gm_field_create(gm_scene* scene, uint64_t seed, double max_cycles, gm_
     for (DevBuf* b : {&f->master, &f->m, &f->v, &f->grad})
         if (e == hipSuccess) e = b->ensure(sizeof(float) * np);
     if (e == hipSuccess) e = f->blob.ensure(field_pack_bytes() * (size_t)f->M);
-    if (e == hipSuccess) e = f->loss.ensure(sizeof(double));
+    if (e == hipSuccess) e = f->loss.ensure(sizeof(double) * (size_t)f->M);
+    if (e == hipSuccess) e = f->geom_d.ensure(sizeof(FieldGeom) * (size_t)f->M);
+    if (e == hipSuccess)
+        e = hipMemcpy(f->geom_d.p, f->geom.data(), sizeof(FieldGeom) * (size_t)f->M, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         delete f;
         return fail(GM_ERR_OUT_OF_MEMORY, "field allocation: %s", hipGetErrorString(e));
@@ -247,59 +250,71 @@ gm_status gm_field_train(gm_field* f, const float* pos, const int32_t* mesh, con
     zero(f->pred.p, 4 * (size_t)n, s);
     double last = NAN;
     std::vector<uint8_t> has_train((size_t)M, 0);
+    // each mesh's training points, compacted one mesh after the other into idx
+    std::vector<int64_t> off((size_t)M, 0), cnt((size_t)M, 0);
+    int64_t total = 0;
     for (int32_t net = 0; net < M; ++net) {
-        // this mesh's training points, compacted
         launch_field_select(f->flag.as<uint32_t>(), mesh, net, n, f->sel.as<uint32_t>(), s);
         launch_exclusive_scan_u32(f->sel.as<uint32_t>(), f->offs.as<uint32_t>(), n, f->scan_tmp.p, s);
-        launch_field_compact(f->sel.as<uint32_t>(), f->offs.as<uint32_t>(), n, f->idx.as<int32_t>(), s);
+        launch_field_compact(f->sel.as<uint32_t>(), f->offs.as<uint32_t>(), n, f->idx.as<int32_t>() + total, s);
         uint32_t last_off = 0, last_sel = 0;
         GM_HIP(hipMemcpyAsync(&last_off, f->offs.as<uint32_t>() + (n - 1), 4, hipMemcpyDeviceToHost, s));
         GM_HIP(hipMemcpyAsync(&last_sel, f->sel.as<uint32_t>() + (n - 1), 4, hipMemcpyDeviceToHost, s));
         GM_HIP(hipStreamSynchronize(s));
-        const int64_t n_train = (int64_t)last_off + last_sel;
-        if (n_train < 1) continue;  // a mesh without training points keeps its gate closed
-        has_train[(size_t)net] = 1;
-
-        float* master = net_master(f, net);
-        float* mom = f->m.as<float>() + (size_t)net * kFieldParams;
-        float* vel = f->v.as<float>() + (size_t)net * kFieldParams;
-        float* gr = f->grad.as<float>() + (size_t)net * kFieldParams;
-        unsigned char* blob = net_blob(f, net);
-        FieldTrain t;
-        t.pos = pos;
-        t.target = target;
-        t.idx = f->idx.as<int32_t>();
-        t.n_idx = n_train;
-        t.batch = P->batch;
-        t.inv_batch = 1.0f / (float)P->batch;
-        t.key0 = key0 ^ 0x5bd1e995u ^ (uint32_t)net;
-        t.key1 = key1 ^ 0x1b873593u;
-        t.grad = gr;
-        t.loss = f->loss.as<double>();
-        double b1t = 1.0, b2t = 1.0;
-        for (int32_t it = 0; it < P->steps; ++it) {
-            t.step = (uint32_t)it;
-            zero(f->loss.p, sizeof(double), s);
-            launch_field_train(blob, f->geom[(size_t)net], t, s);
-            b1t *= P->beta1;
-            b2t *= P->beta2;
-            const double frac = P->steps > 1 ? (double)it / (double)(P->steps - 1) : 1.0;
-            const double lr = P->lr_final + 0.5 * (P->lr - P->lr_final) * (1.0 + std::cos(M_PI * frac));
-            launch_field_adam(master, mom, vel, gr, (float)lr, P->beta1, P->beta2, P->eps, (float)(1.0 / (1.0 - b1t)),
-                              (float)(1.0 / (1.0 - b2t)), s);
-            launch_field_pack(master, blob, s);
-        }
-        GM_HIP(hipGetLastError());
-        if (P->steps > 0) {
-            double l = NAN;
-            GM_HIP(hipMemcpyAsync(&l, f->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
-            GM_HIP(hipStreamSynchronize(s));
-            last = std::isnan(last) ? l : std::max(last, l);
-        }
-        // this network's values at its mesh's points, for the held-out error
-        launch_field_infer(blob, f->geom[(size_t)net], pos, n, f->pred.as<float>(),
-                           FieldRoute{mesh, nullptr, nullptr, 0, net}, s);
+        off[(size_t)net] = total;
+        cnt[(size_t)net] = (int64_t)last_off + last_sel;
+        total += cnt[(size_t)net];
+        has_train[(size_t)net] = cnt[(size_t)net] > 0;  // a mesh without training points keeps its gate closed
     }
+    GM_HIP(f->net_off.ensure(sizeof(int64_t) * (size_t)M));
+    GM_HIP(f->net_cnt.ensure(sizeof(int64_t) * (size_t)M));
+    GM_HIP(hipMemcpyAsync(f->net_off.p, off.data(), sizeof(int64_t) * (size_t)M, hipMemcpyHostToDevice, s));
+    GM_HIP(hipMemcpyAsync(f->net_cnt.p, cnt.data(), sizeof(int64_t) * (size_t)M, hipMemcpyHostToDevice, s));
+    FieldNets nets;
+    nets.geom = f->geom_d.as<FieldGeom>();
+    nets.off = f->net_off.as<int64_t>();
+    nets.cnt = f->net_cnt.as<int64_t>();
+    nets.pack_stride = (int64_t)field_pack_bytes();
+    // every network takes the same steps at once: one launch per step for all of them
+    // (network m draws its batches with key0 ^ m, as a launch of its own would)
+    FieldTrain t;
+    t.pos = pos;
+    t.target = target;
+    t.idx = f->idx.as<int32_t>();
+    t.n_idx = 0;
+    t.batch = P->batch;
+    t.inv_batch = 1.0f / (float)P->batch;
+    t.key0 = key0 ^ 0x5bd1e995u;
+    t.key1 = key1 ^ 0x1b873593u;
+    t.grad = f->grad.as<float>();
+    t.loss = f->loss.as<double>();
+    double b1t = 1.0, b2t = 1.0;
+    for (int32_t it = 0; it < P->steps && total > 0; ++it) {
+        t.step = (uint32_t)it;
+        zero(f->loss.p, sizeof(double) * (size_t)M, s);
+        launch_field_train_nets(f->blob.as<unsigned char>(), nets, M, t, s);
+        b1t *= P->beta1;
+        b2t *= P->beta2;
+        const double frac = P->steps > 1 ? (double)it / (double)(P->steps - 1) : 1.0;
+        const double lr = P->lr_final + 0.5 * (P->lr - P->lr_final) * (1.0 + std::cos(M_PI * frac));
+        launch_field_adam(f->master.as<float>(), f->m.as<float>(), f->v.as<float>(), f->grad.as<float>(),
+                          (int64_t)M * kFieldParams, (float)lr, P->beta1, P->beta2, P->eps,
+                          (float)(1.0 / (1.0 - b1t)), (float)(1.0 / (1.0 - b2t)), s);
+        launch_field_pack_nets(f->master.as<float>(), f->blob.as<unsigned char>(), M, s);
+    }
+    GM_HIP(hipGetLastError());
+    if (P->steps > 0 && total > 0) {
+        std::vector<double> l((size_t)M, NAN);
+        GM_HIP(hipMemcpyAsync(l.data(), f->loss.p, sizeof(double) * (size_t)M, hipMemcpyDeviceToHost, s));
+        GM_HIP(hipStreamSynchronize(s));
+        for (int32_t net = 0; net < M; ++net)
+            if (has_train[(size_t)net]) last = std::isnan(last) ? l[(size_t)net] : std::max(last, l[(size_t)net]);
+    }
+    // each network's values at its mesh's points, for the held-out error
+    for (int32_t net = 0; net < M; ++net)
+        if (has_train[(size_t)net])
+            launch_field_infer(net_blob(f, net), f->geom[(size_t)net], pos, n, f->pred.as<float>(),
+                               FieldRoute{mesh, nullptr, nullptr, 0, net}, s);
 
     // held-out relative L2 per mesh
     zero(f->l2sums.p, 16 * (size_t)M, s);

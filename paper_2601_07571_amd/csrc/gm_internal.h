@@ -251,7 +251,19 @@ struct FieldTrain {
     double* loss;            // sum of squared errors of the step
 };
 
+// Several networks in one launch (blockIdx.y = network): geometry, and the start and
+// number of each network's training indices in FieldTrain::idx (0: nothing to train),
+// packed images pack_stride bytes apart.  off == NULL: one network, as passed.
+struct FieldNets {
+    const FieldGeom* geom = nullptr;
+    const int64_t* off = nullptr;
+    const int64_t* cnt = nullptr;
+    int64_t pack_stride = 0;
+};
+
 void launch_field_pack(const float* master, unsigned char* blob, hipStream_t s);
+// the packed images of M networks (parameters kFieldParams apart, images field_pack_bytes() apart)
+void launch_field_pack_nets(const float* master, unsigned char* blob, int32_t M, hipStream_t s);
 // Points whose mesh (mesh[i], else tri_mesh[tri[i]] for 0 <= tri[i] < T) is `m` get the
 // network's value; m < 0 writes every point.
 struct FieldRoute {
@@ -266,8 +278,11 @@ void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const flo
 // sel[i] = flag[i] && mesh[i] == m
 void launch_field_select(const uint32_t* flag, const int32_t* mesh, int32_t m, int64_t n, uint32_t* sel, hipStream_t s);
 void launch_field_train(const unsigned char* blob, const FieldGeom& g, const FieldTrain& t, hipStream_t s);
-void launch_field_adam(float* master, float* m, float* v, float* grad, float lr, float b1, float b2, float eps,
-                       float c1, float c2, hipStream_t s);
+// one training step of M networks at once (see FieldNets; t.key0 is xored with the network)
+void launch_field_train_nets(const unsigned char* blob, const FieldNets& nets, int32_t M, const FieldTrain& t,
+                             hipStream_t s);
+void launch_field_adam(float* master, float* m, float* v, float* grad, int64_t count, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s);
 // held-out split and per-mesh error sums
 void launch_field_split(int64_t n, uint32_t key0, uint32_t key1, uint32_t threshold, uint32_t* flag_train,
                         hipStream_t s);

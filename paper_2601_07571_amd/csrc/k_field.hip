@@ -140,9 +140,11 @@ __device__ __forceinline__ void stage(unsigned char* dst, const unsigned char* _
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k_field_pack(const float* __restrict__ p, unsigned char* __restrict__ blob)
+__global__ void k_field_pack(const float* __restrict__ p, unsigned char* __restrict__ blob, int64_t pack_stride)
 {
     const int t = blockIdx.x * kThreads + threadIdx.x;
+    p += (int64_t)blockIdx.y * kFieldParams;  // network blockIdx.y
+    blob += (int64_t)blockIdx.y * pack_stride;
     __bf16* bf = reinterpret_cast<__bf16*>(blob);
     float* f32 = reinterpret_cast<float*>(blob);
     const int nF1 = kW * kS1, nH = kW * kSH;
@@ -219,8 +221,21 @@ __global__ void __launch_bounds__(kThreads) k_field_infer(const unsigned char* _
 }
 
 __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* __restrict__ blob, FieldGeom g,
-                                                          FieldTrain t)
+                                                          FieldTrain t, FieldNets nets)
 {
+    if (nets.off) {
+        // network blockIdx.y of several trained in one launch
+        const int m = blockIdx.y;
+        const int64_t c = nets.cnt[m];
+        if (c == 0) return;
+        blob += (int64_t)m * nets.pack_stride;
+        g = nets.geom[m];
+        t.idx += nets.off[m];
+        t.n_idx = c;
+        t.key0 ^= (uint32_t)m;
+        t.grad += (int64_t)m * kFieldParams;
+        t.loss += m;
+    }
     __shared__ __attribute__((aligned(16))) unsigned char s_blob[kPack];
     __shared__ __attribute__((aligned(16))) __bf16 s_dz[kThreads / 64][kW][kTileStride];
     __shared__ __attribute__((aligned(16))) __bf16 s_h[kThreads / 64][kFieldFeat][kTileStride];
@@ -347,10 +362,11 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
 }
 
 __global__ void k_field_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                             float* __restrict__ grad, float lr, float b1, float b2, float eps, float c1, float c2)
+                             float* __restrict__ grad, int64_t count, float lr, float b1, float b2, float eps,
+                             float c1, float c2)
 {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= kFieldParams) return;
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= count) return;
     const float g = grad[i];
     const float mi = b1 * m[i] + (1.0f - b1) * g;
     const float vi = b2 * v[i] + (1.0f - b2) * g * g;
@@ -451,7 +467,12 @@ size_t field_infer_bytes() { return kInfer; }
 
 void launch_field_pack(const float* master, unsigned char* blob, hipStream_t s)
 {
-    k_field_pack<<<blocks(kPackThreads), kThreads, 0, s>>>(master, blob);
+    k_field_pack<<<blocks(kPackThreads), kThreads, 0, s>>>(master, blob, 0);
+}
+
+void launch_field_pack_nets(const float* master, unsigned char* blob, int32_t M, hipStream_t s)
+{
+    if (M > 0) k_field_pack<<<dim3(blocks(kPackThreads), (unsigned)M), kThreads, 0, s>>>(master, blob, kPack);
 }
 
 void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const float* pos, int64_t q, float* out,
@@ -473,13 +494,23 @@ void launch_field_train(const unsigned char* blob, const FieldGeom& g, const Fie
     if (t.batch <= 0) return;
     const int tiles = (t.batch + 31) / 32;
     const unsigned grid = (unsigned)std::min(((tiles + 3) / 4), 1024);
-    k_field_train<<<grid, kThreads, 0, s>>>(blob, g, t);
+    k_field_train<<<grid, kThreads, 0, s>>>(blob, g, t, FieldNets{});
 }
 
-void launch_field_adam(float* master, float* m, float* v, float* grad, float lr, float b1, float b2, float eps,
-                       float c1, float c2, hipStream_t s)
+void launch_field_train_nets(const unsigned char* blob, const FieldNets& nets, int32_t M, const FieldTrain& t,
+                             hipStream_t s)
 {
-    k_field_adam<<<blocks(kFieldParams), kThreads, 0, s>>>(master, m, v, grad, lr, b1, b2, eps, c1, c2);
+    if (t.batch <= 0 || M <= 0) return;
+    const int tiles = (t.batch + 31) / 32;
+    const unsigned grid = (unsigned)std::min(((tiles + 3) / 4), 1024);
+    k_field_train<<<dim3(grid, (unsigned)M), kThreads, 0, s>>>(blob, FieldGeom{}, t, nets);
+}
+
+void launch_field_adam(float* master, float* m, float* v, float* grad, int64_t count, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s)
+{
+    if (count > 0)
+        k_field_adam<<<blocks(count), kThreads, 0, s>>>(master, m, v, grad, count, lr, b1, b2, eps, c1, c2);
 }
 
 void launch_field_split(int64_t n, uint32_t key0, uint32_t key1, uint32_t threshold, uint32_t* flag, hipStream_t s)
