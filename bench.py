@@ -89,14 +89,24 @@ def main():
     torch.cuda.synchronize()
     scene.profile(True)
     torch.cuda.synchronize()
+    # per-step HIP events on the launch stream (no host synchronisation inside the timed
+    # region), for the spread of the step time
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for a, b in evs:
+        a.record()
         step()
+        b.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stage = {s: scene.profile_read(s) for s in ("sample", "prep", "density", "finalize")}
     scene.profile(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
+    per_step = np.array([a.elapsed_time(b) for a, b in evs])
+    sd = float(per_step.std(ddof=1)) if len(per_step) > 1 else 0.0
+    spread = {"mean_ms": float(per_step.mean()), "std_ms": sd,
+              "ci95_ms": [float(per_step.mean() - 1.96 * sd / math.sqrt(len(per_step))),
+                          float(per_step.mean() + 1.96 * sd / math.sqrt(len(per_step)))]}
     pairs = float(N) * F
     dens_ms = stage["density"][0] / max(1, stage["density"][1])
 
@@ -134,7 +144,13 @@ def main():
                                "full occlusion",
                    "triangles": T, "samples": N, "fixations": F, "samples_per_m2": k},
         "map_time_ms": ms_step,
+        "step_spread": spread,
         "stage_ms": {s: v[0] / args.steps for s, v in stage.items()},
+        # the HBM-bound stages priced by their algorithmic bytes: sampling (a1-a3) ~72 B per
+        # triangle and ~60 B per sample, finalisation (a7) 8 B read + 8 B for the maximum +
+        # 8 B written per sample
+        "stage_GBps": {"sample": (72.0 * T + 60.0 * N) / (stage["sample"][0] / args.steps * 1e-3) / 1e9,
+                       "finalize": 24.0 * N / (stage["finalize"][0] / args.steps * 1e-3) / 1e9},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(),
                      "kernel": "k_density (gate + exact value + visibility)", "kernel_ms": dens_ms,
