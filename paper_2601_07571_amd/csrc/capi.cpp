@@ -211,7 +211,6 @@ void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F
     a.tris = sc->tris.as<BvhTri>();
     a.tri_stride = (int64_t)sc->bvh.tris.size();
     a.occ_mode = (int32_t)mode;
-    a.tmax = (float)(1.0 - kEpsV);
     a.cone2 = (float)(16.0 * sigma * sigma);
     a.kexp = (float)(1.0 / (2.0 * sigma * sigma * std::log(2.0)));
     a.fx_shift = w.fx_shift.as<int32_t>();
@@ -523,7 +522,7 @@ gm_status gm_debug_pair_visibility(gm_scene* sc, const float* pos, const int32_t
     gm_status st = check_device(sc);
     if (st != GM_OK) return st;
     launch_pair_visibility(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), eye, pair_s, pair_f, m, n_points, n_eyes, sc->T,
-                           sc->nodes.as<BvhNode>(), sc->tris.as<BvhTri>() + 2 * sc->bvh.tris.size(), (int32_t)mode, (float)(1.0 - kEpsV), vis_out, (hipStream_t)stream);
+                           sc->nodes.as<BvhNode>(), sc->tris.as<BvhTri>() + 2 * sc->bvh.tris.size(), (int32_t)mode, kTmax, vis_out, (hipStream_t)stream);
     GM_HIP(hipGetLastError());
     return GM_OK;
 }

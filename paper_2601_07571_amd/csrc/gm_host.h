@@ -105,7 +105,6 @@ struct StageTimer {
 enum Stage { kStageSample = 0, kStagePrep, kStageDensity, kStageFinalize, kStages };
 const char* const kStageNames[kStages] = {"sample", "prep", "density", "finalize"};
 
-constexpr double kEpsV = 1e-4;         // visibility tolerance along the segment
 // Relative widening of kappa in the cheap cone gate.  The FP32 error of the gate value
 // is below ~1e-6 |r|^2 (|e'| + |x'|)^2 (tile-local coordinates), the widening adds
 // kGateWiden * kappa |p|^2 of margin, so no pair of the exact cone is missed while

@@ -113,6 +113,11 @@ void launch_sample(const float* V, const int32_t* I, const unsigned long long* C
 // density path
 // in-cone pairs, visible pairs, packet traversals, BVH node visits, triangle tests (wave level)
 constexpr int kDensityStats = 5;
+// Tolerance of the exact visibility test (the exact counterpart of the depth test of
+// Sec. 3.2.2): a hit occludes when its segment parameter lies in (0, 1 - kEpsV).  The
+// kernels take the bound as a compile-time constant.
+constexpr double kEpsV = 1e-4;
+constexpr float kTmax = (float)(1.0 - kEpsV);
 // One mesh's BVH inside the concatenated per-mesh arrays: kNodeCopies copies of
 // node_count nodes from node_base, kTriCopies copies of tri_count records from tri_base.
 struct BlasDesc {
@@ -131,7 +136,6 @@ struct DensityLaunch {
     const BvhTri* tris;        // kTriCopies permuted copies
     int64_t tri_stride;        // records per copy
     int32_t occ_mode;
-    float tmax;                // 1 - eps_v
     float cone2;               // 16 sigma^2
     float kexp;                // log2(e) / (2 sigma^2)
     const int32_t* fx_shift;   // device scalar: fixed-point scale exponent

@@ -216,12 +216,14 @@ __device__ __forceinline__ TriEye tri_eye(const BvhTri& t, float e0, float e1, f
 // Watertight segment/triangle test (Woop, Benthin and Wald, JCGT 2013): shear the
 // triangle into the segment's frame, three edge functions with inclusive edges,
 // FP64 re-evaluation when an edge function is exactly zero; hit when the
-// parameter tau = T/det lies in (0, tmax).  Lanes with `active` false get an
-// unspecified answer.  With UNI the vertices are already in
+// parameter tau = T/det lies in (0, tmax).  Returns the wave mask of the lanes of
+// `amask` (the lanes testing) that hit.  With UNI the vertices are already in
 // the segment's axis order; otherwise they are in x, y, z order and each lane
 // permutes them.  Both windings count, so the order of kx and ky does not matter.
+// Predicates are formed as wave masks of single compares (scalar ANDs) rather than
+// as per-lane booleans.
 template <bool UNI>
-__device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, bool active)
+__device__ __forceinline__ uint64_t seg_tri(const Seg& s, const TriEye& u, uint64_t amask)
 {
     float akx, aky, akz, bkx, bky, bkz, ckx, cky, ckz;
     if (UNI) {
@@ -242,27 +244,30 @@ __device__ __forceinline__ bool seg_tri(const Seg& s, const TriEye& u, bool acti
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
-    {
-        // most tests miss for every lane: edge functions of both signs and none zero
-        const bool z = ((int)(U == 0.0f) | (int)(V == 0.0f) | (int)(W == 0.0f)) != 0;
-        const bool mx = ((int)(fminf(fminf(U, V), W) < 0.0f) & (int)(fmaxf(fmaxf(U, V), W) > 0.0f)) != 0;
-        if (ballot(active && (z || !mx)) == 0) return false;
-    }
-    if (active && (U == 0.0f || V == 0.0f || W == 0.0f)) {
+    float lo = fminf(fminf(U, V), W), hi = fmaxf(fmaxf(U, V), W);
+    const float amin = fminf(fminf(fabsf(U), fabsf(V)), fabsf(W));
+    // Most tests miss for every lane: edge functions of both signs and none zero,
+    // exactly when (lo * hi) * amin < 0 (an underflow to -0 only sends the wave on
+    // to the full test).
+    if ((ballot(!((lo * hi) * amin < 0.0f)) & amask) == 0) return 0;
+    const uint64_t zero = ballot(amin == 0.0f) & amask;
+    if (__builtin_amdgcn_inverse_ballot_w64(zero)) {
         // rare: keep it a real branch (the empty asm stops the compiler from
         // evaluating the FP64 products for every lane and selecting afterwards)
         asm volatile("" ::: "memory");
         U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
         W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+        lo = fminf(fminf(U, V), W);
+        hi = fmaxf(fmaxf(U, V), W);
     }
-    const int mixed = (int)(fminf(fminf(U, V), W) < 0.0f) & (int)(fmaxf(fmaxf(U, V), W) > 0.0f);
     const float det = U + V + W;
     // tau = T' / (det d[kz]) with T' = U akz + V bkz + W ckz: scale T' by the sign of
     // det d[kz] so the range test reads 0 < T' < tmax |d[kz]| |det|
     const float Tp = __builtin_fmaf(W, ckz, __builtin_fmaf(V, bkz, U * akz));
     const float Ts = __uint_as_float(__float_as_uint(Tp) ^ ((__float_as_uint(det) ^ __float_as_uint(s.tz)) & 0x80000000u));
-    return ((mixed ^ 1) & (int)(det != 0.0f) & (int)(Ts > 0.0f) & (int)(Ts < fabsf(s.tz) * fabsf(det))) != 0;
+    const uint64_t mixed = ballot(lo < 0.0f) & ballot(hi > 0.0f);
+    return amask & ~mixed & ballot(det != 0.0f) & ballot(Ts > 0.0f) & ballot(Ts < fabsf(s.tz) * fabsf(det));
 }
 
 // Work of packet traversals (wave level): node visits, triangle tests (one per
@@ -298,6 +303,8 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
         hit[r] = 0;
         alive |= live[r];
     }
+    // self occlusion: only triangles of the segment's own mesh occlude
+    const uint64_t self_only = mode == 1 ? ~0ull : 0ull;
     int stack = 0;
     int sp = 0;
     int node = 0;
@@ -342,8 +349,8 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
                     uint64_t tany = 0;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        uint64_t skip = ballot(tr[k].id == own_tri[r]);
-                        if (mode == 1) skip |= ballot(tr[k].mesh != own_mesh[r]);
+                        const uint64_t skip = ballot(tr[k].id == own_tri[r]) |
+                                              (ballot(tr[k].mesh != own_mesh[r]) & self_only);
                         tm[r] = (first ? h0[r] : h1[r]) & ~hit[r] & ~skip;
                         tany |= tm[r];
                     }
@@ -353,8 +360,7 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         if (tm[r] == 0) continue;
-                        const bool t = __builtin_amdgcn_inverse_ballot_w64(tm[r]);
-                        hit[r] |= ballot(seg_tri<UNI>(sg[r], u, t)) & tm[r];
+                        hit[r] |= seg_tri<UNI>(sg[r], u, tm[r]);
                     }
                 }
                 alive = 0;
@@ -1109,7 +1115,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                 }
                 if (!INST) {
                     packet_visibility<SPL>(a.nodes, a.node_stride, a.tris, a.tri_stride, fr.ex, fr.ey, fr.ez, fr.rx,
-                                           fr.ry, fr.rz, p, otri, omesh, a.occ_mode, a.tmax, need, occl, n_visits);
+                                           fr.ry, fr.rz, p, otri, omesh, a.occ_mode, kTmax, need, occl, n_visits);
                     ++n_trav;
                 } else {
                     // One BVH per mesh.  Static scenes (xf NULL): every mesh in the world
@@ -1156,7 +1162,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                         bool o2[SPL];
                         packet_visibility<SPL>(a.blas_nodes + b.node_base, b.node_count, a.blas_tris + b.tri_base,
                                                b.tri_count, fo.ex, fo.ey, fo.ez, fo.rx, fo.ry, fo.rz, q, otri, omesh,
-                                               2, a.tmax, rest, o2, n_visits);
+                                               2, kTmax, rest, o2, n_visits);
 #pragma unroll
                         for (int k = 0; k < SPL; ++k) occl[k] = occl[k] || o2[k];
                         ++n_trav;
