@@ -187,8 +187,9 @@ void launch_fix_prep(const float* eye, const float* gaze, const float* dur, int3
 void launch_zcam_prep(const float* eye, const float* gaze, const float* dur, const float* head, int32_t F,
                       double sigma, double widen, double near_, double far_, FixRec* rec, ZCam* cam,
                       int32_t* fx_shift, hipStream_t s);
-void launch_zbuffer(const BvhNode* nodes, const BvhTri* tris, const FixRec* rec, const ZCam* cam, int32_t F,
-                    int32_t R, float* zbuf, hipStream_t s);
+// nodes: kNodeCopies octant copies node_stride apart; tris: kTriCopies axis copies tri_stride apart
+void launch_zbuffer(const BvhNode* nodes, int64_t node_stride, const BvhTri* tris, int64_t tri_stride,
+                    const FixRec* rec, const ZCam* cam, int32_t F, int32_t R, float* zbuf, hipStream_t s);
 // posed maps: per fixation taken, one record and one pose pair (forward, inverse) per mesh
 void launch_fix_posed(const float* eye, const float* gaze, const float* dur, const double* time, const float* pose,
                       int32_t F, int32_t M, int64_t stride, double t0, double t1, double sigma, double widen,

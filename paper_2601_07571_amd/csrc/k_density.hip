@@ -404,26 +404,41 @@ __device__ __forceinline__ Seg make_ray(float ex, float ey, float ez, float dx, 
     return s;
 }
 
-// The watertight test of seg_tri (per-lane axis order) returning the ray parameter of
-// the hit, T' / (det d[kz]), or +inf when the ray misses the triangle's plane region.
+// The watertight test of seg_tri returning the ray parameter of the hit,
+// T' / (det d[kz]), or +inf when the ray misses the triangle's plane region (and for
+// lanes with `active` false).  UNI as in seg_tri.
+template <bool UNI>
 __device__ __forceinline__ float ray_tri_t(const Seg& s, const TriEye& u, bool active)
 {
-    const float akx = pick(s.kx, u.ax, u.ay, u.az), aky = pick(s.ky, u.ax, u.ay, u.az), akz = pick(s.kz, u.ax, u.ay, u.az);
-    const float bkx = pick(s.kx, u.bx, u.by, u.bz), bky = pick(s.ky, u.bx, u.by, u.bz), bkz = pick(s.kz, u.bx, u.by, u.bz);
-    const float ckx = pick(s.kx, u.cx, u.cy, u.cz), cky = pick(s.ky, u.cx, u.cy, u.cz), ckz = pick(s.kz, u.cx, u.cy, u.cz);
+    float akx, aky, akz, bkx, bky, bkz, ckx, cky, ckz;
+    if (UNI) {
+        akx = u.ax; aky = u.ay; akz = u.az;
+        bkx = u.bx; bky = u.by; bkz = u.bz;
+        ckx = u.cx; cky = u.cy; ckz = u.cz;
+    } else {
+        akx = pick(s.kx, u.ax, u.ay, u.az); aky = pick(s.ky, u.ax, u.ay, u.az); akz = pick(s.kz, u.ax, u.ay, u.az);
+        bkx = pick(s.kx, u.bx, u.by, u.bz); bky = pick(s.ky, u.bx, u.by, u.bz); bkz = pick(s.kz, u.bx, u.by, u.bz);
+        ckx = pick(s.kx, u.cx, u.cy, u.cz); cky = pick(s.ky, u.cx, u.cy, u.cz); ckz = pick(s.kz, u.cx, u.cy, u.cz);
+    }
     const float Ax = __builtin_fmaf(-s.sx, akz, akx), Ay = __builtin_fmaf(-s.sy, akz, aky);
     const float Bx = __builtin_fmaf(-s.sx, bkz, bkx), By = __builtin_fmaf(-s.sy, bkz, bky);
     const float Cx = __builtin_fmaf(-s.sx, ckz, ckx), Cy = __builtin_fmaf(-s.sy, ckz, cky);
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
-    if (active && (U == 0.0f || V == 0.0f || W == 0.0f)) {
+    float lo = fminf(fminf(U, V), W), hi = fmaxf(fmaxf(U, V), W);
+    const float amin = fminf(fminf(fabsf(U), fabsf(V)), fabsf(W));
+    // the wave leaves when every active lane has edge functions of both signs, none zero
+    if (ballot(active && !((lo * hi) * amin < 0.0f)) == 0) return INFINITY;
+    if (active && amin == 0.0f) {
         asm volatile("" ::: "memory");
         U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
         W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+        lo = fminf(fminf(U, V), W);
+        hi = fmaxf(fmaxf(U, V), W);
     }
-    const bool mixed = (fminf(fminf(U, V), W) < 0.0f) && (fmaxf(fmaxf(U, V), W) > 0.0f);
+    const bool mixed = (lo < 0.0f) && (hi > 0.0f);
     const float det = U + V + W;
     if (mixed || det == 0.0f) return INFINITY;
     const float Tp = __builtin_fmaf(W, ckz, __builtin_fmaf(V, bkz, U * akz));
@@ -431,11 +446,14 @@ __device__ __forceinline__ float ray_tri_t(const Seg& s, const TriEye& u, bool a
 }
 
 // Nearest surface along every lane's ray (lanes with `active`), tmin <= t < tbest on
-// entry: the packet walk of occluded_packet over the plain node copy and the x, y, z
-// record copy, except that no lane stops early: each keeps its nearest hit and clips
-// its box tests to it.
-__device__ void closest_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, float ex,
-                               float ey, float ez, int oct, const Seg& sg, float tmin, bool active, float& tbest)
+// entry: the packet walk of occluded_packet, except that no lane stops early: each
+// keeps its nearest hit and clips its box tests to it.  With UNI the rays share their
+// axis order and direction signs: `nodes` is the node copy of octant `oct`, `tris` the
+// record copy in the rays' axis order and (e0, e1, e2) the eye in that order;
+// otherwise the plain node copy, the x, y, z record copy and the eye in x, y, z.
+template <bool UNI>
+__device__ void closest_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, float e0,
+                               float e1, float e2, int oct, const Seg& sg, float tmin, bool active, float& tbest)
 {
     const int lane = lane_id();
     const uint64_t live = ballot(active);
@@ -445,8 +463,8 @@ __device__ void closest_packet(const BvhNode* __restrict__ nodes, const BvhTri* 
     int node = 0;
     for (;;) {
         const BvhNode nd = load_node(nodes, node);
-        const uint64_t h0 = ballot(box_hit(sg, nd.lo0, nd.hi0, tbest)) & live;
-        const uint64_t h1 = ballot(box_hit(sg, nd.lo1, nd.hi1, tbest)) & live;
+        const uint64_t h0 = ballot(UNI ? box_hit_signed(sg, nd.lo0, nd.hi0, tbest) : box_hit(sg, nd.lo0, nd.hi0, tbest)) & live;
+        const uint64_t h1 = ballot(UNI ? box_hit_signed(sg, nd.lo1, nd.hi1, tbest) : box_hit(sg, nd.lo1, nd.hi1, tbest)) & live;
         const bool swap = (oct >> ((nd.count0 >> kSplitAxisShift) & 3)) & 1;
         int next = -1;
 #pragma unroll
@@ -465,7 +483,7 @@ __device__ void closest_packet(const BvhNode* __restrict__ nodes, const BvhTri* 
 #pragma unroll
                 for (int k = 0; k < kLeafMax; ++k) {
                     if (k >= count) break;
-                    const float t = ray_tri_t(sg, tri_eye(tr[k], ex, ey, ez), in);
+                    const float t = ray_tri_t<UNI>(sg, tri_eye(tr[k], e0, e1, e2), in);
                     if (in && t >= tmin && t < tbest) tbest = t;
                 }
             } else if (next < 0) {
@@ -806,7 +824,8 @@ __global__ void k_zcam_prep(const float* __restrict__ eye, const float* __restri
 // each pixel centre, direction x' right + y' up + forward (so the ray parameter is
 // the depth), x' = (x_ndc + ox) / sx; the buffer keeps the nearest hit with depth in
 // [near, far], +inf where there is none.  Fixations with w = 0 get +inf everywhere.
-__global__ void __launch_bounds__(256) k_zbuffer(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris,
+__global__ void __launch_bounds__(256) k_zbuffer(const BvhNode* __restrict__ nodes, int64_t node_stride,
+                                                 const BvhTri* __restrict__ tris, int64_t tri_stride,
                                                  const FixRec* __restrict__ rec, const ZCam* __restrict__ cams,
                                                  int32_t F, int32_t R, float* __restrict__ zbuf)
 {
@@ -828,14 +847,35 @@ __global__ void __launch_bounds__(256) k_zbuffer(const BvhNode* __restrict__ nod
         const float dx = __builtin_fmaf(xc, c.x[0], __builtin_fmaf(yc, c.y[0], c.f[0]));
         const float dy = __builtin_fmaf(xc, c.x[1], __builtin_fmaf(yc, c.y[1], c.f[1]));
         const float dz = __builtin_fmaf(xc, c.x[2], __builtin_fmaf(yc, c.y[2], c.f[2]));
-        int kx, ky, kz;
-        axis_order(dx, dy, dz, kx, ky, kz);
-        const Seg sg = make_ray(fr.ex, fr.ey, fr.ez, dx, dy, dz, kx, ky, kz);
-        const int lead = 0;
-        const int oct = (int)(__shfl(dx, lead) < 0.0f) | ((int)(__shfl(dy, lead) < 0.0f) << 1) |
-                        ((int)(__shfl(dz, lead) < 0.0f) << 2);
         tbest = nextafterf(c.far_, INFINITY);
-        closest_packet(nodes, tris, fr.ex, fr.ey, fr.ez, uniform(oct), sg, c.near_, true, tbest);
+        // the 64 rays of a block share the forward axis' dominant axis as their shear axis
+        // and their direction signs when each keeps 0.4 of its length along it (as the
+        // segments of packet_visibility); then they read the octant node copy and the
+        // record copy in that axis order
+        const float afx = fabsf(c.f[0]), afy = fabsf(c.f[1]), afz = fabsf(c.f[2]);
+        const int kz = uniform(afx > afy ? (afx > afz ? 0 : 2) : (afy > afz ? 1 : 2));
+        const int kx = kz == 2 ? 0 : kz + 1;
+        const int ky = kx == 2 ? 0 : kx + 1;
+        const float dk = pick(kz, dx, dy, dz);
+        const uint64_t neg_x = ballot(signbit(dx)), neg_y = ballot(signbit(dy)), neg_z = ballot(signbit(dz));
+        const bool shared = ballot(!(dk * dk >= 0.16f * (dx * dx + dy * dy + dz * dz))) == 0 &&
+                            (neg_x == 0 || ~neg_x == 0) && (neg_y == 0 || ~neg_y == 0) && (neg_z == 0 || ~neg_z == 0);
+        if (shared) {
+            const int oct = (neg_x != 0 ? 1 : 0) | (neg_y != 0 ? 2 : 0) | (neg_z != 0 ? 4 : 0);
+            const Seg sg = make_ray(fr.ex, fr.ey, fr.ez, dx, dy, dz, kx, ky, kz);
+            closest_packet<true>(nodes + oct * node_stride, tris + kz * tri_stride, pick(kx, fr.ex, fr.ey, fr.ez),
+                                 pick(ky, fr.ex, fr.ey, fr.ez), pick(kz, fr.ex, fr.ey, fr.ez), oct, sg, c.near_,
+                                 true, tbest);
+        } else {
+            int lx, ly, lz;
+            axis_order(dx, dy, dz, lx, ly, lz);
+            const Seg sg = make_ray(fr.ex, fr.ey, fr.ez, dx, dy, dz, lx, ly, lz);
+            const int lead = 0;
+            const int oct = (int)(__shfl(dx, lead) < 0.0f) | ((int)(__shfl(dy, lead) < 0.0f) << 1) |
+                            ((int)(__shfl(dz, lead) < 0.0f) << 2);
+            closest_packet<false>(nodes, tris + 2 * tri_stride, fr.ex, fr.ey, fr.ez, uniform(oct), sg, c.near_, true,
+                                  tbest);
+        }
         if (!(tbest <= c.far_)) tbest = INFINITY;
     } else {
         tbest = INFINITY;
@@ -1348,11 +1388,12 @@ void launch_zcam_prep(const float* eye, const float* gaze, const float* dur, con
     k_fix_shift<<<1, 1, 0, s>>>(wmax, F, fx_shift);
 }
 
-void launch_zbuffer(const BvhNode* nodes, const BvhTri* tris, const FixRec* rec, const ZCam* cam, int32_t F,
-                    int32_t R, float* zbuf, hipStream_t s)
+void launch_zbuffer(const BvhNode* nodes, int64_t node_stride, const BvhTri* tris, int64_t tri_stride,
+                    const FixRec* rec, const ZCam* cam, int32_t F, int32_t R, float* zbuf, hipStream_t s)
 {
     const int64_t waves = (int64_t)F * (R / 8) * (R / 8);
-    if (waves > 0) k_zbuffer<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(nodes, tris, rec, cam, F, R, zbuf);
+    if (waves > 0) k_zbuffer<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(nodes, node_stride, tris, tri_stride, rec, cam, F, R,
+                                                                zbuf);
 }
 
 void launch_fix_posed(const float* eye, const float* gaze, const float* dur, const double* time, const float* pose,

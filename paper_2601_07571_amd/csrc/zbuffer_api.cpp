@@ -45,8 +45,8 @@ gm_status render(gm_scene* sc, DensityWork& w, const gm_fixations* fix, double s
     zero(w.fx_shift.p, 16, s);
     launch_zcam_prep(fix->eye, fix->gaze, fix->duration, zp->head, F, sigma, kGateWiden, zp->near_plane,
                      zp->far_plane, w.fix.as<FixRec>(), w.zcam.as<ZCam>(), w.fx_shift.as<int32_t>(), s);
-    launch_zbuffer(sc->nodes.as<BvhNode>(), sc->tris.as<BvhTri>() + 2 * (int64_t)sc->bvh.tris.size(),
-                   w.fix.as<FixRec>(), w.zcam.as<ZCam>(), F, zp->resolution, zbuf, s);
+    launch_zbuffer(sc->nodes.as<BvhNode>(), (int64_t)sc->bvh.nodes.size(), sc->tris.as<BvhTri>(),
+                   (int64_t)sc->bvh.tris.size(), w.fix.as<FixRec>(), w.zcam.as<ZCam>(), F, zp->resolution, zbuf, s);
     GM_HIP(hipGetLastError());
     return GM_OK;
 }
