@@ -339,12 +339,13 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
                 // all records of the leaf are fetched together (the array is padded so
                 // that kLeafMax records from any leaf start are in bounds)
                 const BvhTri* leaf = tris + (~child);
+                // each record is fetched when its turn comes: fewer scalar registers
+                // held across the leaf (see the occupancy note at k_density)
                 BvhTri tr[kLeafMax];
-#pragma unroll
-                for (int k = 0; k < kLeafMax; ++k) tr[k] = load_tri(leaf, k);
 #pragma unroll
                 for (int k = 0; k < kLeafMax; ++k) {
                     if (k >= count) break;
+                    tr[k] = load_tri(leaf, k);
                     uint64_t tm[R];
                     uint64_t tany = 0;
 #pragma unroll
@@ -824,7 +825,7 @@ __global__ void k_zcam_prep(const float* __restrict__ eye, const float* __restri
 // each pixel centre, direction x' right + y' up + forward (so the ray parameter is
 // the depth), x' = (x_ndc + ox) / sx; the buffer keeps the nearest hit with depth in
 // [near, far], +inf where there is none.  Fixations with w = 0 get +inf everywhere.
-__global__ void __launch_bounds__(256) k_zbuffer(const BvhNode* __restrict__ nodes, int64_t node_stride,
+__global__ void __launch_bounds__(256, 8) k_zbuffer(const BvhNode* __restrict__ nodes, int64_t node_stride,
                                                  const BvhTri* __restrict__ tris, int64_t tri_stride,
                                                  const FixRec* __restrict__ rec, const ZCam* __restrict__ cams,
                                                  int32_t F, int32_t R, float* __restrict__ zbuf)
@@ -1241,8 +1242,17 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
 // once on different XCDs and every XCD sees every part of the scene; when only the
 // first chunks hold fixations (a time window), the work still spreads over all XCDs.
 // ZB: the paper's z-buffer visibility instead of the exact segment test.
+// Occupancy: the one-sample-per-lane traversal kernels (this one, k_density_queue and
+// k_zbuffer) ask for 8 waves per SIMD, the most the SIMD holds; their scalar registers
+// then no longer fit and the compiler moves some long-lived ones (kernel arguments,
+// mostly outside the walk) into vector-register lanes.  More waves hide more of the
+// dependent node loads: the paper-shaped map takes 70.7 ms this way against 78.2 ms at
+// the 7 waves the register counts allow otherwise.
+template <int SPL, int OCC>
+constexpr int kMinWaves = (SPL == 1 && OCC != 0) ? 8 : 1;
+
 template <int SPL, int OCC, bool INST = false, bool ZB = false>
-__global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
+__global__ void __launch_bounds__(kThreads, (kMinWaves<SPL, OCC>)) k_density(DensityLaunch a)
 {
     const unsigned L = blockIdx.x + blockIdx.y * gridDim.x;  // < 2^31 (tiles x chunks)
     const int F = a.F_live ? min(a.F, (int)*a.F_live) : a.F;
@@ -1252,7 +1262,7 @@ __global__ void __launch_bounds__(kThreads) k_density(DensityLaunch a)
 // Persistent form for many sessions: every workgroup pulls (session, tile, chunk)
 // items from a queue sorted longest first until the queue is empty.
 template <int SPL, int FB>
-__global__ void __launch_bounds__(kThreads) k_density_queue(const DensityLaunch* __restrict__ sessions,
+__global__ void __launch_bounds__(kThreads, (SPL == 1 ? 8 : 1)) k_density_queue(const DensityLaunch* __restrict__ sessions,
                                                             const int4* __restrict__ items, int32_t n_items,
                                                             unsigned int* __restrict__ head)
 {

@@ -1,8 +1,9 @@
-"""Register budgets of the density kernels, from the compiler's resource report of a
-device-only gfx950 build (no GPU needed).  Occupancy of the traversal kernels is what
-hides the latency of their dependent node loads: a change that raises their register
-count (it happened once to the persistent batch kernel, 70 -> 132 VGPRs, halving its
-speed) fails here rather than on the bench."""
+"""Register budgets and occupancy of the density kernels, from the compiler's resource
+report of a device-only gfx950 build (no GPU needed).  Occupancy of the traversal kernels
+is what hides the latency of their dependent node loads: a change that raises their
+register count (it happened once to the persistent batch kernel, 70 -> 132 VGPRs, halving
+its speed) or costs the one-sample-per-lane walks their 8 waves per SIMD (7 waves: the
+paper-shaped map 10 % slower) fails here rather than on the bench."""
 import os
 import re
 import subprocess
@@ -32,7 +33,7 @@ def usage(tmp_path_factory):
             cur = m.group(1)
             kernels[cur] = {}
             continue
-        m = re.search(r"remark: \s*([A-Za-z ]+?)(?: \[bytes/lane\])?: (\d+)", line)
+        m = re.search(r"remark: \s*([A-Za-z ]+?)(?: \[[^\]]*\])?: (\d+)", line)
         if cur and m:
             kernels[cur][m.group(1).strip()] = int(m.group(2))
     return kernels
@@ -44,14 +45,17 @@ def _find(usage, pattern):
     return hits
 
 
-@pytest.mark.parametrize("pattern,max_vgpr", [
-    (r"k_densityILi1ELi1ELb0ELb0E", 64),     # full occlusion, scene BVH (the benchmark's kernel)
-    (r"k_densityILi2ELi0ELb0ELb0E", 64),     # gate and exact value only
-    (r"k_densityILi1ELi1ELb1ELb0E", 72),     # one BVH per mesh (posed maps)
-    (r"k_density_queueILi1ELi(64|128|256)E", 80),
-    (r"k_zbuffer", 64),
+@pytest.mark.parametrize("pattern,max_vgpr,min_waves,max_scratch", [
+    (r"k_densityILi1ELi1ELb0ELb0E", 64, 8, 0),     # full occlusion, scene BVH (the benchmark's kernel)
+    (r"k_densityILi2ELi0ELb0ELb0E", 64, 8, 0),     # gate and exact value only
+    (r"k_densityILi1ELi1ELb1ELb0E", 64, 8, 0),     # one BVH per mesh (posed maps)
+    # the persistent batch kernel keeps one 8-byte value in scratch: stored at entry,
+    # read once per work item, outside the walk
+    (r"k_density_queueILi1ELi(64|128|256)E", 64, 8, 16),
+    (r"k_zbuffer", 64, 8, 0),
 ])
-def test_register_budget(usage, pattern, max_vgpr):
+def test_register_budget(usage, pattern, max_vgpr, min_waves, max_scratch):
     for ru in _find(usage, pattern):
         assert ru["VGPRs"] <= max_vgpr, ru
-        assert ru.get("VGPRs Spill", 0) == 0 and ru.get("ScratchSize", 0) == 0, ru
+        assert ru["Occupancy"] >= min_waves, ru
+        assert ru.get("ScratchSize", 0) <= max_scratch, ru
