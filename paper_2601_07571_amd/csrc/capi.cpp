@@ -219,11 +219,11 @@ void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F
     a.spl = spl;
     if (fix_per_chunk <= 0) {
         // The cost of a (tile, chunk) item varies a lot (how many of its fixations see
-        // the tile), so the grid holds many small items: at least ~128k of them and at
+        // the tile), so the grid holds many small items: at least ~512k of them and at
         // most 1024 fixations each, but chunks of no fewer than 128 fixations.
         const int64_t tiles = std::max<int64_t>(1, (n + 256 * spl - 1) / (256 * spl));
         const int64_t max_chunks = std::max<int64_t>(1, (F + 127) / 128);
-        const int64_t want = std::max<int64_t>((131072 + tiles - 1) / tiles, (F + 1023) / 1024);
+        const int64_t want = std::max<int64_t>((524288 + tiles - 1) / tiles, (F + 1023) / 1024);
         // the grid is tiles x chunks: chunks <= 65535 (grid y) and tiles x chunks < 2^31
         const int64_t cap = std::min<int64_t>(65535, std::max<int64_t>(1, INT32_MAX / tiles));
         const int64_t chunks = std::min<int64_t>(std::min(max_chunks, cap), std::max<int64_t>(1, want));
