@@ -177,6 +177,11 @@ gm_status accumulate_density(gm_scene* scene, const float* pos, const int32_t* t
  *   n_points points pos [n_points][3] and the fixations, g_out[i] (device float) = g
  *   (Sec. 3.2.1) if the pair is in the 4-sigma cone, else 0; no visibility.  A pair
  *   index out of range gives NaN.  Blocking (it owns a temporary buffer).
+ * gm_debug_sqrt_f64: y[i] = sqrt(x[i]) for n device doubles, by the FP64 square
+ *   root as the sampler's code evaluates it (the canonical triangle area of Sec. 3.1
+ *   and the square-root warp of the placement both take it); bit-exact sample
+ *   positions need it correctly rounded, which this lets a test check.  Queued on
+ *   `stream`; x and y may be the same buffer.
  * gm_debug_pair_visibility: vis_out[i] (device uint8) = 1 if the segment
  *   eye[pair_f[i]] -> pos[pair_s[i]] is unoccluded under the occlusion mode in
  *   `flags` (Sec. 3.2.2), 0 if occluded, 2 if an index is out of range.
@@ -185,6 +190,7 @@ gm_status accumulate_density(gm_scene* scene, const float* pos, const int32_t* t
 gm_status gm_debug_pair_values(const float* pos, int64_t n_points, const gm_fixations* fix,
                                double theta_deg, const int32_t* pair_s, const int32_t* pair_f,
                                int64_t m, float* g_out, void* stream);
+gm_status gm_debug_sqrt_f64(const double* x, double* y, int64_t n, void* stream);
 gm_status gm_debug_pair_visibility(gm_scene* scene, const float* pos, const int32_t* tri,
                                    const int32_t* mesh, int64_t n_points, const float* eye,
                                    int32_t n_eyes, const int32_t* pair_s, const int32_t* pair_f,

@@ -26,7 +26,7 @@ OCC = {"none": 0, "self": 1, "full": 2}
 SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy", "gm_scene_info",
            "gm_count_surface_samples", "build_surface_samples", "gm_count_lattice_samples",
            "build_lattice_samples", "accumulate_density",
-           "gm_debug_pair_values", "gm_debug_pair_visibility", "gm_profile_enable", "gm_profile_read",
+           "gm_debug_pair_values", "gm_debug_pair_visibility", "gm_debug_sqrt_f64", "gm_profile_enable", "gm_profile_read",
            "gm_density_stats", "gm_field_create", "gm_field_destroy", "gm_field_set_params",
            "gm_field_get_params", "gm_field_train", "gm_field_info", "gm_field_gradient", "gm_field_predict", "query_density",
            "gm_batch_create", "gm_batch_run", "gm_batch_info", "gm_batch_destroy",
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH):
     lib.build_lattice_samples.argtypes = [vp, dbl, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
     lib.accumulate_density.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(_Fix), dbl, u32, vp, vp, vp, vp]
     lib.gm_debug_pair_values.argtypes = [vp, i64, ctypes.POINTER(_Fix), dbl, vp, vp, i64, vp, vp]
+    lib.gm_debug_sqrt_f64.argtypes = [vp, vp, i64, vp]
     lib.gm_debug_pair_visibility.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, i64, u32, vp, vp]
     lib.gm_profile_enable.argtypes = [vp, i32]
     lib.gm_density_stats.argtypes = [vp, ctypes.POINTER(i64)]
@@ -486,6 +487,16 @@ def pair_values(pos, fix: Fixations, theta_deg, pair_s, pair_f):
     _check(_lib.gm_debug_pair_values(_ptr(pos), int(pos.shape[0]), ctypes.byref(fix._c), float(theta_deg),
                                      _ptr(ps), _ptr(pf), int(ps.shape[0]), _ptr(g), _stream()))
     return g
+
+
+def sqrt_f64(x):
+    """The device's FP64 square root as the sampler evaluates it (diagnostic of its rounding)."""
+    load_library()
+    torch = _torch()
+    x = _dev(x, torch.float64)
+    y = torch.empty_like(x)
+    _check(_lib.gm_debug_sqrt_f64(_ptr(x), _ptr(y), int(x.numel()), _stream()))
+    return y
 
 
 class Field:

@@ -485,6 +485,15 @@ gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri,
     return GM_OK;
 }
 
+gm_status gm_debug_sqrt_f64(const double* x, double* y, int64_t n, void* stream)
+{
+    gm::clear_error();
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or negative size");
+    launch_sqrt_f64(x, y, n, (hipStream_t)stream);
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
 gm_status gm_debug_pair_values(const float* pos, int64_t n_points, const gm_fixations* fix, double theta_deg,
                                const int32_t* pair_s, const int32_t* pair_f, int64_t m, float* g_out, void* stream)
 {

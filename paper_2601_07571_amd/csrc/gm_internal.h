@@ -79,6 +79,8 @@ void build_bvh(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_
 // ---------------------------------------------------------------------------
 
 // a1: areas and per-mesh max (max_bits: uint64 [M], zeroed by the caller).
+// y[i] = sqrt(x[i]) in FP64 with the sampler's code generation (a diagnostic of its rounding).
+void launch_sqrt_f64(const double* x, double* y, int64_t n, hipStream_t s);
 void launch_tri_area(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T, double* area,
                      unsigned long long* max_bits, hipStream_t s);
 // a1: per-mesh scale exponent S_m from T_m and the max area.

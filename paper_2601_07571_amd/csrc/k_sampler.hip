@@ -5,6 +5,8 @@
 // sample positions are reproducible bit for bit from the definition.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gm_internal.h"
 #include "gm_philox.h"
 
@@ -237,9 +239,22 @@ k_lattice_sample(const float* __restrict__ V, const int32_t* __restrict__ I, con
     }
 }
 
+// FP64 square root as the sampler evaluates it (same translation unit and flags): the
+// canonical area and the square-root warp both need it correctly rounded.
+__global__ void k_sqrt_f64(const double* __restrict__ x, double* __restrict__ y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        y[i] = sqrt(x[i]);
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
+
+void launch_sqrt_f64(const double* x, double* y, int64_t n, hipStream_t s)
+{
+    if (n > 0) k_sqrt_f64<<<(unsigned)std::min<int64_t>(grid_for(n), 8192), kBlock, 0, s>>>(x, y, n);
+}
 
 void launch_tri_area(const float* V, const int32_t* I, const int32_t* tri_mesh, int64_t T, double* area,
                      unsigned long long* max_bits, hipStream_t s)

@@ -70,3 +70,32 @@ def test_capacity_and_argument_errors(gm):
             scene.count_samples(bad)
     with pytest.raises(gm.GazemapError):
         gm.Scene([(w.meshes[0].V, w.meshes[0].I + 10_000)])
+
+
+def test_fp64_sqrt_is_correctly_rounded(gm):
+    """The canonical area and the square-root warp need the device's FP64 square root
+    correctly rounded for bit-exact positions.  1e8 inputs against the host's IEEE sqrt:
+    the warp's own inputs k * 2^-32 for random 32-bit k, positive doubles over the whole
+    exponent range (subnormals included), squares and their neighbours (where a faithful
+    but not correctly rounded root would show), and the special values."""
+    import torch
+    rng = np.random.default_rng(7)
+    per = 25_000_000
+    special = np.array([0.0, -0.0, 5e-324, 2.2250738585072014e-308, 1.0, 4.0, 2.0, 0.5, 1.7976931348623157e308,
+                        np.inf, 2.0 ** -1074 * 3, 1.0 - 2.0 ** -53], np.float64)
+    for part in range(4):
+        if part == 0:
+            x = rng.integers(0, 2 ** 32, per, dtype=np.uint64).astype(np.float64) * 2.0 ** -32
+        elif part == 1:
+            bits = rng.integers(1, 0x7FF0000000000000, per, dtype=np.uint64)
+            x = bits.view(np.float64)
+        elif part == 2:
+            r = rng.uniform(1.0, 2.0 ** 26, per)
+            sq = r * r
+            x = (sq.view(np.uint64) + rng.integers(-2, 3, per).astype(np.int64).view(np.uint64)).view(np.float64)
+        else:
+            x = np.concatenate([special, rng.uniform(0.0, 1e-3, per - len(special)) ** 2])
+        got = gm.sqrt_f64(torch.from_numpy(x)).cpu().numpy()
+        want = np.sqrt(x)
+        bad = got.view(np.uint64) != want.view(np.uint64)
+        assert not bad.any(), (part, int(bad.sum()), x[bad][:5], got[bad][:5], want[bad][:5])
