@@ -336,11 +336,9 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
             const int child = first ? nd.child0 : nd.child1;
             const int count = (first ? nd.count0 : nd.count1) & kCountMask;
             if (child < 0) {
-                // all records of the leaf are fetched together (the array is padded so
-                // that kLeafMax records from any leaf start are in bounds)
+                // each record is fetched when its turn comes (fewer scalar registers held
+                // across the leaf; see the occupancy note at k_density)
                 const BvhTri* leaf = tris + (~child);
-                // each record is fetched when its turn comes: fewer scalar registers
-                // held across the leaf (see the occupancy note at k_density)
                 BvhTri tr[kLeafMax];
 #pragma unroll
                 for (int k = 0; k < kLeafMax; ++k) {
