@@ -159,13 +159,15 @@ __device__ __forceinline__ void axis_order(float dx, float dy, float dz, int& kx
     }
 }
 
-// Segment eye -> point, sheared along the given axis order.
+// Segment eye -> point, sheared along the given axis order.  The box-test constants
+// (ix .. qz) measure the segment in units of its end bound, t' = t / tmax, so that
+// the slab test of box_hit_signed01 / box_hit01 can clamp to [0, 1].
 __device__ __forceinline__ Seg make_seg(float ex, float ey, float ez, float px, float py, float pz, int kx, int ky,
                                         int kz, float tmax)
 {
     Seg s;
     const float dx = px - ex, dy = py - ey, dz = pz - ez;
-    s.ix = safe_inv(dx); s.iy = safe_inv(dy); s.iz = safe_inv(dz);
+    s.ix = safe_inv(dx * tmax); s.iy = safe_inv(dy * tmax); s.iz = safe_inv(dz * tmax);
     s.qx = -ex * s.ix; s.qy = -ey * s.iy; s.qz = -ez * s.iz;
     s.kx = kx; s.ky = ky; s.kz = kz;
     const float dkz = pick(kz, dx, dy, dz);
@@ -196,6 +198,32 @@ __device__ __forceinline__ bool box_hit(const Seg& s, const float* lo, const flo
     const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
     const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
     return tn <= tf;
+}
+
+// The slab tests of a segment from make_seg, whose parameter runs over [0, 1] up to its
+// end bound: entry and exit clamped to [0, 1] (the clamp is an output modifier of the
+// three-input min/max, so each costs one instruction) and a hit when the entry lies
+// strictly below the exit.  That drops boxes behind the eye and beyond the bound as
+// the unclamped test does; the strict comparison drops only boxes the segment meets
+// in a single point, and the box padding keeps every triangle hit strictly inside.
+__device__ __forceinline__ bool box_hit_signed01(const Seg& s, const float* near, const float* far)
+{
+    const float nx = __builtin_fmaf(near[0], s.ix, s.qx), fx = __builtin_fmaf(far[0], s.ix, s.qx);
+    const float ny = __builtin_fmaf(near[1], s.iy, s.qy), fy = __builtin_fmaf(far[1], s.iy, s.qy);
+    const float nz = __builtin_fmaf(near[2], s.iz, s.qz), fz = __builtin_fmaf(far[2], s.iz, s.qz);
+    const float tn = __builtin_amdgcn_fmed3f(fmaxf(fmaxf(nx, ny), nz), 0.0f, 1.0f);
+    const float tf = __builtin_amdgcn_fmed3f(fminf(fminf(fx, fy), fz), 0.0f, 1.0f);
+    return tn < tf;
+}
+
+__device__ __forceinline__ bool box_hit01(const Seg& s, const float* lo, const float* hi)
+{
+    const float t0x = __builtin_fmaf(lo[0], s.ix, s.qx), t1x = __builtin_fmaf(hi[0], s.ix, s.qx);
+    const float t0y = __builtin_fmaf(lo[1], s.iy, s.qy), t1y = __builtin_fmaf(hi[1], s.iy, s.qy);
+    const float t0z = __builtin_fmaf(lo[2], s.iz, s.qz), t1z = __builtin_fmaf(hi[2], s.iz, s.qz);
+    const float tn = __builtin_amdgcn_fmed3f(fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z)), 0.0f, 1.0f);
+    const float tf = __builtin_amdgcn_fmed3f(fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)), 0.0f, 1.0f);
+    return tn < tf;
 }
 
 // Triangle vertices relative to the eye, in the axis order of the record copy the
@@ -291,7 +319,7 @@ struct TravCount {
 template <int R, bool UNI>
 __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, float e0,
                                 float e1, float e2, int oct, const Seg (&sg)[R],
-                                const int (&own_tri)[R], const int (&own_mesh)[R], int mode, float tmax,
+                                const int (&own_tri)[R], const int (&own_mesh)[R], int mode,
                                 const bool (&active)[R], bool (&occ)[R], TravCount& visits)
 {
     const int lane = lane_id();
@@ -316,11 +344,11 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (UNI) {
-                h0[r] = ballot(box_hit_signed(sg[r], nd.lo0, nd.hi0, tmax)) & live[r];
-                h1[r] = ballot(box_hit_signed(sg[r], nd.lo1, nd.hi1, tmax)) & live[r];
+                h0[r] = ballot(box_hit_signed01(sg[r], nd.lo0, nd.hi0)) & live[r];
+                h1[r] = ballot(box_hit_signed01(sg[r], nd.lo1, nd.hi1)) & live[r];
             } else {
-                h0[r] = ballot(box_hit(sg[r], nd.lo0, nd.hi0, tmax)) & live[r];
-                h1[r] = ballot(box_hit(sg[r], nd.lo1, nd.hi1, tmax)) & live[r];
+                h0[r] = ballot(box_hit01(sg[r], nd.lo0, nd.hi0)) & live[r];
+                h1[r] = ballot(box_hit01(sg[r], nd.lo1, nd.hi1)) & live[r];
             }
             any0 |= h0[r];
             any1 |= h1[r];
@@ -974,7 +1002,7 @@ __device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ no
         for (int k = 0; k < SPL; ++k) sg[k] = make_seg(ex, ey, ez, p[k].x, p[k].y, p[k].z, kx, ky, kz, tmax);
         const int oct = (nx_m != 0 ? 1 : 0) | (ny_m != 0 ? 2 : 0) | (nz_m != 0 ? 4 : 0);
         occluded_packet<SPL, true>(nodes + oct * node_stride, tris + kz * tri_stride, pick(kx, ex, ey, ez),
-                                   pick(ky, ex, ey, ez), pick(kz, ex, ey, ez), oct, sg, otri, omesh, mode, tmax, need,
+                                   pick(ky, ex, ey, ez), pick(kz, ex, ey, ez), oct, sg, otri, omesh, mode, need,
                                    occl, n_visits);
     } else {
 #pragma unroll
@@ -986,7 +1014,7 @@ __device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ no
         // child order from one lane's octant (the order affects speed, not results)
         const int lead = __builtin_ctzll(nx_m | px_m);
         const int oct = (int)((nx_m >> lead) & 1) | (int)(((ny_m >> lead) & 1) << 1) | (int)(((nz_m >> lead) & 1) << 2);
-        occluded_packet<SPL, false>(nodes, tris + 2 * tri_stride, ex, ey, ez, oct, sg, otri, omesh, mode, tmax, need,
+        occluded_packet<SPL, false>(nodes, tris + 2 * tri_stride, ex, ey, ez, oct, sg, otri, omesh, mode, need,
                                     occl, n_visits);
     }
 }
@@ -1365,7 +1393,7 @@ __global__ void __launch_bounds__(64) k_pair_visibility(const float* __restrict_
     const bool act[1] = {mode != 0 && lane == 0};
     bool occ[1] = {false};
     const int oct = (signbit(px - ex) ? 1 : 0) | (signbit(py - ey) ? 2 : 0) | (signbit(pz - ez) ? 4 : 0);
-    occluded_packet<1, false>(nodes, tris, ex, ey, ez, oct, sgs, ot, om, mode, tmax, act, occ, visits);
+    occluded_packet<1, false>(nodes, tris, ex, ey, ez, oct, sgs, ot, om, mode, act, occ, visits);
     if (lane == 0) vis[i] = occ[0] ? 0 : 1;
 }
 
