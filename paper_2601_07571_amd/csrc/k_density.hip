@@ -372,6 +372,9 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
                 for (int k = 0; k < kLeafMax; ++k) {
                     if (k >= count) break;
                     tr[k] = load_tri(leaf, k);
+                    // both parts of the record (vertices; id and mesh) arrive before the
+                    // skip test, one load latency rather than two in sequence
+                    asm volatile("" ::"s"(tr[k].v0[0]), "s"(tr[k].id));
                     uint64_t tm[R];
                     uint64_t tany = 0;
 #pragma unroll
