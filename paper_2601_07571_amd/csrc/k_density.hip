@@ -1066,9 +1066,9 @@ __device__ __forceinline__ float zb_value(float x, float y, float z, const FixRe
 template <int SPL, int OCC, int FB, bool INST = false, bool ZB = false>
 __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t tile, int chunk, int F)
 {
-    __shared__ float4 s_ra[FB];  // rx, ry, rz, c0
-    __shared__ float4 s_rb[FB];  // ax, ay, az, cc
-    __shared__ float s_rc[FB];   // -kappa
+    // per fixation of the block, 48 bytes: (rx, ry, rz, c0), (ax, ay, az, cc), (-kappa, -, -, -);
+    // one base address reaches all three with immediate offsets
+    __shared__ float4 s_co[3 * FB];
     __shared__ unsigned long long s_acc[kThreads * SPL];  // one entry per sample, owned by one lane
     __shared__ float s_rad;
     __shared__ uint32_t s_stats[kDensityStats];
@@ -1105,10 +1105,12 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
 
     const int shift = *a.fx_shift;
     const int f_begin = chunk * a.fix_per_chunk;
-    const int f_end = min(F, f_begin + a.fix_per_chunk);
+    // wave-uniform bounds in scalar registers (F may come from a vector load of the live
+    // count): the fixation loop then counts in scalar instructions
+    const int f_end = uniform(min(F, f_begin + a.fix_per_chunk));
 
     for (int fb = f_begin; fb < f_end; fb += FB) {
-        const int nb = min(FB, f_end - fb);
+        const int nb = uniform(min(FB, f_end - fb));
         __syncthreads();
         if (threadIdx.x < nb) {
             const FixRec fr = a.fix[fb + threadIdx.x];
@@ -1118,15 +1120,15 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
             const float c0 = -__builtin_fmaf(fr.rx, ex, __builtin_fmaf(fr.ry, ey, fr.rz * ez));
             float cc = -k * e2;
             if (e2 <= near2 && fr.w > 0.0f) cc = 3.0e38f;  // force s > 0 for every sample of the tile
-            s_ra[threadIdx.x] = make_float4(fr.rx, fr.ry, fr.rz, c0);
-            s_rb[threadIdx.x] = make_float4(2.0f * k * ex, 2.0f * k * ey, 2.0f * k * ez, cc);
-            s_rc[threadIdx.x] = -k;
+            s_co[3 * threadIdx.x] = make_float4(fr.rx, fr.ry, fr.rz, c0);
+            s_co[3 * threadIdx.x + 1] = make_float4(2.0f * k * ex, 2.0f * k * ey, 2.0f * k * ez, cc);
+            s_co[3 * threadIdx.x + 2].x = -k;
         }
         __syncthreads();
         for (int j = 0; j < nb; ++j) {
-            const float4 ra = s_ra[j];
-            const float4 rb = s_rb[j];
-            const float nk = s_rc[j];
+            const float4 ra = s_co[3 * j];
+            const float4 rb = s_co[3 * j + 1];
+            const float nk = s_co[3 * j + 2].x;
             unsigned cand = 0;
 #pragma unroll
             for (int k = 0; k < SPL; ++k) {
