@@ -262,3 +262,55 @@ def test_counters(gm):
     c0 = scene.density_stats()
     assert c0["in_cone"] == c["in_cone"] and c0["visible"] == c0["in_cone"]
     assert c0["traversals"] == c0["node_visits"] == c0["triangle_tests"] == 0
+
+
+def _grid_occluder(n=8, h=0.125, z=1.0):
+    """An n x n grid of quads at height z (vertices on multiples of h, exact in FP32), each
+    quad split along alternating diagonals."""
+    ks = np.arange(-n // 2, n // 2 + 1)
+    V = np.array([[i * h, j * h, z] for j in ks for i in ks], np.float32)
+    m = n + 1
+    I = []
+    for j in range(n):
+        for i in range(n):
+            a, b, c, d = j * m + i, j * m + i + 1, (j + 1) * m + i + 1, (j + 1) * m + i
+            I += [[a, b, c], [a, c, d]] if (i + j) % 2 == 0 else [[a, b, d], [b, c, d]]
+    return V, np.array(I, np.int32)
+
+
+@pytest.mark.parametrize("eye", [(-0.875, -0.875, 0.0), (0.0625, 0.0625, 0.0)])
+def test_watertight_through_vertices_and_edges(gm, eye):
+    """Segments that pass exactly through a grid occluder's vertices and edge midpoints
+    (sample = 2 v - e, so the segment meets v at tau = 1/2 in exact arithmetic) must be
+    occluded: the watertight test leaves no gap between triangles sharing a vertex or an
+    edge.  The first eye puts every segment in one direction octant (the shared-axis
+    walk), the second mixes signs (per-lane axis order).  Points beside the occluder's
+    shadow stay visible and match the oracle."""
+    import torch
+    e = np.array(eye, np.float64)
+    h = 0.125
+    wall = (np.array([[-3, -3, 2], [4, -3, 2], [4, 4, 2], [-3, 4, 2]], np.float32), np.array([[0, 1, 2], [0, 2, 3]], np.int32))
+    meshes = [wall, _grid_occluder(h=h)]
+    through = np.array([2 * np.array([(i + di) * h, (j + dj) * h, 1.0]) - e
+                        for j in range(-3, 4) for i in range(-3, 4)
+                        for di, dj in ((0, 0), (0.5, 0), (0, 0.5), (0.5, 0.5))], np.float32)
+    assert np.array_equal(((through.astype(np.float64) + e) / 2)[:, 2], np.ones(len(through)))
+    ctrl = (np.array([[-0.5, 0.875, 2], [0.875, -0.5, 2], [-0.375, -0.375, 2]], np.float32) if eye[0] < 0 else
+            np.array([[1.1, 0.0, 2], [0.0, 1.1, 2], [-1.2, 0.0, 2]], np.float32))
+    pos = np.concatenate([through, ctrl])
+    tri = np.where(pos[:, 0] >= pos[:, 1], 0, 1).astype(np.int32)
+    mesh = np.zeros(len(pos), np.int32)
+    gaze = (-e + np.array([0, 0, 1.0]))[None].astype(np.float32)
+    eye32 = e[None].astype(np.float32)
+    scene = gm.Scene(meshes)
+    fix = gm.Fixations(eye32, gaze, np.ones(1, np.float32))
+    got = scene.accumulate(pos, fix, 10.0, occlusion="full", tri=tri, mesh=mesh).density.cpu().numpy()
+    torch.cuda.synchronize()
+    ref = oracle.density(oracle.Scene(meshes), pos, tri, mesh, eye32, gaze, np.ones(1, np.float32), 10.0,
+                         mode=oracle.OCC_FULL)
+    nt = len(through)
+    assert np.all(ref.stats[:, 0] == 1)                  # every pair in the cone
+    assert np.all(ref.rho[:nt] == 0) and np.all(got[:nt] == 0), np.nonzero(got[:nt])[0]
+    assert np.all(ref.rho[nt:] > 0)
+    ok, _ = _parity(got[nt:], oracle.OracleDensity(ref.rho[nt:], ref.budget[nt:], ref.stats[nt:]))
+    assert ok.all()
