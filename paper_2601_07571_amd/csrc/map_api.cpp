@@ -22,6 +22,11 @@ namespace {
 // invalid, over budget
 constexpr int kMapCounters = 5;
 constexpr double kBudgetUnit = 1024.0;  // units per second
+// Blocks of a plain map are gathered: their selected fixation records are appended to
+// one buffer, and one density launch takes them all (at the next read, or when this
+// many fixations are pending).  A launch per block left the GPU idle in each launch's
+// tail; the sum is the same bit for bit (fixed-point accumulation).
+constexpr int64_t kPendingMax = 65536;
 
 }  // namespace
 
@@ -35,7 +40,9 @@ struct gm_map {
     int32_t shift = 0;
     unsigned long long budget_units = 0;
     DensityWork w;     // sorted points, accumulators, records of the last block
-    DevBuf live;       // records of the block being added
+    DevBuf live;       // records taken so far (pending blocks) / of the block being added
+    DevBuf pending;    // plain maps: records of the blocks not yet accumulated [kPendingMax]
+    int64_t pending_hi = 0;  // upper bound of the pending records (sum of the blocks' sizes)
     DevBuf counters;   // [kMapCounters] uint64
     // posed maps: points grouped by mesh, mesh m at sorted entries [moff[m], moff[m + 1]);
     // per block, records [M][stride] and pose pairs [M][stride][24]
@@ -119,9 +126,29 @@ gm_status check_map(const gm_map* m)
     return GM_OK;
 }
 
+// one density launch over the pending records of a plain map
+gm_status map_flush(gm_map* m, hipStream_t s)
+{
+    if (m->pending_hi == 0) return GM_OK;
+    if (m->n > 0) {
+        DensityLaunch a;
+        density_args(m->scene, m->w, m->n, (int32_t)m->pending_hi, m->sigma, m->mode, m->spl, 0, a);
+        a.fix = m->pending.as<FixRec>();
+        a.F_live = m->live.as<unsigned int>();
+        zero(m->w.stats.p, 8 * kDensityStats, s);
+        launch_density(a, s);
+    }
+    zero(m->live.p, 4, s);
+    m->pending_hi = 0;
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
+
 // accumulators, maximum and counters back to zero; the budget total set again
 gm_status map_clear(gm_map* m, hipStream_t s)
 {
+    zero(m->live.p, 4, s);  // pending blocks are dropped with the rest
+    m->pending_hi = 0;
     if (m->n > 0) zero(m->w.acc.p, 8 * (size_t)m->n, s);
     zero(m->counters.p, 8 * kMapCounters, s);
     const unsigned long long b = m->budget_units;  // counters[1], as two little-endian words
@@ -245,18 +272,34 @@ gm_status gm_map_add(gm_map* m, const gm_fixations* fix, const double* time, dou
     hipStream_t s = (hipStream_t)stream;
     const int32_t F = fix->n;
     if (F == 0) return GM_OK;
-    GM_HIP(m->w.fix.ensure(sizeof(FixRec) * (size_t)F));
     unsigned long long* c = m->counters.as<unsigned long long>();
-    zero(m->live.p, 4, s);
-    launch_fix_select(fix->eye, fix->gaze, fix->duration, time, F, t_begin, t_end, m->sigma, kGateWiden,
-                      m->w.fix.as<FixRec>(), m->live.as<unsigned int>(), c, c + 2, s);
-    if (m->n > 0) {
-        DensityLaunch a;
-        density_args(m->scene, m->w, m->n, F, m->sigma, m->mode, m->spl, 0, a);
-        a.F_live = m->live.as<unsigned int>();
-        zero(m->w.stats.p, 8 * kDensityStats, s);
-        launch_density(a, s);
+    if (F > kPendingMax) {
+        // a large block: the pending ones first, then this one in a launch of its own
+        st = map_flush(m, s);
+        if (st != GM_OK) return st;
+        GM_HIP(m->w.fix.ensure(sizeof(FixRec) * (size_t)F));
+        launch_fix_select(fix->eye, fix->gaze, fix->duration, time, F, t_begin, t_end, m->sigma, kGateWiden,
+                          m->w.fix.as<FixRec>(), m->live.as<unsigned int>(), c, c + 2, s);
+        if (m->n > 0) {
+            DensityLaunch a;
+            density_args(m->scene, m->w, m->n, F, m->sigma, m->mode, m->spl, 0, a);
+            a.F_live = m->live.as<unsigned int>();
+            zero(m->w.stats.p, 8 * kDensityStats, s);
+            launch_density(a, s);
+        }
+        zero(m->live.p, 4, s);
+        GM_HIP(hipGetLastError());
+        return GM_OK;
     }
+    if (m->pending_hi + F > kPendingMax) {
+        st = map_flush(m, s);
+        if (st != GM_OK) return st;
+    }
+    // allocated once (nothing pending can be lost by a reallocation)
+    GM_HIP(m->pending.ensure(sizeof(FixRec) * (size_t)kPendingMax));
+    launch_fix_select(fix->eye, fix->gaze, fix->duration, time, F, t_begin, t_end, m->sigma, kGateWiden,
+                      m->pending.as<FixRec>(), m->live.as<unsigned int>(), c, c + 2, s);
+    m->pending_hi += F;
     GM_HIP(hipGetLastError());
     return GM_OK;
 }
@@ -314,6 +357,8 @@ gm_status gm_map_read(gm_map* m, float* density, float* density_norm, float* max
     gm_status st = check_map(m);
     if (st != GM_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    st = map_flush(m, s);
+    if (st != GM_OK) return st;
     zero(m->w.max_acc.p, 8, s);
     return density_finalize(m->w, m->n, density, density_norm, max_out, s);
 }
