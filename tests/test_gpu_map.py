@@ -186,3 +186,48 @@ def test_paper_shaped_blocks_match_the_plain_map(gm):
     assert (d > 0).sum() == (p > 0).sum()
     assert np.all(np.abs(d - p) <= 1e-6 * p + 1e-8)
     assert m.info()["added"] == F
+
+
+def test_gathered_blocks_overflow_and_large_blocks(gm, tiny):
+    """Blocks wait in a buffer of 65,536 fixation records and run in one launch at the
+    next read; a block that would overflow the buffer first runs what is pending, a block
+    larger than the buffer runs alone.  Every split of 140,000 fixations gives the bits of
+    one add of all of them, with the same counts; a reset drops pending blocks."""
+    import torch
+    w, meshes, scene, s, ref_s = tiny
+    rng = np.random.default_rng(11)
+    F = 140_000
+    k = rng.integers(0, len(w.fix.eye), F)
+    eye = (w.fix.eye[k] + rng.normal(0, 0.05, (F, 3))).astype(np.float32)
+    gaze = (w.fix.gaze[k] + rng.normal(0, 0.05, (F, 3))).astype(np.float32)
+    dur = rng.uniform(0.1, 0.5, F).astype(np.float32)
+    fix = gm.Fixations(eye, gaze, dur)
+
+    def run(sizes):
+        m = gm.DensityMap(scene, s.pos, w.theta_deg, occlusion="self", tri=s.tri, mesh=s.mesh,
+                          max_total_duration=1e5)
+        lo = 0
+        for n in sizes:
+            m.add(fix.subset(lo, lo + n))
+            lo += n
+        assert lo == F
+        return _bits(m.read()), m.info()
+
+    one, info = run([F])                                   # larger than the buffer: alone
+    assert info["added"] == F
+    for sizes in ([30_000, 30_000, 30_000, 50_000],        # overflow flushes twice
+                  [10_000, 70_000, 60_000],                # pending, then a large block, then pending
+                  [65_536, 1, 74_463]):                    # exactly full, then overflow by one
+        got, inf = run(sizes)
+        assert np.array_equal(got, one), sizes
+        assert inf == info, sizes
+    # pending blocks are dropped by a reset; the map then holds only what follows
+    m = gm.DensityMap(scene, s.pos, w.theta_deg, occlusion="self", tri=s.tri, mesh=s.mesh, max_total_duration=1e5)
+    m.add(fix.subset(0, 40_000))
+    m.reset()
+    m.add(fix.subset(40_000, 45_000))
+    a = _bits(m.read())
+    m2 = gm.DensityMap(scene, s.pos, w.theta_deg, occlusion="self", tri=s.tri, mesh=s.mesh, max_total_duration=1e5)
+    b = _bits(m2.add(fix.subset(40_000, 45_000)).read())
+    torch.cuda.synchronize()
+    assert np.array_equal(a, b) and a.any()
