@@ -379,8 +379,13 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
                     uint64_t tany = 0;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const uint64_t skip = ballot(tr[k].id == own_tri[r]) |
-                                              (ballot(tr[k].mesh != own_mesh[r]) & self_only);
+                        uint64_t skip = ballot(tr[k].id == own_tri[r]);
+                        if (self_only != 0) {
+                            // a real (uniform) branch: selected with a mask, the compare
+                            // would run in full mode too
+                            asm volatile("" ::: "memory");
+                            skip |= ballot(tr[k].mesh != own_mesh[r]);
+                        }
                         tm[r] = (first ? h0[r] : h1[r]) & ~hit[r] & ~skip;
                         tany |= tm[r];
                     }
