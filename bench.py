@@ -28,6 +28,8 @@ NODE_BYTES, TRI_BYTES = 64, 48 # BVH node and triangle record sizes
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_density_traffic_paper_shaped.md")
 COPY_PROBE_BYTES = 256 << 20   # the calibration copy of --traffic-probe (read and written once each)
 GATE_FLOP_PER_PAIR = 16        # 8 FMA per (sample, fixation) pair in the cone gate
+FIELD_FLOP_PER_POINT = 2 * (96 * 64 + 3 * 64 * 64 + 64)   # the field's four layer products and output
+PEAK_BF16_MFMA = 2.5e15        # MI355X dense BF16 matrix peak, FLOP/s
 K_PAPER_SHAPED = 204240.0      # samples/m^2 giving ~2,000,000 samples on the paper-shaped scene
 
 
@@ -44,6 +46,8 @@ def main():
     ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-map and time-window timing")
     ap.add_argument("--no-posed", action="store_true", help="skip the moving-objects timing")
     ap.add_argument("--no-zbuffer", action="store_true", help="skip the paper's z-buffer approximation")
+    ap.add_argument("--no-scale-up", action="store_true",
+                    help="skip the scale-up workload (5M triangles, 20M samples, 50,000 fixations)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one plain copy of known size, then one full-occlusion step, and exit (for HBM counters)")
     args = ap.parse_args()
@@ -154,10 +158,24 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(),
                      "kernel": "k_density (gate + exact value + visibility)", "kernel_ms": dens_ms,
-                     "flop_per_pair": GATE_FLOP_PER_PAIR},
+                     "flop_per_pair": GATE_FLOP_PER_PAIR,
+                     # the kernel's time is the BVH traversal of the in-cone segments (instruction
+                     # issue of divergent packet tests), which the FLOP count above does not price:
+                     # the two parts separately
+                     "limiter": "BVH traversal of the in-cone segments (VALU issue of divergent packet tests)",
+                     "parts": {"gate": {"kernel_ms": gate_ms,
+                                        "frac_fp32_peak": GATE_FLOP_PER_PAIR * pairs / (gate_ms * 1e-3) / PEAK_FP32_VALU},
+                               "visibility": {"ms": dens_ms - gate_ms,
+                                              "share_of_kernel": (dens_ms - gate_ms) / dens_ms,
+                                              "rays_per_s": counters["in_cone"] / ((dens_ms - gate_ms) * 1e-3),
+                                              "traversal_frac_hbm_peak":
+                                                  (NODE_BYTES * counters["node_visits"] +
+                                                   TRI_BYTES * counters["triangle_tests"]) /
+                                                  ((dens_ms - gate_ms) * 1e-3) / PEAK_HBM}}},
         "gate_only": {"kernel_ms": gate_ms, "pairs_per_s": pairs / (gate_ms * 1e-3),
                       "frac_fp32_peak": GATE_FLOP_PER_PAIR * pairs / (gate_ms * 1e-3) / PEAK_FP32_VALU},
         "visibility": {"in_cone_pairs": counters["in_cone"], "visible_pairs": counters["visible"],
+                       "backface_rule_pairs": counters["backface"],
                        "rays_per_s": counters["in_cone"] / (dens_ms * 1e-3),
                        "packet_traversals": counters["traversals"], "bvh_node_visits": counters["node_visits"],
                        "triangle_tests": counters["triangle_tests"],
@@ -172,7 +190,19 @@ def main():
                           "workload": "the paper's 800k-triangle scene, 2M samples, 6,000 fixations"},
     }
 
+    # a1 + a2 (areas, weights, their scan) do not depend on k: a scene computes them once,
+    # at its first sampling call, so the step above runs only the counts and the sampler;
+    # their one-time cost on a fresh scene object
+    sc_w = gm.Scene(meshes)
+    sc_w.profile(True)
+    sc_w.count_samples(k)
+    torch.cuda.synchronize()
+    out["stage_ms"]["sample_weights_once_per_scene"] = sc_w.profile_read("sample")[0]
+    sc_w.close()
+
     out["lattice"] = bench_lattice(gm, torch, args, scene, k)
+    if not args.no_scale_up:
+        out["scale_up"] = bench_scale_up(gm, workloads, torch, args)
     if not args.no_incremental:
         out["incremental"] = bench_incremental(gm, workloads, torch, np, args, scene, samples, fix, w, ms_step)
     if not args.no_posed:
@@ -204,6 +234,15 @@ def main():
         out["cpu_baseline"] = {"value": n_s * float(F) / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
                                "sample": f"{n_s} random samples of {N} x all {F} fixations, full occlusion, "
                                          f"FP64, {dt:.1f} s wall"}
+        # the same oracle on one thread, on a smaller sample (~a third of the time)
+        n1 = max(8, int(n_s * (args.cpu_seconds / 3.0) / (dt * threads)))
+        pick = rng.choice(N, n1, replace=False)
+        c0 = time.perf_counter()
+        oracle.density(sc, pos[pick], tri[pick], mesh[pick], w.fix.eye, w.fix.gaze, w.fix.dur, w.theta_deg,
+                       mode=oracle.OCC_FULL, nthreads=1)
+        dt1 = time.perf_counter() - c0
+        out["cpu_baseline"]["one_thread"] = {"value": n1 * float(F) / dt1, "unit": "pairs/s", "cores": 1,
+                                             "sample": f"{n1} random samples x all {F} fixations, {dt1:.1f} s wall"}
         del d
     print(json.dumps(out))
 
@@ -265,6 +304,40 @@ def bench_lattice(gm, torch, args, scene, k):
     written = n * (4 + 4 + 8 + 12)
     return {"points": n, "call_ms": call_ms, "kernels_ms": kern_ms,
             "points_per_s": n / (kern_ms * 1e-3), "output_GBps": written / (kern_ms * 1e-3) / 1e9}
+
+
+def bench_scale_up(gm, workloads, torch, args):
+    """The scale-up workload (25 displaced geodesic spheres of 200k triangles on a 5 x 5 grid,
+    5M triangles; 50,000 fixations from 10 head walks; theta 1 degree; full occlusion): the
+    map at 20M samples (pair throughput, and the in-cone segments per second of the density
+    kernel as BVH rays/s), and the literal 10,000 samples/m^2 of the same scene."""
+    w = workloads.scale_up_scene()
+    scene = gm.Scene([(m.V, m.I) for m in w.meshes])
+    fix = gm.Fixations(w.fix.eye, w.fix.gaze, w.fix.dur)
+    res = {"triangles": w.n_triangles, "fixations": fix.n}
+    for name, k in (("n20M", w.k), ("k10000", 10000.0)):
+        s = scene.build_samples(k, w.seed)
+        n = int(s.pos.shape[0])
+        dens = gm.Density(torch.empty(n, device="cuda"), torch.empty(n, device="cuda"), torch.empty(1, device="cuda"))
+
+        def step():
+            scene.build_samples(k, w.seed, out=s)
+            scene.accumulate(s.pos, fix, w.theta_deg, occlusion="full", tri=s.tri, mesh=s.mesh, out=dens)
+        step()
+        torch.cuda.synchronize()
+        reps = 2
+        scene.profile(True)
+        ms = _time(step, torch, reps)
+        d_ms = scene.profile_read("density")[0] / reps
+        scene.profile(False)
+        st = scene.density_stats()
+        res[name] = {"samples": n, "samples_per_m2": k, "map_ms": ms, "pairs_per_s": n * float(fix.n) / (ms * 1e-3),
+                     "density_kernel_ms": d_ms, "in_cone_pairs": st["in_cone"], "visible_pairs": st["visible"],
+                     "backface_rule_pairs": st["backface"],
+                     "rays_per_s": st["in_cone"] / (d_ms * 1e-3)}
+        del s, dens
+    scene.close()
+    return res
 
 
 def bench_incremental(gm, workloads, torch, np, args, scene, samples, fix, w, plain_ms):
@@ -434,7 +507,8 @@ def bench_field(gm, workloads, torch, np, args, scene, samples, fix, dens, w, k)
                            "gate_open": [bool(x) for x in info["gate"]], "train_steps": info["steps"],
                            "train_s": train_s, "field_ms_per_frame": field_ms, "plain_ms_per_frame": plain_ms,
                            "query_density_ms_per_frame": query_ms,
-                           "fallback_fraction": float(used.float().mean().cpu())}
+                           "fallback_fraction": float(used.float().mean().cpu()),
+                           "bf16_mfma_frac": FIELD_FLOP_PER_POINT * int(q.shape[0]) / (field_ms * 1e-3) / PEAK_BF16_MFMA}
     # the tiny scene's geometry and fixations at ~2M samples
     t = workloads.tiny_icosphere_scene()
     sc1 = gm.Scene([(m.V, m.I) for m in t.meshes])
@@ -450,7 +524,9 @@ def bench_field(gm, workloads, torch, np, args, scene, samples, fix, dens, w, k)
     pms = _time(lambda: sc1.accumulate(s1.pos, f1, t.theta_deg, occlusion="self", tri=s1.tri, mesh=s1.mesh,
                                        out=tmp1), torch, args.steps)
     res["tiny_scene_2M"] = {"points": int(s1.pos.shape[0]), "rel_l2": float(i1["rel_l2"][0]),
-                            "gate_open": bool(i1["gate"][0]), "field_ms_per_frame": fms, "plain_ms_per_frame": pms}
+                            "gate_open": bool(i1["gate"][0]), "field_ms_per_frame": fms, "plain_ms_per_frame": pms,
+                            "bf16_mfma_frac": FIELD_FLOP_PER_POINT * int(s1.pos.shape[0]) / (fms * 1e-3) /
+                            PEAK_BF16_MFMA}
     res["network"] = ("one network per mesh: 96 Fourier features (16 bands to 32 cycles per mesh-box edge) -> "
                       "4 x 64 ReLU -> softplus, bf16 MFMA")
     return res

@@ -82,11 +82,43 @@ gm_status gm_scene_info(const gm_scene* scene, int64_t* n_triangles, int32_t* n_
                         int64_t* n_bvh_nodes, int32_t* bvh_depth, float* bbox);
 
 /*
+ * gm_scene_mesh_closed -- host uint8 closed [n_meshes]: 1 for the meshes the visibility
+ * test treats as bounding a solid (gm_mesh_closed at creation, unless cleared).  For such
+ * a mesh a point seen from behind (the eye on the inner side of its triangle's plane by
+ * a cosine of at least 1e-3), from an eye outside the mesh's bounding box, is occluded by
+ * the mesh itself (Sec. 3.2.2's visibility: the segment must enter the solid before it
+ * reaches the point); accumulate_density then skips the BVH walk for the pair when no
+ * triangle of the mesh other than the point's own comes within 1e-4 of the segment's
+ * length of the point (so the entry lies before the tolerance), and walks otherwise
+ * (also for segments longer than twice the scene's diagonal plus 4 m).
+ * gm_scene_set_mesh_closed -- clear (closed = 0) or restore (1; only for a mesh that
+ * passed gm_mesh_closed) the flag of one mesh, e.g. for a closed mesh that intersects
+ * itself with inverted parts.  Blocking (synchronises the device).
+ */
+gm_status gm_scene_mesh_closed(const gm_scene* scene, uint8_t* closed);
+gm_status gm_scene_set_mesh_closed(gm_scene* scene, int32_t mesh, int32_t closed);
+
+/*
+ * gm_mesh_closed -- whether a mesh (host arrays, as gm_mesh) bounds a solid: after
+ * merging vertices at identical positions, every directed edge of its triangles occurs
+ * once and its reverse once (closed, edge-manifold, consistently wound), no triangle
+ * repeats a vertex, and its signed volume is positive (normals (v1 - v0) x (v2 - v0)
+ * point outwards).  Self-intersection is not checked.  Returns 1 or 0, -1 for invalid
+ * arguments.  Host only (no device).  gm_scene_create applies it to every mesh; the
+ * visibility test uses it for the back-face rule (a sample seen from behind on a
+ * closed mesh, from an eye outside the mesh's box, is occluded by that mesh: Sec. 3.2.2).
+ */
+int32_t gm_mesh_closed(const float* vertices, int32_t n_vertices, const int32_t* indices, int32_t n_triangles);
+
+/*
  * gm_count_surface_samples -- per-mesh sample counts for `samples_per_m2` (Sec. 3.1.2:
  * the count follows the surface area): n_m = round(k * area_m), where area_m is
  * the mesh area held as fixed-point triangle weights (floor(A_i * 2^S_m),
  * S_m = 52 - exponent(T_m * max_i A_i)).  n_per_mesh: host int64 [n_meshes].
- * Blocking (one small device-to-host copy).  samples_per_m2 must be finite and > 0.
+ * The weights do not depend on the density: the first sampling call on a scene
+ * computes them on the device and reads the per-mesh totals back (blocking, once);
+ * afterwards the counts are evaluated on the host and this call does no device work.
+ * samples_per_m2 must be finite and > 0.
  */
 gm_status gm_count_surface_samples(gm_scene* scene, double samples_per_m2, int64_t* n_per_mesh,
                                    void* stream);
@@ -105,7 +137,11 @@ gm_status gm_count_surface_samples(gm_scene* scene, double samples_per_m2, int64
  * be NULL): tri [N] scene-global triangle index, mesh [N], bary [N][2] = (b1, b2),
  * pos [N][3].  N = sum of gm_count_surface_samples; N > capacity gives
  * GM_ERR_CAPACITY with *n_out = N and nothing written.  *n_out (host) = N.
- * Blocking (it reads back the counts); the sampling kernels are queued on `stream`.
+ * Queued on `stream` (the per-mesh counts come from the scene's weight totals kept on
+ * the host); only the first sampling call on a scene blocks, once, while a1 and a2
+ * run and their totals are read back.  The scene's count buffers are rewritten by
+ * each call: calls on one scene queued on different streams race unless the caller
+ * synchronises them.
  */
 gm_status build_surface_samples(gm_scene* scene, double samples_per_m2, uint64_t seed,
                                 int32_t* tri, int32_t* mesh, float* bary, float* pos,
@@ -185,14 +221,17 @@ gm_status accumulate_density(gm_scene* scene, const float* pos, const int32_t* t
  * gm_debug_pair_visibility: vis_out[i] (device uint8) = 1 if the segment
  *   eye[pair_f[i]] -> pos[pair_s[i]] is unoccluded under the occlusion mode in
  *   `flags` (Sec. 3.2.2), 0 if occluded, 2 if an index is out of range.
- *   tri / mesh as in accumulate_density.
+ *   tri / mesh as in accumulate_density.  gaze [n_eyes][3] (device, may be NULL):
+ *   with it, each pair is tested with the arithmetic accumulate_density gives that
+ *   pair (the segment's shear axis follows the fixation's gaze), so the answers are
+ *   the density kernel's own; without it, the segment's own dominant axis.
  */
 gm_status gm_debug_pair_values(const float* pos, int64_t n_points, const gm_fixations* fix,
                                double theta_deg, const int32_t* pair_s, const int32_t* pair_f,
                                int64_t m, float* g_out, void* stream);
 gm_status gm_debug_sqrt_f64(const double* x, double* y, int64_t n, void* stream);
 gm_status gm_debug_pair_visibility(gm_scene* scene, const float* pos, const int32_t* tri,
-                                   const int32_t* mesh, int64_t n_points, const float* eye,
+                                   const int32_t* mesh, int64_t n_points, const float* eye, const float* gaze,
                                    int32_t n_eyes, const int32_t* pair_s, const int32_t* pair_f,
                                    int64_t m, uint32_t flags, uint8_t* vis_out, void* stream);
 
@@ -409,8 +448,9 @@ gm_status gm_field_get_params(gm_field* field, float* params);
  * (device, the normalised density in [0, 1]).  For every mesh, runs `steps` Adam
  * steps of mean squared error of its network on its points of the training split,
  * then evaluates the mesh's relative L2 error sqrt(sum (y - t)^2 / sum t^2) on its
- * held-out points and opens the gate of the meshes at or below max_rel_l2.
- * Blocking.
+ * held-out points and opens the gate of the meshes at or below max_rel_l2.  The
+ * gradients of a step are summed in a fixed order (no floating-point atomics), so
+ * training gives the same weights, errors and gates on every run.  Blocking.
  */
 gm_status gm_field_train(gm_field* field, const float* pos, const int32_t* mesh, const float* target,
                          int64_t n, const gm_train_params* params, void* stream);
@@ -423,11 +463,23 @@ gm_status gm_field_info(gm_field* field, float* rel_l2, uint8_t* gate, double* l
  * `stream`. */
 gm_status gm_field_predict(gm_field* field, const float* pos, const int32_t* mesh, int64_t q, float* out,
                            void* stream);
-/* One forward and backward pass of network `net` over all n points (no update): the
- * mean-squared-error gradient (host float [GM_FIELD_PARAMS]) and loss.  Blocking.  For
- * gradient checks. */
+/* One forward and backward pass of network `net` over all n points, n in (0, 65536] (no
+ * update): the mean-squared-error gradient (host float [GM_FIELD_PARAMS]) and loss, summed
+ * in a fixed order (the same bits on every call).  Blocking.  For gradient checks. */
 gm_status gm_field_gradient(gm_field* field, int32_t net, const float* pos, const float* target, int64_t n,
                             float* grad, double* loss);
+
+/*
+ * gm_debug_adam_step -- one Adam update (Kingma and Ba 2015), the training loop's own
+ * kernel, on count parameters (device float32, updated in place):
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   params -= lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps),
+ * then grad is zeroed (as after each training step).  step counts from 1 and is
+ * the update's number, which sets the bias corrections.  For checks of the
+ * optimiser over several steps.  Queued on `stream`.
+ */
+gm_status gm_debug_adam_step(float* params, float* m, float* v, float* grad, int64_t count, int32_t step, float lr,
+                             float beta1, float beta2, float eps, void* stream);
 
 /*
  * query_density -- the normalised density at q query points (device pos [q][3];
@@ -500,7 +552,8 @@ gm_status gm_density_stats(gm_scene* scene, int64_t* out);
 
 /* gm_density_counters: the same counters and more, host int64 out[n_out] = {the four
  * above, triangle tests (one per triangle tested by a packet for at least one of its
- * segments)}; entries past the known counters are set to 0.  Blocking. */
+ * segments), in-cone pairs settled by the back-face rule (see gm_scene_mesh_closed)};
+ * entries past the known counters are set to 0.  Blocking. */
 gm_status gm_density_counters(gm_scene* scene, int64_t* out, int32_t n_out);
 
 /*

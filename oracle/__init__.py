@@ -12,7 +12,8 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
   philox4x32_10 / philox_py ... pinned (published known answers, two codes)
   triangle_areas .............. pinned (Heron in Kahan's ordering, closed forms)
   mesh_weights / sample_count . pinned (exact integer brute force, k*area)
-  sample_scene ................ pinned (chi-square, KS, brute force, invariants)
+  sample_scene / sample_at .... pinned (chi-square, KS, brute force, invariants;
+                                 sample_at equals sample_scene's entries)
   lattice_* ................... pinned (loop enumeration of Eq. (2), the lattice
                                  set, Eq. (1) and (4) closed forms and bounds)
   pair_value / density ........ pinned (plane closed form, 4-sigma mass,
@@ -32,7 +33,12 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
                                  z-buffer depths of planes and spheres in closed
                                  form, an occluder's shadow, eps widening;
                                  a fine z-buffer agrees with the exact test
-                                 away from silhouettes)
+                                 away from silhouettes).  A crop that reaches
+                                 behind the camera, or with a corner 80 degrees
+                                 or more off the gaze, refuses its fixation: the
+                                 builder's reading (Appendix A gives the crop,
+                                 not what to do where it degenerates), shared
+                                 by both sides, not pinned by the paper
   in_window / density_window .. pinned (partition of a recording into back-to-back
                                  windows sums to the whole, boundary and NaN
                                  times, empty window)
@@ -235,6 +241,30 @@ def sample_scene(meshes, k: float, seed: int) -> OracleSamples:
     return OracleSamples(cat[0].astype(np.int32), cat[1].astype(np.int32), cat[2].astype(np.int32),
                          cat[3], cat[4], cat[5].astype(np.float32), cat[6].astype(np.float32),
                          np.array(counts, np.int64), np.array(Ss, np.int32), np.array(Wms, np.uint64))
+
+
+def sample_at(meshes, k: float, seed: int, index: int):
+    """One sample of sample_scene's output, by its global index (mesh order, then
+    Philox counter order), without drawing the others: (pos32 [3], global triangle,
+    mesh)."""
+    lib = _load()
+    tri_base = 0
+    for m, (V, I) in enumerate(meshes):
+        V = np.ascontiguousarray(V, dtype=np.float32)
+        I = np.ascontiguousarray(I, dtype=np.int32)
+        _, C, S, Wm = mesh_weights(triangle_areas(V, I))
+        n = sample_count(Wm, S, k) if Wm > 0 else 0
+        if index < n:
+            tri = np.zeros(1, np.int32)
+            b64 = np.zeros((1, 2)); p64 = np.zeros((1, 3))
+            b32 = np.zeros((1, 2), np.float32); p32 = np.zeros((1, 3), np.float32)
+            lib.or_sample_mesh(_ptr(V, ctypes.c_float), _ptr(I, ctypes.c_int32), _ptr(C, ctypes.c_uint64),
+                               len(I), m, seed, int(index), 1, _ptr(tri, ctypes.c_int32), _ptr(b64, ctypes.c_double),
+                               _ptr(p64, ctypes.c_double), _ptr(b32, ctypes.c_float), _ptr(p32, ctypes.c_float))
+            return p32[0], int(tri[0]) + tri_base, m
+        index -= n
+        tri_base += len(I)
+    raise IndexError("sample index beyond the scene's samples")
 
 
 # ----------------------------------------------------------------------------

@@ -14,7 +14,8 @@ Network: x -> x~ = (x - lo) / ext in [0,1]^3 -> 96 features
 index 6b + 2a + (0 sin | 1 cos) -> 4 x (64, ReLU) -> 1 -> softplus.
 Loss: mean squared error against the normalised density.
 Parity status: pinned (central finite differences in FP64, closed forms of the
-features, softplus and one Adam step).
+features and softplus; Adam: the first step, a constant gradient over ten steps
+and two steps with changing gradients worked out by hand).
 """
 from __future__ import annotations
 

@@ -32,7 +32,8 @@ SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy",
            "gm_batch_create", "gm_batch_run", "gm_batch_info", "gm_batch_destroy",
            "gm_map_create", "gm_map_add", "gm_map_add_posed", "gm_map_read", "gm_map_reset", "gm_map_info",
            "gm_map_destroy", "gm_export_samples", "gm_render_zbuffers", "accumulate_density_zbuffer",
-           "gm_density_counters")
+           "gm_density_counters", "gm_debug_adam_step", "gm_scene_mesh_closed", "gm_scene_set_mesh_closed",
+           "gm_mesh_closed")
 GM_MAP_POSED = 4
 
 # one exported sample (gm_export_record), 48 bytes
@@ -103,10 +104,13 @@ def load_library(path: str = LIB_PATH):
     lib.accumulate_density.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(_Fix), dbl, u32, vp, vp, vp, vp]
     lib.gm_debug_pair_values.argtypes = [vp, i64, ctypes.POINTER(_Fix), dbl, vp, vp, i64, vp, vp]
     lib.gm_debug_sqrt_f64.argtypes = [vp, vp, i64, vp]
-    lib.gm_debug_pair_visibility.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, i64, u32, vp, vp]
+    lib.gm_debug_pair_visibility.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, vp, vp, i64, u32, vp, vp]
     lib.gm_profile_enable.argtypes = [vp, i32]
     lib.gm_density_stats.argtypes = [vp, ctypes.POINTER(i64)]
     lib.gm_density_counters.argtypes = [vp, ctypes.POINTER(i64), i32]
+    lib.gm_scene_mesh_closed.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
+    lib.gm_scene_set_mesh_closed.argtypes = [vp, i32, i32]
+    lib.gm_mesh_closed.argtypes = [vp, i32, vp, i32]
     f32p = ctypes.POINTER(ctypes.c_float)
     lib.gm_field_create.argtypes = [vp, u64, dbl, ctypes.POINTER(vp)]
     lib.gm_field_destroy.argtypes = [vp]
@@ -117,6 +121,8 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.POINTER(i64)]
     lib.gm_field_gradient.argtypes = [vp, i32, vp, vp, i64, f32p, ctypes.POINTER(dbl)]
     lib.gm_field_predict.argtypes = [vp, vp, vp, i64, vp, vp]
+    f32 = ctypes.c_float
+    lib.gm_debug_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp]
     lib.gm_batch_create.argtypes = [ctypes.POINTER(_Session), i32, ctypes.c_char_p, i32, ctypes.POINTER(vp), vp]
     lib.gm_batch_run.argtypes = [vp, vp]
     lib.gm_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -243,10 +249,19 @@ class Scene:
 
     def density_stats(self):
         """Counters of the last accumulate call: in-cone pairs, visible pairs, traversals,
-        node visits, triangle tests (wave level)."""
-        out = (ctypes.c_int64 * 5)()
-        _check(_lib.gm_density_counters(self._h, out, 5))
-        return dict(zip(("in_cone", "visible", "traversals", "node_visits", "triangle_tests"), out[:]))
+        node visits, triangle tests (wave level), pairs settled by the back-face rule."""
+        out = (ctypes.c_int64 * 6)()
+        _check(_lib.gm_density_counters(self._h, out, 6))
+        return dict(zip(("in_cone", "visible", "traversals", "node_visits", "triangle_tests", "backface"), out[:]))
+
+    def mesh_closed(self):
+        """Per mesh: whether the visibility test treats it as bounding a solid."""
+        out = (ctypes.c_uint8 * self.info()["n_meshes"])()
+        _check(_lib.gm_scene_mesh_closed(self._h, out))
+        return np.array(out[:], dtype=bool)
+
+    def set_mesh_closed(self, mesh, closed):
+        _check(_lib.gm_scene_set_mesh_closed(self._h, int(mesh), 1 if closed else 0))
 
     def profile(self, on=True):
         _check(_lib.gm_profile_enable(self._h, 1 if on else 0))
@@ -355,16 +370,19 @@ class Scene:
                                                _ptr(out.max), _stream()))
         return out
 
-    def pair_visibility(self, pos, eye, pair_s, pair_f, occlusion="full", tri=None, mesh=None):
+    def pair_visibility(self, pos, eye, pair_s, pair_f, occlusion="full", tri=None, mesh=None, gaze=None):
+        """Visibility of explicit (sample, fixation) pairs; with the fixations' gaze, the
+        density kernel's own answer for each pair."""
         torch = _torch()
         pos = _dev(pos, torch.float32, 3)
         eye = _dev(eye, torch.float32, 3)
+        gaze = _dev(gaze, torch.float32, 3)
         ps = _dev(pair_s, torch.int32); pf = _dev(pair_f, torch.int32)
         tri = _dev(tri, torch.int32); mesh = _dev(mesh, torch.int32)
         vis = torch.empty(int(ps.shape[0]), dtype=torch.uint8, device="cuda")
         _check(_lib.gm_debug_pair_visibility(self._h, _ptr(pos), _ptr(tri), _ptr(mesh), int(pos.shape[0]),
-                                             _ptr(eye), int(eye.shape[0]), _ptr(ps), _ptr(pf), int(ps.shape[0]),
-                                             OCC[occlusion], _ptr(vis), _stream()))
+                                             _ptr(eye), _ptr(gaze), int(eye.shape[0]), _ptr(ps), _ptr(pf),
+                                             int(ps.shape[0]), OCC[occlusion], _ptr(vis), _stream()))
         return vis
 
 
@@ -497,6 +515,16 @@ def sqrt_f64(x):
     y = torch.empty_like(x)
     _check(_lib.gm_debug_sqrt_f64(_ptr(x), _ptr(y), int(x.numel()), _stream()))
     return y
+
+
+def adam_step(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update with the training loop's kernel, in place on device float32 tensors
+    (params, m, v); grad is zeroed afterwards.  step counts from 1."""
+    load_library()
+    for t in (params, m, v, grad):
+        assert t.is_cuda and t.dtype == _torch().float32 and t.is_contiguous() and t.numel() == params.numel()
+    _check(_lib.gm_debug_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(params.numel()), int(step),
+                                   float(lr), float(beta1), float(beta2), float(eps), _stream()))
 
 
 class Field:

@@ -70,10 +70,11 @@ void zero(void* p, size_t bytes, hipStream_t s) { fill_u32(p, (int64_t)((bytes +
 
 namespace {
 
-// a1 + a2 on the device, then the per-mesh counts (blocking read-back).
-gm_status sample_counts(gm_scene* sc, double k, hipStream_t s, std::vector<int64_t>& counts)
+// a1 + a2 on the device, once per scene: areas, weights, their scan and the per-mesh
+// totals and scale exponents, the last two read back to the host (blocking, once).
+gm_status ensure_weights(gm_scene* sc, hipStream_t s)
 {
-    if (!(k > 0.0) || !std::isfinite(k)) return fail(GM_ERR_INVALID_ARGUMENT, "samples_per_m2 must be finite and > 0");
+    if (sc->weights_ready) return GM_OK;
     const int64_t T = sc->T;
     const int32_t M = sc->M;
     GM_HIP(sc->area.ensure(sizeof(double) * T));
@@ -93,36 +94,53 @@ gm_status sample_counts(gm_scene* sc, double k, hipStream_t s, std::vector<int64
     launch_tri_weight(sc->area.as<double>(), sc->tri_mesh.as<int32_t>(), sc->S.as<int32_t>(), T,
                       sc->W.as<unsigned long long>(), s);
     launch_inclusive_scan_u64(sc->W.as<unsigned long long>(), sc->C.as<unsigned long long>(), T, sc->scan_tmp.p, s);
-    launch_mesh_counts(sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), sc->S.as<int32_t>(), M, k,
+    // the totals (the counts of density 0 are unused)
+    launch_mesh_counts(sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), sc->S.as<int32_t>(), M, 0.0,
                        sc->counts.as<int64_t>(), sc->offsets.as<int64_t>(), sc->mesh_total.as<unsigned long long>(), s);
     GM_HIP(hipGetLastError());
     GM_HIP(sc->tend(kStageSample, s));
-    counts.assign((size_t)M, 0);
-    GM_HIP(hipMemcpyAsync(counts.data(), sc->counts.p, 8 * (size_t)M, hipMemcpyDeviceToHost, s));
+    sc->mesh_total_h.assign((size_t)M, 0ull);
+    sc->S_h.assign((size_t)M, 0);
+    GM_HIP(hipMemcpyAsync(sc->mesh_total_h.data(), sc->mesh_total.p, 8 * (size_t)M, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipMemcpyAsync(sc->S_h.data(), sc->S.p, 4 * (size_t)M, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
+    sc->weights_ready = true;
     return GM_OK;
 }
 
-// Lattice sampler counts: areas (a1's kernel), Eq. (4) resolutions and Eq. (1)
-// counts per triangle, their inclusive scan in sc->C, per-mesh totals (blocking).
+// Per-mesh counts round(k * W_m 2^-S_m), evaluated on the host exactly as k_mesh_counts
+// evaluates them on the device (the same FP64 operations in the same order).
+gm_status sample_counts(gm_scene* sc, double k, hipStream_t s, std::vector<int64_t>& counts)
+{
+    if (!(k > 0.0) || !std::isfinite(k)) return fail(GM_ERR_INVALID_ARGUMENT, "samples_per_m2 must be finite and > 0");
+    gm_status st = ensure_weights(sc, s);
+    if (st != GM_OK) return st;
+    counts.assign((size_t)sc->M, 0);
+    for (int32_t m = 0; m < sc->M; ++m) {
+        const unsigned long long tot = sc->mesh_total_h[(size_t)m];
+        const double area = std::ldexp((double)tot, -sc->S_h[(size_t)m]);
+        counts[(size_t)m] = tot ? (int64_t)std::floor(area * k + 0.5) : 0;
+    }
+    return GM_OK;
+}
+
+// Lattice sampler counts: areas (a1, cached), Eq. (4) resolutions and Eq. (1) counts
+// per triangle, their inclusive scan in sc->lat_C, per-mesh totals (blocking).
 gm_status lattice_counts(gm_scene* sc, double k, hipStream_t s, std::vector<int64_t>& counts)
 {
     if (!(k > 0.0) || !(k <= 1e12)) return fail(GM_ERR_INVALID_ARGUMENT, "samples_per_m2 must be in (0, 1e12]");
+    gm_status st = ensure_weights(sc, s);
+    if (st != GM_OK) return st;
     const int64_t T = sc->T;
     const int32_t M = sc->M;
-    GM_HIP(sc->area.ensure(sizeof(double) * T));
-    GM_HIP(sc->W.ensure(8 * T));
-    GM_HIP(sc->C.ensure(8 * T));
-    GM_HIP(sc->max_bits.ensure(8 * M));
-    GM_HIP(sc->scan_tmp.ensure(scan_tmp_bytes(T)));
-    GM_HIP(sc->counts.ensure(8 * M));
+    GM_HIP(sc->lat_W.ensure(8 * T));
+    GM_HIP(sc->lat_C.ensure(8 * T));
     GM_HIP(sc->tbegin(kStageSample, s));
-    zero(sc->max_bits.p, 8 * (size_t)M, s);
-    launch_tri_area(sc->V.as<float>(), sc->I.as<int32_t>(), sc->tri_mesh.as<int32_t>(), T, sc->area.as<double>(),
-                    sc->max_bits.as<unsigned long long>(), s);
-    launch_lattice_count(sc->area.as<double>(), T, k, sc->W.as<unsigned long long>(), s);
-    launch_inclusive_scan_u64(sc->W.as<unsigned long long>(), sc->C.as<unsigned long long>(), T, sc->scan_tmp.p, s);
-    launch_lattice_mesh_counts(sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), M, sc->counts.as<int64_t>(), s);
+    launch_lattice_count(sc->area.as<double>(), T, k, sc->lat_W.as<unsigned long long>(), s);
+    launch_inclusive_scan_u64(sc->lat_W.as<unsigned long long>(), sc->lat_C.as<unsigned long long>(), T,
+                              sc->scan_tmp.p, s);
+    launch_lattice_mesh_counts(sc->lat_C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), M,
+                               sc->counts.as<int64_t>(), s);
     GM_HIP(hipGetLastError());
     GM_HIP(sc->tend(kStageSample, s));
     counts.assign((size_t)M, 0);
@@ -232,6 +250,35 @@ void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F
     a.fix_per_chunk = fix_per_chunk;
     a.n_chunks = F > 0 ? (int32_t)((F + fix_per_chunk - 1) / fix_per_chunk) : 0;
     a.F_live = nullptr;
+    if (w.backface && mode != GM_OCC_NONE) {
+        a.bface = w.bface.as<float4>();
+        a.bcand = w.bcand.as<int32_t>();
+        a.mbox = sc->mbox_d.as<float4>();
+        a.bf_tris = sc->tris.as<BvhTri>() + 2 * sc->bvh.tris.size();
+        a.bf_L2max = backface_l2max(sc);
+    }
+}
+
+float backface_l2max(const gm_scene* sc)
+{
+    // the rule's longest segment: its last kEpsV stretch stays 1e-3 inside rmax
+    const double lmax = (double)sc->bf_rmax / kEpsV * (1.0 - 1e-3);
+    return (float)(lmax * lmax);
+}
+
+gm_status density_backface(gm_scene* sc, DensityWork& w, int64_t n, uint32_t mode, hipStream_t s, int64_t off)
+{
+    w.backface = false;
+    if (mode == GM_OCC_NONE || !sc->any_closed() || n <= 0) return GM_OK;
+    GM_HIP(w.bface.ensure(16 * (size_t)(off + n)));
+    GM_HIP(w.bcand.ensure(4 * (size_t)kBfCand * (size_t)(off + n)));
+    launch_backface_prep(w.spos.as<float4>() + off, w.smesh.as<int32_t>() + off, n, sc->V.as<float>(),
+                         sc->I.as<int32_t>(), sc->closed_d.as<uint8_t>(), sc->nodes.as<BvhNode>(),
+                         sc->tris.as<BvhTri>() + 2 * sc->bvh.tris.size(), sc->bf_rmax, w.bface.as<float4>() + off,
+                         w.bcand.as<int32_t>() + kBfCand * off, s);
+    GM_HIP(hipGetLastError());
+    w.backface = true;
+    return GM_OK;
 }
 
 gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
@@ -246,6 +293,8 @@ gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int
     launch_fix_prep(fix->eye, fix->gaze, fix->duration, F, sigma, kGateWiden, w.fix.as<FixRec>(), nullptr,
                     w.fx_shift.as<int32_t>(), s);
     density_sort(sc, w, pos, tri, mesh, n, s);
+    gm_status st = density_backface(sc, w, n, mode, s);
+    if (st != GM_OK) return st;
     density_args(sc, w, n, F, sigma, mode, spl, fix_per_chunk, a);
     GM_HIP(hipGetLastError());
     return GM_OK;
@@ -325,6 +374,32 @@ gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** ou
         if (v >= 1 && v <= kLeafMax) leaf_max = v;
     }
     build_bvh(V.data(), I.data(), tm.data(), T, sc->bvh, leaf_max);
+    // meshes that bound a solid, their boxes, and the back-face rule's neighbour radius:
+    // kEpsV of twice the scene's diagonal plus 4 m (segments up to that length, eyes within
+    // a few metres of the scene, use the rule)
+    sc->closed.assign((size_t)n_meshes, 0);
+    std::vector<float> mbox((size_t)8 * n_meshes, 0.0f);
+    for (int32_t m = 0; m < n_meshes; ++m) {
+        const gm_mesh& g = meshes[m];
+        sc->closed[(size_t)m] = mesh_is_closed(g.vertices, g.n_vertices, g.indices, g.n_triangles) ? 1 : 0;
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t t = 0; t < 3 * (int64_t)g.n_triangles; ++t)
+            for (int c = 0; c < 3; ++c) {
+                const float v = g.vertices[3 * (int64_t)g.indices[t] + c];
+                lo[c] = std::min(lo[c], v);
+                hi[c] = std::max(hi[c], v);
+            }
+        for (int c = 0; c < 3; ++c) {
+            mbox[(size_t)8 * m + c] = lo[c];
+            mbox[(size_t)8 * m + 4 + c] = hi[c];
+        }
+    }
+    sc->closed_topology = sc->closed;
+    {
+        double d2 = 0.0;
+        for (int c = 0; c < 3; ++c) d2 += ((double)sc->bvh.hi[c] - sc->bvh.lo[c]) * ((double)sc->bvh.hi[c] - sc->bvh.lo[c]);
+        sc->bf_rmax = (float)(kEpsV * (2.0 * std::sqrt(d2) + 4.0));
+    }
 
     auto up = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
         hipError_t e = b.ensure(bytes);
@@ -342,6 +417,8 @@ gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** ou
     std::vector<BvhTri> tri3;
     permute_tri_copies(sc->bvh.tris, tri3);
     if (e == hipSuccess) e = up(sc->tris, tri3.data(), tri3.size() * sizeof(BvhTri));
+    if (e == hipSuccess) e = up(sc->closed_d, sc->closed.data(), sc->closed.size());
+    if (e == hipSuccess) e = up(sc->mbox_d, mbox.data(), mbox.size() * 4);
     if (e != hipSuccess) {
         delete sc;
         return fail(e == hipErrorOutOfMemory ? GM_ERR_OUT_OF_MEMORY : GM_ERR_DEVICE, "scene upload: %s",
@@ -378,6 +455,29 @@ gm_status gm_scene_info(const gm_scene* sc, int64_t* n_triangles, int32_t* n_mes
     return GM_OK;
 }
 
+gm_status gm_scene_mesh_closed(const gm_scene* sc, uint8_t* closed)
+{
+    gm::clear_error();
+    if (!sc || !closed) return fail(GM_ERR_INVALID_ARGUMENT, "scene and closed must not be NULL");
+    std::memcpy(closed, sc->closed.data(), sc->closed.size());
+    return GM_OK;
+}
+
+gm_status gm_scene_set_mesh_closed(gm_scene* sc, int32_t mesh, int32_t closed)
+{
+    gm::clear_error();
+    if (!sc) return fail(GM_ERR_INVALID_ARGUMENT, "scene is NULL");
+    if (mesh < 0 || mesh >= sc->M) return fail(GM_ERR_INVALID_ARGUMENT, "mesh %d outside [0, %d)", mesh, sc->M);
+    if (closed && !sc->closed_topology[(size_t)mesh])
+        return fail(GM_ERR_INVALID_ARGUMENT, "mesh %d does not bound a solid (gm_mesh_closed)", mesh);
+    gm_status st = check_device(sc);
+    if (st != GM_OK) return st;
+    GM_HIP(hipDeviceSynchronize());
+    sc->closed[(size_t)mesh] = closed ? 1 : 0;
+    GM_HIP(hipMemcpy(sc->closed_d.as<uint8_t>() + mesh, &sc->closed[(size_t)mesh], 1, hipMemcpyHostToDevice));
+    return GM_OK;
+}
+
 gm_status gm_count_lattice_samples(gm_scene* sc, double k, int64_t* n_per_mesh, void* stream)
 {
     gm::clear_error();
@@ -410,7 +510,7 @@ gm_status build_lattice_samples(gm_scene* sc, double k, int32_t* tri, int32_t* m
     if (N >= (int64_t)1 << 31) return fail(GM_ERR_INVALID_ARGUMENT, "more than 2^31 - 1 samples");
     GM_HIP(sc->tbegin(kStageSample, s));
     launch_lattice_sample(sc->V.as<float>(), sc->I.as<int32_t>(), sc->tri_mesh.as<int32_t>(), sc->area.as<double>(),
-                          sc->C.as<unsigned long long>(), sc->T, N, k, tri, mesh, bary, pos, s);
+                          sc->lat_C.as<unsigned long long>(), sc->T, N, k, tri, mesh, bary, pos, s);
     GM_HIP(hipGetLastError());
     GM_HIP(sc->tend(kStageSample, s));
     return GM_OK;
@@ -447,6 +547,8 @@ gm_status build_surface_samples(gm_scene* sc, double k, uint64_t seed, int32_t* 
     if (N > capacity) return fail(GM_ERR_CAPACITY, "%lld samples do not fit capacity %lld", (long long)N, (long long)capacity);
     if (N >= (int64_t)1 << 31) return fail(GM_ERR_INVALID_ARGUMENT, "more than 2^31 - 1 samples");
     GM_HIP(sc->tbegin(kStageSample, s));
+    launch_mesh_counts(sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), sc->S.as<int32_t>(), sc->M, k,
+                       sc->counts.as<int64_t>(), sc->offsets.as<int64_t>(), sc->mesh_total.as<unsigned long long>(), s);
     launch_sample(sc->V.as<float>(), sc->I.as<int32_t>(), sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(),
                   sc->offsets.as<int64_t>(), sc->mesh_total.as<unsigned long long>(), sc->M, N, seed, tri, mesh, bary,
                   pos, s);
@@ -520,8 +622,9 @@ gm_status gm_debug_pair_values(const float* pos, int64_t n_points, const gm_fixa
 }
 
 gm_status gm_debug_pair_visibility(gm_scene* sc, const float* pos, const int32_t* tri, const int32_t* mesh,
-                                   int64_t n_points, const float* eye, int32_t n_eyes, const int32_t* pair_s,
-                                   const int32_t* pair_f, int64_t m, uint32_t flags, uint8_t* vis_out, void* stream)
+                                   int64_t n_points, const float* eye, const float* gaze, int32_t n_eyes,
+                                   const int32_t* pair_s, const int32_t* pair_f, int64_t m, uint32_t flags,
+                                   uint8_t* vis_out, void* stream)
 {
     gm::clear_error();
     if (!sc || m < 0 || n_points < 0 || n_eyes < 0 || (m > 0 && (!pos || !eye || !pair_s || !pair_f || !vis_out)))
@@ -530,8 +633,18 @@ gm_status gm_debug_pair_visibility(gm_scene* sc, const float* pos, const int32_t
     if (mode > GM_OCC_FULL) return fail(GM_ERR_INVALID_ARGUMENT, "unknown occlusion mode");
     gm_status st = check_device(sc);
     if (st != GM_OK) return st;
-    launch_pair_visibility(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), eye, pair_s, pair_f, m, n_points, n_eyes, sc->T,
-                           sc->nodes.as<BvhNode>(), sc->tris.as<BvhTri>() + 2 * sc->bvh.tris.size(), (int32_t)mode, kTmax, vis_out, (hipStream_t)stream);
+    BackfaceArgs bf;
+    if (sc->any_closed()) {
+        bf.V = sc->V.as<float>();
+        bf.I = sc->I.as<int32_t>();
+        bf.closed = sc->closed_d.as<uint8_t>();
+        bf.mbox = sc->mbox_d.as<float4>();
+        bf.rmax = sc->bf_rmax;
+        bf.l2max = backface_l2max(sc);
+    }
+    launch_pair_visibility(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), eye, gaze, pair_s, pair_f, m, n_points, n_eyes,
+                           sc->T, sc->nodes.as<BvhNode>(), sc->tris.as<BvhTri>() + 2 * sc->bvh.tris.size(),
+                           (int32_t)mode, bf, vis_out, (hipStream_t)stream);
     GM_HIP(hipGetLastError());
     return GM_OK;
 }

@@ -23,6 +23,8 @@ struct gm_field {
     DevBuf master, m, v, grad, blob, loss;
     DevBuf flag, sel, offs, idx, scan_tmp, pred, l2sums, geom_d, net_off, net_cnt;
     DevBuf gate_d, need, qoffs, qscan, gpos, gtri, gmesh, gidx, grho, gnorm;
+    DevBuf rcnt, rbase, ridx, take_d;  // routed inference: per-mesh counts, segment starts, point lists
+    DevBuf gpart, lpart;               // training: per-wave gradient and loss slots
     std::vector<float> rel_l2;
     std::vector<uint8_t> gate;
     double norm_max = 0.0;
@@ -34,7 +36,7 @@ struct gm_field {
     {
         for (DevBuf* b : {&master, &m, &v, &grad, &blob, &loss, &flag, &sel, &offs, &idx, &scan_tmp, &pred, &l2sums,
                           &geom_d, &net_off, &net_cnt, &gate_d, &need, &qoffs, &qscan, &gpos, &gtri, &gmesh, &gidx,
-                          &grho, &gnorm})
+                          &grho, &gnorm, &rcnt, &rbase, &ridx, &take_d, &gpart, &lpart})
             b->release();
     }
 };
@@ -66,6 +68,14 @@ void init_params(uint64_t seed, std::vector<float>& p)
 
 unsigned char* net_blob(gm_field* f, int m) { return f->blob.as<unsigned char>() + (size_t)m * field_pack_bytes(); }
 
+// Adam's bias corrections (Kingma and Ba 2015) for update number `step` (from 1):
+// c1 = 1 / (1 - beta1^step), c2 = 1 / (1 - beta2^step), in FP64 then rounded.
+void adam_bias_scales(int32_t step, float beta1, float beta2, float& c1, float& c2)
+{
+    c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)step)));
+    c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)step)));
+}
+
 gm_status upload_params(gm_field* f, const float* host, hipStream_t s)
 {
     GM_HIP(hipMemcpyAsync(f->master.p, host, sizeof(float) * kFieldParams * (size_t)f->M, hipMemcpyHostToDevice, s));
@@ -76,6 +86,21 @@ gm_status upload_params(gm_field* f, const float* host, hipStream_t s)
 }
 
 FieldRoute route_all() { return FieldRoute{nullptr, nullptr, nullptr, 0, -1}; }
+
+// Every network over its own mesh's points (those of the meshes with take[m] set, NULL:
+// all), each point evaluated once, in one launch.
+gm_status infer_routed(gm_field* f, const float* pos, int64_t q, float* out, const FieldRoute& route,
+                       const uint8_t* take, hipStream_t s)
+{
+    GM_HIP(f->rcnt.ensure(4 * (size_t)f->M));
+    GM_HIP(f->rbase.ensure(8 * ((size_t)f->M + 1)));
+    GM_HIP(f->ridx.ensure(4 * (size_t)field_route_slots(q, f->M)));
+    launch_field_infer_routed(f->blob.as<unsigned char>(), (int64_t)field_pack_bytes(), f->geom_d.as<FieldGeom>(),
+                              pos, q, out, route, take, f->M, f->rcnt.as<unsigned int>(), f->rbase.as<int64_t>(),
+                              f->ridx.as<int32_t>(), s);
+    GM_HIP(hipGetLastError());
+    return GM_OK;
+}
 
 }  // namespace
 
@@ -186,15 +211,16 @@ gm_status gm_field_gradient(gm_field* f, int32_t net, const float* pos, const fl
                             double* loss)
 {
     clear_error();
-    if (!f || !pos || !target || !grad || n <= 0 || n > (1 << 30))
-        return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or n outside (0, 2^30]");
+    if (!f || !pos || !target || !grad || n <= 0 || n > 65536)
+        return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or n outside (0, 65536]");
     if (net < 0 || net >= f->M) return fail(GM_ERR_INVALID_ARGUMENT, "network %d outside [0, %d)", net, f->M);
     gm_status st = check_device(f->scene);
     if (st != GM_OK) return st;
     hipStream_t s = nullptr;
     float* gnet = f->grad.as<float>() + (size_t)net * kFieldParams;
-    zero(gnet, sizeof(float) * kFieldParams, s);
-    zero(f->loss.p, sizeof(double), s);
+    const int32_t slots = field_train_slots((int32_t)n, 1);
+    GM_HIP(f->gpart.ensure(sizeof(float) * kFieldParams * (size_t)slots));
+    GM_HIP(f->lpart.ensure(sizeof(double) * (size_t)slots));
     FieldTrain t;
     t.pos = pos;
     t.target = target;
@@ -204,9 +230,9 @@ gm_status gm_field_gradient(gm_field* f, int32_t net, const float* pos, const fl
     t.inv_batch = (float)(1.0 / (double)n);
     t.key0 = t.key1 = 0;
     t.step = 0;
-    t.grad = gnet;
-    t.loss = f->loss.as<double>();
-    launch_field_train(net_blob(f, net), f->geom[(size_t)net], t, s);
+    t.gpart = f->gpart.as<float>();
+    t.lpart = f->lpart.as<double>();
+    launch_field_train(net_blob(f, net), f->geom[(size_t)net], t, gnet, f->loss.as<double>(), s);
     GM_HIP(hipGetLastError());
     double l = 0.0;
     GM_HIP(hipMemcpy(grad, gnet, sizeof(float) * kFieldParams, hipMemcpyDeviceToHost));
@@ -214,6 +240,22 @@ gm_status gm_field_gradient(gm_field* f, int32_t net, const float* pos, const fl
     zero(gnet, sizeof(float) * kFieldParams, s);
     GM_HIP(hipStreamSynchronize(s));
     if (loss) *loss = l / (double)n;
+    return GM_OK;
+}
+
+gm_status gm_debug_adam_step(float* params, float* m, float* v, float* grad, int64_t count, int32_t step, float lr,
+                             float beta1, float beta2, float eps, void* stream)
+{
+    clear_error();
+    if (count < 0 || (count > 0 && (!params || !m || !v || !grad)))
+        return fail(GM_ERR_INVALID_ARGUMENT, "NULL argument or negative size");
+    if (step < 1) return fail(GM_ERR_INVALID_ARGUMENT, "step counts from 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f && std::isfinite(lr)))
+        return fail(GM_ERR_INVALID_ARGUMENT, "beta1, beta2 in [0, 1), eps >= 0, finite lr");
+    float c1, c2;
+    adam_bias_scales(step, beta1, beta2, c1, c2);
+    launch_field_adam(params, m, v, grad, count, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream);
+    GM_HIP(hipGetLastError());
     return GM_OK;
 }
 
@@ -286,20 +328,20 @@ gm_status gm_field_train(gm_field* f, const float* pos, const int32_t* mesh, con
     t.inv_batch = 1.0f / (float)P->batch;
     t.key0 = key0 ^ 0x5bd1e995u;
     t.key1 = key1 ^ 0x1b873593u;
-    t.grad = f->grad.as<float>();
-    t.loss = f->loss.as<double>();
-    double b1t = 1.0, b2t = 1.0;
+    const int32_t slots = field_train_slots(P->batch, M);
+    GM_HIP(f->gpart.ensure(sizeof(float) * kFieldParams * (size_t)slots * (size_t)M));
+    GM_HIP(f->lpart.ensure(sizeof(double) * (size_t)slots * (size_t)M));
+    t.gpart = f->gpart.as<float>();
+    t.lpart = f->lpart.as<double>();
     for (int32_t it = 0; it < P->steps && total > 0; ++it) {
         t.step = (uint32_t)it;
-        zero(f->loss.p, sizeof(double) * (size_t)M, s);
-        launch_field_train_nets(f->blob.as<unsigned char>(), nets, M, t, s);
-        b1t *= P->beta1;
-        b2t *= P->beta2;
+        launch_field_train_nets(f->blob.as<unsigned char>(), nets, M, t, f->grad.as<float>(), f->loss.as<double>(), s);
         const double frac = P->steps > 1 ? (double)it / (double)(P->steps - 1) : 1.0;
         const double lr = P->lr_final + 0.5 * (P->lr - P->lr_final) * (1.0 + std::cos(M_PI * frac));
+        float c1, c2;
+        adam_bias_scales(it + 1, P->beta1, P->beta2, c1, c2);
         launch_field_adam(f->master.as<float>(), f->m.as<float>(), f->v.as<float>(), f->grad.as<float>(),
-                          (int64_t)M * kFieldParams, (float)lr, P->beta1, P->beta2, P->eps,
-                          (float)(1.0 / (1.0 - b1t)), (float)(1.0 / (1.0 - b2t)), s);
+                          (int64_t)M * kFieldParams, (float)lr, P->beta1, P->beta2, P->eps, c1, c2, s);
         launch_field_pack_nets(f->master.as<float>(), f->blob.as<unsigned char>(), M, s);
     }
     GM_HIP(hipGetLastError());
@@ -311,10 +353,13 @@ gm_status gm_field_train(gm_field* f, const float* pos, const int32_t* mesh, con
             if (has_train[(size_t)net]) last = std::isnan(last) ? l[(size_t)net] : std::max(last, l[(size_t)net]);
     }
     // each network's values at its mesh's points, for the held-out error
-    for (int32_t net = 0; net < M; ++net)
-        if (has_train[(size_t)net])
-            launch_field_infer(net_blob(f, net), f->geom[(size_t)net], pos, n, f->pred.as<float>(),
-                               FieldRoute{mesh, nullptr, nullptr, 0, net}, s);
+    GM_HIP(f->take_d.ensure((size_t)M));
+    GM_HIP(hipMemcpyAsync(f->take_d.p, has_train.data(), (size_t)M, hipMemcpyHostToDevice, s));
+    {
+        gm_status rs = infer_routed(f, pos, n, f->pred.as<float>(), FieldRoute{mesh, nullptr, nullptr, 0, -1},
+                                    f->take_d.as<uint8_t>(), s);
+        if (rs != GM_OK) return rs;
+    }
 
     // held-out relative L2 per mesh
     zero(f->l2sums.p, 16 * (size_t)M, s);
@@ -352,13 +397,10 @@ gm_status gm_field_predict(gm_field* f, const float* pos, const int32_t* mesh, i
     hipStream_t s = (hipStream_t)stream;
     if (!mesh) {
         launch_field_infer(net_blob(f, 0), f->geom[0], pos, q, out, route_all(), s);
-    } else {
-        for (int32_t m = 0; m < f->M; ++m)
-            launch_field_infer(net_blob(f, m), f->geom[(size_t)m], pos, q, out, FieldRoute{mesh, nullptr, nullptr, 0, m},
-                               s);
+        GM_HIP(hipGetLastError());
+        return GM_OK;
     }
-    GM_HIP(hipGetLastError());
-    return GM_OK;
+    return infer_routed(f, pos, q, out, FieldRoute{mesh, nullptr, nullptr, 0, -1}, nullptr, s);
 }
 
 gm_status gm_field_info(gm_field* f, float* rel_l2, uint8_t* gate, double* loss, int64_t* steps)
@@ -390,10 +432,13 @@ gm_status query_density(gm_field* f, gm_scene* sc, const gm_fixations* fix, doub
     hipStream_t s = (hipStream_t)stream;
     const bool use_field = f && f->trained;
     if (use_field && (mesh || tri)) {
-        for (int32_t m = 0; m < f->M; ++m)
-            if (f->gate[(size_t)m])
-                launch_field_infer(net_blob(f, m), f->geom[(size_t)m], pos, q, out,
-                                   FieldRoute{mesh, tri, sc->tri_mesh.as<int32_t>(), sc->T, m}, s);
+        bool any = false;
+        for (uint8_t g : f->gate) any = any || g;
+        if (any) {
+            st = infer_routed(f, pos, q, out, FieldRoute{mesh, tri, sc->tri_mesh.as<int32_t>(), sc->T, -1},
+                              f->gate_d.as<uint8_t>(), s);
+            if (st != GM_OK) return st;
+        }
     }
     // scratch lives in the field when there is one, else in per-call buffers
     DevBuf local_need, local_offs, local_scan;

@@ -116,6 +116,8 @@ constexpr double kGateWiden = 3e-5;
 // Device scratch of one density evaluation (one scene, one set of points and fixations).
 struct DensityWork {
     DevBuf fix, fx_shift, key, hist, cursor, scan_tmp, spos, smesh, perm, acc, max_acc, stats, zcam, zbuf;
+    DevBuf bface, bcand;  // back-face rule data of the sorted points (see DensityLaunch::bface)
+    bool backface = false;  // bface / bcand hold the current points' data
     int bits = 1;
     int64_t buckets = 8;
 };
@@ -137,10 +139,30 @@ struct gm_scene {
     HostBvh bvh;
     // static device data
     DevBuf V, I, tri_mesh, tri_off_d, nodes, tris;
-    // sampler scratch
-    DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total;
+    // sampler state: FP64 areas, fixed-point weights W, their inclusive scan C, per-mesh
+    // scale exponents S and weight totals do not depend on the sampling density, so they
+    // are computed once per scene (weights_ready; totals and S also kept on the host,
+    // where the per-density counts follow without a device round trip); counts and
+    // offsets are rewritten by each sampling call; lat_* hold the lattice sampler's
+    // per-triangle counts and their scan
+    DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total, lat_W, lat_C;
+    bool weights_ready = false;
+    std::vector<unsigned long long> mesh_total_h;
+    std::vector<int32_t> S_h;
     // density scratch of the plain entry points
     DensityWork work;
+    // meshes that bound a solid (gm_mesh_closed at creation; the caller may clear a
+    // flag), on the host and the device, their bounding boxes (float4 lo, hi per mesh)
+    // and the radius within which the back-face rule lists a point's neighbours
+    std::vector<uint8_t> closed, closed_topology;
+    DevBuf closed_d, mbox_d;
+    float bf_rmax = 0.0f;
+    bool any_closed() const
+    {
+        for (uint8_t c : closed)
+            if (c) return true;
+        return false;
+    }
     // one BVH per mesh in the mesh's own frame (posed maps), built on first use:
     // BlasDesc per mesh into the concatenated node and record arrays (with copies)
     std::vector<BlasDesc> blas;
@@ -182,6 +204,11 @@ gm_status density_reserve(DensityWork& w, int64_t n, int32_t F);
 gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int32_t* tri, const int32_t* mesh,
                        int64_t n, const gm_fixations* fix, double theta_deg, uint32_t mode, int spl,
                        int32_t fix_per_chunk, DensityLaunch& a, hipStream_t s);
+// the back-face rule's data of the n sorted points from entry off of w (static scenes with
+// a closed mesh and occlusion on; otherwise it marks the rule off)
+gm_status density_backface(gm_scene* sc, DensityWork& w, int64_t n, uint32_t mode, hipStream_t s, int64_t off = 0);
+// squared length of the longest segment the rule takes (see DensityLaunch::bf_L2max)
+float backface_l2max(const gm_scene* sc);
 // the two halves of density_prep's point side: zeroed accumulators and the spatial sort
 // of the points into w (into entries [off, off + n), caller indices off + i); the
 // launch descriptor for F records in w.fix

@@ -113,13 +113,13 @@ void launch_sample(const float* V, const int32_t* I, const unsigned long long* C
                    uint64_t seed, int32_t* tri, int32_t* mesh, float* bary, float* pos, hipStream_t s);
 
 // density path
-// in-cone pairs, visible pairs, packet traversals, BVH node visits, triangle tests (wave level)
-constexpr int kDensityStats = 5;
+// in-cone pairs, visible pairs, packet traversals, BVH node visits, triangle tests (wave level),
+// pairs settled by the back-face rule
+constexpr int kDensityStats = 6;
 // Tolerance of the exact visibility test (the exact counterpart of the depth test of
-// Sec. 3.2.2): a hit occludes when its segment parameter lies in (0, 1 - kEpsV).  The
-// kernels take the bound as a compile-time constant.
+// Sec. 3.2.2): a hit occludes when its parameter tau on the segment eye + tau (x - eye)
+// lies in (0, 1 - kEpsV).  The kernels take the bound as a compile-time constant.
 constexpr double kEpsV = 1e-4;
-constexpr float kTmax = (float)(1.0 - kEpsV);
 // One mesh's BVH inside the concatenated per-mesh arrays: kNodeCopies copies of
 // node_count nodes from node_base, kTriCopies copies of tri_count records from tri_base.
 struct BlasDesc {
@@ -167,7 +167,23 @@ struct DensityLaunch {
     const float* zbuf = nullptr;
     int32_t zres = 0;
     float zeps = 0.0f;
+    // The back-face rule (static scenes; NULL bface: off).  Per sorted point: the unit
+    // normal of its own triangle times the point's distance to that triangle's edges
+    // and, in w, the number of triangles of its mesh within
+    // bf_rmax of it (as int bits; -1: the rule does not apply to the point), whose
+    // record indices (plain x, y, z copy) are bcand[kBfCand * i + j].  mbox: per mesh the
+    // bounding box, lo then hi (2 float4).  A segment longer than sqrt(bf_L2max) is left
+    // to the traversal.
+    const float4* bface = nullptr;
+    const int32_t* bcand = nullptr;
+    const float4* mbox = nullptr;
+    const BvhTri* bf_tris = nullptr;
+    float bf_L2max = 0.0f;
 };
+
+// Triangles of its own mesh listed per point for the back-face rule (more: the rule
+// does not apply to the point).
+constexpr int kBfCand = 8;
 
 // Camera of one fixation for the z-buffer test: right, up, forward unit vectors, the
 // crop's NDC scale and offset (x_ndc = sx x / D - ox, y likewise, D the depth along
@@ -218,10 +234,19 @@ void launch_finalize(const unsigned long long* acc, const int32_t* perm, int64_t
                      hipStream_t s);
 void launch_pair_values(const float* pos, const FixRec* fix, const int32_t* ps, const int32_t* pf, int64_t m,
                         int64_t n_points, int32_t F, float cone2, float kexp, float* g, hipStream_t s);
+// The scene's back-face rule data for gm_debug_pair_visibility (closed NULL: no rule).
+struct BackfaceArgs {
+    const float* V = nullptr;
+    const int32_t* I = nullptr;
+    const uint8_t* closed = nullptr;
+    const float4* mbox = nullptr;
+    float rmax = 0.0f;
+    float l2max = 0.0f;
+};
 void launch_pair_visibility(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
-                            const float* eye, const int32_t* ps, const int32_t* pf, int64_t m, int64_t n_points,
-                            int32_t n_eyes, int64_t T, const BvhNode* nodes, const BvhTri* tris, int32_t occ_mode,
-                            float tmax, uint8_t* vis, hipStream_t s);
+                            const float* eye, const float* gaze, const int32_t* ps, const int32_t* pf, int64_t m,
+                            int64_t n_points, int32_t n_eyes, int64_t T, const BvhNode* nodes, const BvhTri* tris,
+                            int32_t occ_mode, const BackfaceArgs& bf, uint8_t* vis, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Neural density field: 96 Fourier features -> 4 x (64, ReLU) -> 1 -> softplus.
@@ -254,8 +279,9 @@ struct FieldTrain {
     float inv_batch;         // 1 / batch
     uint32_t key0, key1;     // Philox key of the batch draw
     uint32_t step;
-    float* grad;             // [kFieldParams], accumulated with atomics
-    double* loss;            // sum of squared errors of the step
+    float* gpart;            // [slots][kFieldParams] per-wave gradient sums (per network)
+    double* lpart;           // [slots] per-wave sums of squared errors (per network)
+    int32_t slots;           // set by the launchers: field_train_slots(batch, networks)
 };
 
 // Several networks in one launch (blockIdx.y = network): geometry, and the start and
@@ -282,12 +308,26 @@ struct FieldRoute {
 };
 void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const float* pos, int64_t q, float* out,
                         const FieldRoute& route, hipStream_t s);
+// All networks in one launch, each over its own mesh's points only (route: the points'
+// meshes; take[m] != 0 selects the routed meshes, NULL: all).  Scratch: cnt [M], base
+// [M + 1], ridx [field_route_slots(q, M)].
+int64_t field_route_slots(int64_t q, int32_t M);
+void launch_field_infer_routed(const unsigned char* blobs, int64_t pack_stride, const FieldGeom* geoms,
+                               const float* pos, int64_t q, float* out, const FieldRoute& route,
+                               const uint8_t* take, int32_t M, unsigned int* cnt, int64_t* base, int32_t* ridx,
+                               hipStream_t s);
 // sel[i] = flag[i] && mesh[i] == m
 void launch_field_select(const uint32_t* flag, const int32_t* mesh, int32_t m, int64_t n, uint32_t* sel, hipStream_t s);
-void launch_field_train(const unsigned char* blob, const FieldGeom& g, const FieldTrain& t, hipStream_t s);
-// one training step of M networks at once (see FieldNets; t.key0 is xored with the network)
-void launch_field_train_nets(const unsigned char* blob, const FieldNets& nets, int32_t M, const FieldTrain& t,
-                             hipStream_t s);
+// One training step's forward and backward pass: the gradient grad [kFieldParams] and the
+// sum of squared errors loss [1], reduced in a fixed order from the per-wave slots
+// t.gpart / t.lpart (field_train_slots(batch, 1) of them).
+int32_t field_train_slots(int32_t batch, int32_t M);
+void launch_field_train(const unsigned char* blob, const FieldGeom& g, FieldTrain t, float* grad, double* loss,
+                        hipStream_t s);
+// the same for M networks at once (see FieldNets; t.key0 is xored with the network):
+// grad [M][kFieldParams], loss [M], slots field_train_slots(batch, M) per network
+void launch_field_train_nets(const unsigned char* blob, const FieldNets& nets, int32_t M, FieldTrain t, float* grad,
+                             double* loss, hipStream_t s);
 void launch_field_adam(float* master, float* m, float* v, float* grad, int64_t count, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t s);
 // held-out split and per-mesh error sums
@@ -305,5 +345,15 @@ void launch_gather_points(const float* pos, const int32_t* tri, const int32_t* m
 void launch_scatter_fallback(const float* rho, const int32_t* gidx, int64_t m, const float* norm, float* out,
                              hipStream_t s);
 void launch_used_flags(const uint32_t* need, int64_t q, uint8_t* used, hipStream_t s);
+
+// true when the mesh bounds a solid: closed, consistently wound, outward (host)
+bool mesh_is_closed(const float* V, int64_t nv, const int32_t* I, int64_t T);
+// Per sorted point, the data of the back-face rule (see DensityLaunch::bface): normal of
+// its own triangle and the triangles of its mesh whose boxes come within rmax of it,
+// found by a packet walk of the scene BVH (plain node copy `nodes`, record copy `tris`
+// in x, y, z order).  closed [M] (device): meshes the rule may use.
+void launch_backface_prep(const float4* spos, const int32_t* smesh, int64_t n, const float* V, const int32_t* I,
+                          const uint8_t* closed, const BvhNode* nodes, const BvhTri* tris, float rmax,
+                          float4* bface, int32_t* bcand, hipStream_t s);
 
 }  // namespace gm

@@ -63,6 +63,19 @@ __device__ __forceinline__ BvhTri load_tri(const BvhTri* base, int i)
     return t;
 }
 
+// the same record at a lane-dependent index (vector loads)
+__device__ __forceinline__ BvhTri load_tri_v(const BvhTri* base, int i)
+{
+    const float4* q = reinterpret_cast<const float4*>(base + i);
+    const float4 a = q[0], b = q[1], c = q[2];
+    BvhTri t;
+    t.v0[0] = a.x; t.v0[1] = a.y; t.v0[2] = a.z;
+    t.v1[0] = a.w; t.v1[1] = b.x; t.v1[2] = b.y;
+    t.v2[0] = b.z; t.v2[1] = b.w; t.v2[2] = c.x;
+    t.id = __float_as_int(c.y); t.mesh = __float_as_int(c.z); t.pad = 0;
+    return t;
+}
+
 __device__ __forceinline__ FixRec load_fix(const FixRec* base, int i)
 {
     const CVec4Ptr q = (CVec4Ptr)(base + i);
@@ -127,15 +140,25 @@ __device__ __forceinline__ float pair_value(float x, float y, float z, float ex,
 }
 
 // ---------------------------------------------------------------------------
-// packet visibility: every active lane holds one segment eye -> its point
+// packet visibility: every active lane holds one segment between its point and the
+// wave's eye
 // ---------------------------------------------------------------------------
+// A visibility segment starts at the surface point x (t = 0) and ends at the eye e
+// (t = 1): t = 1 - tau in the parameter tau of the segment e + tau (x - e), so a
+// triangle occludes when it crosses at kEpsV < t < 1.  Starting at the point keeps
+// the triangles near it (the ones a segment grazes when the eye sees the point almost
+// edge-on) in coordinates of their own small size: vertices relative to the eye carry
+// FP32 rounding of ~1e-7 of the eye distance, which the shear amplifies by the inverse
+// incidence cosine at grazing incidence.
 struct Seg {
     float ix, iy, iz;  // 1 / direction (finite)
-    float qx, qy, qz;  // -eye / direction
+    float qx, qy, qz;  // -x / direction
     float sx, sy;      // watertight shear: d[kx] / d[kz], d[ky] / d[kz]
-    float tz;          // tmax * d[kz]
+    float tz;          // d[kz]
     int kx, ky, kz;    // axis order of the shear
 };
+
+constexpr float kTlo = (float)kEpsV;  // t of the segment's point end at which occluders start
 
 __device__ __forceinline__ float safe_inv(float d)
 {
@@ -159,21 +182,45 @@ __device__ __forceinline__ void axis_order(float dx, float dy, float dz, int& kx
     }
 }
 
-// Segment eye -> point, sheared along the given axis order.  The box-test constants
-// (ix .. qz) measure the segment in units of its end bound, t' = t / tmax, so that
-// the slab test of box_hit_signed01 / box_hit01 can clamp to [0, 1].
-__device__ __forceinline__ Seg make_seg(float ex, float ey, float ez, float px, float py, float pz, int kx, int ky,
-                                        int kz, float tmax)
+// The other two axes after kz in cyclic order.  The segment test counts both
+// windings, so the order need not follow the sign of d[kz].
+__device__ __forceinline__ void cyclic_axes(int kz, int& kx, int& ky)
+{
+    kx = kz == 2 ? 0 : kz + 1;
+    ky = kx == 2 ? 0 : kx + 1;
+}
+
+__device__ __forceinline__ int dominant_axis(float dx, float dy, float dz)
+{
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    return ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+}
+
+// The shear axis of a visibility segment with direction d under a fixation whose gaze
+// has dominant axis gz: gz while d keeps at least 0.4 of its length along it (every
+// in-cone segment while the cone half-angle is below ~14 degrees), else d's own
+// dominant axis.  A lane's choice depends on its own segment only, so its arithmetic
+// does not depend on the other segments of its packet.
+__device__ __forceinline__ int segment_axis(int gz, float dx, float dy, float dz)
+{
+    const float dk = pick(gz, dx, dy, dz);
+    return dk * dk >= 0.16f * (dx * dx + dy * dy + dz * dz) ? gz : dominant_axis(dx, dy, dz);
+}
+
+// Segment from the point x (t = 0) to the eye e (t = 1), sheared along the given axis
+// order; the slab tests of box_hit_signed01 / box_hit01 clamp to [kTlo, 1].
+__device__ __forceinline__ Seg make_seg(float xx, float xy, float xz, float ex, float ey, float ez, int kx, int ky,
+                                        int kz)
 {
     Seg s;
-    const float dx = px - ex, dy = py - ey, dz = pz - ez;
-    s.ix = safe_inv(dx * tmax); s.iy = safe_inv(dy * tmax); s.iz = safe_inv(dz * tmax);
-    s.qx = -ex * s.ix; s.qy = -ey * s.iy; s.qz = -ez * s.iz;
+    const float dx = ex - xx, dy = ey - xy, dz = ez - xz;
+    s.ix = safe_inv(dx); s.iy = safe_inv(dy); s.iz = safe_inv(dz);
+    s.qx = -xx * s.ix; s.qy = -xy * s.iy; s.qz = -xz * s.iz;
     s.kx = kx; s.ky = ky; s.kz = kz;
     const float dkz = pick(kz, dx, dy, dz);
     s.sx = pick(kx, dx, dy, dz) / dkz;
     s.sy = pick(ky, dx, dy, dz) / dkz;
-    s.tz = tmax * dkz;
+    s.tz = dkz;
     return s;
 }
 
@@ -200,19 +247,18 @@ __device__ __forceinline__ bool box_hit(const Seg& s, const float* lo, const flo
     return tn <= tf;
 }
 
-// The slab tests of a segment from make_seg, whose parameter runs over [0, 1] up to its
-// end bound: entry and exit clamped to [0, 1] (the clamp is an output modifier of the
-// three-input min/max, so each costs one instruction) and a hit when the entry lies
-// strictly below the exit.  That drops boxes behind the eye and beyond the bound as
-// the unclamped test does; the strict comparison drops only boxes the segment meets
-// in a single point, and the box padding keeps every triangle hit strictly inside.
+// The slab tests of a segment from make_seg: entry and exit clamped to [kTlo, 1], the
+// part of the segment where occluders count (the clamp is a three-input median, one
+// instruction each), and a hit when the entry lies strictly below the exit.  The
+// strict comparison drops only boxes the segment meets in a single point, and the box
+// padding keeps every triangle hit strictly inside.
 __device__ __forceinline__ bool box_hit_signed01(const Seg& s, const float* near, const float* far)
 {
     const float nx = __builtin_fmaf(near[0], s.ix, s.qx), fx = __builtin_fmaf(far[0], s.ix, s.qx);
     const float ny = __builtin_fmaf(near[1], s.iy, s.qy), fy = __builtin_fmaf(far[1], s.iy, s.qy);
     const float nz = __builtin_fmaf(near[2], s.iz, s.qz), fz = __builtin_fmaf(far[2], s.iz, s.qz);
-    const float tn = __builtin_amdgcn_fmed3f(fmaxf(fmaxf(nx, ny), nz), 0.0f, 1.0f);
-    const float tf = __builtin_amdgcn_fmed3f(fminf(fminf(fx, fy), fz), 0.0f, 1.0f);
+    const float tn = __builtin_amdgcn_fmed3f(fmaxf(fmaxf(nx, ny), nz), kTlo, 1.0f);
+    const float tf = __builtin_amdgcn_fmed3f(fminf(fminf(fx, fy), fz), kTlo, 1.0f);
     return tn < tf;
 }
 
@@ -221,13 +267,14 @@ __device__ __forceinline__ bool box_hit01(const Seg& s, const float* lo, const f
     const float t0x = __builtin_fmaf(lo[0], s.ix, s.qx), t1x = __builtin_fmaf(hi[0], s.ix, s.qx);
     const float t0y = __builtin_fmaf(lo[1], s.iy, s.qy), t1y = __builtin_fmaf(hi[1], s.iy, s.qy);
     const float t0z = __builtin_fmaf(lo[2], s.iz, s.qz), t1z = __builtin_fmaf(hi[2], s.iz, s.qz);
-    const float tn = __builtin_amdgcn_fmed3f(fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z)), 0.0f, 1.0f);
-    const float tf = __builtin_amdgcn_fmed3f(fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)), 0.0f, 1.0f);
+    const float tn = __builtin_amdgcn_fmed3f(fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z)), kTlo, 1.0f);
+    const float tf = __builtin_amdgcn_fmed3f(fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)), kTlo, 1.0f);
     return tn < tf;
 }
 
-// Triangle vertices relative to the eye, in the axis order of the record copy the
-// wave reads (the eye is passed in that same order).
+// Triangle vertices relative to a segment's start (a ray's eye, or a visibility
+// segment's point), in the axis order of the record copy the wave reads (the start is
+// passed in that same order).
 struct TriEye {
     float ax, ay, az, bx, by, bz, cx, cy, cz;
 };
@@ -244,7 +291,7 @@ __device__ __forceinline__ TriEye tri_eye(const BvhTri& t, float e0, float e1, f
 // Watertight segment/triangle test (Woop, Benthin and Wald, JCGT 2013): shear the
 // triangle into the segment's frame, three edge functions with inclusive edges,
 // FP64 re-evaluation when an edge function is exactly zero; hit when the
-// parameter tau = T/det lies in (0, tmax).  Returns the wave mask of the lanes of
+// parameter t = T/det lies in (kTlo, 1).  Returns the wave mask of the lanes of
 // `amask` (the lanes testing) that hit.  With UNI the vertices are already in
 // the segment's axis order; otherwise they are in x, y, z order and each lane
 // permutes them.  Both windings count, so the order of kx and ky does not matter.
@@ -290,12 +337,13 @@ __device__ __forceinline__ uint64_t seg_tri(const Seg& s, const TriEye& u, uint6
         hi = fmaxf(fmaxf(U, V), W);
     }
     const float det = U + V + W;
-    // tau = T' / (det d[kz]) with T' = U akz + V bkz + W ckz: scale T' by the sign of
-    // det d[kz] so the range test reads 0 < T' < tmax |d[kz]| |det|
+    // t = T' / (det d[kz]) with T' = U akz + V bkz + W ckz: scale T' by the sign of
+    // det d[kz] so the range test reads kTlo |d[kz]| |det| < T' < |d[kz]| |det|
     const float Tp = __builtin_fmaf(W, ckz, __builtin_fmaf(V, bkz, U * akz));
     const float Ts = __uint_as_float(__float_as_uint(Tp) ^ ((__float_as_uint(det) ^ __float_as_uint(s.tz)) & 0x80000000u));
+    const float lim = fabsf(s.tz) * fabsf(det);
     const uint64_t mixed = ballot(lo < 0.0f) & ballot(hi > 0.0f);
-    return amask & ~mixed & ballot(det != 0.0f) & ballot(Ts > 0.0f) & ballot(Ts < fabsf(s.tz) * fabsf(det));
+    return amask & ~mixed & ballot(det != 0.0f) & ballot(Ts > kTlo * lim) & ballot(Ts < lim);
 }
 
 // Work of packet traversals (wave level): node visits, triangle tests (one per
@@ -305,20 +353,21 @@ struct TravCount {
 };
 
 // Packet visibility.  Every lane carries up to R segments (R sample slots of the
-// wave), all starting at the wave's eye; `active[r]` marks the segments to test and
+// wave), all ending at the wave's eye; `active[r]` marks the segments to test and
 // occ[r] receives the answer.  One traversal serves all R * 64 segments: the node
 // index is wave-uniform (scalar loads), each lane tests its own segments against both
-// child boxes, children are visited near first (by the node's split axis and the
-// packet's direction octant `oct`) and the stack is one VGPR, lane i holding entry i.
-// Per-lane predicates are kept as 64-bit wave masks (scalar registers) rather than
-// per-lane booleans.
-// `tris` is the record copy whose axis order matches (e0, e1, e2), the eye in that
-// order: with UNI the packet's shared order, otherwise copy 2 (x, y, z).  With UNI
-// the packet's segments also share their direction signs and `nodes` is the node
-// copy of that octant; otherwise the plain copy.
+// child boxes, children are visited eye side first (by the node's split axis and the
+// octant `oct` of the eye-to-point directions) and the stack is one VGPR, lane i
+// holding entry i.  Per-lane predicates are kept as 64-bit wave masks (scalar
+// registers) rather than per-lane booleans.
+// `tris` is the record copy whose axis order matches the segments' start points
+// `org[r]` (each lane's point, passed in that order): with UNI the packet's shared
+// order, otherwise copy 2 (x, y, z) and each lane permutes.  With UNI the packet's
+// segments also share their direction signs and `nodes` is the node copy of the
+// octant of their (point-to-eye) directions; otherwise the plain copy.
 template <int R, bool UNI>
-__device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris, float e0,
-                                float e1, float e2, int oct, const Seg (&sg)[R],
+__device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris,
+                                const float (&org)[R][3], int oct, const Seg (&sg)[R],
                                 const int (&own_tri)[R], const int (&own_mesh)[R], int mode,
                                 const bool (&active)[R], bool (&occ)[R], TravCount& visits)
 {
@@ -391,11 +440,10 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
                     }
                     if (tany == 0) continue;
                     ++visits.tests;
-                    const TriEye u = tri_eye(tr[k], e0, e1, e2);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         if (tm[r] == 0) continue;
-                        hit[r] |= seg_tri<UNI>(sg[r], u, tm[r]);
+                        hit[r] |= seg_tri<UNI>(sg[r], tri_eye(tr[k], org[r][0], org[r][1], org[r][2]), tm[r]);
                     }
                 }
                 alive = 0;
@@ -422,6 +470,232 @@ __device__ void occluded_packet(const BvhNode* __restrict__ nodes, const BvhTri*
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) occ[r] = __builtin_amdgcn_inverse_ballot_w64(hit[r]);
+}
+
+// ---------------------------------------------------------------------------
+// The back-face rule.  A point x on a triangle of a closed mesh M (a surface that bounds
+// a solid: winding number 0 outside, +1 across a triangle against its normal), seen from
+// an eye e outside M's bounding box with (e - x) . n < 0, has some triangle of M crossing
+// the open segment (e, x): the winding number is 0 at e and at least 1 just behind x.  If
+// no triangle of M but x's own crosses the segment's last stretch, from x to
+// y = x + kEpsV (e - x), the crossing lies between e and y, at tau < 1 - kEpsV in the
+// oracle's parameter, and the pair is occluded: no traversal is needed.  That stretch is
+// shorter than rmax (the rule is used for segments up to rmax / kEpsV long), so only
+// triangles of M within rmax of x can cross it; they are listed per point by the packet
+// walk below, and each is tested against the stretch with margins that make the test
+// answer "may cross" whenever FP32 rounding could hide a crossing.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float box_dist2(float x, float y, float z, const float* lo, const float* hi)
+{
+    const float dx = fmaxf(fmaxf(lo[0] - x, x - hi[0]), 0.0f);
+    const float dy = fmaxf(fmaxf(lo[1] - y, y - hi[1]), 0.0f);
+    const float dz = fmaxf(fmaxf(lo[2] - z, z - hi[2]), 0.0f);
+    return __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+}
+
+// The back-face data of one point per lane (points of a wave close together, as the
+// sorted points are): the unit normal of its own triangle t scaled by the point's
+// distance D to the triangle's edges (in its plane), and the record indices (plain x, y,
+// z copy) of the triangles of its mesh m, other than t, whose boxes come within rmax of
+// it, by one packet walk of the scene BVH per wave (wave-uniform node, the lane's sphere
+// against both child boxes; squared distances against rmax^2 widened by 1e-3).  cnt =
+// -1: the rule does not apply (no closed mesh, degenerate triangle, more than kBfCand
+// neighbours).  Every lane of the wave must call it.
+__device__ __forceinline__ void backface_point(float px, float py, float pz, int t, int m, bool on,
+                                               const float* __restrict__ V, const int32_t* __restrict__ I,
+                                               const uint8_t* __restrict__ closed,
+                                               const BvhNode* __restrict__ nodes, const BvhTri* __restrict__ tris,
+                                               float rmax, float& nx, float& ny, float& nz, int& cnt,
+                                               int (&cand)[kBfCand])
+{
+    const int lane = lane_id();
+    nx = ny = nz = 0.0f;
+    on = on && t >= 0 && m >= 0 && closed[m] != 0;
+    if (on) {
+        const int i0 = I[3 * t], i1 = I[3 * t + 1], i2 = I[3 * t + 2];
+        const float ax = V[3 * i0], ay = V[3 * i0 + 1], az = V[3 * i0 + 2];
+        const float ux = V[3 * i1] - ax, uy = V[3 * i1 + 1] - ay, uz = V[3 * i1 + 2] - az;
+        const float vx = V[3 * i2] - ax, vy = V[3 * i2 + 1] - ay, vz = V[3 * i2 + 2] - az;
+        nx = diff_of_products(uy, vz, uz, vy);
+        ny = diff_of_products(uz, vx, ux, vz);
+        nz = diff_of_products(ux, vy, uy, vx);
+        const float l2 = __builtin_fmaf(nx, nx, __builtin_fmaf(ny, ny, nz * nz));
+        on = l2 > 0.0f && isfinite(l2);
+        // distance to the edge opposite each vertex: its barycentric times 2 area / edge
+        // length (2 area = |n|); a point outside any edge gets 0
+        const float wx = px - ax, wy = py - ay, wz = pz - az;
+        const float c1x = diff_of_products(wy, vz, wz, vy), c1y = diff_of_products(wz, vx, wx, vz),
+                    c1z = diff_of_products(wx, vy, wy, vx);
+        const float c2x = diff_of_products(uy, wz, uz, wy), c2y = diff_of_products(uz, wx, ux, wz),
+                    c2z = diff_of_products(ux, wy, uy, wx);
+        const float a1 = __builtin_fmaf(c1x, nx, __builtin_fmaf(c1y, ny, c1z * nz));  // 2 area * |n| * b1
+        const float a2 = __builtin_fmaf(c2x, nx, __builtin_fmaf(c2y, ny, c2z * nz));  // ... * b2
+        const float a0 = l2 - a1 - a2;                                                // ... * b0
+        const float ex1 = V[3 * i2] - V[3 * i1], ey1 = V[3 * i2 + 1] - V[3 * i1 + 1], ez1 = V[3 * i2 + 2] - V[3 * i1 + 2];
+        const float e0 = sqrtf(__builtin_fmaf(ex1, ex1, __builtin_fmaf(ey1, ey1, ez1 * ez1)));  // edge opposite v0
+        const float e1 = sqrtf(__builtin_fmaf(vx, vx, __builtin_fmaf(vy, vy, vz * vz)));        // opposite v1
+        const float e2 = sqrtf(__builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz)));        // opposite v2
+        const float inv = on ? rsqrtf(l2) : 0.0f;
+        // D = min over edges of b_i |n| / e_i = a_i / (|n| e_i)
+        const float D = fminf(fminf(fmaxf(a0, 0.0f) / e0, fmaxf(a1, 0.0f) / e1), fmaxf(a2, 0.0f) / e2) * inv;
+        on = on && D > 0.0f && isfinite(D);
+        const float sc = on ? inv * D : 0.0f;
+        nx *= sc; ny *= sc; nz *= sc;
+    }
+    const float r2 = rmax * rmax * 1.001f;
+    cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kBfCand; ++j) cand[j] = 0;
+    uint64_t live = ballot(on);
+    int stack = 0, sp = 0, node = 0;
+    while (live != 0) {
+        const BvhNode nd = load_node(nodes, node);
+        const uint64_t h0 = ballot(box_dist2(px, py, pz, nd.lo0, nd.hi0) <= r2) & live;
+        const uint64_t h1 = ballot(box_dist2(px, py, pz, nd.lo1, nd.hi1) <= r2) & live;
+        int next = -1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint64_t hm = c == 0 ? h0 : h1;
+            if (hm == 0) continue;
+            const int child = c == 0 ? nd.child0 : nd.child1;
+            const int count = (c == 0 ? nd.count0 : nd.count1) & kCountMask;
+            if (child < 0) {
+                const bool in = __builtin_amdgcn_inverse_ballot_w64(hm);
+                for (int k = 0; k < count; ++k) {
+                    const int r = ~child + k;
+                    const BvhTri tr = load_tri(tris, r);
+                    if (in && tr.mesh == m && tr.id != t) {
+                        const float lo[3] = {fminf(fminf(tr.v0[0], tr.v1[0]), tr.v2[0]),
+                                             fminf(fminf(tr.v0[1], tr.v1[1]), tr.v2[1]),
+                                             fminf(fminf(tr.v0[2], tr.v1[2]), tr.v2[2])};
+                        const float hi[3] = {fmaxf(fmaxf(tr.v0[0], tr.v1[0]), tr.v2[0]),
+                                             fmaxf(fmaxf(tr.v0[1], tr.v1[1]), tr.v2[1]),
+                                             fmaxf(fmaxf(tr.v0[2], tr.v1[2]), tr.v2[2])};
+                        if (box_dist2(px, py, pz, lo, hi) <= r2) {
+#pragma unroll
+                            for (int j = 0; j < kBfCand; ++j) cand[j] = j == cnt ? r : cand[j];
+                            ++cnt;
+                        }
+                    }
+                }
+            } else if (next < 0) {
+                next = child;
+            } else {
+                stack = lane == sp ? child : stack;
+                ++sp;
+            }
+        }
+        if (next < 0) {
+            if (sp == 0) break;
+            --sp;
+            next = __builtin_amdgcn_readlane(stack, sp);
+        }
+        node = uniform(next);
+    }
+    if (!on || cnt > kBfCand) cnt = -1;
+}
+
+__global__ void __launch_bounds__(256) k_backface_prep(const float4* __restrict__ spos,
+                                                       const int32_t* __restrict__ smesh, int64_t n,
+                                                       const float* __restrict__ V, const int32_t* __restrict__ I,
+                                                       const uint8_t* __restrict__ closed,
+                                                       const BvhNode* __restrict__ nodes,
+                                                       const BvhTri* __restrict__ tris, float rmax,
+                                                       float4* __restrict__ bface, int32_t* __restrict__ bcand)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float4 p = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+    int m = -1;
+    if (i < n) {
+        p = spos[i];
+        m = smesh[i];
+    }
+    float nx, ny, nz;
+    int cnt, cand[kBfCand];
+    backface_point(p.x, p.y, p.z, __float_as_int(p.w), m, i < n, V, I, closed, nodes, tris, rmax, nx, ny, nz, cnt,
+                   cand);
+    if (i < n) {
+        bface[i] = make_float4(nx, ny, nz, __int_as_float(cnt));
+#pragma unroll
+        for (int j = 0; j < kBfCand; ++j)
+            if (j < cnt) bcand[kBfCand * i + j] = cand[j];
+    }
+}
+
+// May the stretch x + t (e - x), 0 <= t <= kEpsV, of a segment cross the triangle (v0,
+// v1, v2) (x, y, z order)?  Watertight shear with x as origin, then "no" only when FP32
+// rounding cannot explain the answer: some edge function clearly negative and another
+// clearly positive (beyond 1e-4 of their magnitudes), or a parameter clearly outside
+// [0, kEpsV] (beyond 1e-3 of kEpsV); a triangle nearly parallel to the segment may cross.
+__device__ __forceinline__ bool stretch_may_cross(float xx, float xy, float xz, float ux, float uy, float uz,
+                                                  const BvhTri& tr)
+{
+    const int kz = dominant_axis(ux, uy, uz);
+    int kx, ky;
+    cyclic_axes(kz, kx, ky);
+    const float dkz = pick(kz, ux, uy, uz);
+    const float sx = pick(kx, ux, uy, uz) / dkz, sy = pick(ky, ux, uy, uz) / dkz;
+    const float o[3] = {xx, xy, xz};
+    float X[3], Y[3], Z[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const float* q = v == 0 ? tr.v0 : (v == 1 ? tr.v1 : tr.v2);
+        const float a = q[0] - o[0], b = q[1] - o[1], c = q[2] - o[2];
+        const float ak = pick(kx, a, b, c), bk = pick(ky, a, b, c), ck = pick(kz, a, b, c);
+        X[v] = __builtin_fmaf(-sx, ck, ak);
+        Y[v] = __builtin_fmaf(-sy, ck, bk);
+        Z[v] = ck;
+    }
+    const float U = X[2] * Y[1] - Y[2] * X[1];
+    const float W1 = X[0] * Y[2] - Y[0] * X[2];
+    const float W2 = X[1] * Y[0] - Y[1] * X[0];
+    const float mag = fabsf(U) + fabsf(W1) + fabsf(W2);
+    const float tol = 1e-4f * mag;
+    const bool neg = fminf(fminf(U, W1), W2) < -tol, pos = fmaxf(fmaxf(U, W1), W2) > tol;
+    if (neg && pos) return false;
+    const float det = U + W1 + W2;
+    if (!(fabsf(det) > 1e-5f * mag)) return true;
+    const float T = __builtin_fmaf(W2, Z[2], __builtin_fmaf(W1, Z[1], U * Z[0]));
+    const float tp = T / (det * dkz);
+    return tp >= -1e-3f * kTlo && tp <= kTlo * 1.001f;
+}
+
+// The rule for the point x with back-face data (normal n scaled by the point's distance
+// D to its triangle's edges, cnt neighbours cand[]) and eye e: true when the pair is
+// occluded by the point's own closed mesh, whose bounding box is (lo, hi), without a
+// traversal; segments longer than sqrt(l2max) are left to it.  The point is the FP32
+// rounding of a point of its triangle and may lie off the plane by eta = 2^-24 (|x| + |y|
+// + |z|); the segment then meets the plane within eta / c of x (c the cosine to the
+// inward normal), inside the triangle while c D >= 4 eta, which the rule requires: so
+// the segment does enter the solid through the triangle (or starts inside it).
+template <class Cand>
+__device__ __forceinline__ bool backface_rule(float nx, float ny, float nz, int cnt, const Cand& cand, float xx,
+                                              float xy, float xz, float ex, float ey, float ez, float4 lo, float4 hi,
+                                              float l2max, const BvhTri* __restrict__ tris)
+{
+    if (cnt < 0) return false;
+    const float ux = ex - xx, uy = ey - xy, uz = ez - xz;
+    const float l2 = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+    const float dn = __builtin_fmaf(nx, ux, __builtin_fmaf(ny, uy, nz * uz));  // -c D |u|
+    const float eta = 5.9604645e-8f * (fabsf(xx) + fabsf(xy) + fabsf(xz));
+    if (!(dn < 0.0f && dn * dn >= 16.0f * eta * eta * l2 && l2 <= l2max)) return false;
+    if (!(ex < lo.x || ex > hi.x || ey < lo.y || ey > hi.y || ez < lo.z || ez > hi.z)) return false;
+    for (int j = 0; j < cnt; ++j)
+        if (stretch_may_cross(xx, xy, xz, ux, uy, uz, load_tri_v(tris, cand(j)))) return false;
+    return true;
+}
+
+// the rule for point i of a density launch (sorted order)
+__device__ __forceinline__ bool backface_occluded(const DensityLaunch& a, int64_t i, float xx, float xy, float xz,
+                                                  float ex, float ey, float ez)
+{
+    const float4 bf = a.bface[i];
+    const int c = __float_as_int(bf.w);
+    if (c < 0) return false;
+    const int m = a.smesh[i];
+    const int32_t* cand = a.bcand + kBfCand * i;
+    return backface_rule(bf.x, bf.y, bf.z, c, [cand](int j) { return cand[j]; }, xx, xy, xz, ex, ey, ez,
+                         a.mbox[2 * m], a.mbox[2 * m + 1], a.bf_L2max, a.bf_tris);
 }
 
 // Ray e + t d in the same sheared form as a segment with tmax = 1 (so s.tz = d[kz]).
@@ -966,34 +1240,33 @@ __global__ void k_scatter(const float* __restrict__ pos, const int32_t* __restri
 // a5 + a6: gate, exact value, visibility, fixed-point accumulation
 // ---------------------------------------------------------------------------
 // Visibility of the wave's slots that need it, for one fixation, in one frame: the
-// segments run from the eye (ex, ey, ez) to the points p[k], both in the frame of the
-// BVH whose octant node copies start at `nodes` (node_stride nodes apart) and whose
-// axis-permuted record copies start at `tris` (tri_stride records apart); only the
-// gaze's dominant axis is used.
+// segments run between the points p[k] and the eye (ex, ey, ez), both in the frame of
+// the BVH whose octant node copies start at `nodes` (node_stride nodes apart) and
+// whose axis-permuted record copies start at `tris` (tri_stride records apart).
 template <int SPL>
 __device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ nodes, int64_t node_stride,
                                                   const BvhTri* __restrict__ tris, int64_t tri_stride, float ex,
                                                   float ey, float ez, float rx, float ry, float rz,
                                                   const float4 (&p)[SPL], const int (&otri)[SPL],
-                                                  const int (&omesh)[SPL], int mode, float tmax,
-                                                  const bool (&need)[SPL], bool (&occl)[SPL], TravCount& n_visits)
+                                                  const int (&omesh)[SPL], int mode, const bool (&need)[SPL],
+                                                  bool (&occl)[SPL], TravCount& n_visits)
 {
-    // The packet shares the axis order of the gaze's dominant axis when every
-    // segment keeps at least 0.4 of its length along that axis (true for every
-    // in-cone segment while the cone half-angle stays under ~14 degrees); it
-    // then reads the record copy already permuted into that order.
-    const float agx = fabsf(rx), agy = fabsf(ry), agz = fabsf(rz);
-    const int kz = uniform(agx > agy ? (agx > agz ? 0 : 2) : (agy > agz ? 1 : 2));
-    const int kx = kz == 2 ? 0 : kz + 1;
-    const int ky = kx == 2 ? 0 : kx + 1;
+    // Every lane shears along segment_axis: the gaze's dominant axis for every in-cone
+    // segment at the cone angles in use.  When all of the packet's segments take it and
+    // share their direction signs, the packet reads the record copy permuted into that
+    // order and the node copy of its octant (no per-lane permutation or min/max).
+    const int gz = uniform(dominant_axis(rx, ry, rz));
+    int gx, gy;
+    cyclic_axes(gz, gx, gy);
     bool shared = true;
-    // per axis: lanes with a segment (any slot) running towards -axis / +axis
+    // per axis: lanes with a segment (any slot) running from the eye towards -axis / +axis
     uint64_t nx_m = 0, ny_m = 0, nz_m = 0, px_m = 0, py_m = 0, pz_m = 0;
+    int kz[SPL];
 #pragma unroll
     for (int k = 0; k < SPL; ++k) {
         const float dx = p[k].x - ex, dy = p[k].y - ey, dz = p[k].z - ez;
-        const float dk = pick(kz, dx, dy, dz);
-        shared = shared && (!need[k] || dk * dk >= 0.16f * (dx * dx + dy * dy + dz * dz));
+        kz[k] = segment_axis(gz, dx, dy, dz);
+        shared = shared && (!need[k] || kz[k] == gz);
         nx_m |= ballot(need[k] && signbit(dx));
         ny_m |= ballot(need[k] && signbit(dy));
         nz_m |= ballot(need[k] && signbit(dz));
@@ -1005,25 +1278,32 @@ __device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ no
     shared = ballot(!shared) == 0 && (nx_m == 0 || px_m == 0) && (ny_m == 0 || py_m == 0) &&
              (nz_m == 0 || pz_m == 0);
     Seg sg[SPL];
+    float org[SPL][3];
     if (shared) {
 #pragma unroll
-        for (int k = 0; k < SPL; ++k) sg[k] = make_seg(ex, ey, ez, p[k].x, p[k].y, p[k].z, kx, ky, kz, tmax);
+        for (int k = 0; k < SPL; ++k) {
+            sg[k] = make_seg(p[k].x, p[k].y, p[k].z, ex, ey, ez, gx, gy, gz);
+            org[k][0] = pick(gx, p[k].x, p[k].y, p[k].z);
+            org[k][1] = pick(gy, p[k].x, p[k].y, p[k].z);
+            org[k][2] = pick(gz, p[k].x, p[k].y, p[k].z);
+        }
+        // eye-to-point octant (child order); the segments run the other way (node copy)
         const int oct = (nx_m != 0 ? 1 : 0) | (ny_m != 0 ? 2 : 0) | (nz_m != 0 ? 4 : 0);
-        occluded_packet<SPL, true>(nodes + oct * node_stride, tris + kz * tri_stride, pick(kx, ex, ey, ez),
-                                   pick(ky, ex, ey, ez), pick(kz, ex, ey, ez), oct, sg, otri, omesh, mode, need,
-                                   occl, n_visits);
+        occluded_packet<SPL, true>(nodes + (oct ^ 7) * node_stride, tris + gz * tri_stride, org, oct, sg, otri,
+                                   omesh, mode, need, occl, n_visits);
     } else {
 #pragma unroll
         for (int k = 0; k < SPL; ++k) {
-            int lx, ly, lz;
-            axis_order(p[k].x - ex, p[k].y - ey, p[k].z - ez, lx, ly, lz);
-            sg[k] = make_seg(ex, ey, ez, p[k].x, p[k].y, p[k].z, lx, ly, lz, tmax);
+            int lx, ly;
+            cyclic_axes(kz[k], lx, ly);
+            sg[k] = make_seg(p[k].x, p[k].y, p[k].z, ex, ey, ez, lx, ly, kz[k]);
+            org[k][0] = p[k].x; org[k][1] = p[k].y; org[k][2] = p[k].z;
         }
         // child order from one lane's octant (the order affects speed, not results)
         const int lead = __builtin_ctzll(nx_m | px_m);
         const int oct = (int)((nx_m >> lead) & 1) | (int)(((ny_m >> lead) & 1) << 1) | (int)(((nz_m >> lead) & 1) << 2);
-        occluded_packet<SPL, false>(nodes, tris + 2 * tri_stride, ex, ey, ez, oct, sg, otri, omesh, mode, need,
-                                    occl, n_visits);
+        occluded_packet<SPL, false>(nodes, tris + 2 * tri_stride, org, oct, sg, otri, omesh, mode, need, occl,
+                                    n_visits);
     }
 }
 
@@ -1089,7 +1369,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
     if (threadIdx.x == 0) s_rad = 0.0f;
     if (threadIdx.x < kDensityStats) s_stats[threadIdx.x] = 0u;
     __syncthreads();
-    uint32_t n_in = 0, n_vis = 0, n_trav = 0;  // wave-uniform counters
+    uint32_t n_in = 0, n_vis = 0, n_trav = 0, n_bf = 0;  // wave-uniform counters
     TravCount n_visits;
 
     float px[SPL], py[SPL], pz[SPL], pq[SPL];
@@ -1182,6 +1462,20 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
             bool occl[SPL];
 #pragma unroll
             for (int k = 0; k < SPL; ++k) occl[k] = false;
+            if (OCC != 0 && !INST && !ZB && a.bface && ballot(any_need) != 0) {
+                // the back-face rule first: pairs it settles leave the packet
+                any_need = false;
+#pragma unroll
+                for (int k = 0; k < SPL; ++k) {
+                    const int64_t i = wave_base + k * 64 + lane;
+                    if (need[k] && backface_occluded(a, i, p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez)) {
+                        need[k] = false;
+                        occl[k] = true;
+                    }
+                    n_bf += (uint32_t)__popcll(ballot(occl[k]));
+                    any_need = any_need || need[k];
+                }
+            }
             if (OCC != 0 && ballot(any_need) != 0) {
                 int otri[SPL], omesh[SPL];
 #pragma unroll
@@ -1191,8 +1485,12 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                     omesh[k] = need[k] ? a.smesh[i] : -1;
                 }
                 if (!INST) {
+                    // the walk answers the lanes it tests; lanes the back-face rule settled keep it
+                    bool o1[SPL];
                     packet_visibility<SPL>(a.nodes, a.node_stride, a.tris, a.tri_stride, fr.ex, fr.ey, fr.ez, fr.rx,
-                                           fr.ry, fr.rz, p, otri, omesh, a.occ_mode, kTmax, need, occl, n_visits);
+                                           fr.ry, fr.rz, p, otri, omesh, a.occ_mode, need, o1, n_visits);
+#pragma unroll
+                    for (int k = 0; k < SPL; ++k) occl[k] = occl[k] || o1[k];
                     ++n_trav;
                 } else {
                     // One BVH per mesh.  Static scenes (xf NULL): every mesh in the world
@@ -1239,7 +1537,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                         bool o2[SPL];
                         packet_visibility<SPL>(a.blas_nodes + b.node_base, b.node_count, a.blas_tris + b.tri_base,
                                                b.tri_count, fo.ex, fo.ey, fo.ez, fo.rx, fo.ry, fo.rz, q, otri, omesh,
-                                               2, kTmax, rest, o2, n_visits);
+                                               2, rest, o2, n_visits);
 #pragma unroll
                         for (int k = 0; k < SPL; ++k) occl[k] = occl[k] || o2[k];
                         ++n_trav;
@@ -1266,6 +1564,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
         atomicAdd(&s_stats[2], n_trav);
         atomicAdd(&s_stats[3], n_visits.nodes);
         atomicAdd(&s_stats[4], n_visits.tests);
+        atomicAdd(&s_stats[5], n_bf);
     }
     __syncthreads();
     if (threadIdx.x < kDensityStats && s_stats[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], (unsigned long long)s_stats[threadIdx.x]);
@@ -1371,14 +1670,19 @@ __global__ void k_pair_values(const float* __restrict__ pos, const FixRec* __res
                       cone2, kexp);
 }
 
-// one wave per pair, lane 0 active
+// one wave per pair, lane 0 active: the segment, its shear axis and its arithmetic
+// are those the density kernel gives this pair (segment_axis of the fixation's gaze,
+// or the segment's own dominant axis when `gaze` is NULL), and so is the back-face rule
+// (bf.closed non-NULL); a pair's answer does not depend on the other segments of a
+// packet.
 __global__ void __launch_bounds__(64) k_pair_visibility(const float* __restrict__ pos, const int32_t* __restrict__ tri,
                                                         const int32_t* __restrict__ mesh,
                                                         const int32_t* __restrict__ tri_mesh,
-                                                        const float* __restrict__ eye, const int32_t* __restrict__ ps,
+                                                        const float* __restrict__ eye, const float* __restrict__ gaze,
+                                                        const int32_t* __restrict__ ps,
                                                         const int32_t* __restrict__ pf, int64_t m, int64_t n_points,
                                                         int32_t n_eyes, int64_t T, const BvhNode* __restrict__ nodes,
-                                                        const BvhTri* __restrict__ tris, int mode, float tmax,
+                                                        const BvhTri* __restrict__ tris, int mode, BackfaceArgs bf,
                                                         uint8_t* __restrict__ vis)
 {
     const int64_t i = blockIdx.x;
@@ -1395,15 +1699,31 @@ __global__ void __launch_bounds__(64) k_pair_visibility(const float* __restrict_
     const int me = mesh ? mesh[s] : (t >= 0 ? tri_mesh[t] : -1);
     const float ex = eye[3 * f], ey = eye[3 * f + 1], ez = eye[3 * f + 2];
     const float px = pos[3 * s], py = pos[3 * s + 1], pz = pos[3 * s + 2];
-    int kx, ky, kz;
-    axis_order(px - ex, py - ey, pz - ez, kx, ky, kz);
-    const Seg sgs[1] = {make_seg(ex, ey, ez, px, py, pz, kx, ky, kz, tmax)};
+    const float dx = px - ex, dy = py - ey, dz = pz - ez;
+    const int kz = gaze ? segment_axis(dominant_axis(gaze[3 * f], gaze[3 * f + 1], gaze[3 * f + 2]), dx, dy, dz)
+                        : dominant_axis(dx, dy, dz);
+    int kx, ky;
+    cyclic_axes(kz, kx, ky);
+    const Seg sgs[1] = {make_seg(px, py, pz, ex, ey, ez, kx, ky, kz)};
+    const float org[1][3] = {{px, py, pz}};
     TravCount visits;
     const int ot[1] = {t}, om[1] = {me};
     const bool act[1] = {mode != 0 && lane == 0};
     bool occ[1] = {false};
-    const int oct = (signbit(px - ex) ? 1 : 0) | (signbit(py - ey) ? 2 : 0) | (signbit(pz - ez) ? 4 : 0);
-    occluded_packet<1, false>(nodes, tris, ex, ey, ez, oct, sgs, ot, om, mode, act, occ, visits);
+    const int oct = (signbit(dx) ? 1 : 0) | (signbit(dy) ? 2 : 0) | (signbit(dz) ? 4 : 0);
+    if (bf.closed && mode != 0) {
+        float nx, ny, nz;
+        int cnt, cand[kBfCand];
+        backface_point(px, py, pz, t, me, lane == 0, bf.V, bf.I, bf.closed, nodes, tris, bf.rmax, nx, ny, nz, cnt,
+                       cand);
+        if (lane == 0 && me >= 0 &&
+            backface_rule(nx, ny, nz, cnt, [&cand](int j) { return cand[j]; }, px, py, pz, ex, ey, ez,
+                          bf.mbox[2 * me], bf.mbox[2 * me + 1], bf.l2max, tris)) {
+            vis[i] = 0;
+            return;
+        }
+    }
+    occluded_packet<1, false>(nodes, tris, org, oct, sgs, ot, om, mode, act, occ, visits);
     if (lane == 0) vis[i] = occ[0] ? 0 : 1;
 }
 
@@ -1558,14 +1878,22 @@ void launch_pair_values(const float* pos, const FixRec* fix, const int32_t* ps, 
     if (m > 0) k_pair_values<<<blocks(m, 256), 256, 0, s>>>(pos, fix, ps, pf, m, n_points, F, cone2, kexp, g);
 }
 
+void launch_backface_prep(const float4* spos, const int32_t* smesh, int64_t n, const float* V, const int32_t* I,
+                          const uint8_t* closed, const BvhNode* nodes, const BvhTri* tris, float rmax,
+                          float4* bface, int32_t* bcand, hipStream_t s)
+{
+    if (n > 0)
+        k_backface_prep<<<blocks(n, 256), 256, 0, s>>>(spos, smesh, n, V, I, closed, nodes, tris, rmax, bface, bcand);
+}
+
 void launch_pair_visibility(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
-                            const float* eye, const int32_t* ps, const int32_t* pf, int64_t m, int64_t n_points,
-                            int32_t n_eyes, int64_t T, const BvhNode* nodes, const BvhTri* tris, int32_t occ_mode,
-                            float tmax, uint8_t* vis, hipStream_t s)
+                            const float* eye, const float* gaze, const int32_t* ps, const int32_t* pf, int64_t m,
+                            int64_t n_points, int32_t n_eyes, int64_t T, const BvhNode* nodes, const BvhTri* tris,
+                            int32_t occ_mode, const BackfaceArgs& bf, uint8_t* vis, hipStream_t s)
 {
     if (m > 0)
-        k_pair_visibility<<<(unsigned)m, 64, 0, s>>>(pos, tri, mesh, tri_mesh, eye, ps, pf, m, n_points, n_eyes, T,
-                                                     nodes, tris, occ_mode, tmax, vis);
+        k_pair_visibility<<<(unsigned)m, 64, 0, s>>>(pos, tri, mesh, tri_mesh, eye, gaze, ps, pf, m, n_points, n_eyes,
+                                                     T, nodes, tris, occ_mode, bf, vis);
 }
 
 }  // namespace gm

@@ -12,8 +12,11 @@
 // matrix in that order, so activations never leave registers between layers.
 // The backward pass reuses the same trick for dH = W dZ and takes the weight
 // gradients dW = H dZ^T as MFMA products over the 32 points of the wave (a
-// transpose of H and dZ through per-wave LDS tiles), accumulated with fp32
-// atomics.  Adam (Kingma and Ba 2015) keeps fp32 master weights and moments.
+// transpose of H and dZ through per-wave LDS tiles).  Each wave adds its tiles'
+// gradients, in its own tile order, into a slot of its own (plain loads and stores,
+// no atomics), and a second kernel sums the slots in slot order: the gradient, and
+// so training, is the same bit for bit on every run.  Adam (Kingma and Ba 2015)
+// keeps fp32 master weights and moments.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -220,6 +223,178 @@ __global__ void __launch_bounds__(kThreads) k_field_infer(const unsigned char* _
     }
 }
 
+// Routed inference: the points of every network are listed together (ridx, one
+// segment per mesh in mesh order, each padded with -1 to a whole number of kGroup
+// points, segment m starting at base[m]), so every network evaluates only its own
+// mesh's points, all networks in one launch.  A workgroup takes groups of kGroup
+// points (one 32-point tile per wave) and stages the weights of the group's network,
+// again only when the network changes (its groups run in mesh order).
+constexpr int kGroup = 32 * (kThreads / 64);
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__device__ __forceinline__ int group_mesh(const int64_t* __restrict__ base, int32_t M, int64_t first)
+{
+    int lo = 0, hi = M - 1;  // last m with base[m] <= first
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= first) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kThreads) k_field_infer_routed(const unsigned char* __restrict__ blobs,
+                                                                 int64_t pack_stride,
+                                                                 const FieldGeom* __restrict__ geoms,
+                                                                 const float* __restrict__ pos,
+                                                                 const int32_t* __restrict__ ridx,
+                                                                 const int64_t* __restrict__ base, int32_t M,
+                                                                 float* __restrict__ out)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char s_blob[kInfer];
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const int64_t groups = base[M] / kGroup;
+    int staged = -1;
+    FieldGeom g;
+    for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
+        const int m = group_mesh(base, M, gi * kGroup);
+        if (m != staged) {
+            __syncthreads();
+            stage(s_blob, blobs + (int64_t)m * pack_stride, kInfer);
+            __syncthreads();
+            staged = m;
+            g = geoms[m];
+        }
+        asm volatile("" ::: "memory");  // weights stay in LDS (see k_field_infer)
+        const int32_t i = ridx[gi * kGroup + 32 * wave + (lane & 31)];
+        const int64_t ii = i >= 0 ? i : 0;
+        Acts A;
+        const float o = field_forward(s_blob, g, pos[3 * ii], pos[3 * ii + 1], pos[3 * ii + 2], lane, A);
+        if (i >= 0 && lane < 32) out[i] = softplus(o);
+    }
+}
+
+// point counts of the routed meshes: the point's mesh (mesh[i], or tri_mesh[tri[i]]), when
+// it has a network and take[m] is set (NULL: every mesh)
+__device__ __forceinline__ int route_mesh(const int32_t* __restrict__ mesh, const int32_t* __restrict__ tri,
+                                          const int32_t* __restrict__ tri_mesh, int64_t T,
+                                          const uint8_t* __restrict__ take, int32_t M, int64_t i)
+{
+    int m = -1;
+    if (mesh) {
+        m = mesh[i];
+    } else if (tri) {
+        const int t = tri[i];
+        m = t >= 0 && t < T ? tri_mesh[t] : -1;
+    }
+    if (m < 0 || m >= M || (take && !take[m])) return -1;
+    return m;
+}
+
+// Lanes of a wave that route to the same mesh take their slots with one atomic: the
+// wave serves one mesh per round (the first pending lane's), so a wave of points of one
+// mesh costs one atomic however many points share it.  Returns this lane's slot among
+// the points of its mesh, counted from the value the atomic returned.
+__device__ __forceinline__ unsigned int wave_reserve(int m, unsigned int* __restrict__ ctr)
+{
+    const int lane = __lane_id();
+    uint64_t pending = __ballot(m >= 0);
+    unsigned int mine = 0u;
+    while (pending) {
+        const int lead = __builtin_ctzll(pending);
+        const int mm = __builtin_amdgcn_readlane(m, lead);
+        const uint64_t same = __ballot(m == mm) & pending;
+        unsigned int base = 0u;
+        if (lane == lead) base = atomicAdd(&ctr[mm], (unsigned int)__popcll(same));
+        base = __builtin_amdgcn_readlane(base, lead);
+        if ((same >> lane) & 1ull) mine = base + (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
+        pending &= ~same;
+    }
+    return mine;
+}
+
+// Routing works on chunks of kRouteChunk points per workgroup: the chunk's per-mesh
+// counts are gathered in LDS (one LDS atomic per wave and mesh) and added to the global
+// ones with one atomic per mesh, so a few hundred global atomics route millions of points.
+constexpr int kRouteChunk = 16 * kThreads;
+constexpr int kRouteLds = 1024;  // meshes counted in LDS (more: one global atomic per wave and mesh)
+
+__global__ void __launch_bounds__(kThreads) k_route_count(const int32_t* __restrict__ mesh,
+                                                          const int32_t* __restrict__ tri,
+                                                          const int32_t* __restrict__ tri_mesh, int64_t T,
+                                                          const uint8_t* __restrict__ take, int32_t M, int64_t q,
+                                                          unsigned int* __restrict__ cnt)
+{
+    __shared__ unsigned int lc[kRouteLds];
+    const bool lds = M <= kRouteLds;
+    for (int m = threadIdx.x; lds && m < M; m += kThreads) lc[m] = 0u;
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * kRouteChunk;
+#pragma unroll 4
+    for (int j = 0; j < kRouteChunk / kThreads; ++j) {
+        const int64_t i = c0 + j * kThreads + threadIdx.x;
+        const int m = i < q ? route_mesh(mesh, tri, tri_mesh, T, take, M, i) : -1;
+        (void)wave_reserve(m, lds ? lc : cnt);
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; lds && m < M; m += kThreads)
+        if (lc[m]) atomicAdd(&cnt[m], lc[m]);
+}
+
+// one thread: padded segment starts, and the per-mesh cursors cleared
+__global__ void k_route_base(unsigned int* __restrict__ cnt, int32_t M, int64_t* __restrict__ base)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t run = 0;
+    for (int m = 0; m < M; ++m) {
+        base[m] = run;
+        run += ((int64_t)cnt[m] + kGroup - 1) / kGroup * kGroup;
+        cnt[m] = 0u;
+    }
+    base[M] = run;
+}
+
+__global__ void __launch_bounds__(kThreads) k_route_scatter(const int32_t* __restrict__ mesh,
+                                                            const int32_t* __restrict__ tri,
+                                                            const int32_t* __restrict__ tri_mesh, int64_t T,
+                                                            const uint8_t* __restrict__ take, int32_t M, int64_t q,
+                                                            const int64_t* __restrict__ base,
+                                                            unsigned int* __restrict__ cur,
+                                                            int32_t* __restrict__ ridx)
+{
+    constexpr int kPer = kRouteChunk / kThreads;
+    __shared__ unsigned int lc[kRouteLds];
+    const bool lds = M <= kRouteLds;
+    for (int m = threadIdx.x; lds && m < M; m += kThreads) lc[m] = 0u;
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * kRouteChunk;
+    int mm[kPer];
+    unsigned int rank[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = c0 + j * kThreads + threadIdx.x;
+        mm[j] = i < q ? route_mesh(mesh, tri, tri_mesh, T, take, M, i) : -1;
+        rank[j] = wave_reserve(mm[j], lds ? lc : cur);  // rank in the chunk (LDS) or the mesh (global)
+    }
+    __syncthreads();
+    // the chunk's range of each mesh: one global atomic per mesh
+    for (int m = threadIdx.x; lds && m < M; m += kThreads)
+        lc[m] = lc[m] ? atomicAdd(&cur[m], lc[m]) : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = c0 + j * kThreads + threadIdx.x;
+        if (mm[j] >= 0) ridx[base[mm[j]] + (lds ? lc[mm[j]] : 0u) + rank[j]] = (int32_t)i;
+    }
+}
+
+// a wave's gradient slot: its first tile writes, the later ones add (one lane per entry)
+__device__ __forceinline__ void put(float* p, float v, bool first) { *p = first ? v : *p + v; }
+
 __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* __restrict__ blob, FieldGeom g,
                                                           FieldTrain t, FieldNets nets)
 {
@@ -233,8 +408,8 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
         t.idx += nets.off[m];
         t.n_idx = c;
         t.key0 ^= (uint32_t)m;
-        t.grad += (int64_t)m * kFieldParams;
-        t.loss += m;
+        t.gpart += (int64_t)m * t.slots * kFieldParams;
+        t.lpart += (int64_t)m * t.slots;
     }
     __shared__ __attribute__((aligned(16))) unsigned char s_blob[kPack];
     __shared__ __attribute__((aligned(16))) __bf16 s_dz[kThreads / 64][kW][kTileStride];
@@ -247,9 +422,13 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
     const int tiles = (t.batch + 31) / 32;
     for (int tile = blockIdx.x * (kThreads / 64) + wave; tile < tiles; tile += gridDim.x * (kThreads / 64)) {
         asm volatile("" ::: "memory");  // weights stay in LDS (see k_field_infer)
-        // fresh copy of the gradient base each tile: otherwise the ~300 lane-dependent
-        // atomic addresses below are hoisted out of the loop and spilled
-        float* grad = t.grad;
+        // this wave's gradient slot (blockIdx.x * waves + wave < t.slots), written by its
+        // first tile and added to by the later ones; a fresh copy of the base each tile:
+        // otherwise the ~300 lane-dependent addresses below are hoisted out of the loop
+        // and spilled
+        const int slot = __builtin_amdgcn_readfirstlane(blockIdx.x * (kThreads / 64) + wave);
+        const bool first = tile == slot;
+        float* grad = t.gpart + (int64_t)slot * kFieldParams;
         asm volatile("" : "+s"(grad));
         const int j = tile * 32 + n;
         const bool ok = j < t.batch;
@@ -272,8 +451,8 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
             sb += __shfl_xor(sb, d, 64);
         }
         if (lane == 0) {
-            atomicAdd(t.loss, (double)se);
-            atomicAdd(&grad[kFieldOffB5], sb);
+            t.lpart[slot] = first ? (double)se : t.lpart[slot] + (double)se;
+            put(&grad[kFieldOffB5], sb, first);
         }
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
@@ -282,7 +461,7 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
                 float gw = (float)A.h[3][ks][jj] * dO;
 #pragma unroll
                 for (int d = 1; d < 32; d <<= 1) gw += __shfl_xor(gw, d, 64);
-                if (n == 0) atomicAdd(&grad[kFieldOffW5 + 16 * ks + slot_feature(8 * h + jj)], gw);
+                if (n == 0) put(&grad[kFieldOffW5 + 16 * ks + slot_feature(8 * h + jj)], gw, first);
             }
         asm volatile("" ::: "memory");
         // dZ of layer 4 in the accumulator layout
@@ -334,14 +513,14 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
                     const int krow = L == 1 ? input_feature(nb * 32 + n) : nb * 32 + n;
                     float* gW = grad + kFieldOffW[L] + krow * kW + mb * 32 + 4 * h;
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) atomicAdd(gW + 8 * (v >> 2) + (v & 3), c[v]);
+                    for (int v = 0; v < 16; ++v) put(gW + 8 * (v >> 2) + (v & 3), c[v], first);
                 }
             // bias gradient: row sums of dZ (lane = output feature)
             {
                 float sbias = 0.0f;
 #pragma unroll
                 for (int p = 0; p < 32; ++p) sbias += (float)s_dz[wave][lane][p];
-                atomicAdd(&grad[kFieldOffB[L] + lane], sbias);
+                put(&grad[kFieldOffB[L] + lane], sbias, first);
             }
             if (L >= 2) {
                 const unsigned char* Bm = s_blob + kOffB2 + (L - 2) * kMatH;
@@ -358,6 +537,28 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
                 }
             }
         }
+    }
+}
+
+// grad[net][p] = sum of the first `used` slots of network net in slot order; loss[net]
+// likewise (networks with no training points: cnt[net] == 0, nothing written, 0)
+__global__ void k_field_grad_reduce(const float* __restrict__ gpart, const double* __restrict__ lpart, int32_t used,
+                                    int32_t slots, int32_t M, const int64_t* __restrict__ cnt,
+                                    float* __restrict__ grad, double* __restrict__ loss)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= (int64_t)M * kFieldParams) return;
+    const int net = (int)(i / kFieldParams);
+    const int p = (int)(i % kFieldParams);
+    const bool live = !cnt || cnt[net] > 0;
+    const float* src = gpart + (int64_t)net * slots * kFieldParams + p;
+    float sum = 0.0f;
+    for (int w = 0; live && w < used; ++w) sum += src[(int64_t)w * kFieldParams];
+    grad[i] = sum;
+    if (p == 0) {
+        double l = 0.0;
+        for (int w = 0; live && w < used; ++w) l += lpart[(int64_t)net * slots + w];
+        loss[net] = l;
     }
 }
 
@@ -484,26 +685,62 @@ void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const flo
     k_field_infer<<<grid, kThreads, 0, s>>>(blob, g, pos, q, out, route);
 }
 
+int64_t field_route_slots(int64_t q, int32_t M) { return q + (int64_t)kGroup * M; }
+
+void launch_field_infer_routed(const unsigned char* blobs, int64_t pack_stride, const FieldGeom* geoms,
+                               const float* pos, int64_t q, float* out, const FieldRoute& route,
+                               const uint8_t* take, int32_t M, unsigned int* cnt, int64_t* base, int32_t* ridx,
+                               hipStream_t s)
+{
+    if (q <= 0 || M <= 0) return;
+    const int64_t slots = field_route_slots(q, M);
+    k_fill_i32<<<blocks(slots), kThreads, 0, s>>>(ridx, slots, -1);
+    k_fill_i32<<<blocks(M), kThreads, 0, s>>>(reinterpret_cast<int32_t*>(cnt), M, 0);
+    const unsigned chunks = (unsigned)((q + kRouteChunk - 1) / kRouteChunk);
+    k_route_count<<<chunks, kThreads, 0, s>>>(route.mesh, route.tri, route.tri_mesh, route.T, take, M, q, cnt);
+    k_route_base<<<1, 1, 0, s>>>(cnt, M, base);
+    k_route_scatter<<<chunks, kThreads, 0, s>>>(route.mesh, route.tri, route.tri_mesh, route.T, take, M, q, base,
+                                                   cnt, ridx);
+    const unsigned grid = (unsigned)std::min<int64_t>(slots / kGroup + 1, 2048);
+    k_field_infer_routed<<<grid, kThreads, 0, s>>>(blobs, pack_stride, geoms, pos, ridx, base, M, out);
+}
+
 void launch_field_select(const uint32_t* flag, const int32_t* mesh, int32_t m, int64_t n, uint32_t* sel, hipStream_t s)
 {
     if (n > 0) k_field_select<<<blocks(n), kThreads, 0, s>>>(flag, mesh, m, n, sel);
 }
 
-void launch_field_train(const unsigned char* blob, const FieldGeom& g, const FieldTrain& t, hipStream_t s)
+int32_t field_train_slots(int32_t batch, int32_t M)
+{
+    const int tiles = (batch + 31) / 32;
+    const int waves = kThreads / 64;
+    // at most ~256 MB of slots over all networks, at least one workgroup per network
+    const int64_t cap = std::max<int64_t>(1, ((int64_t)256 << 20) / ((int64_t)M * waves * kFieldParams * 4));
+    const int64_t grid = std::min<int64_t>(std::min<int64_t>((tiles + waves - 1) / waves, 1024), cap);
+    return (int32_t)(std::max<int64_t>(grid, 1) * waves);
+}
+
+void launch_field_train(const unsigned char* blob, const FieldGeom& g, FieldTrain t, float* grad, double* loss,
+                        hipStream_t s)
 {
     if (t.batch <= 0) return;
     const int tiles = (t.batch + 31) / 32;
-    const unsigned grid = (unsigned)std::min(((tiles + 3) / 4), 1024);
-    k_field_train<<<grid, kThreads, 0, s>>>(blob, g, t, FieldNets{});
+    t.slots = field_train_slots(t.batch, 1);
+    k_field_train<<<(unsigned)(t.slots / (kThreads / 64)), kThreads, 0, s>>>(blob, g, t, FieldNets{});
+    k_field_grad_reduce<<<blocks(kFieldParams), kThreads, 0, s>>>(t.gpart, t.lpart, std::min(tiles, t.slots), t.slots,
+                                                                  1, nullptr, grad, loss);
 }
 
-void launch_field_train_nets(const unsigned char* blob, const FieldNets& nets, int32_t M, const FieldTrain& t,
-                             hipStream_t s)
+void launch_field_train_nets(const unsigned char* blob, const FieldNets& nets, int32_t M, FieldTrain t, float* grad,
+                             double* loss, hipStream_t s)
 {
     if (t.batch <= 0 || M <= 0) return;
     const int tiles = (t.batch + 31) / 32;
-    const unsigned grid = (unsigned)std::min(((tiles + 3) / 4), 1024);
-    k_field_train<<<dim3(grid, (unsigned)M), kThreads, 0, s>>>(blob, FieldGeom{}, t, nets);
+    t.slots = field_train_slots(t.batch, M);
+    k_field_train<<<dim3((unsigned)(t.slots / (kThreads / 64)), (unsigned)M), kThreads, 0, s>>>(blob, FieldGeom{}, t,
+                                                                                                  nets);
+    k_field_grad_reduce<<<blocks((int64_t)M * kFieldParams), kThreads, 0, s>>>(
+        t.gpart, t.lpart, std::min(tiles, t.slots), t.slots, M, nets.cnt, grad, loss);
 }
 
 void launch_field_adam(float* master, float* m, float* v, float* grad, int64_t count, float lr, float b1, float b2,

@@ -243,6 +243,11 @@ gm_status gm_map_create(gm_scene* sc, const float* pos, const int32_t* tri, cons
     fill_u32(m->w.fx_shift.p, 1, (uint32_t)m->shift, s);
     if (!posed) {
         density_sort(sc, m->w, pos, tri, mesh, n, s);
+        st = density_backface(sc, m->w, n, m->mode, s);
+        if (st != GM_OK) {
+            delete m;
+            return st;
+        }
     } else {
         for (int32_t k = 0; k < sc->M; ++k) {
             const int64_t off = moff[(size_t)k], nk = moff[(size_t)k + 1] - off;

@@ -4,8 +4,9 @@ The tolerance has two parts: per sample, |rho_gpu - rho_oracle| <= 1e-5 rho_orac
 (B_s: the oracle's g summed over the sample's ambiguous pairs); and visibility decisions
 may disagree with the oracle on at most 1e-4 of the in-cone pairs.  A sample outside the
 first bound passes when its GPU value equals, within the first bound, the oracle's sum
-over the pairs the GPU's own visibility stage calls visible, and the disagreeing pairs of
-all checked samples together stay within the second bound."""
+over the pairs the density kernel calls visible (each pair re-tested with the kernel's
+own arithmetic for it: gm_debug_pair_visibility given the fixations' gaze), and the
+disagreeing pairs of all checked samples together stay within the second bound."""
 import numpy as np
 
 import oracle
@@ -37,7 +38,7 @@ def check(gm, scene, meshes, pos, tri, mesh, eye, gaze, dur, theta_deg, mode, go
         inc = np.where(inside)[0]
         vis_o, frag = sc.pair_visibility(pos, tri, mesh, eye, np.full(len(inc), b), inc, mode=mode)
         vis_g = scene.pair_visibility(pos_d, eye, np.full(len(inc), b, np.int32), inc.astype(np.int32),
-                                      occlusion=occ, tri=tri_d, mesh=mesh_d).cpu().numpy().astype(bool)
+                                      occlusion=occ, tri=tri_d, mesh=mesh_d, gaze=gaze).cpu().numpy().astype(bool)
         flips += int(((vis_g != vis_o) & ~frag).sum())
         rho_g = float(g[inc][vis_g].sum())
         assert abs(got[b] - rho_g) <= REL * rho_g + ref.budget[b] + 1e-30, \
@@ -45,3 +46,23 @@ def check(gm, scene, meshes, pos, tri, mesh, eye, gaze, dur, theta_deg, mode, go
         explained += 1
     assert flips <= FLIP_RATE * in_cone, f"{flips} visibility flips in {in_cone} in-cone pairs"
     return flips, in_cone, explained
+
+
+def count_flips(scene, meshes, pos, tri, mesh, eye, gaze, dur, theta_deg, mode):
+    """Visibility decisions of the density kernel (its own arithmetic for each pair) against
+    the oracle's over every in-cone pair of the given samples.  Returns (disagreements
+    outside the oracle's fragile set, disagreements inside it, in-cone pairs)."""
+    import torch
+    N, F = len(pos), len(eye)
+    ps = np.repeat(np.arange(N), F)
+    pf = np.tile(np.arange(F), N)
+    _, _, inside = oracle.pair_values(pos, eye, gaze, dur, ps, pf, theta_deg)
+    ps, pf = ps[inside], pf[inside]
+    occ = {oracle.OCC_SELF: "self", oracle.OCC_FULL: "full"}[mode]
+    vo, frag = oracle.Scene(meshes).pair_visibility(pos, tri, mesh, eye, ps, pf, mode=mode)
+    vg = scene.pair_visibility(torch.tensor(np.ascontiguousarray(pos, np.float32), device="cuda"), eye,
+                               ps.astype(np.int32), pf.astype(np.int32), occlusion=occ,
+                               tri=np.ascontiguousarray(tri, np.int32), mesh=np.ascontiguousarray(mesh, np.int32),
+                               gaze=gaze).cpu().numpy().astype(bool)
+    dis = vg != vo
+    return int((dis & ~frag).sum()), int((dis & frag).sum()), int(len(ps))

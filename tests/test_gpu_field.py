@@ -100,6 +100,44 @@ def test_adam_step_matches_oracle(gm, tiny):
     assert np.mean(np.abs(np.abs(step[moved]) - 1e-3) < 2e-6) > 0.98
 
 
+def test_adam_steps_match_oracle_step_for_step(gm):
+    """Six Adam updates with the training loop's kernel on given, changing gradients
+    (ragged count, zero and tiny gradients included), each compared with the oracle's
+    update iterated from the same start: moments carried over and bias corrections
+    taken at each step's number, to FP32 rounding."""
+    import torch
+    rng = np.random.default_rng(7)
+    n = 18753 + 5
+    b1, b2, eps = np.float32(0.9), np.float32(0.999), np.float32(1e-8)
+    p0 = rng.normal(0, 0.1, n).astype(np.float32)
+    grads = rng.normal(0, 1, (6, n)).astype(np.float32) * rng.choice([1e-4, 1.0, 30.0], (6, n)).astype(np.float32)
+    grads[:, :7] = 0.0
+    grads[2, 7:20] = 1e-9
+    lrs = np.array([3e-3, 2e-3, 1e-3, 5e-4, 1e-3, 2e-3], np.float32)
+    p = torch.tensor(p0, device="cuda")
+    m = torch.zeros(n, device="cuda")
+    v = torch.zeros(n, device="cuda")
+    rp, rm, rv = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    am = np.zeros(n)           # the first moment's running magnitude (sum of |terms|): its rounding scale
+    for k in range(6):
+        g = torch.tensor(grads[k], device="cuda")
+        gm.adam_step(p, m, v, g, k + 1, float(lrs[k]), float(b1), float(b2), float(eps))
+        g64 = grads[k].astype(np.float64)
+        rp, rm, rv = fo.adam_step(rp, rm, rv, g64, k + 1, lr=float(lrs[k]), b1=float(b1), b2=float(b2),
+                                  eps=float(eps))
+        am = float(b1) * am + (1 - float(b1)) * np.abs(g64)
+        torch.cuda.synchronize()
+        assert float(g.abs().max()) == 0.0          # the gradient is cleared after the update
+        gp, gmm, gv = (t.cpu().numpy().astype(np.float64) for t in (p, m, v))
+        assert np.all(np.abs(gmm - rm) <= 1e-6 * am), k
+        assert np.allclose(gv, rv, rtol=3e-6, atol=1e-30), k
+        # an update is at most ~3.2 lr (beta1, beta2 as here), rounded to ~1e-5 of that; the
+        # running parameter adds its own rounding each step.  A bias correction taken at
+        # another step, or moments not carried over, moves parameters by a good part of lr.
+        tol = 4e-7 * (k + 1) * np.abs(rp) + 3e-5 * float(lrs[:k + 1].sum())
+        assert np.all(np.abs(gp - rp) <= tol), (k, float(np.max(np.abs(gp - rp) - tol)))
+
+
 def test_training_reaches_gate_and_query_paths(gm, tiny):
     """Train on the tiny scene's map at ~300k samples; the held-out error gates the
     field; query_density answers by the field where the gate is open and by the plain
@@ -184,3 +222,42 @@ def test_one_network_per_mesh(gm):
     out, used = gm.query_density(f, scene, fix, 1.0, s.pos, tri=s.tri, occlusion="full")
     assert not bool(used.any())
     assert np.allclose(out.cpu().numpy(), f.predict(s.pos, mesh=s.mesh).cpu().numpy())
+
+
+def test_training_and_gradient_are_bit_reproducible(gm):
+    """Gradients are summed in a fixed order (per-wave slots, then slot order): two
+    trainings from the same start give the same weights, errors and gates bit for bit,
+    and two gradient calls the same gradient; routed inference leaves points of no mesh
+    untouched."""
+    import torch
+    sph = workloads.sphere_mesh(level=3, radius=0.4, displace=0.05, seed=3)
+    cube = workloads.cube_mesh(0.4)
+    Vc = (cube.V + np.array([1.2, 0.0, 0.3], np.float32)).astype(np.float32)
+    scene = gm.Scene([(sph.V, sph.I), (Vc, cube.I)])
+    s = scene.build_samples(30000.0, 2)
+    n = int(s.pos.shape[0])
+    tgt = torch.linspace(0.0, 1.0, n, device="cuda")
+    runs = []
+    for _ in range(2):
+        f = gm.Field(scene, seed=11)
+        info = f.train(s.pos, s.mesh, tgt, steps=120, batch=3000, lr=3e-3, lr_final=1e-4, max_rel_l2=0.5,
+                       target_max=1.0, seed=12)
+        runs.append((f.get_params(), np.asarray(info["rel_l2"]), np.asarray(info["gate"]), info["loss"]))
+        f.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+    assert runs[0][3] == runs[1][3]
+    f = gm.Field(scene, seed=13)
+    x = s.pos[:5000].cpu().numpy()
+    t = tgt[:5000].cpu().numpy()
+    g1, l1 = f.gradient(x, t, net=0)
+    g2, l2 = f.gradient(x, t, net=0)
+    assert np.array_equal(g1, g2) and l1 == l2
+    # points whose mesh id is outside [0, M) are not written
+    ids = s.mesh[:4096].clone()
+    ids[::7] = -1
+    ids[3::11] = 2
+    out = torch.full((4096,), 7.0, device="cuda")
+    f.predict(s.pos[:4096], mesh=ids, out=out)
+    keep = (ids < 0) | (ids > 1)
+    assert bool((out[keep] == 7.0).all()) and not bool((out[~keep] == 7.0).any())

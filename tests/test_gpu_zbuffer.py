@@ -127,3 +127,32 @@ def test_refused_fixations_and_arguments(gm):
     with pytest.raises(gm.GazemapError):
         scene.accumulate_zbuffer(s.pos, fix, 20.0)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("R,eps", [(128, 1e-2), (256, 1e-2), (256, 1e-3)])
+def test_paper_shaped_at_bench_resolutions(gm, R, eps):
+    """The resolutions and tolerances the benchmark reports, on the paper-shaped scene
+    (806k triangles, full occlusion), for ten fixations of its recording: z-buffers pixel by
+    pixel, and the density of 20,000 seeded samples plus the densest ones."""
+    import torch
+    w = workloads.paper_shaped_scene()
+    meshes = [(m.V, m.I) for m in w.meshes]
+    scene = gm.Scene(meshes)
+    pick_f = np.arange(0, len(w.fix.eye), 600)[:10]
+    eye, gaze, dur = w.fix.eye[pick_f], w.fix.gaze[pick_f], w.fix.dur[pick_f]
+    fix = gm.Fixations(eye, gaze, dur)
+    s = scene.build_samples(204240.0, w.seed)
+    zb = scene.render_zbuffers(fix, w.theta_deg, resolution=R).cpu().numpy()
+    got = scene.accumulate_zbuffer(s.pos, fix, w.theta_deg, resolution=R, depth_eps=eps)
+    torch.cuda.synchronize()
+    d = got.density.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(R)
+    pick = np.unique(np.concatenate([rng.choice(len(d), 20000, replace=False), np.argsort(d)[-50:]]))
+    pos = s.pos.cpu().numpy()[pick]
+    ref = oracle.density_zbuffer(oracle.Scene(meshes), pos, eye, gaze, dur, w.theta_deg, resolution=R,
+                                 eps_depth=eps)
+    assert ref.ok.all()
+    _compare_zbuffers(zb, ref)
+    ok = np.abs(d[pick] - ref.rho) <= 1e-5 * ref.rho + ref.budget + 1e-30
+    assert ok.all(), f"{(~ok).sum()} samples off"
+    assert (ref.rho > 0).sum() > 500

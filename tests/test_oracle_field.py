@@ -74,6 +74,41 @@ def test_adam_first_step_is_signed_learning_rate():
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
 
 
+def test_adam_constant_gradient_moves_by_signed_learning_rate_every_step():
+    """With a constant gradient g, the bias-corrected moments equal g and g^2 after every
+    step n (m_n = (1 - b1^n) g, v_n = (1 - b2^n) g^2), so each update is lr g / (|g| + eps)
+    and n updates move the parameters by n lr g / (|g| + eps).  Moments dropped between
+    steps, or a bias correction taken at the wrong step, break it from step 2 on."""
+    g = np.array([0.5, -2.0, 3e-4, -7.0])
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    p, m, v = np.full(4, 0.25), np.zeros(4), np.zeros(4)
+    for n in range(1, 11):
+        p, m, v = fo.adam_step(p, m, v, g, n, lr=lr, b1=b1, b2=b2, eps=eps)
+        assert np.allclose(m, (1 - b1 ** n) * g, rtol=1e-12)
+        assert np.allclose(v, (1 - b2 ** n) * g * g, rtol=1e-12)
+        assert np.allclose(p, 0.25 - n * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_two_steps_with_changing_gradients_by_hand():
+    """Two updates with gradients g1 then g2, worked out by hand: the first moves by
+    lr g1 / (|g1| + eps); the second uses m^ = (b1 g1 + g2) / (1 + b1) and
+    v^ = (b2 g1^2 + g2^2) / (1 + b2) (the moments carried over, corrected with step 2)."""
+    lr, b1, b2, eps = 0.05, 0.8, 0.95, 1e-6
+    g1 = np.array([1.0, -0.5, 2.0, 0.0])
+    g2 = np.array([-3.0, -0.5, 0.25, 1.0])
+    p0 = np.array([0.1, -0.2, 0.3, 0.4])
+    p1, m1, v1 = fo.adam_step(p0, np.zeros(4), np.zeros(4), g1, 1, lr=lr, b1=b1, b2=b2, eps=eps)
+    p2, m2, v2 = fo.adam_step(p1, m1, v1, g2, 2, lr=lr, b1=b1, b2=b2, eps=eps)
+    e1 = p0 - lr * g1 / (np.abs(g1) + eps)
+    mh = (b1 * g1 + g2) / (1 + b1)
+    vh = (b2 * g1 ** 2 + g2 ** 2) / (1 + b2)
+    e2 = e1 - lr * mh / (np.sqrt(vh) + eps)
+    assert np.allclose(p1, e1, rtol=1e-13, atol=1e-16)
+    assert np.allclose(p2, e2, rtol=1e-13, atol=1e-16)
+    # the second component: equal gradients, so the second step is the first one again
+    assert np.isclose(p2[1] - p1[1], p1[1] - p0[1], rtol=1e-12)
+
+
 def test_bf16_network_is_close_to_fp64_network():
     rng = np.random.default_rng(2)
     flat = fo.init_params(4)

@@ -173,3 +173,17 @@ def test_multi_mesh_order_and_counts():
     assert s.counts[0] == 3000
     assert np.all(s.mesh[:3000] == 0) and np.all(s.mesh[3000:] == 1)
     assert np.all(s.tri[3000:] >= len(m1.I))
+
+
+def test_sample_at_is_one_entry_of_sample_scene():
+    """sample_at draws the sample of a global index alone: the same position, scene-global
+    triangle and mesh as sample_scene's entry, across the mesh boundary and at both ends."""
+    m1 = workloads.cube_mesh(1.0)
+    m2 = workloads.sphere_mesh(level=2, radius=0.3)
+    meshes = [(m1.V, m1.I), (m2.V, m2.I)]
+    s = oracle.sample_scene(meshes, k=500.0, seed=9)
+    for i in (0, 1, 2999, 3000, 3001, len(s.tri) - 1):
+        p, t, m = oracle.sample_at(meshes, 500.0, 9, i)
+        assert np.array_equal(p, s.pos32[i]) and t == s.tri[i] and m == s.mesh[i], i
+    with pytest.raises(IndexError):
+        oracle.sample_at(meshes, 500.0, 9, len(s.tri))
