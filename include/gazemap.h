@@ -208,6 +208,25 @@ gm_status accumulate_density(gm_scene* scene, const float* pos, const int32_t* t
                              float* density_norm, float* max_out, void* stream);
 
 /*
+ * accumulate_density_noalloc -- accumulate_density for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, kernels and results (bit for bit) as
+ * accumulate_density; its intermediate buffers live in one fixed device array of
+ * gm_noalloc_scratch_bytes() bytes per device, held until the process ends, so it
+ * calls no device allocation.  Limits: n <= GM_NOALLOC_MAX_POINTS points and
+ * fix->n <= GM_NOALLOC_MAX_FIXATIONS fixations, else GM_ERR_CAPACITY with nothing
+ * queued.  All calls on one device share that array: calls that overlap on one
+ * device (different streams or threads) race; serialise them.  Queued on `stream`.
+ */
+#define GM_NOALLOC_MAX_POINTS 524288
+#define GM_NOALLOC_MAX_FIXATIONS 65536
+gm_status accumulate_density_noalloc(gm_scene* scene, const float* pos, const int32_t* tri,
+                                     const int32_t* mesh, int64_t n, const gm_fixations* fix,
+                                     double theta_deg, uint32_t flags, float* density,
+                                     float* density_norm, float* max_out, void* stream);
+int64_t gm_noalloc_scratch_bytes(void);
+
+/*
  * Stage-isolated checks (same device code as accumulate_density), for tests.
  * gm_debug_pair_values: for m pairs (pair_s[i], pair_f[i]) (device int32) of the
  *   n_points points pos [n_points][3] and the fixations, g_out[i] (device float) = g

@@ -21,6 +21,10 @@ GM_OK = 0
 STATUS = {0: "GM_OK", -1: "GM_ERR_INVALID_ARGUMENT", -2: "GM_ERR_OUT_OF_MEMORY", -3: "GM_ERR_DEVICE",
           -4: "GM_ERR_CAPACITY", -5: "GM_ERR_NOT_READY", -99: "GM_ERR_INTERNAL"}
 OCC = {"none": 0, "self": 1, "full": 2}
+GM_ERR_CAPACITY = -4
+# limits of accumulate_density_noalloc (include/gazemap.h)
+NOALLOC_MAX_POINTS = 524288
+NOALLOC_MAX_FIXATIONS = 65536
 
 # exported symbols of include/gazemap.h
 SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy", "gm_scene_info",
@@ -33,7 +37,7 @@ SYMBOLS = ("gm_last_error", "gm_version", "gm_scene_create", "gm_scene_destroy",
            "gm_map_create", "gm_map_add", "gm_map_add_posed", "gm_map_read", "gm_map_reset", "gm_map_info",
            "gm_map_destroy", "gm_export_samples", "gm_render_zbuffers", "accumulate_density_zbuffer",
            "gm_density_counters", "gm_debug_adam_step", "gm_scene_mesh_closed", "gm_scene_set_mesh_closed",
-           "gm_mesh_closed")
+           "gm_mesh_closed", "accumulate_density_noalloc")
 GM_MAP_POSED = 4
 
 # one exported sample (gm_export_record), 48 bytes
@@ -122,6 +126,10 @@ def load_library(path: str = LIB_PATH):
     lib.gm_field_gradient.argtypes = [vp, i32, vp, vp, i64, f32p, ctypes.POINTER(dbl)]
     lib.gm_field_predict.argtypes = [vp, vp, vp, i64, vp, vp]
     f32 = ctypes.c_float
+    lib.accumulate_density_noalloc.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(_Fix), dbl, u32, vp, vp, vp,
+                                               vp]
+    lib.gm_noalloc_scratch_bytes.restype = i64
+    lib.gm_noalloc_scratch_bytes.argtypes = []
     lib.gm_debug_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp]
     lib.gm_batch_create.argtypes = [ctypes.POINTER(_Session), i32, ctypes.c_char_p, i32, ctypes.POINTER(vp), vp]
     lib.gm_batch_run.argtypes = [vp, vp]
@@ -334,6 +342,26 @@ class Scene:
         _check(_lib.accumulate_density(self._h, _ptr(pos), _ptr(tri), _ptr(mesh), n, ctypes.byref(fix._c),
                                        float(theta_deg), OCC[occlusion] if isinstance(occlusion, str) else occlusion,
                                        _ptr(out.density), _ptr(out.density_norm), _ptr(out.max), _stream()))
+        return out
+
+    def accumulate_noalloc(self, pos, fix: Fixations, theta_deg, occlusion="full", tri=None, mesh=None, out=None):
+        """accumulate() through accumulate_density_noalloc: no device allocation inside the
+        call (the caller passes `out`; its intermediate buffers are the library's fixed
+        per-device array)."""
+        torch = _torch()
+        pos = _dev(pos, torch.float32, 3)
+        tri = _dev(tri, torch.int32)
+        mesh = _dev(mesh, torch.int32)
+        n = int(pos.shape[0])
+        if out is None:
+            out = Density(torch.empty(n, dtype=torch.float32, device="cuda"),
+                          torch.empty(n, dtype=torch.float32, device="cuda"),
+                          torch.empty(1, dtype=torch.float32, device="cuda"))
+        _check(_lib.accumulate_density_noalloc(self._h, _ptr(pos), _ptr(tri), _ptr(mesh), n, ctypes.byref(fix._c),
+                                               float(theta_deg),
+                                               OCC[occlusion] if isinstance(occlusion, str) else occlusion,
+                                               _ptr(out.density), _ptr(out.density_norm), _ptr(out.max),
+                                               _stream()))
         return out
 
     def _zparams(self, resolution, depth_eps, near, far, head, n):

@@ -21,7 +21,7 @@ HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", os.p
 
 HIP_SOURCES = ["k_sampler.hip", "k_scan.hip", "k_density.hip", "k_field.hip", "capi.cpp", "field_api.cpp", "batch_api.cpp",
                "map_api.cpp", "export_api.cpp",
-               "zbuffer_api.cpp"]
+               "zbuffer_api.cpp", "noalloc_api.cpp"]
 HOST_SOURCES = ["bvh_build.cpp", "mesh_topology.cpp"]
 
 

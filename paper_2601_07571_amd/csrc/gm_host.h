@@ -24,10 +24,12 @@ const char* last_error();
         if (e_ != hipSuccess) return gm::fail(GM_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-// Device buffer that only grows.
+// Device buffer that only grows, or a borrowed range of memory owned elsewhere (never
+// grown or freed: ensure() beyond its size fails).
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -35,6 +37,7 @@ struct DevBuf {
     hipError_t ensure(size_t want)
     {
         if (want <= bytes) return hipSuccess;
+        if (borrowed) return hipErrorOutOfMemory;
         if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
@@ -43,11 +46,19 @@ struct DevBuf {
         if (e == hipSuccess) bytes = cap;
         return e;
     }
+    void borrow(void* q, size_t n)
+    {
+        release();
+        p = q;
+        bytes = n;
+        borrowed = true;
+    }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && !borrowed) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        borrowed = false;
     }
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
