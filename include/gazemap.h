@@ -303,12 +303,12 @@ gm_status gm_map_create(gm_scene* scene, const float* pos, const int32_t* tri, c
  * budget D rounded up to units of 2^-10 s; a fixation that does not fit in what
  * is left is not added and is counted as over budget (which ones, when a block
  * overruns the budget, is unspecified).  Queued on `stream`; the fixation arrays
- * must stay valid until the work completes.  Adds on one map are serialised by
- * the stream: calls on different streams for one map race.  The block's fixations
+ * must stay valid until the work completes.  The block's fixations
  * are selected and recorded on `stream` at once; their density work is gathered
  * with that of later blocks (up to 65,536 fixations, a larger block runs alone)
- * and runs in one launch at the next gm_map_read, on that call's stream (the same
- * stream as the adds, or synchronise first).  The sum is the same, bit for bit.
+ * and runs in one launch at the next gm_map_read, on that call's stream.  Each add
+ * records an event that the next add and the gathered launch wait for, so adds and
+ * the read may come on different streams.  The sum is the same, bit for bit.
  */
 gm_status gm_map_add(gm_map* map, const gm_fixations* fix, const double* time, double t_begin,
                      double t_end, void* stream);

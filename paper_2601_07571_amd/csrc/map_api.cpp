@@ -49,6 +49,14 @@ struct gm_map {
     bool posed = false;
     std::vector<int64_t> moff;
     DevBuf recs, xf;
+    // recorded on the stream of every add whose records are pending: the next add (on any
+    // stream) and the gathered launch wait for it, so pending blocks are complete whichever
+    // streams queued them
+    hipEvent_t added = nullptr;
+    ~gm_map()
+    {
+        if (added) (void)hipEventDestroy(added);
+    }
 };
 
 namespace gm {
@@ -130,6 +138,7 @@ gm_status check_map(const gm_map* m)
 gm_status map_flush(gm_map* m, hipStream_t s)
 {
     if (m->pending_hi == 0) return GM_OK;
+    GM_HIP(hipStreamWaitEvent(s, m->added, 0));
     if (m->n > 0) {
         DensityLaunch a;
         density_args(m->scene, m->w, m->n, (int32_t)m->pending_hi, m->sigma, m->mode, m->spl, 0, a);
@@ -219,6 +228,14 @@ gm_status gm_map_create(gm_scene* sc, const float* pos, const int32_t* tri, cons
     }
 
     gm_map* m = new gm_map;
+    {
+        const hipError_t e = hipEventCreateWithFlags(&m->added, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            m->added = nullptr;
+            delete m;
+            return fail(GM_ERR_DEVICE, "hipEventCreateWithFlags: %s", hipGetErrorString(e));
+        }
+    }
     m->posed = posed;
     m->moff = moff;
     m->scene = sc;
@@ -302,10 +319,12 @@ gm_status gm_map_add(gm_map* m, const gm_fixations* fix, const double* time, dou
     }
     // allocated once (nothing pending can be lost by a reallocation)
     GM_HIP(m->pending.ensure(sizeof(FixRec) * (size_t)kPendingMax));
+    if (m->pending_hi > 0) GM_HIP(hipStreamWaitEvent(s, m->added, 0));  // after the pending adds
     launch_fix_select(fix->eye, fix->gaze, fix->duration, time, F, t_begin, t_end, m->sigma, kGateWiden,
                       m->pending.as<FixRec>(), m->live.as<unsigned int>(), c, c + 2, s);
     m->pending_hi += F;
     GM_HIP(hipGetLastError());
+    GM_HIP(hipEventRecord(m->added, s));
     return GM_OK;
 }
 

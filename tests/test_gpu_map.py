@@ -231,3 +231,27 @@ def test_gathered_blocks_overflow_and_large_blocks(gm, tiny):
     b = _bits(m2.add(fix.subset(40_000, 45_000)).read())
     torch.cuda.synchronize()
     assert np.array_equal(a, b) and a.any()
+
+
+def test_adds_and_read_on_different_streams(gm):
+    """Blocks added on two streams and read on a third give the map of one add: each add
+    records an event that the next add and the gathered launch wait for."""
+    import torch
+    w = workloads.tiny_icosphere_scene()
+    scene = gm.Scene([(m.V, m.I) for m in w.meshes])
+    s = scene.build_samples(w.k, w.seed)
+    fix = gm.Fixations(w.fix.eye, w.fix.gaze, w.fix.dur)
+    one = gm.DensityMap(scene, s.pos, w.theta_deg, occlusion="self", tri=s.tri, mesh=s.mesh)
+    one.add(fix)
+    ref = one.read()
+    torch.cuda.synchronize()
+    m = gm.DensityMap(scene, s.pos, w.theta_deg, occlusion="self", tri=s.tri, mesh=s.mesh)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    for k, lo in enumerate(range(0, fix.n, 25)):
+        with torch.cuda.stream(streams[k % 2]):
+            m.add(fix.subset(lo, min(fix.n, lo + 25)))
+    with torch.cuda.stream(streams[2]):
+        got = m.read()
+    torch.cuda.synchronize()
+    assert np.array_equal(got.density.cpu().numpy(), ref.density.cpu().numpy())
