@@ -92,8 +92,8 @@ FieldRoute route_all() { return FieldRoute{nullptr, nullptr, nullptr, 0, -1}; }
 gm_status infer_routed(gm_field* f, const float* pos, int64_t q, float* out, const FieldRoute& route,
                        const uint8_t* take, hipStream_t s)
 {
-    GM_HIP(f->rcnt.ensure(4 * (size_t)f->M));
-    GM_HIP(f->rbase.ensure(8 * ((size_t)f->M + 1)));
+    GM_HIP(f->rcnt.ensure(4 * 3 * (size_t)f->M));
+    GM_HIP(f->rbase.ensure(8 * (3 * (size_t)f->M + 1)));
     GM_HIP(f->ridx.ensure(4 * (size_t)field_route_slots(q, f->M)));
     launch_field_infer_routed(f->blob.as<unsigned char>(), (int64_t)field_pack_bytes(), f->geom_d.as<FieldGeom>(),
                               pos, q, out, route, take, f->M, f->rcnt.as<unsigned int>(), f->rbase.as<int64_t>(),

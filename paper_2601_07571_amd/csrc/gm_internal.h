@@ -309,8 +309,9 @@ struct FieldRoute {
 void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const float* pos, int64_t q, float* out,
                         const FieldRoute& route, hipStream_t s);
 // All networks in one launch, each over its own mesh's points only (route: the points'
-// meshes; take[m] != 0 selects the routed meshes, NULL: all).  Scratch: cnt [M], base
-// [M + 1], ridx [field_route_slots(q, M)].
+// meshes; take[m] != 0 selects the routed meshes, NULL: all).  Scratch: cnt [3 M], base
+// [3 M + 1], ridx [field_route_slots(q, M)].  A mesh whose points are contiguous in the
+// input is read in place (no list entries).
 int64_t field_route_slots(int64_t q, int32_t M);
 void launch_field_infer_routed(const unsigned char* blobs, int64_t pack_stride, const FieldGeom* geoms,
                                const float* pos, int64_t q, float* out, const FieldRoute& route,

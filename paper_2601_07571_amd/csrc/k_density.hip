@@ -1352,8 +1352,10 @@ template <int SPL, int OCC, int FB, bool INST = false, bool ZB = false>
 __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t tile, int chunk, int F)
 {
     // per fixation of the block, 48 bytes: (rx, ry, rz, c0), (ax, ay, az, cc), (-kappa, -, -, -);
-    // one base address reaches all three with immediate offsets
-    __shared__ float4 s_co[3 * FB];
+    // one base address reaches all three with immediate offsets.  kGateGroup - 1 entries past
+    // the block's last fixation never pass the gate, so the gate takes fixations in groups.
+    constexpr int kGateGroup = OCC != 0 ? 1 : 4;  // fixations per gate test (one where registers are tight)
+    __shared__ float4 s_co[3 * (FB + kGateGroup - 1)];
     __shared__ unsigned long long s_acc[kThreads * SPL];  // one entry per sample, owned by one lane
     __shared__ float s_rad;
     __shared__ uint32_t s_stats[kDensityStats];
@@ -1409,146 +1411,173 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
             s_co[3 * threadIdx.x + 1] = make_float4(2.0f * k * ex, 2.0f * k * ey, 2.0f * k * ez, cc);
             s_co[3 * threadIdx.x + 2].x = -k;
         }
+        if (threadIdx.x < kGateGroup - 1) {
+            // s = 0 * |0| + (-3e38) < 0 at every point: never a candidate
+            s_co[3 * (nb + threadIdx.x)] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            s_co[3 * (nb + threadIdx.x) + 1] = make_float4(0.0f, 0.0f, 0.0f, -3.0e38f);
+            s_co[3 * (nb + threadIdx.x) + 2].x = 0.0f;
+        }
         __syncthreads();
-        for (int j = 0; j < nb; ++j) {
-            const float4 ra = s_co[3 * j];
-            const float4 rb = s_co[3 * j + 1];
-            const float nk = s_co[3 * j + 2].x;
-            unsigned cand = 0;
+        for (int jg = 0; jg < nb; jg += kGateGroup) {
+            // the gate of kGateGroup fixations, one wave mask per fixation and slot; a group
+            // with no candidate costs one scalar test
+            uint64_t gm[kGateGroup][SPL];
+            uint64_t gany = 0;
 #pragma unroll
-            for (int k = 0; k < SPL; ++k) {
-                float d = __builtin_fmaf(ra.x, px[k], ra.w);
-                d = __builtin_fmaf(ra.y, py[k], d);
-                d = __builtin_fmaf(ra.z, pz[k], d);
-                float m = __builtin_fmaf(rb.x, px[k], rb.w);
-                m = __builtin_fmaf(rb.y, py[k], m);
-                m = __builtin_fmaf(rb.z, pz[k], m);
-                m = __builtin_fmaf(nk, pq[k], m);
-                const float sv = __builtin_fmaf(d, fabsf(d), m);
-                cand |= (sv > 0.0f ? 1u : 0u) << k;
+            for (int h = 0; h < kGateGroup; ++h) {
+                const float4 ra = s_co[3 * (jg + h)];
+                const float4 rb = s_co[3 * (jg + h) + 1];
+                const float nk = s_co[3 * (jg + h) + 2].x;
+#pragma unroll
+                for (int k = 0; k < SPL; ++k) {
+                    float d = __builtin_fmaf(ra.x, px[k], ra.w);
+                    d = __builtin_fmaf(ra.y, py[k], d);
+                    d = __builtin_fmaf(ra.z, pz[k], d);
+                    float m = __builtin_fmaf(rb.x, px[k], rb.w);
+                    m = __builtin_fmaf(rb.y, py[k], m);
+                    m = __builtin_fmaf(rb.z, pz[k], m);
+                    m = __builtin_fmaf(nk, pq[k], m);
+                    const float sv = __builtin_fmaf(d, fabsf(d), m);
+                    gm[h][k] = ballot(sv > 0.0f);
+                    gany |= gm[h][k];
+                }
             }
-            if (ballot(cand != 0) == 0) continue;
+            if (gany == 0) continue;
+#pragma unroll 1
+            for (int h = 0; h < kGateGroup; ++h) {
+                uint64_t cm[SPL];
+                uint64_t cany = 0;
+#pragma unroll
+                for (int k = 0; k < SPL; ++k) {
+                    // a uniform select, not an index into gm (which would put it in memory)
+                    cm[k] = gm[0][k];
+#pragma unroll
+                    for (int hh = 1; hh < kGateGroup; ++hh) cm[k] = h == hh ? gm[hh][k] : cm[k];
+                    cany |= cm[k];
+                }
+                if (cany == 0) continue;
 
-            // exact path for this fixation: values of the passing slots, then one packet
-            // traversal for every slot that needs a visibility answer
-            const int f = uniform(fb + j);
-            const FixRec fr = load_fix(a.fix, f);
-            float g[SPL];
-            float4 p[SPL];
-            bool need[SPL];
-            bool any_need = false;
-            ZCam zc;
-            if (ZB) zc = reinterpret_cast<const ZCam*>(a.zcam)[f];
-#pragma unroll
-            for (int k = 0; k < SPL; ++k) {
-                const int64_t i = wave_base + k * 64 + lane;
-                const bool c = ((cand >> k) & 1u) && i < n;
-                g[k] = 0.0f;
-                p[k] = make_float4(fr.ex, fr.ey, fr.ez, __int_as_float(-1));
-                bool in = false;
-                if (ballot(c) != 0 && c) {
-                    p[k] = a.spos[i];
-                    if (ZB)
-                        g[k] = zb_value(p[k].x, p[k].y, p[k].z, fr, zc, a.zbuf + (int64_t)f * a.zres * a.zres, a.zres,
-                                        a.zeps, a.kexp, in);
-                    else
-                        g[k] = pair_value(p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w,
-                                          a.cone2, a.kexp);
-                }
-                need[k] = OCC != 0 && a.occ_mode != 0 && g[k] > 0.0f;
-                any_need = any_need || need[k];
-                n_in += (uint32_t)__popcll(ballot(ZB ? in : g[k] > 0.0f));
-            }
-            bool occl[SPL];
-#pragma unroll
-            for (int k = 0; k < SPL; ++k) occl[k] = false;
-            if (OCC != 0 && !INST && !ZB && a.bface && ballot(any_need) != 0) {
-                // the back-face rule first: pairs it settles leave the packet
-                any_need = false;
+                // exact path for this fixation: values of the passing slots, then one packet
+                // traversal for every slot that needs a visibility answer
+                const int f = uniform(fb + jg + h);
+                const FixRec fr = load_fix(a.fix, f);
+                float g[SPL];
+                float4 p[SPL];
+                bool need[SPL];
+                bool any_need = false;
+                ZCam zc;
+                if (ZB) zc = reinterpret_cast<const ZCam*>(a.zcam)[f];
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
                     const int64_t i = wave_base + k * 64 + lane;
-                    if (need[k] && backface_occluded(a, i, p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez)) {
-                        need[k] = false;
-                        occl[k] = true;
+                    const bool c = __builtin_amdgcn_inverse_ballot_w64(cm[k]) && i < n;
+                    g[k] = 0.0f;
+                    p[k] = make_float4(fr.ex, fr.ey, fr.ez, __int_as_float(-1));
+                    bool in = false;
+                    if (ballot(c) != 0 && c) {
+                        p[k] = a.spos[i];
+                        if (ZB)
+                            g[k] = zb_value(p[k].x, p[k].y, p[k].z, fr, zc, a.zbuf + (int64_t)f * a.zres * a.zres, a.zres,
+                                            a.zeps, a.kexp, in);
+                        else
+                            g[k] = pair_value(p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez, fr.rx, fr.ry, fr.rz, fr.w,
+                                              a.cone2, a.kexp);
                     }
-                    n_bf += (uint32_t)__popcll(ballot(occl[k]));
+                    need[k] = OCC != 0 && a.occ_mode != 0 && g[k] > 0.0f;
                     any_need = any_need || need[k];
+                    n_in += (uint32_t)__popcll(ballot(ZB ? in : g[k] > 0.0f));
                 }
-            }
-            if (OCC != 0 && ballot(any_need) != 0) {
-                int otri[SPL], omesh[SPL];
+                bool occl[SPL];
 #pragma unroll
-                for (int k = 0; k < SPL; ++k) {
-                    const int64_t i = wave_base + k * 64 + lane;
-                    otri[k] = need[k] ? __float_as_int(p[k].w) : -1;
-                    omesh[k] = need[k] ? a.smesh[i] : -1;
-                }
-                if (!INST) {
-                    // the walk answers the lanes it tests; lanes the back-face rule settled keep it
-                    bool o1[SPL];
-                    packet_visibility<SPL>(a.nodes, a.node_stride, a.tris, a.tri_stride, fr.ex, fr.ey, fr.ez, fr.rx,
-                                           fr.ry, fr.rz, p, otri, omesh, a.occ_mode, need, o1, n_visits);
+                for (int k = 0; k < SPL; ++k) occl[k] = false;
+                if (OCC != 0 && !INST && !ZB && a.bface && ballot(any_need) != 0) {
+                    // the back-face rule first: pairs it settles leave the packet
+                    any_need = false;
 #pragma unroll
-                    for (int k = 0; k < SPL; ++k) occl[k] = occl[k] || o1[k];
-                    ++n_trav;
-                } else {
-                    // One BVH per mesh.  Static scenes (xf NULL): every mesh in the world
-                    // frame, the segments as they are.  Posed launches: every mesh in its
-                    // own frame at this fixation's time; the points move with their mesh
-                    // (forward pose of this launch's mesh), then into the occluding mesh's
-                    // frame (its inverse pose), whose eye and gaze are that mesh's fixation
-                    // record; tau is unchanged by the (affine) change of frame.  With
-                    // GM_OCC_SELF a lane takes part only in its own mesh.
-                    const bool moving = a.xf != nullptr;
-                    const float* fw = moving ? a.xf + ((int64_t)a.self_mesh * a.fix_stride + f) * 24 : nullptr;
-                    for (int mi = 0; mi < a.n_inst; ++mi) {
-                        bool rest[SPL];
-                        bool left = false, any = false;
-#pragma unroll
-                        for (int k = 0; k < SPL; ++k) {
-                            const bool r = need[k] && !occl[k];
-                            left = left || r;
-                            rest[k] = r && (a.occ_mode != 1 || omesh[k] == mi);
-                            any = any || rest[k];
+                    for (int k = 0; k < SPL; ++k) {
+                        const int64_t i = wave_base + k * 64 + lane;
+                        if (need[k] && backface_occluded(a, i, p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez)) {
+                            need[k] = false;
+                            occl[k] = true;
                         }
-                        if (ballot(left) == 0) break;
-                        if (ballot(any) == 0) continue;
-                        const BlasDesc b = a.blas[mi];
-                        FixRec fo = fr;
-                        float4 q[SPL];
+                        n_bf += (uint32_t)__popcll(ballot(occl[k]));
+                        any_need = any_need || need[k];
+                    }
+                }
+                if (OCC != 0 && ballot(any_need) != 0) {
+                    int otri[SPL], omesh[SPL];
 #pragma unroll
-                        for (int k = 0; k < SPL; ++k) q[k] = p[k];
-                        if (moving) {
-                            fo = load_fix(a.fix_all + (int64_t)mi * a.fix_stride, f);
-                            if (mi != a.self_mesh) {
-                                const float* iv = a.xf + ((int64_t)mi * a.fix_stride + f) * 24 + 12;
+                    for (int k = 0; k < SPL; ++k) {
+                        const int64_t i = wave_base + k * 64 + lane;
+                        otri[k] = need[k] ? __float_as_int(p[k].w) : -1;
+                        omesh[k] = need[k] ? a.smesh[i] : -1;
+                    }
+                    if (!INST) {
+                        // the walk answers the lanes it tests; lanes the back-face rule settled keep it
+                        bool o1[SPL];
+                        packet_visibility<SPL>(a.nodes, a.node_stride, a.tris, a.tri_stride, fr.ex, fr.ey, fr.ez, fr.rx,
+                                               fr.ry, fr.rz, p, otri, omesh, a.occ_mode, need, o1, n_visits);
 #pragma unroll
-                                for (int k = 0; k < SPL; ++k) {
-                                    const float wx = __builtin_fmaf(fw[0], p[k].x, __builtin_fmaf(fw[1], p[k].y, __builtin_fmaf(fw[2], p[k].z, fw[3])));
-                                    const float wy = __builtin_fmaf(fw[4], p[k].x, __builtin_fmaf(fw[5], p[k].y, __builtin_fmaf(fw[6], p[k].z, fw[7])));
-                                    const float wz = __builtin_fmaf(fw[8], p[k].x, __builtin_fmaf(fw[9], p[k].y, __builtin_fmaf(fw[10], p[k].z, fw[11])));
-                                    q[k].x = __builtin_fmaf(iv[0], wx, __builtin_fmaf(iv[1], wy, __builtin_fmaf(iv[2], wz, iv[3])));
-                                    q[k].y = __builtin_fmaf(iv[4], wx, __builtin_fmaf(iv[5], wy, __builtin_fmaf(iv[6], wz, iv[7])));
-                                    q[k].z = __builtin_fmaf(iv[8], wx, __builtin_fmaf(iv[9], wy, __builtin_fmaf(iv[10], wz, iv[11])));
+                        for (int k = 0; k < SPL; ++k) occl[k] = occl[k] || o1[k];
+                        ++n_trav;
+                    } else {
+                        // One BVH per mesh.  Static scenes (xf NULL): every mesh in the world
+                        // frame, the segments as they are.  Posed launches: every mesh in its
+                        // own frame at this fixation's time; the points move with their mesh
+                        // (forward pose of this launch's mesh), then into the occluding mesh's
+                        // frame (its inverse pose), whose eye and gaze are that mesh's fixation
+                        // record; tau is unchanged by the (affine) change of frame.  With
+                        // GM_OCC_SELF a lane takes part only in its own mesh.
+                        const bool moving = a.xf != nullptr;
+                        const float* fw = moving ? a.xf + ((int64_t)a.self_mesh * a.fix_stride + f) * 24 : nullptr;
+                        for (int mi = 0; mi < a.n_inst; ++mi) {
+                            bool rest[SPL];
+                            bool left = false, any = false;
+#pragma unroll
+                            for (int k = 0; k < SPL; ++k) {
+                                const bool r = need[k] && !occl[k];
+                                left = left || r;
+                                rest[k] = r && (a.occ_mode != 1 || omesh[k] == mi);
+                                any = any || rest[k];
+                            }
+                            if (ballot(left) == 0) break;
+                            if (ballot(any) == 0) continue;
+                            const BlasDesc b = a.blas[mi];
+                            FixRec fo = fr;
+                            float4 q[SPL];
+#pragma unroll
+                            for (int k = 0; k < SPL; ++k) q[k] = p[k];
+                            if (moving) {
+                                fo = load_fix(a.fix_all + (int64_t)mi * a.fix_stride, f);
+                                if (mi != a.self_mesh) {
+                                    const float* iv = a.xf + ((int64_t)mi * a.fix_stride + f) * 24 + 12;
+#pragma unroll
+                                    for (int k = 0; k < SPL; ++k) {
+                                        const float wx = __builtin_fmaf(fw[0], p[k].x, __builtin_fmaf(fw[1], p[k].y, __builtin_fmaf(fw[2], p[k].z, fw[3])));
+                                        const float wy = __builtin_fmaf(fw[4], p[k].x, __builtin_fmaf(fw[5], p[k].y, __builtin_fmaf(fw[6], p[k].z, fw[7])));
+                                        const float wz = __builtin_fmaf(fw[8], p[k].x, __builtin_fmaf(fw[9], p[k].y, __builtin_fmaf(fw[10], p[k].z, fw[11])));
+                                        q[k].x = __builtin_fmaf(iv[0], wx, __builtin_fmaf(iv[1], wy, __builtin_fmaf(iv[2], wz, iv[3])));
+                                        q[k].y = __builtin_fmaf(iv[4], wx, __builtin_fmaf(iv[5], wy, __builtin_fmaf(iv[6], wz, iv[7])));
+                                        q[k].z = __builtin_fmaf(iv[8], wx, __builtin_fmaf(iv[9], wy, __builtin_fmaf(iv[10], wz, iv[11])));
+                                    }
                                 }
                             }
-                        }
-                        bool o2[SPL];
-                        packet_visibility<SPL>(a.blas_nodes + b.node_base, b.node_count, a.blas_tris + b.tri_base,
-                                               b.tri_count, fo.ex, fo.ey, fo.ez, fo.rx, fo.ry, fo.rz, q, otri, omesh,
-                                               2, rest, o2, n_visits);
+                            bool o2[SPL];
+                            packet_visibility<SPL>(a.blas_nodes + b.node_base, b.node_count, a.blas_tris + b.tri_base,
+                                                   b.tri_count, fo.ex, fo.ey, fo.ez, fo.rx, fo.ry, fo.rz, q, otri, omesh,
+                                                   2, rest, o2, n_visits);
 #pragma unroll
-                        for (int k = 0; k < SPL; ++k) occl[k] = occl[k] || o2[k];
-                        ++n_trav;
+                            for (int k = 0; k < SPL; ++k) occl[k] = occl[k] || o2[k];
+                            ++n_trav;
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int k = 0; k < SPL; ++k) {
-                const bool ok = g[k] > 0.0f && !occl[k];
-                n_vis += (uint32_t)__popcll(ballot(ok));
-                if (ok) s_acc[wave * (64 * SPL) + k * 64 + lane] += to_fixed(g[k], shift);
+                for (int k = 0; k < SPL; ++k) {
+                    const bool ok = g[k] > 0.0f && !occl[k];
+                    n_vis += (uint32_t)__popcll(ballot(ok));
+                    if (ok) s_acc[wave * (64 * SPL) + k * 64 + lane] += to_fixed(g[k], shift);
+                }
             }
         }
     }

@@ -223,12 +223,15 @@ __global__ void __launch_bounds__(kThreads) k_field_infer(const unsigned char* _
     }
 }
 
-// Routed inference: the points of every network are listed together (ridx, one
-// segment per mesh in mesh order, each padded with -1 to a whole number of kGroup
-// points, segment m starting at base[m]), so every network evaluates only its own
-// mesh's points, all networks in one launch.  A workgroup takes groups of kGroup
-// points (one 32-point tile per wave) and stages the weights of the group's network,
-// again only when the network changes (its groups run in mesh order).
+// Routed inference: the points of every network are listed together, one segment per
+// mesh in mesh order, each padded to a whole number of kGroup points, segment m starting
+// at base[m] (route layout: base [M + 1], then start [M], then count [M]).  A mesh whose
+// points already lie contiguously in the input (start[m] >= 0: they are
+// start[m] .. start[m] + count[m] - 1, as for samples generated mesh by mesh) is read in
+// place; the others through the index list ridx.  Every network evaluates only its own
+// mesh's points, all networks in one launch.  A workgroup takes groups of kGroup points
+// (one 32-point tile per wave) and stages the weights of the group's network, again only
+// when the network changes (its groups run in mesh order).
 constexpr int kGroup = 32 * (kThreads / 64);
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
@@ -258,6 +261,8 @@ __global__ void __launch_bounds__(kThreads) k_field_infer_routed(const unsigned 
     __shared__ __attribute__((aligned(16))) unsigned char s_blob[kInfer];
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const int64_t groups = base[M] / kGroup;
+    const int64_t* start = base + M + 1;
+    const int64_t* count = base + 2 * M + 1;
     int staged = -1;
     FieldGeom g;
     for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
@@ -270,7 +275,10 @@ __global__ void __launch_bounds__(kThreads) k_field_infer_routed(const unsigned 
             g = geoms[m];
         }
         asm volatile("" ::: "memory");  // weights stay in LDS (see k_field_infer)
-        const int32_t i = ridx[gi * kGroup + 32 * wave + (lane & 31)];
+        const int64_t slot = gi * kGroup + 32 * wave + (lane & 31);
+        const int64_t off = slot - base[m];
+        const int64_t s0 = start[m];
+        const int64_t i = off >= count[m] ? -1 : s0 >= 0 ? s0 + off : (int64_t)ridx[slot];
         const int64_t ii = i >= 0 ? i : 0;
         Acts A;
         const float o = field_forward(s_blob, g, pos[3 * ii], pos[3 * ii + 1], pos[3 * ii + 2], lane, A);
@@ -299,7 +307,11 @@ __device__ __forceinline__ int route_mesh(const int32_t* __restrict__ mesh, cons
 // wave serves one mesh per round (the first pending lane's), so a wave of points of one
 // mesh costs one atomic however many points share it.  Returns this lane's slot among
 // the points of its mesh, counted from the value the atomic returned.
-__device__ __forceinline__ unsigned int wave_reserve(int m, unsigned int* __restrict__ ctr)
+// With lo/hi set, the same round also keeps the smallest and largest point index of each
+// mesh (lanes hold increasing indices i, so the first and last lane of a round have them).
+__device__ __forceinline__ unsigned int wave_reserve(int m, unsigned int* __restrict__ ctr,
+                                                     unsigned int* __restrict__ lo = nullptr,
+                                                     unsigned int* __restrict__ hi = nullptr, int64_t i = 0)
 {
     const int lane = __lane_id();
     uint64_t pending = __ballot(m >= 0);
@@ -308,6 +320,10 @@ __device__ __forceinline__ unsigned int wave_reserve(int m, unsigned int* __rest
         const int lead = __builtin_ctzll(pending);
         const int mm = __builtin_amdgcn_readlane(m, lead);
         const uint64_t same = __ballot(m == mm) & pending;
+        if (lo) {
+            if (lane == lead) atomicMin(&lo[mm], (unsigned int)i);
+            if (lane == 63 - __builtin_clzll(same)) atomicMax(&hi[mm], (unsigned int)i);
+        }
         unsigned int base = 0u;
         if (lane == lead) base = atomicAdd(&ctr[mm], (unsigned int)__popcll(same));
         base = __builtin_amdgcn_readlane(base, lead);
@@ -329,30 +345,53 @@ __global__ void __launch_bounds__(kThreads) k_route_count(const int32_t* __restr
                                                           const uint8_t* __restrict__ take, int32_t M, int64_t q,
                                                           unsigned int* __restrict__ cnt)
 {
-    __shared__ unsigned int lc[kRouteLds];
+    // cnt: counts [M], then the smallest [M] and the largest [M] point index per mesh
+    __shared__ unsigned int lc[3 * kRouteLds];
     const bool lds = M <= kRouteLds;
-    for (int m = threadIdx.x; lds && m < M; m += kThreads) lc[m] = 0u;
+    unsigned int* c = lds ? lc : cnt;
+    const int stride = lds ? kRouteLds : M;
+    for (int m = threadIdx.x; lds && m < M; m += kThreads) {
+        lc[m] = 0u;
+        lc[kRouteLds + m] = 0xffffffffu;
+        lc[2 * kRouteLds + m] = 0u;
+    }
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * kRouteChunk;
 #pragma unroll 4
     for (int j = 0; j < kRouteChunk / kThreads; ++j) {
         const int64_t i = c0 + j * kThreads + threadIdx.x;
         const int m = i < q ? route_mesh(mesh, tri, tri_mesh, T, take, M, i) : -1;
-        (void)wave_reserve(m, lds ? lc : cnt);
+        (void)wave_reserve(m, c, c + stride, c + 2 * stride, i);
     }
     __syncthreads();
     for (int m = threadIdx.x; lds && m < M; m += kThreads)
-        if (lc[m]) atomicAdd(&cnt[m], lc[m]);
+        if (lc[m]) {
+            atomicAdd(&cnt[m], lc[m]);
+            atomicMin(&cnt[M + m], lc[kRouteLds + m]);
+            atomicMax(&cnt[2 * M + m], lc[2 * kRouteLds + m]);
+        }
 }
 
-// one thread: padded segment starts, and the per-mesh cursors cleared
+__global__ void k_route_init(unsigned int* __restrict__ cnt, int32_t M)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < 3 * M) cnt[i] = i >= M && i < 2 * M ? 0xffffffffu : 0u;
+}
+
+// one thread: padded segment starts, the in-place start of every mesh whose points are
+// contiguous in the input (largest - smallest index + 1 == count; else -1), the counts,
+// and the per-mesh cursors cleared
 __global__ void k_route_base(unsigned int* __restrict__ cnt, int32_t M, int64_t* __restrict__ base)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     int64_t run = 0;
     for (int m = 0; m < M; ++m) {
+        const int64_t c = cnt[m];
         base[m] = run;
-        run += ((int64_t)cnt[m] + kGroup - 1) / kGroup * kGroup;
+        run += (c + kGroup - 1) / kGroup * kGroup;
+        const bool contiguous = c > 0 && (int64_t)cnt[2 * M + m] - (int64_t)cnt[M + m] + 1 == c;
+        base[M + 1 + m] = contiguous ? (int64_t)cnt[M + m] : -1;
+        base[2 * M + 1 + m] = c;
         cnt[m] = 0u;
     }
     base[M] = run;
@@ -378,6 +417,7 @@ __global__ void __launch_bounds__(kThreads) k_route_scatter(const int32_t* __res
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = c0 + j * kThreads + threadIdx.x;
         mm[j] = i < q ? route_mesh(mesh, tri, tri_mesh, T, take, M, i) : -1;
+        if (mm[j] >= 0 && base[M + 1 + mm[j]] >= 0) mm[j] = -1;  // read in place: no list entry
         rank[j] = wave_reserve(mm[j], lds ? lc : cur);  // rank in the chunk (LDS) or the mesh (global)
     }
     __syncthreads();
@@ -540,25 +580,52 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
     }
 }
 
-// grad[net][p] = sum of the first `used` slots of network net in slot order; loss[net]
-// likewise (networks with no training points: cnt[net] == 0, nothing written, 0)
+// grad[net][p] = sum of the first `used` slots of network net; loss[net] likewise
+// (networks with no training points: cnt[net] == 0, nothing summed, 0).  A workgroup takes
+// kRedParams consecutive parameters of one network (blockIdx.y) and splits the slots into
+// kRedGroups contiguous runs, one per thread row; each row sums its run in slot order, then
+// one thread per parameter adds the rows in row order.  The order of every addition is fixed
+// by (used, slot), so the result is the same on every run.
+constexpr int kRedParams = 32;
+constexpr int kRedGroups = kThreads / kRedParams;
+
 __global__ void k_field_grad_reduce(const float* __restrict__ gpart, const double* __restrict__ lpart, int32_t used,
-                                    int32_t slots, int32_t M, const int64_t* __restrict__ cnt,
-                                    float* __restrict__ grad, double* __restrict__ loss)
+                                    int32_t slots, const int64_t* __restrict__ cnt, float* __restrict__ grad,
+                                    double* __restrict__ loss)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= (int64_t)M * kFieldParams) return;
-    const int net = (int)(i / kFieldParams);
-    const int p = (int)(i % kFieldParams);
+    __shared__ float rows[kRedGroups][kRedParams];
+    __shared__ double lrows[kThreads];
+    const int net = blockIdx.y;
     const bool live = !cnt || cnt[net] > 0;
-    const float* src = gpart + (int64_t)net * slots * kFieldParams + p;
+    const int n = live ? used : 0;
+    const int col = threadIdx.x % kRedParams, row = threadIdx.x / kRedParams;
+    const int p = blockIdx.x * kRedParams + col;
+    const int per = (n + kRedGroups - 1) / kRedGroups;
+    const int w0 = row * per, w1 = min(n, w0 + per);
     float sum = 0.0f;
-    for (int w = 0; live && w < used; ++w) sum += src[(int64_t)w * kFieldParams];
-    grad[i] = sum;
-    if (p == 0) {
+    if (p < kFieldParams) {
+        const float* src = gpart + (int64_t)net * slots * kFieldParams + p;
+        for (int w = w0; w < w1; ++w) sum += src[(int64_t)w * kFieldParams];
+    }
+    rows[row][col] = sum;
+    if (blockIdx.x == 0) {
+        // the loss: thread i sums slots i, i + kThreads, ... in order, then a fixed pairwise tree
         double l = 0.0;
-        for (int w = 0; live && w < used; ++w) l += lpart[(int64_t)net * slots + w];
-        loss[net] = l;
+        for (int w = threadIdx.x; w < n; w += kThreads) l += lpart[(int64_t)net * slots + w];
+        lrows[threadIdx.x] = l;
+    }
+    __syncthreads();
+    if (row == 0 && p < kFieldParams) {
+        float s = rows[0][col];
+        for (int r = 1; r < kRedGroups; ++r) s += rows[r][col];
+        grad[(int64_t)net * kFieldParams + p] = s;
+    }
+    if (blockIdx.x == 0) {
+        for (int h = kThreads / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) lrows[threadIdx.x] += lrows[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) loss[net] = lrows[0];
     }
 }
 
@@ -694,8 +761,7 @@ void launch_field_infer_routed(const unsigned char* blobs, int64_t pack_stride, 
 {
     if (q <= 0 || M <= 0) return;
     const int64_t slots = field_route_slots(q, M);
-    k_fill_i32<<<blocks(slots), kThreads, 0, s>>>(ridx, slots, -1);
-    k_fill_i32<<<blocks(M), kThreads, 0, s>>>(reinterpret_cast<int32_t*>(cnt), M, 0);
+    k_route_init<<<blocks(3 * (int64_t)M), kThreads, 0, s>>>(cnt, M);
     const unsigned chunks = (unsigned)((q + kRouteChunk - 1) / kRouteChunk);
     k_route_count<<<chunks, kThreads, 0, s>>>(route.mesh, route.tri, route.tri_mesh, route.T, take, M, q, cnt);
     k_route_base<<<1, 1, 0, s>>>(cnt, M, base);
@@ -727,8 +793,8 @@ void launch_field_train(const unsigned char* blob, const FieldGeom& g, FieldTrai
     const int tiles = (t.batch + 31) / 32;
     t.slots = field_train_slots(t.batch, 1);
     k_field_train<<<(unsigned)(t.slots / (kThreads / 64)), kThreads, 0, s>>>(blob, g, t, FieldNets{});
-    k_field_grad_reduce<<<blocks(kFieldParams), kThreads, 0, s>>>(t.gpart, t.lpart, std::min(tiles, t.slots), t.slots,
-                                                                  1, nullptr, grad, loss);
+    k_field_grad_reduce<<<dim3((kFieldParams + kRedParams - 1) / kRedParams, 1), kThreads, 0, s>>>(
+        t.gpart, t.lpart, std::min(tiles, t.slots), t.slots, nullptr, grad, loss);
 }
 
 void launch_field_train_nets(const unsigned char* blob, const FieldNets& nets, int32_t M, FieldTrain t, float* grad,
@@ -739,8 +805,8 @@ void launch_field_train_nets(const unsigned char* blob, const FieldNets& nets, i
     t.slots = field_train_slots(t.batch, M);
     k_field_train<<<dim3((unsigned)(t.slots / (kThreads / 64)), (unsigned)M), kThreads, 0, s>>>(blob, FieldGeom{}, t,
                                                                                                   nets);
-    k_field_grad_reduce<<<blocks((int64_t)M * kFieldParams), kThreads, 0, s>>>(
-        t.gpart, t.lpart, std::min(tiles, t.slots), t.slots, M, nets.cnt, grad, loss);
+    k_field_grad_reduce<<<dim3((kFieldParams + kRedParams - 1) / kRedParams, (unsigned)M), kThreads, 0, s>>>(
+        t.gpart, t.lpart, std::min(tiles, t.slots), t.slots, nets.cnt, grad, loss);
 }
 
 void launch_field_adam(float* master, float* m, float* v, float* grad, int64_t count, float lr, float b1, float b2,

@@ -224,6 +224,54 @@ def test_one_network_per_mesh(gm):
     assert np.allclose(out.cpu().numpy(), f.predict(s.pos, mesh=s.mesh).cpu().numpy())
 
 
+def test_routed_inference_in_place_and_listed(gm):
+    """Routed inference reads a mesh's points in place when they are contiguous in the
+    input and through an index list otherwise: every arrangement of the same points (mesh
+    blocks in order, shuffled, one block beside interleaved points of no mesh, a mesh split
+    in two blocks) gives every point the same bits, and those match the oracle."""
+    import torch
+    sph = workloads.sphere_mesh(level=2, radius=0.3, displace=0.05, seed=4)
+    cube = workloads.cube_mesh(0.5)
+    Vc = (cube.V + np.array([1.5, 0.2, -0.4], np.float32)).astype(np.float32)
+    meshes = [(sph.V, sph.I), (Vc, cube.I)]
+    scene = gm.Scene(meshes)
+    f = gm.Field(scene, seed=5)
+    params = np.stack([fo.init_params(31), fo.init_params(32)]).astype(np.float32)
+    f.set_params(params)
+    rng = np.random.default_rng(6)
+    xs, refs = [], []
+    for m, (V, _) in enumerate(meshes):
+        lo32 = V.min(axis=0).astype(np.float32)
+        ext = float(np.max(V.max(axis=0).astype(np.float32) - lo32))
+        x = (lo32 + rng.uniform(0, ext, (5000 + 3000 * m, 3))).astype(np.float32)  # several route chunks
+        ref, _ = fo.forward(params[m].astype(np.float64), x, lo32.astype(np.float64), ext, bf=True)
+        xs.append(x); refs.append(ref)
+    n0, n1 = len(xs[0]), len(xs[1])
+    x = np.concatenate(xs); ids = np.concatenate([np.zeros(n0, np.int32), np.ones(n1, np.int32)])
+    ref = np.concatenate(refs)
+    base = f.predict(x, mesh=ids).cpu().numpy()
+    rel = np.abs(base.astype(np.float64) - ref) / np.maximum(np.abs(ref), 1e-3)
+    assert np.median(rel) < 2e-3 and rel.max() < 5e-2, (np.median(rel), rel.max())
+    arrangements = {"shuffled": rng.permutation(n0 + n1)}
+    # mesh 1's points spread over a block twice its size; the gaps hold points of no mesh
+    gap = np.full(n0 + 2 * n1, -1, np.int64)
+    gap[np.arange(n0)] = np.arange(n0)
+    gap[n0 + 2 * np.arange(n1)] = n0 + np.arange(n1)
+    arrangements["block_and_interleaved"] = gap
+    # mesh 0 in two blocks with mesh 1 between them
+    h = n0 // 2
+    arrangements["split"] = np.concatenate([np.arange(h), n0 + np.arange(n1), np.arange(h, n0)])
+    for name, order in arrangements.items():
+        src = order.copy()
+        xa = x[np.maximum(src, 0)]
+        ia = np.where(src >= 0, ids[np.maximum(src, 0)], -1).astype(np.int32)
+        out = torch.full((len(src),), -5.0, device="cuda")
+        f.predict(xa, mesh=ia, out=out)
+        y = out.cpu().numpy()
+        assert np.array_equal(y[src >= 0], base[src[src >= 0]]), name
+        assert bool((y[src < 0] == -5.0).all()), name
+
+
 def test_training_and_gradient_are_bit_reproducible(gm):
     """Gradients are summed in a fixed order (per-wave slots, then slot order): two
     trainings from the same start give the same weights, errors and gates bit for bit,
