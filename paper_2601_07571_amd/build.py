@@ -23,6 +23,9 @@ HIP_SOURCES = ["k_sampler.hip", "k_scan.hip", "k_density.hip", "k_field.hip", "c
                "map_api.cpp", "export_api.cpp",
                "zbuffer_api.cpp", "noalloc_api.cpp"]
 HOST_SOURCES = ["bvh_build.cpp", "mesh_topology.cpp"]
+# per-file flags: the field kernels keep matrix-core results in ordinary vector registers
+# (no copies out of the accumulation registers before the bias/ReLU/convert steps)
+EXTRA_FLAGS = {"k_field.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(cmd):
@@ -37,7 +40,7 @@ def build(verbose=False):
     jobs = []
     for src in HIP_SOURCES:
         o = os.path.join(OBJ, src + ".o")
-        jobs.append([HIPCC, *HIP_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", o])
+        jobs.append([HIPCC, *HIP_FLAGS, *EXTRA_FLAGS.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", o])
     for src in HOST_SOURCES:
         o = os.path.join(OBJ, src + ".o")
         jobs.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])

@@ -21,9 +21,10 @@ struct gm_field {
     int32_t M = 0;
     std::vector<FieldGeom> geom;  // [M]
     DevBuf master, m, v, grad, blob, loss;
-    DevBuf flag, sel, offs, idx, scan_tmp, pred, l2sums, geom_d, net_off, net_cnt;
+    DevBuf flag, sel, offs, idx, scan_tmp, pred, l2sums, l2part, geom_d, net_off, net_cnt;
     DevBuf gate_d, need, qoffs, qscan, gpos, gtri, gmesh, gidx, grho, gnorm;
-    DevBuf rcnt, rbase, ridx, take_d;  // routed inference: per-mesh counts, segment starts, point lists
+    DevBuf rcnt, rpart, rbase, ridx, take_d;  // routed inference: per-mesh counts, per-chunk counts,
+                                              // segment starts, point lists
     DevBuf gpart, lpart;               // training: per-wave gradient and loss slots
     std::vector<float> rel_l2;
     std::vector<uint8_t> gate;
@@ -35,8 +36,8 @@ struct gm_field {
     ~gm_field()
     {
         for (DevBuf* b : {&master, &m, &v, &grad, &blob, &loss, &flag, &sel, &offs, &idx, &scan_tmp, &pred, &l2sums,
-                          &geom_d, &net_off, &net_cnt, &gate_d, &need, &qoffs, &qscan, &gpos, &gtri, &gmesh, &gidx,
-                          &grho, &gnorm, &rcnt, &rbase, &ridx, &take_d, &gpart, &lpart})
+                          &l2part, &geom_d, &net_off, &net_cnt, &gate_d, &need, &qoffs, &qscan, &gpos, &gtri, &gmesh,
+                          &gidx, &grho, &gnorm, &rcnt, &rpart, &rbase, &ridx, &take_d, &gpart, &lpart})
             b->release();
     }
 };
@@ -95,8 +96,11 @@ gm_status infer_routed(gm_field* f, const float* pos, int64_t q, float* out, con
     GM_HIP(f->rcnt.ensure(4 * 3 * (size_t)f->M));
     GM_HIP(f->rbase.ensure(8 * (3 * (size_t)f->M + 1)));
     GM_HIP(f->ridx.ensure(4 * (size_t)field_route_slots(q, f->M)));
+    const int64_t pb = field_route_part_bytes(q, f->M);
+    if (pb > 0) GM_HIP(f->rpart.ensure((size_t)pb));
     launch_field_infer_routed(f->blob.as<unsigned char>(), (int64_t)field_pack_bytes(), f->geom_d.as<FieldGeom>(),
-                              pos, q, out, route, take, f->M, f->rcnt.as<unsigned int>(), f->rbase.as<int64_t>(),
+                              pos, q, out, route, take, f->M, f->rcnt.as<unsigned int>(),
+                              pb > 0 ? f->rpart.as<unsigned int>() : nullptr, f->rbase.as<int64_t>(),
                               f->ridx.as<int32_t>(), s);
     GM_HIP(hipGetLastError());
     return GM_OK;
@@ -280,6 +284,7 @@ gm_status gm_field_train(gm_field* f, const float* pos, const int32_t* mesh, con
     GM_HIP(f->scan_tmp.ensure(scan_tmp_bytes(n)));
     GM_HIP(f->pred.ensure(4 * (size_t)n));
     GM_HIP(f->l2sums.ensure(16 * (size_t)M));
+    GM_HIP(f->l2part.ensure((size_t)field_l2_part_bytes(n, M)));
 
     // held-out split (one Philox draw per point, for every network)
     const uint32_t key0 = (uint32_t)P->seed, key1 = (uint32_t)(P->seed >> 32);
@@ -362,8 +367,8 @@ gm_status gm_field_train(gm_field* f, const float* pos, const int32_t* mesh, con
     }
 
     // held-out relative L2 per mesh
-    zero(f->l2sums.p, 16 * (size_t)M, s);
-    launch_field_l2(f->pred.as<float>(), target, mesh, f->flag.as<uint32_t>(), n, M, f->l2sums.as<double>(), s);
+    launch_field_l2(f->pred.as<float>(), target, mesh, f->flag.as<uint32_t>(), n, M, f->l2part.as<double>(),
+                    f->l2sums.as<double>(), s);
     GM_HIP(hipGetLastError());
     std::vector<double> sums((size_t)(2 * M));
     GM_HIP(hipMemcpyAsync(sums.data(), f->l2sums.p, 16 * (size_t)M, hipMemcpyDeviceToHost, s));

@@ -310,13 +310,16 @@ void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const flo
                         const FieldRoute& route, hipStream_t s);
 // All networks in one launch, each over its own mesh's points only (route: the points'
 // meshes; take[m] != 0 selects the routed meshes, NULL: all).  Scratch: cnt [3 M], base
-// [3 M + 1], ridx [field_route_slots(q, M)].  A mesh whose points are contiguous in the
-// input is read in place (no list entries).
+// [3 M + 1], ridx [field_route_slots(q, M)], and per-chunk counts part
+// [field_route_part_bytes(q, M) bytes] (0 bytes: pass NULL, the counts then go through
+// global atomics).  A mesh whose points are contiguous in the input is read in place (no
+// list entries).
 int64_t field_route_slots(int64_t q, int32_t M);
+int64_t field_route_part_bytes(int64_t q, int32_t M);
 void launch_field_infer_routed(const unsigned char* blobs, int64_t pack_stride, const FieldGeom* geoms,
                                const float* pos, int64_t q, float* out, const FieldRoute& route,
-                               const uint8_t* take, int32_t M, unsigned int* cnt, int64_t* base, int32_t* ridx,
-                               hipStream_t s);
+                               const uint8_t* take, int32_t M, unsigned int* cnt, unsigned int* part, int64_t* base,
+                               int32_t* ridx, hipStream_t s);
 // sel[i] = flag[i] && mesh[i] == m
 void launch_field_select(const uint32_t* flag, const int32_t* mesh, int32_t m, int64_t n, uint32_t* sel, hipStream_t s);
 // One training step's forward and backward pass: the gradient grad [kFieldParams] and the
@@ -335,8 +338,11 @@ void launch_field_adam(float* master, float* m, float* v, float* grad, int64_t c
 void launch_field_split(int64_t n, uint32_t key0, uint32_t key1, uint32_t threshold, uint32_t* flag_train,
                         hipStream_t s);
 void launch_field_compact(const uint32_t* flag, const uint32_t* offs, int64_t n, int32_t* idx, hipStream_t s);
+// sums[2 m], sums[2 m + 1]: squared error and squared target over the held-out points of
+// mesh m, summed in a fixed order; part: field_l2_part_bytes(n, M) bytes of scratch
+int64_t field_l2_part_bytes(int64_t n, int32_t M);
 void launch_field_l2(const float* pred, const float* target, const int32_t* mesh, const uint32_t* flag_train,
-                     int64_t n, int32_t M, double* sums, hipStream_t s);
+                     int64_t n, int32_t M, double* part, double* sums, hipStream_t s);
 // query helpers
 void launch_gate_flags(const int32_t* mesh, const int32_t* tri, const int32_t* tri_mesh, int64_t T,
                        const uint8_t* gate, int32_t M, int64_t q, uint32_t* need, hipStream_t s);

@@ -29,6 +29,9 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kW = kFieldWidth;              // 64
 constexpr int kS1 = 104;                     // LDS row stride (bf16) of the layer-1 weights, padded
@@ -75,18 +78,43 @@ struct Acts {
     bf16x8 h[4][4];   // hidden layers 1..4, k-steps of the next product
 };
 
-__device__ __forceinline__ float softplus(float o) { return fmaxf(o, 0.0f) + log1pf(expf(-fabsf(o))); }
+// log(1 + e) with e = exp(-|o|) in (0, 1], through the hardware exp2/log2: 1 + e rounds away
+// at most 2^-24 of the sum, an absolute error below 1e-7 in the output
+__device__ __forceinline__ float softplus(float o) { return fmaxf(o, 0.0f) + __logf(1.0f + __expf(-fabsf(o))); }
 
-__device__ __forceinline__ void bias_relu(const unsigned char* lds, int layer, int h, const f32x16& a0,
-                                          const f32x16& a1, bf16x8 (&out)[4])
+// The accumulators of a layer start from its bias (in the accumulator layout), so the
+// products add onto it.
+__device__ __forceinline__ void bias_init(const unsigned char* lds, int layer, int h, f32x16& a0, f32x16& a1)
 {
     const float* bias = reinterpret_cast<const float*>(lds + kOffBias) + layer * kW;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int f = 8 * (v >> 2) + 4 * h + (v & 3);
-        out[v >> 3][v & 7] = (__bf16)fmaxf(a0[v] + bias[f], 0.0f);
-        out[2 + (v >> 3)][v & 7] = (__bf16)fmaxf(a1[v] + bias[32 + f], 0.0f);
+        a0[v] = bias[f];
+        a1[v] = bias[32 + f];
     }
+}
+
+// ReLU and BF16 rounding of a layer's accumulators into the next product's operand layout.
+// The ReLU acts on the rounded values (the same bits as rounding after it: rounding keeps
+// the sign), two at a time as 16-bit integers: a BF16 value is negative exactly when its
+// sign bit is set, so max(bits, 0) zeroes the negative ones.
+__device__ __forceinline__ bf16x8 relu_bf16x8(const f32x16& a, int v0)
+{
+    const f32x8 f = {a[v0], a[v0 + 1], a[v0 + 2], a[v0 + 3], a[v0 + 4], a[v0 + 5], a[v0 + 6], a[v0 + 7]};
+    // the empty asm keeps the conversion and the max apart: combined, the compiler would
+    // convert one value per instruction and repack the halves
+    u32x4 u = __builtin_bit_cast(u32x4, __builtin_convertvector(f, bf16x8));
+    asm("" : "+v"(u));
+    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(i16x8, u), i16x8{}));
+}
+
+__device__ __forceinline__ void relu_bf16(const f32x16& a0, const f32x16& a1, bf16x8 (&out)[4])
+{
+    out[0] = relu_bf16x8(a0, 0);
+    out[1] = relu_bf16x8(a0, 8);
+    out[2] = relu_bf16x8(a1, 0);
+    out[3] = relu_bf16x8(a1, 8);
 }
 
 // Forward pass of the 32 points of a wave (lane & 31 = point, lane >> 5 = half).
@@ -104,35 +132,37 @@ __device__ __forceinline__ float field_forward(const unsigned char* lds, const F
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int pr = 8 * ks + j;
-            const float arg = g.freq[pr / 3] * xt[pr % 3];
-            const float rev = (arg - floorf(arg)) + quarter;   // revolutions in [0, 1.25)
+            // revolutions, reduced to [0, 1) (the hardware sine takes a bounded range)
+            const float rev = __builtin_amdgcn_fractf(__builtin_fmaf(g.freq[pr / 3], xt[pr % 3], quarter));
             A.x0[ks][j] = (__bf16)__builtin_amdgcn_sinf(rev);  // sin(2 pi rev)
         }
     }
-    f32x16 c0 = {}, c1 = {};
+    f32x16 c0, c1;
+    bias_init(lds, 0, h, c0, c1);
 #pragma unroll
     for (int ks = 0; ks < 6; ++ks) {
         c0 = mfma(lds8(lds + kOffF1, n * kS1 + 16 * ks + 8 * h), A.x0[ks], c0);
         c1 = mfma(lds8(lds + kOffF1, (32 + n) * kS1 + 16 * ks + 8 * h), A.x0[ks], c1);
     }
-    bias_relu(lds, 0, h, c0, c1, A.h[0]);
+    relu_bf16(c0, c1, A.h[0]);
 #pragma unroll
     for (int L = 1; L < 4; ++L) {
         const unsigned char* F = lds + kOffF2 + (L - 1) * kMatH;
-        f32x16 d0 = {}, d1 = {};
+        f32x16 d0, d1;
+        bias_init(lds, L, h, d0, d1);
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             d0 = mfma(lds8(F, n * kSH + 16 * ks + 8 * h), A.h[L - 1][ks], d0);
             d1 = mfma(lds8(F, (32 + n) * kSH + 16 * ks + 8 * h), A.h[L - 1][ks], d1);
         }
-        bias_relu(lds, L, h, d0, d1, A.h[L]);
+        relu_bf16(d0, d1, A.h[L]);
     }
     const float* w5 = reinterpret_cast<const float*>(lds + kOffW5);
     float part = 0.0f;
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) part += w5[16 * ks + slot_feature(8 * h + j)] * (float)A.h[3][ks][j];
+        for (int j = 0; j < 8; ++j) part = __builtin_fmaf(w5[16 * ks + slot_feature(8 * h + j)], (float)A.h[3][ks][j], part);
     return part + __shfl_xor(part, 32, 64) + *reinterpret_cast<const float*>(lds + kOffB5);
 }
 
@@ -265,7 +295,10 @@ __global__ void __launch_bounds__(kThreads) k_field_infer_routed(const unsigned 
     const int64_t* count = base + 2 * M + 1;
     int staged = -1;
     FieldGeom g;
-    for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
+    // a contiguous run of groups per workgroup: it crosses at most a few mesh boundaries,
+    // so the weights are staged about once per workgroup
+    const int64_t g0 = groups * blockIdx.x / gridDim.x, g1 = groups * (blockIdx.x + 1) / gridDim.x;
+    for (int64_t gi = g0; gi < g1; ++gi) {
         const int m = group_mesh(base, M, gi * kGroup);
         if (m != staged) {
             __syncthreads();
@@ -336,16 +369,18 @@ __device__ __forceinline__ unsigned int wave_reserve(int m, unsigned int* __rest
 // Routing works on chunks of kRouteChunk points per workgroup: the chunk's per-mesh
 // counts are gathered in LDS (one LDS atomic per wave and mesh) and added to the global
 // ones with one atomic per mesh, so a few hundred global atomics route millions of points.
-constexpr int kRouteChunk = 16 * kThreads;
+constexpr int kRouteChunk = 8 * kThreads;
 constexpr int kRouteLds = 1024;  // meshes counted in LDS (more: one global atomic per wave and mesh)
 
 __global__ void __launch_bounds__(kThreads) k_route_count(const int32_t* __restrict__ mesh,
                                                           const int32_t* __restrict__ tri,
                                                           const int32_t* __restrict__ tri_mesh, int64_t T,
                                                           const uint8_t* __restrict__ take, int32_t M, int64_t q,
-                                                          unsigned int* __restrict__ cnt)
+                                                          unsigned int* __restrict__ cnt, unsigned int* __restrict__ part)
 {
-    // cnt: counts [M], then the smallest [M] and the largest [M] point index per mesh
+    // cnt: counts [M], then the smallest [M] and the largest [M] point index per mesh.  With
+    // part set, the chunk stores its own three rows at part[chunk][3 M] instead (no two
+    // chunks touch one address; k_route_reduce combines them)
     __shared__ unsigned int lc[3 * kRouteLds];
     const bool lds = M <= kRouteLds;
     unsigned int* c = lds ? lc : cnt;
@@ -357,13 +392,26 @@ __global__ void __launch_bounds__(kThreads) k_route_count(const int32_t* __restr
     }
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * kRouteChunk;
-#pragma unroll 4
-    for (int j = 0; j < kRouteChunk / kThreads; ++j) {
+    constexpr int kPer = kRouteChunk / kThreads;
+    int mm[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {  // every load in flight before the first reservation
         const int64_t i = c0 + j * kThreads + threadIdx.x;
-        const int m = i < q ? route_mesh(mesh, tri, tri_mesh, T, take, M, i) : -1;
-        (void)wave_reserve(m, c, c + stride, c + 2 * stride, i);
+        mm[j] = i < q ? route_mesh(mesh, tri, tri_mesh, T, take, M, i) : -1;
     }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        (void)wave_reserve(mm[j], c, c + stride, c + 2 * stride, c0 + j * kThreads + threadIdx.x);
     __syncthreads();
+    if (lds && part) {
+        unsigned int* row = part + (int64_t)blockIdx.x * 3 * M;
+        for (int m = threadIdx.x; m < M; m += kThreads) {
+            row[m] = lc[m];
+            row[M + m] = lc[kRouteLds + m];
+            row[2 * M + m] = lc[2 * kRouteLds + m];
+        }
+        return;
+    }
     for (int m = threadIdx.x; lds && m < M; m += kThreads)
         if (lc[m]) {
             atomicAdd(&cnt[m], lc[m]);
@@ -376,6 +424,36 @@ __global__ void k_route_init(unsigned int* __restrict__ cnt, int32_t M)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < 3 * M) cnt[i] = i >= M && i < 2 * M ? 0xffffffffu : 0u;
+}
+
+// one workgroup per mesh: its count, smallest and largest index over the chunks' rows
+__global__ void __launch_bounds__(kThreads) k_route_reduce(const unsigned int* __restrict__ part, int64_t chunks,
+                                                           int32_t M, unsigned int* __restrict__ cnt)
+{
+    __shared__ unsigned int rs[kThreads], rl[kThreads], rh[kThreads];
+    const int m = blockIdx.x;
+    unsigned int s = 0u, lo = 0xffffffffu, hi = 0u;
+    for (int64_t c = threadIdx.x; c < chunks; c += kThreads) {
+        const unsigned int* row = part + c * 3 * M;
+        s += row[m];
+        lo = min(lo, row[M + m]);
+        hi = max(hi, row[2 * M + m]);
+    }
+    rs[threadIdx.x] = s; rl[threadIdx.x] = lo; rh[threadIdx.x] = hi;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            rs[threadIdx.x] += rs[threadIdx.x + h];
+            rl[threadIdx.x] = min(rl[threadIdx.x], rl[threadIdx.x + h]);
+            rh[threadIdx.x] = max(rh[threadIdx.x], rh[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cnt[m] = rs[0];
+        cnt[M + m] = rl[0];
+        cnt[2 * M + m] = rh[0];
+    }
 }
 
 // one thread: padded segment starts, the in-place start of every mesh whose points are
@@ -432,9 +510,12 @@ __global__ void __launch_bounds__(kThreads) k_route_scatter(const int32_t* __res
     }
 }
 
-// a wave's gradient slot: its first tile writes, the later ones add (one lane per entry)
-__device__ __forceinline__ void put(float* p, float v, bool first) { *p = first ? v : *p + v; }
+// a wave's gradient slot: its first tile writes, the later ones add (one lane per entry);
+// ONE: every wave takes at most one tile, so every write is the first
+template <bool ONE>
+__device__ __forceinline__ void put(float* p, float v, bool first) { *p = ONE || first ? v : *p + v; }
 
+template <bool ONE>
 __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* __restrict__ blob, FieldGeom g,
                                                           FieldTrain t, FieldNets nets)
 {
@@ -482,7 +563,7 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
         const float o = field_forward(s_blob, g, t.pos[3 * i], t.pos[3 * i + 1], t.pos[3 * i + 2], lane, A);
         const float y = softplus(o);
         const float diff = ok ? y - t.target[i] : 0.0f;
-        const float dO = 2.0f * diff * t.inv_batch / (1.0f + expf(-o));  // d loss / d o
+        const float dO = __fdividef(2.0f * diff * t.inv_batch, 1.0f + __expf(-o));  // d loss / d o
         // loss and the output-layer gradients, reduced over the 32 points of the wave
         float se = h == 0 ? diff * diff : 0.0f, sb = h == 0 ? dO : 0.0f;
 #pragma unroll
@@ -491,8 +572,8 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
             sb += __shfl_xor(sb, d, 64);
         }
         if (lane == 0) {
-            t.lpart[slot] = first ? (double)se : t.lpart[slot] + (double)se;
-            put(&grad[kFieldOffB5], sb, first);
+            t.lpart[slot] = ONE || first ? (double)se : t.lpart[slot] + (double)se;
+            put<ONE>(&grad[kFieldOffB5], sb, first);
         }
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
@@ -501,7 +582,7 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
                 float gw = (float)A.h[3][ks][jj] * dO;
 #pragma unroll
                 for (int d = 1; d < 32; d <<= 1) gw += __shfl_xor(gw, d, 64);
-                if (n == 0) put(&grad[kFieldOffW5 + 16 * ks + slot_feature(8 * h + jj)], gw, first);
+                if (n == 0) put<ONE>(&grad[kFieldOffW5 + 16 * ks + slot_feature(8 * h + jj)], gw, first);
             }
         asm volatile("" ::: "memory");
         // dZ of layer 4 in the accumulator layout
@@ -553,14 +634,14 @@ __global__ void __launch_bounds__(kThreads) k_field_train(const unsigned char* _
                     const int krow = L == 1 ? input_feature(nb * 32 + n) : nb * 32 + n;
                     float* gW = grad + kFieldOffW[L] + krow * kW + mb * 32 + 4 * h;
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) put(gW + 8 * (v >> 2) + (v & 3), c[v], first);
+                    for (int v = 0; v < 16; ++v) put<ONE>(gW + 8 * (v >> 2) + (v & 3), c[v], first);
                 }
             // bias gradient: row sums of dZ (lane = output feature)
             {
                 float sbias = 0.0f;
 #pragma unroll
                 for (int p = 0; p < 32; ++p) sbias += (float)s_dz[wave][lane][p];
-                put(&grad[kFieldOffB[L] + lane], sbias, first);
+                put<ONE>(&grad[kFieldOffB[L] + lane], sbias, first);
             }
             if (L >= 2) {
                 const unsigned char* Bm = s_blob + kOffB2 + (L - 2) * kMatH;
@@ -605,7 +686,15 @@ __global__ void k_field_grad_reduce(const float* __restrict__ gpart, const doubl
     float sum = 0.0f;
     if (p < kFieldParams) {
         const float* src = gpart + (int64_t)net * slots * kFieldParams + p;
-        for (int w = w0; w < w1; ++w) sum += src[(int64_t)w * kFieldParams];
+        int w = w0;
+        for (; w + 8 <= w1; w += 8) {  // eight loads in flight, added in slot order
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = src[(int64_t)(w + k) * kFieldParams];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sum += v[k];
+        }
+        for (; w < w1; ++w) sum += src[(int64_t)w * kFieldParams];
     }
     rows[row][col] = sum;
     if (blockIdx.x == 0) {
@@ -667,17 +756,70 @@ __global__ void k_field_compact(const uint32_t* __restrict__ flag, const uint32_
     if (i < n && flag[i]) idx[offs[i]] = (int32_t)i;
 }
 
-__global__ void k_field_l2(const float* __restrict__ pred, const float* __restrict__ target,
-                           const int32_t* __restrict__ mesh, const uint32_t* __restrict__ flag, int64_t n, int32_t M,
-                           double* __restrict__ sums)
+// Held-out error sums per mesh, in a fixed order: workgroup (chunk, m) adds the squared
+// error and squared target of the held-out points of mesh m in its chunk of kL2Chunk points
+// (each thread its points in index order, then a fixed pairwise tree) into part[m][chunk];
+// k_field_l2_sum adds the chunks of each mesh the same way.  No atomics: the gate decision
+// is the same on every run.
+constexpr int kL2Chunk = 16 * kThreads;
+
+__device__ __forceinline__ void tree_sum2(double* a, double* b)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n || flag[i]) return;
-    const int m = mesh[i];
-    if (m < 0 || m >= M) return;
-    const double d = (double)pred[i] - (double)target[i];
-    atomicAdd(&sums[2 * m], d * d);
-    atomicAdd(&sums[2 * m + 1], (double)target[i] * (double)target[i]);
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            a[threadIdx.x] += a[threadIdx.x + h];
+            b[threadIdx.x] += b[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_field_l2(const float* __restrict__ pred, const float* __restrict__ target,
+                                                       const int32_t* __restrict__ mesh,
+                                                       const uint32_t* __restrict__ flag, int64_t n, int32_t M,
+                                                       double* __restrict__ part)
+{
+    __shared__ double se[kThreads], st[kThreads];
+    const int m = blockIdx.y;
+    const int64_t c0 = (int64_t)blockIdx.x * kL2Chunk;
+    double e = 0.0, s = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < kL2Chunk / kThreads; ++j) {
+        const int64_t i = c0 + j * kThreads + threadIdx.x;
+        if (i < n && !flag[i] && mesh[i] == m) {
+            const double d = (double)pred[i] - (double)target[i];
+            e += d * d;
+            s += (double)target[i] * (double)target[i];
+        }
+    }
+    se[threadIdx.x] = e;
+    st[threadIdx.x] = s;
+    __syncthreads();
+    tree_sum2(se, st);
+    if (threadIdx.x == 0) {
+        part[2 * ((int64_t)m * gridDim.x + blockIdx.x)] = se[0];
+        part[2 * ((int64_t)m * gridDim.x + blockIdx.x) + 1] = st[0];
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_field_l2_sum(const double* __restrict__ part, int64_t chunks,
+                                                           double* __restrict__ sums)
+{
+    __shared__ double se[kThreads], st[kThreads];
+    const int m = blockIdx.x;
+    double e = 0.0, s = 0.0;
+    for (int64_t c = threadIdx.x; c < chunks; c += kThreads) {
+        e += part[2 * (m * chunks + c)];
+        s += part[2 * (m * chunks + c) + 1];
+    }
+    se[threadIdx.x] = e;
+    st[threadIdx.x] = s;
+    __syncthreads();
+    tree_sum2(se, st);
+    if (threadIdx.x == 0) {
+        sums[2 * m] = se[0];
+        sums[2 * m + 1] = st[0];
+    }
 }
 
 __global__ void k_gate_flags(const int32_t* __restrict__ mesh, const int32_t* __restrict__ tri,
@@ -754,16 +896,24 @@ void launch_field_infer(const unsigned char* blob, const FieldGeom& g, const flo
 
 int64_t field_route_slots(int64_t q, int32_t M) { return q + (int64_t)kGroup * M; }
 
+int64_t field_route_part_bytes(int64_t q, int32_t M)
+{
+    const int64_t chunks = (q + kRouteChunk - 1) / kRouteChunk;
+    const int64_t b = chunks * 3 * (int64_t)M * 4;
+    return M <= kRouteLds && b <= ((int64_t)64 << 20) ? b : 0;
+}
+
 void launch_field_infer_routed(const unsigned char* blobs, int64_t pack_stride, const FieldGeom* geoms,
                                const float* pos, int64_t q, float* out, const FieldRoute& route,
-                               const uint8_t* take, int32_t M, unsigned int* cnt, int64_t* base, int32_t* ridx,
-                               hipStream_t s)
+                               const uint8_t* take, int32_t M, unsigned int* cnt, unsigned int* part, int64_t* base,
+                               int32_t* ridx, hipStream_t s)
 {
     if (q <= 0 || M <= 0) return;
     const int64_t slots = field_route_slots(q, M);
-    k_route_init<<<blocks(3 * (int64_t)M), kThreads, 0, s>>>(cnt, M);
     const unsigned chunks = (unsigned)((q + kRouteChunk - 1) / kRouteChunk);
-    k_route_count<<<chunks, kThreads, 0, s>>>(route.mesh, route.tri, route.tri_mesh, route.T, take, M, q, cnt);
+    if (!part) k_route_init<<<blocks(3 * (int64_t)M), kThreads, 0, s>>>(cnt, M);
+    k_route_count<<<chunks, kThreads, 0, s>>>(route.mesh, route.tri, route.tri_mesh, route.T, take, M, q, cnt, part);
+    if (part) k_route_reduce<<<(unsigned)M, kThreads, 0, s>>>(part, chunks, M, cnt);
     k_route_base<<<1, 1, 0, s>>>(cnt, M, base);
     k_route_scatter<<<chunks, kThreads, 0, s>>>(route.mesh, route.tri, route.tri_mesh, route.T, take, M, q, base,
                                                    cnt, ridx);
@@ -792,7 +942,10 @@ void launch_field_train(const unsigned char* blob, const FieldGeom& g, FieldTrai
     if (t.batch <= 0) return;
     const int tiles = (t.batch + 31) / 32;
     t.slots = field_train_slots(t.batch, 1);
-    k_field_train<<<(unsigned)(t.slots / (kThreads / 64)), kThreads, 0, s>>>(blob, g, t, FieldNets{});
+    if (tiles <= t.slots)
+        k_field_train<true><<<(unsigned)(t.slots / (kThreads / 64)), kThreads, 0, s>>>(blob, g, t, FieldNets{});
+    else
+        k_field_train<false><<<(unsigned)(t.slots / (kThreads / 64)), kThreads, 0, s>>>(blob, g, t, FieldNets{});
     k_field_grad_reduce<<<dim3((kFieldParams + kRedParams - 1) / kRedParams, 1), kThreads, 0, s>>>(
         t.gpart, t.lpart, std::min(tiles, t.slots), t.slots, nullptr, grad, loss);
 }
@@ -803,8 +956,11 @@ void launch_field_train_nets(const unsigned char* blob, const FieldNets& nets, i
     if (t.batch <= 0 || M <= 0) return;
     const int tiles = (t.batch + 31) / 32;
     t.slots = field_train_slots(t.batch, M);
-    k_field_train<<<dim3((unsigned)(t.slots / (kThreads / 64)), (unsigned)M), kThreads, 0, s>>>(blob, FieldGeom{}, t,
-                                                                                                  nets);
+    const dim3 grid((unsigned)(t.slots / (kThreads / 64)), (unsigned)M);
+    if (tiles <= t.slots)
+        k_field_train<true><<<grid, kThreads, 0, s>>>(blob, FieldGeom{}, t, nets);
+    else
+        k_field_train<false><<<grid, kThreads, 0, s>>>(blob, FieldGeom{}, t, nets);
     k_field_grad_reduce<<<dim3((kFieldParams + kRedParams - 1) / kRedParams, (unsigned)M), kThreads, 0, s>>>(
         t.gpart, t.lpart, std::min(tiles, t.slots), t.slots, nets.cnt, grad, loss);
 }
@@ -826,10 +982,16 @@ void launch_field_compact(const uint32_t* flag, const uint32_t* offs, int64_t n,
     if (n > 0) k_field_compact<<<blocks(n), kThreads, 0, s>>>(flag, offs, n, idx);
 }
 
+int64_t field_l2_part_bytes(int64_t n, int32_t M) { return 16 * ((n + kL2Chunk - 1) / kL2Chunk) * (int64_t)M; }
+
 void launch_field_l2(const float* pred, const float* target, const int32_t* mesh, const uint32_t* flag, int64_t n,
-                     int32_t M, double* sums, hipStream_t s)
+                     int32_t M, double* part, double* sums, hipStream_t s)
 {
-    if (n > 0) k_field_l2<<<blocks(n), kThreads, 0, s>>>(pred, target, mesh, flag, n, M, sums);
+    if (M <= 0) return;
+    const int64_t chunks = (n + kL2Chunk - 1) / kL2Chunk;
+    if (chunks > 0)
+        k_field_l2<<<dim3((unsigned)chunks, (unsigned)M), kThreads, 0, s>>>(pred, target, mesh, flag, n, M, part);
+    k_field_l2_sum<<<(unsigned)M, kThreads, 0, s>>>(part, chunks, sums);
 }
 
 void launch_gate_flags(const int32_t* mesh, const int32_t* tri, const int32_t* tri_mesh, int64_t T,
