@@ -255,7 +255,7 @@ __device__ __forceinline__ bool box_hit(const Seg& s, const float* lo, const flo
 // The slab parameters are clamped to [0, 1] by the multiply-adds themselves (the clamp bit
 // of v_fma_f32, no extra instruction).  With M the largest entry and m the smallest exit
 // parameter, the segment part [kTlo, 1] meets the box iff max(M, kTlo) < min(m, 1), which
-// for clamped values is C(M) < C(m) and C(m) > kTlo: two compares, no clamp of M or m.
+// for clamped values C is max(C(M), kTlo) < C(m): one max and one compare.
 __device__ __forceinline__ float fma01(float a, float b, float c)
 {
     return __builtin_amdgcn_fmed3f(__builtin_fmaf(a, b, c), 0.0f, 1.0f);
@@ -266,9 +266,9 @@ __device__ __forceinline__ bool box_hit_signed01(const Seg& s, const float* near
     const float nx = fma01(near[0], s.ix, s.qx), fx = fma01(far[0], s.ix, s.qx);
     const float ny = fma01(near[1], s.iy, s.qy), fy = fma01(far[1], s.iy, s.qy);
     const float nz = fma01(near[2], s.iz, s.qz), fz = fma01(far[2], s.iz, s.qz);
-    const float tn = fmaxf(fmaxf(nx, ny), nz);
+    const float tn = fmaxf(fmaxf(fmaxf(nx, ny), nz), kTlo);
     const float tf = fminf(fminf(fx, fy), fz);
-    return tn < tf && tf > kTlo;
+    return tn < tf;
 }
 
 __device__ __forceinline__ bool box_hit01(const Seg& s, const float* lo, const float* hi)
@@ -276,9 +276,9 @@ __device__ __forceinline__ bool box_hit01(const Seg& s, const float* lo, const f
     const float t0x = fma01(lo[0], s.ix, s.qx), t1x = fma01(hi[0], s.ix, s.qx);
     const float t0y = fma01(lo[1], s.iy, s.qy), t1y = fma01(hi[1], s.iy, s.qy);
     const float t0z = fma01(lo[2], s.iz, s.qz), t1z = fma01(hi[2], s.iz, s.qz);
-    const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
+    const float tn = fmaxf(fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z)), kTlo);
     const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
-    return tn < tf && tf > kTlo;
+    return tn < tf;
 }
 
 // Triangle vertices relative to a segment's start (a ray's eye, or a visibility
