@@ -125,6 +125,13 @@ def main():
     g_ms, g_n = scene.profile_read("density")
     scene.profile(False)
     gate_ms = g_ms / max(1, g_n)
+    # the tile cone test skips, per tile, the fixations whose cone cannot reach it: the
+    # per-sample gate runs for the (tile, fixation) pairs it keeps, on 512 samples each
+    # (two per lane, the library's choice with occlusion off)
+    gate_kept = scene.density_stats()["gate_fixations"]
+    gate_tiles = -(-N // 512)
+    gate_evaluated = float(gate_kept) * 512
+    gate_frac = GATE_FLOP_PER_PAIR * gate_evaluated / (gate_ms * 1e-3) / PEAK_FP32_VALU
     step()
     torch.cuda.synchronize()
     counters = scene.density_stats()
@@ -163,8 +170,7 @@ def main():
                      # issue of divergent packet tests), which the FLOP count above does not price:
                      # the two parts separately
                      "limiter": "BVH traversal of the in-cone segments (VALU issue of divergent packet tests)",
-                     "parts": {"gate": {"kernel_ms": gate_ms,
-                                        "frac_fp32_peak": GATE_FLOP_PER_PAIR * pairs / (gate_ms * 1e-3) / PEAK_FP32_VALU},
+                     "parts": {"gate": {"kernel_ms": gate_ms, "frac_fp32_peak_evaluated": gate_frac},
                                "visibility": {"ms": dens_ms - gate_ms,
                                               "share_of_kernel": (dens_ms - gate_ms) / dens_ms,
                                               "rays_per_s": counters["in_cone"] / ((dens_ms - gate_ms) * 1e-3),
@@ -173,7 +179,10 @@ def main():
                                                    TRI_BYTES * counters["triangle_tests"]) /
                                                   ((dens_ms - gate_ms) * 1e-3) / PEAK_HBM}}},
         "gate_only": {"kernel_ms": gate_ms, "pairs_per_s": pairs / (gate_ms * 1e-3),
-                      "frac_fp32_peak": GATE_FLOP_PER_PAIR * pairs / (gate_ms * 1e-3) / PEAK_FP32_VALU},
+                      "tile_fixations_kept": gate_kept, "tile_fixations_total": gate_tiles * F,
+                      "evaluated_pairs": gate_evaluated,
+                      # 16 FLOP per pair over the pairs the per-sample gate actually evaluated
+                      "frac_fp32_peak_evaluated": gate_frac},
         "visibility": {"in_cone_pairs": counters["in_cone"], "visible_pairs": counters["visible"],
                        "backface_rule_pairs": counters["backface"],
                        "rays_per_s": counters["in_cone"] / (dens_ms * 1e-3),
@@ -467,6 +476,9 @@ def bench_batched(gm, workloads, torch, args):
             x["scene"].accumulate(x["pos"], x["fix"], x["theta_deg"], occlusion="full", tri=x["tri"], mesh=x["mesh"],
                                   out=o)
     plain()
+    torch.cuda.synchronize()
+    st = [x["scene"].density_stats() for x in sessions]   # counters of each session's call
+    in_cone = float(sum(s["in_cone"] for s in st))
     plain_ms = _time(plain, torch, max(1, args.steps // 2))
     cache = os.environ.get("GM_TUNE_CACHE") or "/tmp/gazemap_tune.json"
     t0 = time.perf_counter()
@@ -475,8 +487,10 @@ def bench_batched(gm, workloads, torch, args):
     batch.run()
     batched_ms = _time(batch.run, torch, max(1, args.steps // 2))
     same = all(bool(torch.equal(a.density, b.density)) for a, b in zip(outs, batch.outputs))
-    return {"sessions": 64, "pairs": pairs, "plain_sequential_ms": plain_ms, "batched_graph_ms": batched_ms,
-            "speedup": plain_ms / batched_ms, "bit_equal_to_plain": same, "plan_and_tune_s": tune_s,
+    return {"sessions": 64, "pairs": pairs, "in_cone_pairs": in_cone,
+            "in_cone_fraction": in_cone / pairs, "plain_sequential_ms": plain_ms, "batched_graph_ms": batched_ms,
+            "speedup": plain_ms / batched_ms, "pairs_per_s": pairs / (batched_ms * 1e-3),
+            "rays_per_s": in_cone / (batched_ms * 1e-3), "bit_equal_to_plain": same, "plan_and_tune_s": tune_s,
             "tile_config": batch.info()}
 
 

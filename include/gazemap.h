@@ -571,8 +571,11 @@ gm_status gm_density_stats(gm_scene* scene, int64_t* out);
 
 /* gm_density_counters: the same counters and more, host int64 out[n_out] = {the four
  * above, triangle tests (one per triangle tested by a packet for at least one of its
- * segments), in-cone pairs settled by the back-face rule (see gm_scene_mesh_closed)};
- * entries past the known counters are set to 0.  Blocking. */
+ * segments), in-cone pairs settled by the back-face rule (see gm_scene_mesh_closed),
+ * fixations that the per-sample cone gate evaluated, summed over work items (a work item is
+ * a tile of samples and a chunk of fixations; a fixation whose cone cannot reach the tile's
+ * bounding sphere is skipped for the whole tile)}; entries past the known counters are set
+ * to 0.  Blocking. */
 gm_status gm_density_counters(gm_scene* scene, int64_t* out, int32_t n_out);
 
 /*

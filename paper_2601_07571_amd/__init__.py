@@ -257,10 +257,12 @@ class Scene:
 
     def density_stats(self):
         """Counters of the last accumulate call: in-cone pairs, visible pairs, traversals,
-        node visits, triangle tests (wave level), pairs settled by the back-face rule."""
-        out = (ctypes.c_int64 * 6)()
-        _check(_lib.gm_density_counters(self._h, out, 6))
-        return dict(zip(("in_cone", "visible", "traversals", "node_visits", "triangle_tests", "backface"), out[:]))
+        node visits, triangle tests (wave level), pairs settled by the back-face rule,
+        (work item, fixation) pairs that passed the tile cone test."""
+        out = (ctypes.c_int64 * 7)()
+        _check(_lib.gm_density_counters(self._h, out, 7))
+        return dict(zip(("in_cone", "visible", "traversals", "node_visits", "triangle_tests", "backface",
+                         "gate_fixations"), out[:]))
 
     def mesh_closed(self):
         """Per mesh: whether the visibility test treats it as bounding a solid."""

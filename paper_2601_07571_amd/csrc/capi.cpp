@@ -238,9 +238,14 @@ void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F
     if (fix_per_chunk <= 0) {
         // The cost of a (tile, chunk) item varies a lot (how many of its fixations see
         // the tile), so the grid holds many small items: at least ~512k of them and at
-        // most 1024 fixations each, but chunks of no fewer than 128 fixations.
+        // most 1024 fixations each, but chunks of no fewer than 128 fixations.  Without
+        // a visibility test an item costs little beyond its fixed part (its samples,
+        // the staging and the tile cone test of every fixation, the flush), so chunks
+        // are at least 512 fixations long there (the paper-shaped gate: 2.43 ms at 128,
+        // 1.71 ms at 512, 1.74 ms at 1024).
         const int64_t tiles = std::max<int64_t>(1, (n + 256 * spl - 1) / (256 * spl));
-        const int64_t max_chunks = std::max<int64_t>(1, (F + 127) / 128);
+        const int64_t min_chunk = mode == GM_OCC_NONE ? 512 : 128;
+        const int64_t max_chunks = std::max<int64_t>(1, (F + min_chunk - 1) / min_chunk);
         const int64_t want = std::max<int64_t>((524288 + tiles - 1) / tiles, (F + 1023) / 1024);
         // the grid is tiles x chunks: chunks <= 65535 (grid y) and tiles x chunks < 2^31
         const int64_t cap = std::min<int64_t>(65535, std::max<int64_t>(1, INT32_MAX / tiles));
@@ -340,6 +345,7 @@ gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** ou
     if (T >= (int64_t)1 << 31) return fail(GM_ERR_INVALID_ARGUMENT, "more than 2^31 - 1 triangles");
     gm_scene* sc = new (std::nothrow) gm_scene();
     if (!sc) return fail(GM_ERR_OUT_OF_MEMORY, "host allocation failed");
+    if (const char* e = std::getenv("GM_FIX_PER_CHUNK")) sc->fix_per_chunk = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("GM_SAMPLES_PER_LANE")) {
         const int v = std::atoi(e);
         if (v == 1 || v == 2 || v == 4) sc->spl = v;
@@ -571,7 +577,7 @@ gm_status accumulate_density(gm_scene* sc, const float* pos, const int32_t* tri,
     DensityLaunch a;
     GM_HIP(sc->tbegin(kStagePrep, s));
     const int spl = sc->spl ? sc->spl : ((flags & GM_OCC_MASK) != GM_OCC_NONE ? 1 : 2);
-    st = density_prep(sc, w, pos, tri, mesh, n, fix, theta_deg, flags & GM_OCC_MASK, spl, 0, a, s);
+    st = density_prep(sc, w, pos, tri, mesh, n, fix, theta_deg, flags & GM_OCC_MASK, spl, sc->fix_per_chunk, a, s);
     if (st != GM_OK) return st;
 
     GM_HIP(sc->tend(kStagePrep, s));

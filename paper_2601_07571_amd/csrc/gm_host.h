@@ -181,6 +181,8 @@ struct gm_scene {
     // samples per lane of the plain density kernel; 0 = by occlusion mode (1 with a
     // visibility test, whose cost is per segment, 2 for the gate-only kernel)
     int32_t spl = 0;
+    // fixations per work item of the plain density kernel; 0 = automatic (GM_FIX_PER_CHUNK)
+    int32_t fix_per_chunk = 0;
     bool profiling = false;
     StageTimer timers[kStages];
 

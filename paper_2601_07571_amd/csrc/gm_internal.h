@@ -114,8 +114,8 @@ void launch_sample(const float* V, const int32_t* I, const unsigned long long* C
 
 // density path
 // in-cone pairs, visible pairs, packet traversals, BVH node visits, triangle tests (wave level),
-// pairs settled by the back-face rule
-constexpr int kDensityStats = 6;
+// pairs settled by the back-face rule, (work item, fixation) pairs kept by the tile cone test
+constexpr int kDensityStats = 7;
 // Tolerance of the exact visibility test (the exact counterpart of the depth test of
 // Sec. 3.2.2): a hit occludes when its parameter tau on the segment eye + tau (x - eye)
 // lies in (0, 1 - kEpsV).  The kernels take the bound as a compile-time constant.

@@ -1368,6 +1368,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
     __shared__ unsigned long long s_acc[kThreads * SPL];  // one entry per sample, owned by one lane
     __shared__ float s_rad;
     __shared__ uint32_t s_stats[kDensityStats];
+    __shared__ uint32_t s_keep[kThreads / 64];  // fixations of the block kept by each staging wave
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -1406,26 +1407,68 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
     const int f_end = uniform(min(F, f_begin + a.fix_per_chunk));
 
     for (int fb = f_begin; fb < f_end; fb += FB) {
-        const int nb = uniform(min(FB, f_end - fb));
+        const int nbf = uniform(min(FB, f_end - fb));
         __syncthreads();
-        if (threadIdx.x < nb) {
+        // Staging, one thread per fixation of the block.  Only fixations whose gate cone
+        // can reach the tile are kept (listed in order, with their index): a sample x
+        // passes the gate iff the angle between r and x - e is below psi_g, cos^2 psi_g =
+        // kappa / |r|^2, and every sample lies within rad_t of the origin o, so the tile
+        // can hold a passing sample only if angle(r, o - e) < psi_g + delta, sin delta =
+        // rad_t / |o - e|.  The test adds 1e-4 rad to that angle, far above the FP32
+        // error of the gate itself, so every fixation that the per-sample gate would pass
+        // for some sample of the tile is kept; the others could only be skipped there.
+        bool keep = false;
+        if (threadIdx.x < nbf) {
             const FixRec fr = a.fix[fb + threadIdx.x];
+            const float ex = fr.ex - o4.x, ey = fr.ey - o4.y, ez = fr.ez - o4.z;
+            const float e2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+            const float c0 = -__builtin_fmaf(fr.rx, ex, __builtin_fmaf(fr.ry, ey, fr.rz * ez));
+            if (fr.w > 0.0f) {  // zero weight: contributes nothing anywhere
+                // the tile's bounding radius about its origin, rounded up
+                const float rad_t = __builtin_fmaf(sqrtf(s_rad), 1.001f, 1e-6f);
+                const float rr = __builtin_fmaf(fr.rx, fr.rx, __builtin_fmaf(fr.ry, fr.ry, fr.rz * fr.rz));
+                const float cg2 = fminf(fr.kappa / rr, 1.0f);
+                const float cg = sqrtf(cg2), sg = sqrtf(1.0f - cg2);
+                const float sd = fminf(rad_t * __frsqrt_rn(e2), 1.0f);
+                const float cd = sqrtf(fmaxf(1.0f - sd * sd, 0.0f));
+                const float cA = cg * cd - sg * sd, sA = sg * cd + cg * sd;  // cos, sin (psi_g + delta)
+                const float cT = __builtin_fmaf(-1e-4f, sA, cA);            // cos (psi_g + delta + 1e-4)
+                keep = e2 <= near2 || !(cT > 0.0f) || (c0 > 0.0f && c0 * c0 > cT * cT * rr * e2);
+            }
+        }
+        // the kept fixations in block order: a wave-level prefix, then the waves in order
+        const uint64_t kb = ballot(keep);
+        if (lane == 0) s_keep[wave] = (uint32_t)__popcll(kb);
+        __syncthreads();
+        uint32_t pos = (uint32_t)__popcll(kb & ((1ull << lane) - 1ull)), nb_all = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            const uint32_t c = s_keep[w];
+            pos += w < wave ? c : 0u;
+            nb_all += c;
+        }
+        const int nb = uniform((int)nb_all);
+        if (keep) {
+            // the record again (a cached reload: fewer registers held across the barrier)
+            const int fidx = fb + threadIdx.x;
+            const FixRec fr = a.fix[fidx];
             const float ex = fr.ex - o4.x, ey = fr.ey - o4.y, ez = fr.ez - o4.z;
             const float e2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
             const float k = fr.kappa;
             const float c0 = -__builtin_fmaf(fr.rx, ex, __builtin_fmaf(fr.ry, ey, fr.rz * ez));
-            float cc = -k * e2;
-            if (e2 <= near2 && fr.w > 0.0f) cc = 3.0e38f;  // force s > 0 for every sample of the tile
-            s_co[3 * threadIdx.x] = make_float4(fr.rx, fr.ry, fr.rz, c0);
-            s_co[3 * threadIdx.x + 1] = make_float4(2.0f * k * ex, 2.0f * k * ey, 2.0f * k * ez, cc);
-            s_co[3 * threadIdx.x + 2].x = -k;
+            // an eye within 2 tile radii: s > 0 for every sample of the tile
+            const float cc = e2 <= near2 ? 3.0e38f : -k * e2;
+            s_co[3 * pos] = make_float4(fr.rx, fr.ry, fr.rz, c0);
+            s_co[3 * pos + 1] = make_float4(2.0f * k * ex, 2.0f * k * ey, 2.0f * k * ez, cc);
+            s_co[3 * pos + 2] = make_float4(-k, __int_as_float(fidx), 0.0f, 0.0f);
         }
         if (threadIdx.x < kGateGroup - 1) {
             // s = 0 * |0| + (-3e38) < 0 at every point: never a candidate
             s_co[3 * (nb + threadIdx.x)] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             s_co[3 * (nb + threadIdx.x) + 1] = make_float4(0.0f, 0.0f, 0.0f, -3.0e38f);
-            s_co[3 * (nb + threadIdx.x) + 2].x = 0.0f;
+            s_co[3 * (nb + threadIdx.x) + 2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
+        if (threadIdx.x == 0) s_stats[6] += (uint32_t)nb;  // only thread 0 writes it until the end
         __syncthreads();
         for (int jg = 0; jg < nb; jg += kGateGroup) {
             // the gate of kGateGroup fixations, one wave mask per fixation and slot; a group
@@ -1468,7 +1511,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
 
                 // exact path for this fixation: values of the passing slots, then one packet
                 // traversal for every slot that needs a visibility answer
-                const int f = uniform(fb + jg + h);
+                const int f = uniform(__float_as_int(s_co[3 * (jg + h) + 2].y));
                 const FixRec fr = load_fix(a.fix, f);
                 float g[SPL];
                 float4 p[SPL];

@@ -257,10 +257,13 @@ def test_counters(gm):
     c = scene.density_stats()
     four = (ctypes.c_int64 * 4)()
     assert gm._lib.gm_density_stats(scene._h, four) == 0
-    seven = (ctypes.c_int64 * 7)()
-    assert gm._lib.gm_density_counters(scene._h, seven, 7) == 0
+    eight = (ctypes.c_int64 * 8)()
+    assert gm._lib.gm_density_counters(scene._h, eight, 8) == 0
     assert list(four) == [c["in_cone"], c["visible"], c["traversals"], c["node_visits"]]
-    assert list(seven)[:6] == list(c.values()) and seven[6] == 0
+    assert list(eight)[:7] == list(c.values()) and eight[7] == 0
+    # the tile cone test keeps some but not all (tile, fixation) pairs of the 100 fixations
+    tiles = -(-int(s.pos.shape[0]) // 256)
+    assert 0 < c["gate_fixations"] < tiles * fix.n
     assert 0 < c["visible"] < c["in_cone"] and c["traversals"] > 0
     assert 0 < c["backface"] < c["in_cone"] - c["visible"]      # the closed sphere's far side
     assert 0 < c["triangle_tests"] <= 2 * 4 * c["node_visits"]
