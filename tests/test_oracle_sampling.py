@@ -59,6 +59,23 @@ def test_weights_exact_integer_brute_force():
     assert W[5] == 0
 
 
+def test_weights_literal_examples():
+    """The integer weights written out: with n areas and the largest M, the scale is
+    S = 52 - e where n M = f 2^e, f in [0.5, 1), and W_i = floor(A_i 2^S).  Binary fractions
+    0.5, 0.25, 0.125 (n M = 2 = 0.5 * 2^2, S = 50) give 2^49, 2^48, 2^47; the doubles nearest
+    0.3 and 0.1 (n M = 0.6, S = 52) give floor(0.29999999999999998889... * 2^52) and
+    floor(0.10000000000000000555... * 2^52)."""
+    W, C, S, tot = oracle.mesh_weights(np.array([0.5, 0.25, 0.125, 0.0]))
+    assert S == 50
+    assert [int(x) for x in W] == [562949953421312, 281474976710656, 140737488355328, 0]
+    assert [int(x) for x in C] == [562949953421312, 844424930131968, 985162418487296, 985162418487296]
+    assert tot == 985162418487296
+    W, C, S, tot = oracle.mesh_weights(np.array([0.3, 0.1]))
+    assert S == 52
+    assert [int(x) for x in W] == [1351079888211148, 450359962737049]
+    assert tot == 1351079888211148 + 450359962737049
+
+
 def test_count_config1_is_k_times_area():
     w = workloads.tiny_icosphere_scene()
     m = w.meshes[0]
