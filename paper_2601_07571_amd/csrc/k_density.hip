@@ -695,16 +695,40 @@ __device__ __forceinline__ bool backface_rule(float nx, float ny, float nz, int 
 }
 
 // the rule for point i of a density launch (sorted order)
-__device__ __forceinline__ bool backface_occluded(const DensityLaunch& a, int64_t i, float xx, float xy, float xz,
-                                                  float ex, float ey, float ez)
+// The rule's buffers, copied to LDS once per work item and read back where the rule runs:
+// the kernel arguments then need not stay in scalar registers across the whole kernel
+// (which cost the posed-map kernel its register budget).
+struct BfArgs {
+    const float4* bface;
+    const int32_t* bcand;
+    const float4* mbox;
+    const BvhTri* tris;
+    float l2max;
+};
+
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p)
 {
-    const float4 bf = a.bface[i];
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T*)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ bool backface_occluded(const BfArgs& s_bf, const int32_t* smesh, int64_t i, float xx,
+                                                  float xy, float xz, float ex, float ey, float ez)
+{
+    const float4* bface = uniform_ptr(s_bf.bface);
+    const float4 bf = bface[i];
     const int c = __float_as_int(bf.w);
     if (c < 0) return false;
-    const int m = a.smesh[i];
-    const int32_t* cand = a.bcand + kBfCand * i;
+    const int m = smesh[i];
+    const int32_t* cand = uniform_ptr(s_bf.bcand) + kBfCand * i;
+    const float4* mbox = uniform_ptr(s_bf.mbox);
     return backface_rule(bf.x, bf.y, bf.z, c, [cand](int j) { return cand[j]; }, xx, xy, xz, ex, ey, ez,
-                         a.mbox[2 * m], a.mbox[2 * m + 1], a.bf_L2max, a.bf_tris);
+                         mbox[2 * m], mbox[2 * m + 1],
+                         __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(s_bf.l2max))),
+                         uniform_ptr(s_bf.tris));
 }
 
 // Ray e + t d in the same sheared form as a segment with tmax = 1 (so s.tz = d[kz]).
@@ -1369,6 +1393,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
     __shared__ float s_rad;
     __shared__ uint32_t s_stats[kDensityStats];
     __shared__ uint32_t s_keep[kThreads / 64];  // fixations of the block kept by each staging wave
+    __shared__ BfArgs s_bf;                      // the back-face rule's buffers
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -1380,6 +1405,7 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
     const float4 o4 = a.spos[tile_base];
     if (threadIdx.x == 0) s_rad = 0.0f;
     if (threadIdx.x < kDensityStats) s_stats[threadIdx.x] = 0u;
+    if (OCC != 0 && !ZB && threadIdx.x == 0) s_bf = BfArgs{a.bface, a.bcand, a.mbox, a.bf_tris, a.bf_L2max};
     __syncthreads();
     uint32_t n_in = 0, n_vis = 0, n_trav = 0, n_bf = 0;  // wave-uniform counters
     TravCount n_visits;
@@ -1542,13 +1568,15 @@ __device__ __forceinline__ void density_item(const DensityLaunch& a, int64_t til
                 bool occl[SPL];
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) occl[k] = false;
-                if (OCC != 0 && !INST && !ZB && a.bface && ballot(any_need) != 0) {
-                    // the back-face rule first: pairs it settles leave the packet
+                if (OCC != 0 && !ZB && a.bface && ballot(any_need) != 0) {
+                    // the back-face rule first: pairs it settles leave the packet (posed
+                    // launches: sample and eye in the sample's own mesh frame)
                     any_need = false;
 #pragma unroll
                     for (int k = 0; k < SPL; ++k) {
                         const int64_t i = wave_base + k * 64 + lane;
-                        if (need[k] && backface_occluded(a, i, p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez)) {
+                        if (need[k] &&
+                            backface_occluded(s_bf, a.smesh, i, p[k].x, p[k].y, p[k].z, fr.ex, fr.ey, fr.ez)) {
                             need[k] = false;
                             occl[k] = true;
                         }

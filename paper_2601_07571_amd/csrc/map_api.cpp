@@ -270,6 +270,28 @@ gm_status gm_map_create(gm_scene* sc, const float* pos, const int32_t* tri, cons
             const int64_t off = moff[(size_t)k], nk = moff[(size_t)k + 1] - off;
             density_sort(sc, m->w, pos + 3 * off, tri ? tri + off : nullptr, mesh + off, nk, s, off);
         }
+        // The back-face rule per mesh segment, in the meshes' own frames: a launch for mesh
+        // k sees its samples and the fixations in k's frame, where the rule's closedness,
+        // box and neighbour data hold for every pose (the motion is rigid).  The buffers
+        // are sized for all points first (a segment call must not reallocate them).
+        if (m->mode != GM_OCC_NONE && sc->any_closed() && n > 0) {
+            st = (m->w.bface.ensure(16 * (size_t)n) == hipSuccess &&
+                  m->w.bcand.ensure(4 * (size_t)kBfCand * (size_t)n) == hipSuccess)
+                     ? GM_OK
+                     : fail(GM_ERR_OUT_OF_MEMORY, "back-face rule data");
+            bool all = true;
+            for (int32_t k = 0; k < sc->M && st == GM_OK; ++k) {
+                const int64_t off = moff[(size_t)k], nk = moff[(size_t)k + 1] - off;
+                if (nk <= 0) continue;
+                st = density_backface(sc, m->w, nk, m->mode, s, off);
+                all = all && m->w.backface;
+            }
+            m->w.backface = st == GM_OK && all;
+            if (st != GM_OK) {
+                delete m;
+                return st;
+            }
+        }
     }
     st = map_clear(m, s);
     if (st == GM_OK) {
@@ -359,6 +381,10 @@ gm_status gm_map_add_posed(gm_map* m, const gm_fixations* fix, const float* pose
         a.acc += off;
         a.fix = m->recs.as<FixRec>() + (int64_t)k * stride;
         a.F_live = m->live.as<unsigned int>();
+        if (a.bface) {
+            a.bface += off;
+            a.bcand += kBfCand * off;
+        }
         if (m->mode != GM_OCC_NONE) {
             a.blas = sc->blas_desc.as<BlasDesc>();
             a.blas_nodes = sc->blas_nodes.as<BvhNode>();
