@@ -84,8 +84,10 @@ gm_status gm_scene_info(const gm_scene* scene, int64_t* n_triangles, int32_t* n_
 /*
  * gm_scene_mesh_closed -- host uint8 closed [n_meshes]: 1 for the meshes the visibility
  * test treats as bounding a solid (gm_mesh_closed at creation, unless cleared).  For such
- * a mesh a point seen from behind (the eye on the inner side of its triangle's plane by
- * a cosine of at least 1e-3), from an eye outside the mesh's bounding box, is occluded by
+ * a mesh a point seen from behind (the eye on the inner side of its triangle's plane, with
+ * c D >= 4 eta: c the cosine between the segment and the plane's normal, D the point's
+ * distance to its triangle's edges, eta = 2^-24 (|x| + |y| + |z|) the FP32 spacing at the
+ * point), from an eye outside the mesh's bounding box, is occluded by
  * the mesh itself (Sec. 3.2.2's visibility: the segment must enter the solid before it
  * reaches the point); accumulate_density then skips the BVH walk for the pair when no
  * triangle of the mesh other than the point's own comes within 1e-4 of the segment's
