@@ -26,6 +26,10 @@ PEAK_FP32_VALU = 157.3e12      # MI355X FP32 vector peak, FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E peak, bytes/s
 NODE_BYTES, TRI_BYTES = 64, 48 # BVH node and triangle record sizes
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_density_traffic_paper_shaped.md")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "k_density_valu_paper_shaped.md")
+SIMDS = 256 * 4                # compute units x SIMDs
+CLOCK_HZ = 2.4e9
+VALU_CYCLES = 4                # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
 COPY_PROBE_BYTES = 256 << 20   # the calibration copy of --traffic-probe (read and written once each)
 GATE_FLOP_PER_PAIR = 16        # 8 FMA per (sample, fixation) pair in the cone gate
 FIELD_FLOP_PER_POINT = 2 * (96 * 64 + 3 * 64 * 64 + 64)   # the field's four layer products and output
@@ -137,6 +141,7 @@ def main():
     counters = scene.density_stats()
 
     achieved = GATE_FLOP_PER_PAIR * pairs / (dens_ms * 1e-3)
+    valu_n = measured_valu()
     out = {
         "metric": "fixation-sample pairs/s (map of 2M samples x 6k fixations)",
         "value": pairs / (ms_step * 1e-3),
@@ -171,6 +176,12 @@ def main():
                      # the two parts separately
                      "limiter": "BVH traversal of the in-cone segments (VALU issue of divergent packet tests)",
                      "parts": {"gate": {"kernel_ms": gate_ms, "frac_fp32_peak_evaluated": gate_frac},
+                               # the instruction-issue roof the kernel actually meets: its VALU
+                               # wave instructions (counted by rocprofv3 on this kernel) at 4 cycles
+                               # each, against every SIMD's cycles over the kernel's time
+                               "valu_issue": {"instructions": valu_n,
+                                              "frac": (valu_n * VALU_CYCLES / (SIMDS * CLOCK_HZ * dens_ms * 1e-3)
+                                                       if valu_n else None)},
                                "visibility": {"ms": dens_ms - gate_ms,
                                               "share_of_kernel": (dens_ms - gate_ms) / dens_ms,
                                               "rays_per_s": counters["in_cone"] / ((dens_ms - gate_ms) * 1e-3),
@@ -267,25 +278,37 @@ def traffic_sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the full-occlusion density kernel from the committed
-    counter summary, or None when the kernel or its launch configuration changed since
-    it was taken."""
+def summary_field(path, key):
+    """A number recorded in a committed rocprofv3 summary ("- key: `value`" lines), or None
+    when the density kernel or its launch configuration changed since it was taken (the
+    summary's "k_density.hip + capi.cpp sha256" no longer matches)."""
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(path).read()
     except OSError:
         return None
     fields = {}
     for line in text.splitlines():
         if line.startswith("- ") and ":" in line:
-            key, val = line[2:].split(":", 1)
-            fields[key.strip()] = val.strip().strip("`")
+            k, val = line[2:].split(":", 1)
+            fields[k.strip()] = val.strip().strip("`")
     if fields.get("k_density.hip + capi.cpp sha256") != traffic_sources_digest():
         return None
     try:
-        return float(fields["traffic bytes per launch"])
+        return float(fields[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the full-occlusion density kernel (FETCH_SIZE + WRITE_SIZE,
+    calibrated), from the committed counter summary."""
+    return summary_field(TRAFFIC_SUMMARY, "traffic bytes per launch")
+
+
+def measured_valu():
+    """VALU wave instructions per launch of the full-occlusion density kernel
+    (SQ_INSTS_VALU), from the committed counter summary."""
+    return summary_field(VALU_SUMMARY, "full-occlusion VALU instructions per launch")
 
 
 def _time(fn, torch, reps):
