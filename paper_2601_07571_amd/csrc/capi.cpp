@@ -187,7 +187,7 @@ gm_status density_reserve(DensityWork& w, int64_t n, int32_t F)
     GM_HIP(w.scan_tmp.ensure(scan_tmp_bytes(w.buckets)));
     GM_HIP(w.spos.ensure(16 * nn));
     GM_HIP(w.smesh.ensure(4 * nn));
-    GM_HIP(w.perm.ensure(4 * nn));
+    GM_HIP(w.inv.ensure(4 * nn));
     GM_HIP(w.acc.ensure(8 * nn));
     GM_HIP(w.max_acc.ensure(8));
     GM_HIP(w.stats.ensure(8 * kDensityStats));
@@ -213,7 +213,7 @@ void density_sort(gm_scene* sc, DensityWork& w, const float* pos, const int32_t*
     launch_exclusive_scan_u32(w.hist.as<uint32_t>(), w.cursor.as<uint32_t>(), w.buckets, w.scan_tmp.p, s);
     launch_scatter(pos, tri, mesh, sc->tri_mesh.as<int32_t>(), sc->T, n, w.key.as<uint32_t>(),
                    w.cursor.as<uint32_t>(), w.spos.as<float4>() + off, w.smesh.as<int32_t>() + off,
-                   w.perm.as<int32_t>() + off, (int32_t)off, s);
+                   w.inv.as<int32_t>() + off, (int32_t)off, s);
 }
 
 void density_args(const gm_scene* sc, const DensityWork& w, int64_t n, int32_t F, double sigma, uint32_t mode,
@@ -308,7 +308,7 @@ gm_status density_prep(gm_scene* sc, DensityWork& w, const float* pos, const int
 gm_status density_finalize(DensityWork& w, int64_t n, float* density, float* density_norm, float* max_out,
                            hipStream_t s)
 {
-    launch_finalize(w.acc.as<unsigned long long>(), w.perm.as<int32_t>(), n, w.fx_shift.as<int32_t>(),
+    launch_finalize(w.acc.as<unsigned long long>(), w.inv.as<int32_t>(), n, w.fx_shift.as<int32_t>(),
                     w.max_acc.as<unsigned long long>(), density, density_norm, max_out, s);
     GM_HIP(hipGetLastError());
     return GM_OK;

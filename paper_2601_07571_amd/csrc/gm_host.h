@@ -126,7 +126,8 @@ constexpr double kGateWiden = 3e-5;
 
 // Device scratch of one density evaluation (one scene, one set of points and fixations).
 struct DensityWork {
-    DevBuf fix, fx_shift, key, hist, cursor, scan_tmp, spos, smesh, perm, acc, max_acc, stats, zcam, zbuf;
+    // inv: the sorted position of every input point (input order)
+    DevBuf fix, fx_shift, key, hist, cursor, scan_tmp, spos, smesh, inv, acc, max_acc, stats, zcam, zbuf;
     DevBuf bface, bcand;  // back-face rule data of the sorted points (see DensityLaunch::bface)
     bool backface = false;  // bface / bcand hold the current points' data
     int bits = 1;

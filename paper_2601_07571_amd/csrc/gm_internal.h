@@ -222,14 +222,14 @@ void launch_morton(const float* pos, const int32_t* tri, const int32_t* mesh, co
                    hipStream_t s);
 void launch_scatter(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
                     int64_t T, int64_t n, const uint32_t* key, uint32_t* cursor, float4* spos, int32_t* smesh,
-                    int32_t* perm, int32_t base, hipStream_t s);
+                    int32_t* inv, int32_t base, hipStream_t s);  // inv[i] = base + sorted position of point i
 void launch_density(const DensityLaunch& a, hipStream_t s);
 // persistent multi-session form: items are (session, tile, chunk, 0); head is zeroed by the caller
 void launch_density_queue(const DensityLaunch* sessions, const int4* items, int32_t n_items, unsigned int* head,
                           int spl, int fb, int grid, hipStream_t s);
 // persistent workgroups that fit on the device at once for that kernel
 int density_queue_grid(int spl, int fb);
-void launch_finalize(const unsigned long long* acc, const int32_t* perm, int64_t n, const int32_t* fx_shift,
+void launch_finalize(const unsigned long long* acc, const int32_t* inv, int64_t n, const int32_t* fx_shift,
                      unsigned long long* max_acc, float* density, float* density_norm, float* max_out,
                      hipStream_t s);
 void launch_pair_values(const float* pos, const FixRec* fix, const int32_t* ps, const int32_t* pf, int64_t m,

@@ -1256,7 +1256,7 @@ __global__ void k_morton(const float* __restrict__ pos, int64_t n, float lox, fl
 __global__ void k_scatter(const float* __restrict__ pos, const int32_t* __restrict__ tri,
                           const int32_t* __restrict__ mesh, const int32_t* __restrict__ tri_mesh, int64_t T, int64_t n,
                           const uint32_t* __restrict__ key, uint32_t* __restrict__ cursor, float4* __restrict__ spos,
-                          int32_t* __restrict__ smesh, int32_t* __restrict__ perm, int32_t base)
+                          int32_t* __restrict__ smesh, int32_t* __restrict__ inv, int32_t base)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1266,7 +1266,7 @@ __global__ void k_scatter(const float* __restrict__ pos, const int32_t* __restri
     const int32_t m = mesh ? mesh[i] : (t >= 0 ? tri_mesh[t] : -1);
     spos[dst] = make_float4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], __int_as_float(t));
     smesh[dst] = m;
-    perm[dst] = base + (int32_t)i;
+    inv[i] = base + (int32_t)dst;  // where input point i sits in sorted order (written in input order)
 }
 
 // ---------------------------------------------------------------------------
@@ -1744,19 +1744,20 @@ __global__ void __launch_bounds__(256) k_max(const unsigned long long* __restric
     }
 }
 
-__global__ void k_finalize(const unsigned long long* __restrict__ acc, const int32_t* __restrict__ perm, int64_t n,
+// In input order: each output is written where the caller expects it (coalesced), and
+// gathers its accumulator from the point's sorted position.
+__global__ void k_finalize(const unsigned long long* __restrict__ acc, const int32_t* __restrict__ inv, int64_t n,
                            const int32_t* __restrict__ shift_p, const unsigned long long* __restrict__ max_acc,
                            float* __restrict__ density, float* __restrict__ density_norm, float* __restrict__ max_out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int shift = *shift_p;
     const unsigned long long mx = *max_acc;
-    if (i == 0 && max_out) *max_out = (float)ldexp((double)mx, -shift);
-    if (i >= n) return;
-    const unsigned long long v = acc[i];
-    const int32_t o = perm[i];
-    if (density) density[o] = (float)ldexp((double)v, -shift);
-    if (density_norm) density_norm[o] = mx ? (float)((double)v / (double)mx) : 0.0f;
+    if (j == 0 && max_out) *max_out = (float)ldexp((double)mx, -shift);
+    if (j >= n) return;
+    const unsigned long long v = acc[inv[j]];
+    if (density) density[j] = (float)ldexp((double)v, -shift);
+    if (density_norm) density_norm[j] = mx ? (float)((double)v / (double)mx) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -1904,11 +1905,11 @@ void launch_morton(const float* pos, const int32_t* tri, const int32_t* mesh, co
 }
 
 void launch_scatter(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh, int64_t T,
-                    int64_t n, const uint32_t* key, uint32_t* cursor, float4* spos, int32_t* smesh, int32_t* perm,
+                    int64_t n, const uint32_t* key, uint32_t* cursor, float4* spos, int32_t* smesh, int32_t* inv,
                     int32_t base, hipStream_t s)
 {
     if (n > 0)
-        k_scatter<<<blocks(n, 256), 256, 0, s>>>(pos, tri, mesh, tri_mesh, T, n, key, cursor, spos, smesh, perm,
+        k_scatter<<<blocks(n, 256), 256, 0, s>>>(pos, tri, mesh, tri_mesh, T, n, key, cursor, spos, smesh, inv,
                                                  base);
 }
 
@@ -1973,11 +1974,11 @@ int density_queue_grid(int spl, int fb)
     return std::max(1, cus) * per;
 }
 
-void launch_finalize(const unsigned long long* acc, const int32_t* perm, int64_t n, const int32_t* fx_shift,
+void launch_finalize(const unsigned long long* acc, const int32_t* inv, int64_t n, const int32_t* fx_shift,
                      unsigned long long* max_acc, float* density, float* density_norm, float* max_out, hipStream_t s)
 {
     if (n > 0) k_max<<<std::min<unsigned>(blocks(n, 256), 512u), 256, 0, s>>>(acc, n, max_acc);
-    k_finalize<<<blocks(n > 0 ? n : 1, 256), 256, 0, s>>>(acc, perm, n, fx_shift, max_acc, density, density_norm,
+    k_finalize<<<blocks(n > 0 ? n : 1, 256), 256, 0, s>>>(acc, inv, n, fx_shift, max_acc, density, density_norm,
                                                           max_out);
 }
 

@@ -1,7 +1,7 @@
 // noalloc_api.cpp -- accumulate_density without device allocation, for callers that
 // cannot allocate (code under HIP graph capture, tight serving loops).  Every
 // intermediate buffer of the density path (fixation records, spatial-sort keys,
-// histogram and scan, sorted points, permutation, fixed-point accumulators, maximum,
+// histogram and scan, sorted points, sorted positions, fixed-point accumulators, maximum,
 // counters, the back-face rule's per-point data) lives in one file-scope device array
 // of fixed size, laid out for at most
 // kMaxPoints points and kMaxFixations fixations.  Each device the library runs on holds
@@ -88,7 +88,7 @@ void borrow_work(unsigned char* base, DensityWork& w)
     take(w.scan_tmp, kScanTmpMax);
     take(w.spos, kSposBytes);
     take(w.smesh, kKeyBytes);
-    take(w.perm, kKeyBytes);
+    take(w.inv, kKeyBytes);
     take(w.acc, kAccBytes);
     take(w.max_acc, 256);
     take(w.stats, kStatsBytes);
