@@ -104,6 +104,30 @@ gm_status ensure_weights(gm_scene* sc, hipStream_t s)
     GM_HIP(hipMemcpyAsync(sc->mesh_total_h.data(), sc->mesh_total.p, 8 * (size_t)M, hipMemcpyDeviceToHost, s));
     GM_HIP(hipMemcpyAsync(sc->S_h.data(), sc->S.p, 4 * (size_t)M, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
+    // the guide table: per mesh about one bucket per triangle (a power of two >= its
+    // triangle count, at most 2^24), each 2^gsh targets wide, plus a closing entry
+    std::vector<int64_t> goff((size_t)M + 1, 0);
+    std::vector<int32_t> gsh((size_t)M, 0);
+    for (int32_t m = 0; m < M; ++m) {
+        const int64_t nt = sc->tri_off[(size_t)m + 1] - sc->tri_off[(size_t)m];
+        int g = 0;
+        while (g < 24 && ((int64_t)1 << g) < nt) ++g;
+        const unsigned long long tot = sc->mesh_total_h[(size_t)m];
+        int len = 0;  // bit length of tot - 1: targets lie in [0, tot)
+        for (unsigned long long v = tot > 1 ? tot - 1 : 0; v; v >>= 1) ++len;
+        gsh[(size_t)m] = std::max(0, len - g);
+        const int64_t buckets = tot > 0 ? (int64_t)((tot - 1) >> gsh[(size_t)m]) + 1 : 1;
+        goff[(size_t)m + 1] = goff[(size_t)m] + buckets + 1;
+    }
+    GM_HIP(sc->goff.ensure(8 * ((size_t)M + 1)));
+    GM_HIP(sc->gsh.ensure(4 * (size_t)M));
+    GM_HIP(sc->guide.ensure(4 * (size_t)goff[(size_t)M]));
+    GM_HIP(hipMemcpyAsync(sc->goff.p, goff.data(), 8 * ((size_t)M + 1), hipMemcpyHostToDevice, s));
+    GM_HIP(hipMemcpyAsync(sc->gsh.p, gsh.data(), 4 * (size_t)M, hipMemcpyHostToDevice, s));
+    launch_sample_guide(sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), sc->goff.as<int64_t>(),
+                        sc->gsh.as<int32_t>(), M, goff[(size_t)M], sc->guide.as<int32_t>(), s);
+    GM_HIP(hipGetLastError());
+    GM_HIP(hipStreamSynchronize(s));  // the host vectors above go out of scope
     sc->weights_ready = true;
     return GM_OK;
 }
@@ -556,8 +580,8 @@ gm_status build_surface_samples(gm_scene* sc, double k, uint64_t seed, int32_t* 
     launch_mesh_counts(sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(), sc->S.as<int32_t>(), sc->M, k,
                        sc->counts.as<int64_t>(), sc->offsets.as<int64_t>(), sc->mesh_total.as<unsigned long long>(), s);
     launch_sample(sc->V.as<float>(), sc->I.as<int32_t>(), sc->C.as<unsigned long long>(), sc->tri_off_d.as<int64_t>(),
-                  sc->offsets.as<int64_t>(), sc->mesh_total.as<unsigned long long>(), sc->M, N, seed, tri, mesh, bary,
-                  pos, s);
+                  sc->offsets.as<int64_t>(), sc->mesh_total.as<unsigned long long>(), sc->guide.as<int32_t>(),
+                  sc->goff.as<int64_t>(), sc->gsh.as<int32_t>(), sc->M, N, seed, tri, mesh, bary, pos, s);
     GM_HIP(hipGetLastError());
     GM_HIP(sc->tend(kStageSample, s));
     return GM_OK;

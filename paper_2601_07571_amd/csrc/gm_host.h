@@ -158,6 +158,10 @@ struct gm_scene {
     // offsets are rewritten by each sampling call; lat_* hold the lattice sampler's
     // per-triangle counts and their scan
     DevBuf area, W, C, max_bits, S, scan_tmp, counts, offsets, mesh_total, lat_W, lat_C;
+    // the sampler's guide table (built with the weights): per mesh m, buckets of equal
+    // width 2^gsh[m] in its target range, guide[goff[m] + k] = the triangle that the
+    // bucket's lowest target selects, and one closing entry per mesh
+    DevBuf guide, goff, gsh;
     bool weights_ready = false;
     std::vector<unsigned long long> mesh_total_h;
     std::vector<int32_t> S_h;

@@ -109,8 +109,14 @@ void launch_mesh_counts(const unsigned long long* C, const int64_t* tri_off, con
                         hipStream_t s);
 // a3: the sampler.
 void launch_sample(const float* V, const int32_t* I, const unsigned long long* C, const int64_t* tri_off,
-                   const int64_t* offsets, const unsigned long long* mesh_total, int32_t M, int64_t N,
-                   uint64_t seed, int32_t* tri, int32_t* mesh, float* bary, float* pos, hipStream_t s);
+                   const int64_t* offsets, const unsigned long long* mesh_total, const int32_t* guide,
+                   const int64_t* goff, const int32_t* gsh, int32_t M, int64_t N, uint64_t seed, int32_t* tri,
+                   int32_t* mesh, float* bary, float* pos, hipStream_t s);
+// guide[goff[m] + k] for k <= (mesh_total[m] - 1) >> gsh[m]: the first triangle t of mesh m
+// with C[t] > C[start of m] + (k << gsh[m]); the entry after the last bucket holds the mesh's
+// last triangle (G entries in all)
+void launch_sample_guide(const unsigned long long* C, const int64_t* tri_off, const int64_t* goff,
+                         const int32_t* gsh, int32_t M, int64_t G, int32_t* guide, hipStream_t s);
 
 // density path
 // in-cone pairs, visible pairs, packet traversals, BVH node visits, triangle tests (wave level),

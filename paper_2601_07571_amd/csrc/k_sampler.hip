@@ -97,11 +97,44 @@ __global__ void k_mesh_counts(const unsigned long long* __restrict__ C, const in
     offsets[M] = run;
 }
 
+// The guide table: for bucket k of mesh m (targets k 2^gsh .. (k + 1) 2^gsh - 1), the
+// triangle that its lowest target selects, found by the full binary search; the closing
+// entry of each mesh is its last triangle.  Selection is monotone in the target, so every
+// target of bucket k selects a triangle between guide[k] and guide[k + 1].
+__global__ void k_sample_guide(const unsigned long long* __restrict__ C, const int64_t* __restrict__ tri_off,
+                               const int64_t* __restrict__ goff, const int32_t* __restrict__ gsh, int32_t M,
+                               int64_t G, int32_t* __restrict__ guide)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= G) return;
+    int32_t lo = 0, hi = M - 1;  // last m with goff[m] <= e
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (goff[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int32_t m = lo;
+    const int64_t a = tri_off[m], b = tri_off[m + 1];
+    if (b <= a) return;
+    const int64_t k = e - goff[m];
+    if (e == goff[m + 1] - 1) {  // closing entry
+        guide[e] = (int32_t)(b - 1);
+        return;
+    }
+    const unsigned long long goal = (a > 0 ? C[a - 1] : 0ull) + ((unsigned long long)k << gsh[m]);
+    int64_t l = a, h = b - 1;
+    while (l < h) {
+        const int64_t mid = l + ((h - l) >> 1);
+        if (C[mid] > goal) h = mid; else l = mid + 1;
+    }
+    guide[e] = (int32_t)l;
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_sample(const float* __restrict__ V, const int32_t* __restrict__ I, const unsigned long long* __restrict__ C,
          const int64_t* __restrict__ tri_off, const int64_t* __restrict__ offsets,
-         const unsigned long long* __restrict__ mesh_total, int32_t M, int64_t N, uint32_t key0, uint32_t key1,
-         int32_t* __restrict__ tri_out, int32_t* __restrict__ mesh_out, float* __restrict__ bary_out,
+         const unsigned long long* __restrict__ mesh_total, const int32_t* __restrict__ guide,
+         const int64_t* __restrict__ goff, const int32_t* __restrict__ gsh, int32_t M, int64_t N, uint32_t key0,
+         uint32_t key1, int32_t* __restrict__ tri_out, int32_t* __restrict__ mesh_out, float* __restrict__ bary_out,
          float* __restrict__ pos_out)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -122,7 +155,9 @@ k_sample(const float* __restrict__ V, const int32_t* __restrict__ I, const unsig
     const uint64_t target = __umul64hi(U, mesh_total[m]);
     const int64_t a = tri_off[m];
     const uint64_t goal = (a > 0 ? C[a - 1] : 0ull) + target;
-    int64_t l = a, h = tri_off[m + 1] - 1;
+    // the guide bucket bounds the search (usually to one or two triangles)
+    const int64_t gk = goff[m] + (int64_t)(target >> gsh[m]);
+    int64_t l = guide[gk], h = guide[gk + 1];
     while (l < h) {
         const int64_t mid = l + ((h - l) >> 1);
         if (C[mid] > goal) h = mid; else l = mid + 1;
@@ -282,12 +317,19 @@ void launch_mesh_counts(const unsigned long long* C, const int64_t* tri_off, con
 }
 
 void launch_sample(const float* V, const int32_t* I, const unsigned long long* C, const int64_t* tri_off,
-                   const int64_t* offsets, const unsigned long long* mesh_total, int32_t M, int64_t N,
-                   uint64_t seed, int32_t* tri, int32_t* mesh, float* bary, float* pos, hipStream_t s)
+                   const int64_t* offsets, const unsigned long long* mesh_total, const int32_t* guide,
+                   const int64_t* goff, const int32_t* gsh, int32_t M, int64_t N, uint64_t seed, int32_t* tri,
+                   int32_t* mesh, float* bary, float* pos, hipStream_t s)
 {
     if (N > 0)
-        k_sample<<<grid_for(N), kBlock, 0, s>>>(V, I, C, tri_off, offsets, mesh_total, M, N, (uint32_t)seed,
-                                                (uint32_t)(seed >> 32), tri, mesh, bary, pos);
+        k_sample<<<grid_for(N), kBlock, 0, s>>>(V, I, C, tri_off, offsets, mesh_total, guide, goff, gsh, M, N,
+                                                (uint32_t)seed, (uint32_t)(seed >> 32), tri, mesh, bary, pos);
+}
+
+void launch_sample_guide(const unsigned long long* C, const int64_t* tri_off, const int64_t* goff,
+                         const int32_t* gsh, int32_t M, int64_t G, int32_t* guide, hipStream_t s)
+{
+    if (G > 0) k_sample_guide<<<grid_for(G), kBlock, 0, s>>>(C, tri_off, goff, gsh, M, G, guide);
 }
 
 void launch_lattice_count(const double* area, int64_t T, double k, unsigned long long* cnt, hipStream_t s)
