@@ -59,6 +59,25 @@ def test_single_triangle_and_zero_area_triangles(gm):
     assert np.all(ref.tri == 0)
 
 
+def test_uneven_areas_and_an_all_degenerate_mesh(gm):
+    """The triangle search starts from a per-mesh guide table of equal-width target buckets:
+    one huge triangle spanning most buckets beside thousands of tiny ones packed into a few,
+    and a mesh whose triangles are all degenerate (no targets, no samples)."""
+    rng = np.random.default_rng(5)
+    n = 5000
+    base = rng.uniform(-1, 1, (n, 3)).astype(np.float32)
+    tiny = np.concatenate([base, base + np.float32(1e-2) * rng.uniform(0, 1, (n, 3)).astype(np.float32),
+                           base + np.float32(1e-2) * rng.uniform(0, 1, (n, 3)).astype(np.float32)])
+    big = np.array([[-3, -3, 0], [3, -3, 0], [0, 3, 0]], np.float32)
+    V = np.concatenate([big, tiny]).astype(np.float32)
+    I = np.concatenate([np.array([[0, 1, 2]]),
+                        np.stack([3 + np.arange(n), 3 + n + np.arange(n), 3 + 2 * n + np.arange(n)], 1)]).astype(np.int32)
+    Vd = np.array([[0, 0, 0], [1, 1, 1], [2, 2, 2]], np.float32)   # collinear: zero area
+    Id = np.array([[0, 1, 2], [2, 1, 0]], np.int32)
+    s, ref = _compare(gm, [(V, I), (Vd, Id)], 3000.0, 11)
+    assert ref.counts[1] == 0 and (ref.tri > 0).any() and (ref.tri == 0).any()
+
+
 def test_capacity_and_argument_errors(gm):
     w = workloads.tiny_icosphere_scene()
     scene = gm.Scene([(m.V, m.I) for m in w.meshes])
