@@ -604,15 +604,31 @@ __device__ __forceinline__ void backface_point(float px, float py, float pz, int
     if (!on || cnt > kBfCand) cnt = -1;
 }
 
+// 2^lg consecutive (sorted) points per wave, the other lanes idle.  A wave's radius queries
+// walk the union of its points' neighbourhoods; when the points are few and sparse (a small
+// session: a few thousand samples over a whole scene) that union spans most of the tree and
+// a handful of such walks take the whole launch, so small launches spread their points over
+// more waves.
+constexpr int64_t kPrepWaves = 4096;  // 16 waves per CU
+
+__host__ __device__ constexpr int prep_lanes_log2(int64_t n)
+{
+    int lg = 6;
+    while (lg > 0 && (n >> lg) < kPrepWaves) --lg;
+    return lg;
+}
+
 __global__ void __launch_bounds__(256) k_backface_prep(const float4* __restrict__ spos,
                                                        const int32_t* __restrict__ smesh, int64_t n,
                                                        const float* __restrict__ V, const int32_t* __restrict__ I,
                                                        const uint8_t* __restrict__ closed,
                                                        const BvhNode* __restrict__ nodes,
-                                                       const BvhTri* __restrict__ tris, float rmax,
+                                                       const BvhTri* __restrict__ tris, float rmax, int lg,
                                                        float4* __restrict__ bface, int32_t* __restrict__ bcand)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)(g & 63);
+    const int64_t i = lane < (1 << lg) ? ((g >> 6) << lg) + lane : n;  // n: an idle lane
     float4 p = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
     int m = -1;
     if (i < n) {
@@ -1992,8 +2008,12 @@ void launch_backface_prep(const float4* spos, const int32_t* smesh, int64_t n, c
                           const uint8_t* closed, const BvhNode* nodes, const BvhTri* tris, float rmax,
                           float4* bface, int32_t* bcand, hipStream_t s)
 {
-    if (n > 0)
-        k_backface_prep<<<blocks(n, 256), 256, 0, s>>>(spos, smesh, n, V, I, closed, nodes, tris, rmax, bface, bcand);
+    if (n > 0) {
+        const int lg = prep_lanes_log2(n);
+        const int64_t waves = (n + (int64_t(1) << lg) - 1) >> lg;
+        k_backface_prep<<<blocks(waves * 64, 256), 256, 0, s>>>(spos, smesh, n, V, I, closed, nodes, tris, rmax, lg,
+                                                                bface, bcand);
+    }
 }
 
 void launch_pair_visibility(const float* pos, const int32_t* tri, const int32_t* mesh, const int32_t* tri_mesh,
