@@ -524,7 +524,7 @@ def bench_field(gm, workloads, torch, np, args, scene, samples, fix, dens, w, k)
     open, plain elsewhere)."""
     res = {}
     tmax = float(dens.max.cpu()[0])
-    field = gm.Field(scene, seed=1, max_cycles=32.0)
+    field = gm.Field(scene, seed=1, max_cycles=128.0)
     t0 = time.perf_counter()
     info = field.train(samples.pos, samples.mesh, dens.density_norm, steps=args.field_steps, batch=16384, lr=3e-3,
                        lr_final=1e-5, max_rel_l2=0.02, target_max=tmax, seed=3)
