@@ -162,3 +162,27 @@ def test_fine_zbuffer_agrees_with_the_exact_test_away_from_the_silhouette():
         errs[name] = np.linalg.norm(zb.rho - ex.rho) / np.linalg.norm(ex.rho)
     assert errs["front"] < 0.01, errs
     assert errs["grazing"] > 5 * errs["front"], errs
+
+
+def test_crop_refusals_in_closed_form():
+    """The two refusals of the crop (a builder rule, not a passage of Appendix A), pinned
+    where they have closed forms.  A gaze along the view axis gets the square of half-width
+    n 4 sigma, whose corners lie atan(4 sigma sqrt 2) off the gaze: refused from 80 degrees
+    on, i.e. from theta = atan(tan 80 / (4 sqrt 2)) = 45.07 deg.  A gaze psi off the view
+    axis has a cone edge psi + phi (phi = atan(4 sigma)) off it, which reaches behind the
+    camera (no crop at all) once psi + phi >= 90 degrees."""
+    cut = math.degrees(math.atan(math.tan(math.radians(80.0)) / (4.0 * math.sqrt(2.0))))
+    assert 45.07 < cut < 45.08
+    for theta, expect in ((10.0, True), (45.0, True), (45.15, False), (60.0, False)):
+        _, ok = oracle.crop_cameras([[0.0, 0.0, -1.0]], None, theta, 0.05)
+        assert bool(ok[0]) is expect, theta
+    psi = math.radians(60.0)
+    gaze = [[math.sin(psi), 0.0, -math.cos(psi)]]
+    head = [[0.0, 0.0, -1.0]]
+    for phi_deg, behind in ((29.5, False), (30.5, True)):
+        theta = math.degrees(math.atan(math.tan(math.radians(phi_deg)) / 4.0))
+        rc = [math.sin(psi), 0.0, -math.cos(psi)]   # the gaze in camera coordinates (right = x)
+        assert (oracle.crop_bounds(rc, theta, 0.05) is None) is behind, phi_deg
+        if behind:
+            _, ok = oracle.crop_cameras(gaze, head, theta, 0.05)
+            assert not ok[0]
