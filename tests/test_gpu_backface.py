@@ -156,3 +156,38 @@ def test_rule_off_by_flag_gives_the_oracle_map_too(gm):
     for o in (on, off):
         parity_util.check(gm, scene, meshes, pos, tri, mesh, w.fix.eye, w.fix.gaze, w.fix.dur, w.theta_deg,
                           oracle.OCC_SELF, o.density.cpu().numpy().astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("lg", range(7))
+def test_preparation_at_every_points_per_wave(gm, lg):
+    """The back-face preparation packs 2^lg sorted points per wave, lg the largest (at most 6)
+    that still leaves 4,096 waves.  Sample counts are chosen here so that every lg occurs: the
+    sphere's map with its closed flag set (the rule settles pairs) against the same map with
+    the flag cleared (every pair walked), which the other tests pin to the oracle.  A point
+    given another point's data would settle pairs the walk finds visible."""
+    import torch
+    w = workloads.tiny_icosphere_scene()
+    meshes = [(m.V, m.I) for m in w.meshes]
+    scene = gm.Scene(meshes)
+    want = int(4096 * (1 << lg) * (1.5 if lg < 6 else 2.0))
+    s = scene.build_samples(want / 3.1266231, 7)
+    n = int(s.pos.shape[0])
+    got = 6
+    while got > 0 and (n >> got) < 4096:
+        got -= 1
+    assert got == lg, (n, got)
+    fix = gm.Fixations(w.fix.eye, w.fix.gaze, w.fix.dur)
+    on = scene.accumulate(s.pos, fix, w.theta_deg, occlusion="self", tri=s.tri, mesh=s.mesh)
+    torch.cuda.synchronize()
+    st_on = scene.density_stats()
+    scene.set_mesh_closed(0, False)
+    off = scene.accumulate(s.pos, fix, w.theta_deg, occlusion="self", tri=s.tri, mesh=s.mesh)
+    torch.cuda.synchronize()
+    st_off = scene.density_stats()
+    assert st_on["backface"] > 0.05 * st_on["in_cone"], st_on
+    assert st_off["backface"] == 0
+    assert st_on["in_cone"] == st_off["in_cone"]
+    assert abs(st_on["visible"] - st_off["visible"]) <= 1e-4 * st_on["in_cone"], (st_on, st_off)
+    a = on.density.cpu().numpy().astype(np.float64); b = off.density.cpu().numpy().astype(np.float64)
+    differ = int(np.count_nonzero(a != b))
+    assert differ <= max(1, int(1e-4 * n)), differ
