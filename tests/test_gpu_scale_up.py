@@ -44,7 +44,7 @@ def test_scale_up_sampled_parity():
     # plus the three samples that an FP32 segment test from the eye once saw edge-on the
     # wrong way (golden/grazing_pairs.json)
     grazing = [11090699, 12686781, 18763059]
-    pick = np.unique(np.concatenate([rng.choice(N, 1200, replace=False), np.argsort(d)[-10:], grazing]))
+    pick = np.unique(np.concatenate([rng.choice(N, 6000, replace=False), np.argsort(d)[-10:], grazing]))
     pos = s.pos.cpu().numpy()[pick]; tri = s.tri.cpu().numpy()[pick]; mesh = s.mesh.cpu().numpy()[pick]
     sc = oracle.Scene(meshes)
     ref = oracle.density(sc, pos, tri, mesh, w.fix.eye, w.fix.gaze, w.fix.dur, w.theta_deg, mode=oracle.OCC_FULL)
