@@ -119,7 +119,7 @@ def test_batch_matches_oracle_and_every_tile_configuration(gm, tmp_path):
     for x, (d, dn, mx) in zip(ss, ref_maps):
         w = x["w"]
         n = len(d)
-        pick = np.unique(np.concatenate([rng.choice(n, min(n, 150), replace=False), np.argsort(d)[-8:]]))
+        pick = np.unique(np.concatenate([rng.choice(n, min(n, 600), replace=False), np.argsort(d)[-8:]]))
         pos = x["pos"].cpu().numpy()[pick]; tri = x["tri"].cpu().numpy()[pick]; mesh = x["mesh"].cpu().numpy()[pick]
         sc = oracle.Scene(x["meshes"])
         ref = oracle.density(sc, pos, tri, mesh, w.fix.eye, w.fix.gaze, w.fix.dur, w.theta_deg, mode=oracle.OCC_FULL)
