@@ -72,6 +72,13 @@ typedef struct gm_scene gm_scene;
  * leaf order).  Blocking.  Rejects: n_meshes < 1 or > 4096, a mesh with no
  * triangles, an index outside its mesh, a non-finite vertex.  Degenerate
  * (zero-area) triangles are accepted: they are never sampled and never occlude.
+ * Three environment variables, read here, override tuning choices for measurement
+ * (results are bit-identical under each; invalid values are ignored):
+ *   GM_BVH_LEAF          most triangles per BVH leaf, 1..4 (default 4);
+ *   GM_SAMPLES_PER_LANE  sample slots per lane of the density kernels, 1, 2 or 4
+ *                        (default 1 with a visibility test, 2 without);
+ *   GM_FIX_PER_CHUNK     fixations per work item of a density launch, > 0
+ *                        (default: chosen per launch from the tile and fixation counts).
  */
 gm_status gm_scene_create(const gm_mesh* meshes, int32_t n_meshes, gm_scene** out);
 gm_status gm_scene_destroy(gm_scene* scene);
