@@ -56,8 +56,8 @@ def main():
                     help="run one plain copy of known size, then one full-occlusion step, and exit (for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the path on a single MI355X "
-              "(the multi-GPU design is described, not launched)", file=sys.stderr)
+        print("bench.py measures one GPU: the path runs on a single MI355X; sharding over "
+              "several GPUs is a design, not an implemented launch", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
