@@ -510,7 +510,13 @@ def bench_batched(gm, workloads, torch, args):
     batch.run()
     batched_ms = _time(batch.run, torch, max(1, args.steps // 2))
     same = all(bool(torch.equal(a.density, b.density)) for a, b in zip(outs, batch.outputs))
-    return {"sessions": 64, "pairs": pairs, "in_cone_pairs": in_cone,
+    tot = {k: float(sum(s[k] for s in st)) for k in ("backface", "traversals", "node_visits", "triangle_tests")}
+    walk = {"backface_rule_pairs": tot["backface"], "packet_traversals": tot["traversals"],
+            "bvh_node_visits": tot["node_visits"], "triangle_tests": tot["triangle_tests"],
+            "walked_pairs_per_traversal": (in_cone - tot["backface"]) / max(tot["traversals"], 1.0),
+            "node_visits_per_traversal": tot["node_visits"] / max(tot["traversals"], 1.0),
+            "triangle_tests_per_traversal": tot["triangle_tests"] / max(tot["traversals"], 1.0)}
+    return {"sessions": 64, "pairs": pairs, "in_cone_pairs": in_cone, "visibility": walk,
             "in_cone_fraction": in_cone / pairs, "plain_sequential_ms": plain_ms, "batched_graph_ms": batched_ms,
             "speedup": plain_ms / batched_ms, "pairs_per_s": pairs / (batched_ms * 1e-3),
             "rays_per_s": in_cone / (batched_ms * 1e-3), "bit_equal_to_plain": same, "plan_and_tune_s": tune_s,
