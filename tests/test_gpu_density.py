@@ -353,3 +353,36 @@ def test_grazing_segments_match_the_oracle(gm):
         want = float(g[0]) if c["oracle_visible"] else 0.0
         assert abs(got - want) <= 1e-5 * want, (c["sample"], got, want)
         scene.close()
+
+
+def test_tuning_overrides_keep_maps_bit_identical(gm, monkeypatch):
+    """The overrides read at scene creation (BVH leaf size, sample slots per lane, fixations
+    per work item) change the launch, not the result: the paper-shaped geometry with fewer
+    samples and fixations gives the same map bits and the same in-cone and visible counts
+    under each."""
+    import torch
+    w = workloads.paper_shaped_scene(n_samples=100_000, F=300)
+    meshes = [(m.V, m.I) for m in w.meshes]
+
+    def run(env):
+        for k in ("GM_BVH_LEAF", "GM_SAMPLES_PER_LANE", "GM_FIX_PER_CHUNK"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        scene = gm.Scene(meshes)
+        s = scene.build_samples(w.k, w.seed)
+        fix = gm.Fixations(w.fix.eye, w.fix.gaze, w.fix.dur)
+        out = scene.accumulate(s.pos, fix, w.theta_deg, occlusion="full", tri=s.tri, mesh=s.mesh)
+        torch.cuda.synchronize()
+        st = scene.density_stats()
+        d = out.density.cpu().numpy().copy()
+        scene.close()
+        return d, st
+
+    base, st0 = run({})
+    assert st0["in_cone"] > 0 and 0 < st0["visible"] < st0["in_cone"] and st0["backface"] > 0
+    for env in ({"GM_BVH_LEAF": "1"}, {"GM_BVH_LEAF": "2"}, {"GM_SAMPLES_PER_LANE": "2"},
+                {"GM_SAMPLES_PER_LANE": "4"}, {"GM_FIX_PER_CHUNK": "37"}):
+        d, st = run(env)
+        assert np.array_equal(d, base), env
+        assert (st["in_cone"], st["visible"]) == (st0["in_cone"], st0["visible"]), (env, st, st0)
