@@ -198,13 +198,15 @@ gm_status check_density_args(const gm_scene* sc, const float* pos, int64_t n, co
 gm_status density_reserve(DensityWork& w, int64_t n, int32_t F)
 {
     // spatial buckets: about one sample per bucket of the scene's box, at most 2^21; launches
-    // of more than 2^20 points take 2^24.  Samples lie on surfaces, so an occupied bucket of
-    // the coarser grid holds about a hundred of them in no particular order (the scatter's
-    // atomic cursor) and a wave's 64 segments would start anywhere in it: on the paper-shaped
-    // map the finer grid cuts node visits by 6 % and triangle tests by 11 % (the same map).
+    // of more than 2^20 points take 2^24, of more than 2^23 points 2^27.  Samples lie on
+    // surfaces, so an occupied bucket of the coarser grid holds about a hundred of them in no
+    // particular order (the scatter's atomic cursor) and a wave's 64 segments would start
+    // anywhere in it: the finer grids cut node visits by 6 % on the paper-shaped map (2M
+    // points) and by 10 % on the scale-up map (20M points).
     int bits = 1;
     while (bits < 7 && ((int64_t)1 << (3 * bits)) < n) ++bits;
     if (n > ((int64_t)1 << 20)) bits = 8;
+    if (n > ((int64_t)1 << 23)) bits = 9;
     w.bits = bits;
     w.buckets = (int64_t)1 << (3 * bits);
     const int64_t nn = std::max<int64_t>(n, 1);

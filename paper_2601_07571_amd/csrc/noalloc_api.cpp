@@ -33,6 +33,7 @@ constexpr int64_t max_buckets()
     int bits = 1;
     while (bits < 7 && ((int64_t)1 << (3 * bits)) < kMaxPoints) ++bits;
     if (kMaxPoints > ((int64_t)1 << 20)) bits = 8;
+    if (kMaxPoints > ((int64_t)1 << 23)) bits = 9;
     return (int64_t)1 << (3 * bits);
 }
 
