@@ -874,7 +874,10 @@ __device__ __forceinline__ unsigned long long to_fixed(float g, int shift)
 __device__ __forceinline__ bool fix_record_v(float ex, float ey, float ez, float rx, float ry, float rz, float t,
                                              double inv_norm, double kappa_scale, float t_cap, FixRec& r)
 {
-    r.ex = ex; r.ey = ey; r.ez = ez;
+    // + 0: a -0 eye coordinate is stored as +0, so that e - x, whose sign the slab inverse
+    // takes, is +0 whenever x equals the eye coordinate (the sign the packet's octant
+    // classification gives a zero component)
+    r.ex = ex + 0.0f; r.ey = ey + 0.0f; r.ez = ez + 0.0f;
     r.rx = rx; r.ry = ry; r.rz = rz;
     const double r2 = (double)r.rx * r.rx + (double)r.ry * r.ry + (double)r.rz * r.rz;
     const bool ok = isfinite(r.ex) && isfinite(r.ey) && isfinite(r.ez) && isfinite(r2) && r2 > 0.0 &&
@@ -1308,7 +1311,11 @@ __device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ no
     int gx, gy;
     cyclic_axes(gz, gx, gy);
     bool shared = true;
-    // per axis: lanes with a segment (any slot) running from the eye towards -axis / +axis
+    // per axis: lanes with a segment (any slot) running from the eye towards -axis / +axis.
+    // An exactly zero component counts as -axis here: the segment then runs towards +axis
+    // for the node copy, as its slab inverse (+1e30 for the +0 of e - x) does; counted by its
+    // sign bit, a +0 would pick the copy stored for the other direction, whose boxes that
+    // lane could miss.
     uint64_t nx_m = 0, ny_m = 0, nz_m = 0, px_m = 0, py_m = 0, pz_m = 0;
     int kz[SPL];
 #pragma unroll
@@ -1316,12 +1323,12 @@ __device__ __forceinline__ void packet_visibility(const BvhNode* __restrict__ no
         const float dx = p[k].x - ex, dy = p[k].y - ey, dz = p[k].z - ez;
         kz[k] = segment_axis(gz, dx, dy, dz);
         shared = shared && (!need[k] || kz[k] == gz);
-        nx_m |= ballot(need[k] && signbit(dx));
-        ny_m |= ballot(need[k] && signbit(dy));
-        nz_m |= ballot(need[k] && signbit(dz));
-        px_m |= ballot(need[k] && !signbit(dx));
-        py_m |= ballot(need[k] && !signbit(dy));
-        pz_m |= ballot(need[k] && !signbit(dz));
+        nx_m |= ballot(need[k] && dx <= 0.0f);
+        ny_m |= ballot(need[k] && dy <= 0.0f);
+        nz_m |= ballot(need[k] && dz <= 0.0f);
+        px_m |= ballot(need[k] && dx > 0.0f);
+        py_m |= ballot(need[k] && dy > 0.0f);
+        pz_m |= ballot(need[k] && dz > 0.0f);
     }
     // ... and every segment of every slot has the same direction signs
     shared = ballot(!shared) == 0 && (nx_m == 0 || px_m == 0) && (ny_m == 0 || py_m == 0) &&
