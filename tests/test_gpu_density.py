@@ -386,3 +386,34 @@ def test_tuning_overrides_keep_maps_bit_identical(gm, monkeypatch):
         d, st = run(env)
         assert np.array_equal(d, base), env
         assert (st["in_cone"], st["visible"]) == (st0["in_cone"], st0["visible"]), (env, st, st0)
+
+
+def test_zero_direction_component_finds_the_occluder(gm):
+    """Points sharing the eye's x coordinate exactly (every segment has a zero x component),
+    all on one side of the eye so that their packets take the shared-octant walk, under an
+    occluding plate: every in-cone pair is occluded (the oracle's answer; the walk once read
+    the node copy of the other x direction for such segments and missed the plate)."""
+    import torch
+    quad = np.array([[-1, -1, 0], [1, -1, 0], [1, 1, 0], [-1, 1, 0]], np.float32)
+    idx = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    lid = quad * np.array([0.5, 0.5, 1.0], np.float32) + np.array([0.0, 0.0, 0.5], np.float32)
+    meshes = [(quad, idx), (lid, idx)]
+    scene = gm.Scene(meshes)
+    s = scene.build_samples(4000.0, 11)
+    pos = s.pos.cpu().numpy().copy(); tri = s.tri.cpu().numpy(); mesh = s.mesh.cpu().numpy()
+    sel = np.nonzero((mesh == 0) & (pos[:, 1] > 0.05) & (pos[:, 1] < 0.3))[0]
+    assert len(sel) > 200
+    pos = pos[sel]; pos[:, 0] = 0.25; pos[:, 2] = 0.0
+    eye = np.array([[0.25, 0.0, 2.0]], np.float32)
+    gaze = np.array([[0.0, 0.1, -1.0]], np.float32)
+    dur = np.array([0.3], np.float32)
+    fix = gm.Fixations(eye, gaze, dur)
+    out = scene.accumulate(torch.from_numpy(pos).cuda(), fix, 5.0, occlusion="full",
+                           tri=torch.from_numpy(tri[sel]).cuda(), mesh=torch.from_numpy(mesh[sel]).cuda())
+    torch.cuda.synchronize()
+    st = scene.density_stats()
+    assert st["in_cone"] == len(sel) and st["traversals"] > 0, st
+    assert st["visible"] == 0, st
+    assert float(out.density.abs().max().cpu()) == 0.0
+    ref = oracle.density(oracle.Scene(meshes), pos, tri[sel], mesh[sel], eye, gaze, dur, 5.0, mode=oracle.OCC_FULL)
+    assert float(np.abs(ref.rho).max()) == 0.0
